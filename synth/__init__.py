@@ -1,0 +1,114 @@
+"""Seeded synthetic workload descriptions shared by tests, bench and oracle
+checks.  Holds none of the generators' arithmetic: only the sizes, seeds,
+offsets and request mixes, drawn from numpy's default_rng with fixed
+meta-seeds (1329 + k for workload k).
+
+Shapes follow the paper's two workloads (arXiv:2109.01329):
+  * the RNG burner: Philox4x32x10 uniform FP32 batches of 1 .. 10^8
+    (Sec. 5.1 and Sec. 6);
+  * FastCaloSim: three uniforms per calorimeter hit, hits per event ranging
+    from a few to O(10^4) secondaries (Sec. 5.2) -- here a lognormal hit
+    count per event plus one Gaussian per hit.
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+
+META_SEED = 1329
+
+PHILOX, MRG = 1, 2
+BITS_U32, UNIFORM_F32, UNIFORM_F64, GAUSSIAN_F32 = 1, 2, 3, 4
+KINDS = (UNIFORM_F32, UNIFORM_F64, GAUSSIAN_F32, BITS_U32)
+ENGINES = (PHILOX, MRG)
+KIND_NAME = {BITS_U32: "bits_u32", UNIFORM_F32: "uniform_f32",
+             UNIFORM_F64: "uniform_f64", GAUSSIAN_F32: "gaussian_f32"}
+ENGINE_NAME = {PHILOX: "philox4x32_10", MRG: "mrg32k3a"}
+ELEM_BYTES = {BITS_U32: 4, UNIFORM_F32: 4, UNIFORM_F64: 8, GAUSSIAN_F32: 4}
+
+
+def rng(k: int) -> np.random.Generator:
+    return np.random.default_rng(META_SEED + k)
+
+
+# --- small single-engine case: Philox, seed 42, offset 0, n = 2^20 -------
+SMALL = dict(engine=PHILOX, seed=42, offset=0, n=1 << 20)
+
+
+# --- plain bulk case: both engines x four outputs, n = 2^28 --------------
+BULK_N = 1 << 28
+
+
+def bulk_draws(count: int = 3):
+    """(engine, kind, seed, offset) cells of the bulk case: seeds uniform in
+    [0, 2^64), offsets uniform in [0, 2^40); `count` draws per cell."""
+    g = rng(2)
+    cells = []
+    for engine in ENGINES:
+        for kind in KINDS:
+            for _ in range(count):
+                seed = int(g.integers(0, 2**64, dtype=np.uint64))
+                offset = int(g.integers(0, 2**40, dtype=np.uint64))
+                cells.append((engine, kind, seed, offset))
+    return cells
+
+
+# --- MRG32k3a substreams: 65536 x 4096 uniform FP64 ----------------------
+SUBSTREAMS = dict(count=65536, per_stream=4096,
+                  check_streams=(0, 1, 2, 3, 4095, 32768, 65534, 65535),
+                  check_len=1024)
+
+
+def substream_seed() -> int:
+    return int(rng(3).integers(0, 2**64, dtype=np.uint64))
+
+
+# --- batched calorimeter-shaped events ----------------------------------
+@dataclasses.dataclass
+class EventBatch:
+    hits: np.ndarray          # hits per event (int64)
+    seed32: int = 42          # low key word shared by all events
+
+    @property
+    def n_events(self) -> int:
+        return int(self.hits.size)
+
+    @property
+    def total_samples(self) -> int:
+        return int(4 * self.hits.sum())
+
+
+def calo_events(n_events: int = 20000, median: float = 2000.0,
+                sigma: float = 1.0, k: int = 4) -> EventBatch:
+    """Hits per event h = max(1, round(exp(ln(median) + sigma N(0,1))))."""
+    g = rng(k)
+    z = g.standard_normal(n_events)
+    h = np.maximum(1, np.rint(np.exp(np.log(median) + sigma * z))).astype(np.int64)
+    return EventBatch(hits=h)
+
+
+# --- served request trace ------------------------------------------------
+@dataclasses.dataclass
+class Trace:
+    arrival_s: np.ndarray     # scheduled arrival times (seconds, from 0)
+    n: np.ndarray             # samples per request
+    engine: np.ndarray        # PHILOX / MRG
+    kind: np.ndarray          # distribution kind
+    seed: np.ndarray          # uint64
+    offset: np.ndarray        # uint64 in [0, 2^40)
+
+
+def request_trace(rate_per_s: float, count: int, k: int = 5,
+                  log10_min: float = 3.0, log10_max: float = 8.0) -> Trace:
+    """Open-loop Poisson arrivals at `rate_per_s`; sizes floor(10^U(a,b));
+    engine and distribution uniform over the 2 x 4 mix."""
+    g = rng(k)
+    gaps = g.exponential(1.0 / rate_per_s, count)
+    arrival = np.cumsum(gaps) - gaps[0]
+    n = np.floor(10.0 ** g.uniform(log10_min, log10_max, count)).astype(np.int64)
+    engine = g.choice(np.array(ENGINES), count)
+    kind = g.choice(np.array(KINDS), count)
+    seed = g.integers(0, 2**64, count, dtype=np.uint64)
+    offset = g.integers(0, 2**40, count, dtype=np.uint64)
+    return Trace(arrival, n, engine, kind, seed, offset)
