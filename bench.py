@@ -1,0 +1,216 @@
+#!/usr/bin/env python3
+"""Benchmark of the mirng hot path on one MI355X.
+
+Headline (one "step"): create a Philox4x32-10 engine at a bulk-workload seed
+and offset and generate n = 2^28 uniform FP32 samples into a resident 1 GiB
+device buffer -- the generator and output the paper measures (Philox4x32x10
+uniform FP32 batches, arXiv:2109.01329 Sec. 6), at the bulk size.  `value`
+is samples per second of those steps (Gsamples/s); the roofline object
+prices the generation kernel's average duration (HIP events on the stream it
+runs on) against HBM write bandwidth.
+
+Also reported (one line, extra keys): every other engine x output cell of
+the bulk workload at n = 2^28, MRG32k3a substreams (65536 x 4096 FP64),
+the store-only and no-store ceilings, and the oracle timed on the host
+cores over the same headline workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--quick]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=20)
+    p.add_argument("--warmup", type=int, default=5)
+    p.add_argument("--quick", action="store_true", help="headline only")
+    p.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
+    return p.parse_args()
+
+
+def time_kernel_calls(fn, reps, stream):
+    """Average duration (ms) of `fn()` over `reps` calls, each bracketed by
+    HIP events recorded on `stream` (the stream the kernels run on)."""
+    import torch
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(reps)]
+    for a, b in evs:
+        a.record(stream)
+        fn()
+        b.record(stream)
+    stream.synchronize()
+    ts = sorted(a.elapsed_time(b) for a, b in evs)
+    return sum(ts) / len(ts), ts[len(ts) // 2], ts[int(0.9 * (len(ts) - 1))]
+
+
+def cpu_baseline(seed, offset, n):
+    """The oracle over the full headline workload, split into consecutive
+    slices over the host's cores (ctypes releases the GIL)."""
+    import concurrent.futures
+    import oracle
+    threads = min(16, os.cpu_count() or 1)
+    step = (n + threads - 1) // threads
+    oracle.lib()
+
+    def one(s):
+        m = min(step, n - s)
+        oracle.philox_generate(seed, offset + s, oracle.UNIFORM_F32, m)
+        return m
+
+    t0 = time.perf_counter()
+    with concurrent.futures.ThreadPoolExecutor(max_workers=threads) as ex:
+        done = sum(ex.map(one, range(0, n, step)))
+    dt = time.perf_counter() - t0
+    return {"value": round(done / dt / 1e9, 4), "unit": "Gsamples/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"full headline workload: {n} Philox4x32-10 uniform FP32 samples "
+                      f"(seed/offset of the bulk draw), {threads} threads, {dt:.2f} s wall"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path "
+              "shards by counter ranges with no exchange, see the design notes", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_2109_01329_amd as mr
+    import synth
+
+    mr.lib()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.Stream()
+    n = synth.BULK_N
+    cells = synth.bulk_draws(count=1)
+    head = [c for c in cells if c[0] == mr.PHILOX4X32_10 and c[1] == mr.UNIFORM_F32][0]
+    _, _, seed, offset = head
+    out = torch.empty(n, dtype=torch.float32, device=dev)
+
+    def step():
+        e = mr.Engine(mr.PHILOX4X32_10, seed, offset)
+        e.generate(mr.UNIFORM_F32, n, out, stream=stream)
+        return e
+
+    with torch.cuda.stream(stream):
+        for _ in range(args.warmup):
+            step()
+        stream.synchronize()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step()
+        stream.synchronize()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+    ms_per_step = wall * 1e3 / args.steps
+    value = n / (wall / args.steps) / 1e9
+
+    # kernel duration of the dominant kernel (one launch per generate)
+    avg_ms, med_ms, p90_ms = time_kernel_calls(step, 50, stream)
+    bytes_per_launch = n * 4
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "philox_fill_kernel<uniform_f32>",
+                "kernel_ms": {"avg": round(avg_ms, 4), "median": round(med_ms, 4),
+                              "p90": round(p90_ms, 4)},
+                "algorithmic_bytes_per_launch": bytes_per_launch}
+
+    extra = {}
+    if not args.quick:
+        # ceilings on the same GPU
+        buf = torch.empty(n * 4, dtype=torch.uint8, device=dev)
+        st_ms = time_kernel_calls(lambda: mr.bench_store(buf, n * 4, True, stream), 20, stream)[0]
+        st2_ms = time_kernel_calls(lambda: mr.bench_store(buf, n * 4, False, stream), 20,
+                                   stream)[0]
+        sink = torch.empty(n // 4 // 64 + 64, dtype=torch.int32, device=dev)
+        ns_ms = time_kernel_calls(lambda: mr.bench_philox_nostore(n // 4, sink, stream=stream),
+                                  20, stream)[0]
+        extra["ceilings"] = {
+            "store_only_nt_GBs": round(n * 4 / (st_ms * 1e-3) / 1e9, 1),
+            "store_only_GBs": round(n * 4 / (st2_ms * 1e-3) / 1e9, 1),
+            "philox_nostore_Gsamples_s": round(n / (ns_ms * 1e-3) / 1e9, 1),
+        }
+        vsink = torch.empty(256 * 4096, dtype=torch.int32, device=dev)
+        rates = {}
+        for op, name in [(0, "mad_u64_u32"), (1, "xor_b32"), (2, "fma_f64"), (3, "floor_f64"),
+                         (4, "fma_f32")]:
+            threads, iters = 256 * 4096, 256
+            ms = time_kernel_calls(lambda: mr.bench_valu(op, threads, iters, vsink, stream), 5,
+                                   stream)[0]
+            rates[name + "_Gops_s"] = round(threads * iters * 8 / (ms * 1e-3) / 1e9, 1)
+        extra["valu_rates"] = rates
+        # every bulk cell
+        res = {}
+        big = torch.empty(n * 2, dtype=torch.float32, device=dev)   # 2 GiB
+        for engine, kind, s, o in cells:
+            name = f"{synth.ENGINE_NAME[engine]}/{synth.KIND_NAME[kind]}"
+
+            def gen(engine=engine, kind=kind, s=s, o=o):
+                mr.Engine(engine, s, o).generate(kind, n, big, stream=stream)
+
+            gen()
+            ms = time_kernel_calls(gen, 10, stream)[0]
+            nbytes = n * synth.ELEM_BYTES[kind]
+            res[name] = {"ms": round(ms, 4), "Gsamples_s": round(n / (ms * 1e-3) / 1e9, 1),
+                         "GBs": round(nbytes / (ms * 1e-3) / 1e9, 1),
+                         "hbm_frac": round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        cfg = synth.SUBSTREAMS
+        e = mr.Engine(mr.MRG32K3A, synth.substream_seed(), 0)
+
+        def subs():
+            e.generate_substreams(mr.UNIFORM_F64, 0, cfg["count"], cfg["per_stream"], big,
+                                  stream=stream)
+
+        subs()
+        ms = time_kernel_calls(subs, 10, stream)[0]
+        tot = cfg["count"] * cfg["per_stream"]
+        res["mrg32k3a/substreams_65536x4096_f64"] = {
+            "ms": round(ms, 4), "Gsamples_s": round(tot / (ms * 1e-3) / 1e9, 1),
+            "GBs": round(tot * 8 / (ms * 1e-3) / 1e9, 1),
+            "hbm_frac": round(tot * 8 / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        extra["cells"] = res
+        del big, buf
+
+    line = {
+        "metric": "Gsamples/s + HBM write GB/s (% peak), Philox FP32 uniform n=2^28; batched p99 ms",
+        "value": round(value, 2),
+        "unit": "Gsamples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "philox4x32_10 uniform_f32 n=2^28, seed/offset from the bulk "
+                               "draw (offset uniform in [0, 2^40))",
+                   "n": n, "seed": seed, "offset": offset, "parallelism": "single GPU"},
+        "write_GBs": round(n * 4 / (ms_per_step * 1e-3) / 1e9, 1),
+        "hbm_write_frac": round(n * 4 / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "roofline": roofline,
+    }
+    line.update(extra)
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(seed, offset, n)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

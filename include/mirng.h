@@ -1,0 +1,198 @@
+/*
+ * mirng -- bulk random-number generation on one AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of the library (libmirng.so).  Plain C types only: device buffers
+ * are passed as raw device pointers and streams as `void *` holding a
+ * hipStream_t (NULL selects the null stream).  No C++ exception, abort or
+ * longjmp crosses this boundary; every entry point returns a mirng_status.
+ *
+ * The operations follow the problem statement of Pascuzzi & Goli,
+ * arXiv:2109.01329:
+ *   - the native host-API flow "create a generator of a type -> set seed and
+ *     offset -> allocate device memory -> generate -> destroy" (Sec. 4.2);
+ *   - oneMKL-style generate calls taking a distribution object with a range
+ *     (a, b) or (mean, standard deviation) (Sec. 4.1, Sec. 4.3 listings);
+ *   - the range transform r * (b - a) + a, which the paper runs as a second
+ *     kernel after vendor generation (Sec. 4.3) and which is fused here
+ *     into the generation kernel's epilogue;
+ *   - pointer-based (USM-style) memory: the caller owns device memory and
+ *     orders work with streams, as the paper's USM API does (Sec. 4.1).
+ * The engines are the ones the paper names (Philox4x32x10 and an MRG-based
+ * generator, Sec. 4.1 and Sec. 6), defined by Salmon et al. (SC'11) and
+ * L'Ecuyer (Oper. Res. 1999); substreams follow L'Ecuyer et al. (Oper.
+ * Res. 2002).
+ *
+ * Conventions (fixed by this library where the paper is silent):
+ *   Philox position p counts 32-bit engine words from the seed state and is
+ *     a 130-bit integer; word p is word (p mod 4) of the Philox4x32-10
+ *     output for the 128-bit counter floor(p / 4); key = (lo32(seed),
+ *     hi32(seed)).
+ *   MRG32k3a position counts recurrence steps; state words are
+ *     (x1[n-3], x1[n-2], x1[n-1], x2[n-3], x2[n-2], x2[n-1]); the seed maps
+ *     to x1 = (lo32(seed) mod m1, 1, 1), x2 = (hi32(seed) mod m2, 1, 1);
+ *     output n is y = x1[n] - x2[n] (+ m1 when x1[n] <= x2[n]), in [1, m1].
+ *   Outputs: bits = the engine word (Philox) or y (MRG); uniform FP32 =
+ *     (w >> 8) * 2^-24; uniform FP64 = 53 bits of two Philox words (first
+ *     word low) * 2^-53, or y / (m1 + 1) for MRG; Gaussian FP32 = Box-Muller
+ *     on word pairs (u1 = ((w_a >> 8) + 1) 2^-24, u2 = (w_b >> 8) 2^-24,
+ *     z0 = sqrt(-2 ln u1) cos(2 pi u2), z1 = ... sin(2 pi u2)).
+ *   Range: uniform r = fma(u, RN(b - a), RN(a)) in the output precision;
+ *     Gaussian r = fma(z, RN32(stddev), RN32(mean)).
+ *   Consumption per call: n words, except uniform FP64 on Philox (2n) and
+ *     Gaussian (2 * ceil(n / 2); for odd n the last z1 is dropped).
+ */
+#ifndef MIRNG_H
+#define MIRNG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MIRNG_ABI_VERSION 1
+
+typedef struct mirng_engine_s *mirng_engine;
+
+typedef enum {
+    MIRNG_PHILOX4X32_10 = 1,
+    MIRNG_MRG32K3A = 2
+} mirng_engine_type;
+
+typedef enum {
+    MIRNG_BITS_U32 = 1,      /* uint32 out, engine words                     */
+    MIRNG_UNIFORM_F32 = 2,   /* float out, [a, b); default (0, 1)            */
+    MIRNG_UNIFORM_F64 = 3,   /* double out, [a, b); default (0, 1)           */
+    MIRNG_GAUSSIAN_F32 = 4   /* float out, mean p0, stddev p1; default (0,1) */
+} mirng_dist_kind;
+
+/* A distribution: kind plus two parameters.  Uniform: p0 = a, p1 = b with
+ * a < b, both finite.  Gaussian: p0 = mean (finite), p1 = stddev (finite,
+ * > 0).  Bits: parameters ignored. */
+typedef struct {
+    int32_t kind;       /* a mirng_dist_kind */
+    int32_t reserved;   /* must be 0 */
+    double p0;
+    double p1;
+} mirng_distribution;
+
+typedef enum {
+    MIRNG_OK = 0,
+    MIRNG_E_INVALID_ARG = 1,   /* bad pointer, alignment, parameter or size */
+    MIRNG_E_UNSUPPORTED = 2,   /* unknown engine type or distribution kind  */
+    MIRNG_E_ALLOC = 3,         /* library-internal allocation failed        */
+    MIRNG_E_LAUNCH = 4,        /* a kernel launch or async copy failed      */
+    MIRNG_E_DEVICE = 5,        /* no usable gfx950 device / runtime error   */
+    MIRNG_E_CAPACITY = 6       /* request can never fit a configured cap    */
+} mirng_status;
+
+/* Engine state, for checkpoint / resume.
+ * Philox: words[0], words[1] = key (k0, k1); words[2..5] = 0;
+ *         pos = 130-bit word position, little-endian 64-bit limbs, pos[2] < 4.
+ * MRG32k3a: words = (x1[n-3], x1[n-2], x1[n-1], x2[n-3], x2[n-2], x2[n-1]),
+ *         x1 words < m1 = 2^32 - 209, x2 words < m2 = 2^32 - 22853, neither
+ *         component all zero; pos = steps since the seed state mod 2^192
+ *         (informational: it does not define the stream). */
+typedef struct {
+    int32_t engine_type;
+    uint32_t words[6];
+    uint32_t reserved;
+    uint64_t pos[3];
+} mirng_state;
+
+/* One independent request of a batch: the same result as
+ * mirng_engine_create(engine_type, seed, offset) followed by
+ * mirng_generate(dist, n, out) on a fresh engine. */
+typedef struct {
+    int32_t engine_type;
+    int32_t reserved;
+    mirng_distribution dist;
+    uint64_t seed;
+    uint64_t offset;   /* words (Philox) or steps (MRG) from the seed state */
+    uint64_t n;        /* outputs */
+    void *out;         /* device pointer, aligned to the output element */
+} mirng_request;
+
+/* ---------------------------------------------------------------- engines */
+
+/* Create an engine of `type` at position `offset` (engine words for Philox,
+ * recurrence steps for MRG32k3a) from the seed state of `seed`.  The library
+ * owns the engine; release it with mirng_engine_destroy.  Host-only: no
+ * device call.  Errors: out == NULL -> INVALID_ARG; unknown type ->
+ * UNSUPPORTED; allocation -> ALLOC (then *out is untouched). */
+mirng_status mirng_engine_create(int32_t type, uint64_t seed, uint64_t offset,
+                                 mirng_engine *out);
+
+/* Destroy an engine.  NULL is accepted and ignored.  Work already enqueued
+ * from this engine is unaffected (it holds no device resources). */
+mirng_status mirng_engine_destroy(mirng_engine e);
+
+/* Advance the engine by n words (Philox, modulo 2^130) or n steps
+ * (MRG32k3a) without generating.  Host-only.  e == NULL -> INVALID_ARG. */
+mirng_status mirng_skip_ahead(mirng_engine e, uint64_t n);
+
+/* Same with a multi-word count n = sum(limbs[i] * 2^(64 i)), i < nlimbs,
+ * nlimbs <= 3 (counts up to 2^192 - 1; e.g. 2^76 for a substream or 2^127
+ * for a stream).  nlimbs > 3, or limbs == NULL with nlimbs > 0 ->
+ * INVALID_ARG and the engine is unchanged. */
+mirng_status mirng_skip_ahead_multi(mirng_engine e, const uint64_t *limbs,
+                                    size_t nlimbs);
+
+/* Copy the engine state out (host memory).  NULL arguments -> INVALID_ARG. */
+mirng_status mirng_engine_get_state(mirng_engine e, mirng_state *s);
+
+/* Replace the engine state.  The state's engine_type must equal the
+ * engine's; Philox pos[2] must be < 4; MRG words must be in range and
+ * neither component all zero.  Otherwise INVALID_ARG, engine unchanged. */
+mirng_status mirng_engine_set_state(mirng_engine e, const mirng_state *s);
+
+/* ---------------------------------------------------------------- generate */
+
+/* Write n outputs of distribution d, drawn from the engine's current
+ * position onward, to the device buffer `out` (caller-owned; element type
+ * per d->kind; must be aligned to the element size), asynchronously on
+ * `stream` (a hipStream_t, NULL = null stream).  The engine advances at
+ * enqueue by the words the call consumes, so generate(n1); generate(n2)
+ * gives the same values as one generate(n1 + n2) (for Gaussians when n1 is
+ * even: an odd n1 drops the second value of its last pair).  No host
+ * synchronisation.
+ * n == 0 -> OK, nothing enqueued, engine unchanged.
+ * Errors (engine unchanged): e, d NULL, or out NULL with n > 0, or
+ * misaligned out, or bad parameters (uniform a >= b or non-finite;
+ * Gaussian stddev <= 0 or non-finite; reserved != 0) -> INVALID_ARG;
+ * unknown kind -> UNSUPPORTED; no usable device -> DEVICE.
+ * A failed kernel launch returns LAUNCH; the engine has then already been
+ * advanced, as the work was accepted for enqueue. */
+mirng_status mirng_generate(mirng_engine e, const mirng_distribution *d,
+                            uint64_t n, void *out, void *stream);
+
+/* MRG32k3a substreams: for s in [first, first + count), write n_each
+ * outputs of d from the state 2^76 * s steps past the engine's current
+ * state into out[(s - first) * n_each ...], contiguous per substream.
+ * One launch.  The engine itself is not advanced.  first + count must not
+ * exceed 2^30 (else INVALID_ARG).  Philox engines -> UNSUPPORTED; other
+ * errors as mirng_generate. */
+mirng_status mirng_generate_substreams(mirng_engine e,
+                                       const mirng_distribution *d,
+                                       uint64_t first, uint64_t count,
+                                       uint64_t n_each, void *out,
+                                       void *stream);
+
+/* ------------------------------------------------------------------ misc */
+
+/* Static description of a status code (never NULL). */
+const char *mirng_status_string(mirng_status s);
+
+/* Library ABI version (MIRNG_ABI_VERSION of the build). */
+int32_t mirng_abi_version(void);
+
+/* Words (Philox) or steps (MRG32k3a) that n outputs of kind consume; 0 for
+ * an unknown kind.  Host-only. */
+uint64_t mirng_words_consumed(int32_t engine_type, int32_t kind, uint64_t n);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MIRNG_H */

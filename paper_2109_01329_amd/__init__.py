@@ -1,0 +1,211 @@
+"""mirng: bulk Philox4x32-10 / MRG32k3a generation on one MI355X (gfx950).
+
+Python binding of libmirng.so (C ABI in include/mirng.h).  This module only
+marshals arguments: every step of generation runs in the library's HIP
+kernels.  PyTorch is used, when given, only for device memory (tensor data
+pointers) and streams.  If the shared library is missing the import of the
+binding fails loudly; there is no fallback implementation.
+
+Build the library with ``python -m paper_2109_01329_amd.build``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmirng.so")
+
+PHILOX4X32_10, MRG32K3A = 1, 2
+BITS_U32, UNIFORM_F32, UNIFORM_F64, GAUSSIAN_F32 = 1, 2, 3, 4
+
+STATUS = {0: "MIRNG_OK", 1: "MIRNG_E_INVALID_ARG", 2: "MIRNG_E_UNSUPPORTED",
+          3: "MIRNG_E_ALLOC", 4: "MIRNG_E_LAUNCH", 5: "MIRNG_E_DEVICE",
+          6: "MIRNG_E_CAPACITY"}
+
+ELEM_BYTES = {BITS_U32: 4, UNIFORM_F32: 4, UNIFORM_F64: 8, GAUSSIAN_F32: 4}
+
+
+class MirngError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {STATUS.get(status, status)}")
+
+
+class Distribution(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("p0", ctypes.c_double), ("p1", ctypes.c_double)]
+
+
+class State(ctypes.Structure):
+    _fields_ = [("engine_type", ctypes.c_int32), ("words", ctypes.c_uint32 * 6),
+                ("reserved", ctypes.c_uint32), ("pos", ctypes.c_uint64 * 3)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("engine_type", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("dist", Distribution), ("seed", ctypes.c_uint64),
+                ("offset", ctypes.c_uint64), ("n", ctypes.c_uint64),
+                ("out", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libmirng.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} not found: build it with "
+                          "`python -m paper_2109_01329_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    E = ctypes.c_void_p
+    vp = ctypes.c_void_p
+    u64 = ctypes.c_uint64
+    sig = {
+        "mirng_engine_create": ([ctypes.c_int32, u64, u64, ctypes.POINTER(E)], ctypes.c_int),
+        "mirng_engine_destroy": ([E], ctypes.c_int),
+        "mirng_skip_ahead": ([E, u64], ctypes.c_int),
+        "mirng_skip_ahead_multi": ([E, ctypes.POINTER(u64), ctypes.c_size_t], ctypes.c_int),
+        "mirng_engine_get_state": ([E, ctypes.POINTER(State)], ctypes.c_int),
+        "mirng_engine_set_state": ([E, ctypes.POINTER(State)], ctypes.c_int),
+        "mirng_generate": ([E, ctypes.POINTER(Distribution), u64, vp, vp], ctypes.c_int),
+        "mirng_generate_substreams": ([E, ctypes.POINTER(Distribution), u64, u64, u64, vp, vp],
+                                      ctypes.c_int),
+        "mirng_status_string": ([ctypes.c_int], ctypes.c_char_p),
+        "mirng_abi_version": ([], ctypes.c_int32),
+        "mirng_words_consumed": ([ctypes.c_int32, ctypes.c_int32, u64], u64),
+        "mirng_bench_store": ([vp, u64, ctypes.c_int32, vp], ctypes.c_int),
+        "mirng_bench_philox_nostore": ([u64, ctypes.c_uint32, ctypes.c_uint32, vp, vp],
+                                       ctypes.c_int),
+        "mirng_bench_valu": ([ctypes.c_int32, ctypes.c_uint32, ctypes.c_uint32, vp, vp],
+                             ctypes.c_int),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+def _check(status: int, where: str) -> None:
+    if status != 0:
+        raise MirngError(status, where)
+
+
+def _limbs(n: int):
+    if n < 0 or n >= 1 << 192:
+        raise ValueError("count must be in [0, 2^192)")
+    return (ctypes.c_uint64 * 3)(*[(n >> (64 * i)) & (2**64 - 1) for i in range(3)])
+
+
+def _ptr(out) -> int:
+    """Device pointer of a torch tensor, or an int taken as a pointer."""
+    if out is None:
+        return 0
+    if isinstance(out, int):
+        return out
+    return int(out.data_ptr())
+
+
+def _stream(stream) -> int:
+    """hipStream_t of a torch stream (current stream when None), or an int."""
+    if isinstance(stream, int):
+        return stream
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream)
+
+
+def words_consumed(engine_type: int, kind: int, n: int) -> int:
+    return int(lib().mirng_words_consumed(engine_type, kind, n))
+
+
+def distribution(kind: int, p0: float | None = None, p1: float | None = None) -> Distribution:
+    if p0 is None:
+        p0 = 0.0
+    if p1 is None:
+        p1 = 1.0
+    return Distribution(kind, 0, float(p0), float(p1))
+
+
+class Engine:
+    """An engine (Philox4x32-10 or MRG32k3a) at a position in its stream."""
+
+    def __init__(self, engine_type: int, seed: int, offset: int = 0):
+        h = ctypes.c_void_p()
+        _check(lib().mirng_engine_create(engine_type, seed & (2**64 - 1), offset,
+                                         ctypes.byref(h)), "engine_create")
+        self._h = h
+        self.engine_type = engine_type
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().mirng_engine_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def skip_ahead(self, n: int) -> None:
+        if n < 2**64:
+            _check(lib().mirng_skip_ahead(self._h, n), "skip_ahead")
+        else:
+            _check(lib().mirng_skip_ahead_multi(self._h, _limbs(n), 3), "skip_ahead_multi")
+
+    def get_state(self) -> State:
+        s = State()
+        _check(lib().mirng_engine_get_state(self._h, ctypes.byref(s)), "get_state")
+        return s
+
+    def set_state(self, s: State) -> None:
+        _check(lib().mirng_engine_set_state(self._h, ctypes.byref(s)), "set_state")
+
+    @property
+    def position(self) -> int:
+        s = self.get_state()
+        return s.pos[0] | (s.pos[1] << 64) | (s.pos[2] << 128)
+
+    def generate(self, kind: int, n: int, out, p0: float | None = None,
+                 p1: float | None = None, stream=None) -> None:
+        """Enqueue n outputs of `kind` into `out` (torch CUDA tensor or device
+        pointer) on `stream`; asynchronous."""
+        d = distribution(kind, p0, p1)
+        _check(lib().mirng_generate(self._h, ctypes.byref(d), n, _ptr(out), _stream(stream)),
+               "generate")
+
+    def generate_substreams(self, kind: int, first: int, count: int, n_each: int, out,
+                            p0: float | None = None, p1: float | None = None,
+                            stream=None) -> None:
+        d = distribution(kind, p0, p1)
+        _check(lib().mirng_generate_substreams(self._h, ctypes.byref(d), first, count, n_each,
+                                               _ptr(out), _stream(stream)),
+               "generate_substreams")
+
+
+# ------------------------------------------------------------ measurement
+
+def bench_store(out, nbytes: int, nontemporal: bool = True, stream=None) -> None:
+    _check(lib().mirng_bench_store(_ptr(out), nbytes, 1 if nontemporal else 0,
+                                   _stream(stream)), "bench_store")
+
+
+def bench_philox_nostore(nblocks: int, sink, k0: int = 1, k1: int = 2, stream=None) -> None:
+    _check(lib().mirng_bench_philox_nostore(nblocks, k0, k1, _ptr(sink), _stream(stream)),
+           "bench_philox_nostore")
+
+
+def bench_valu(op: int, threads: int, iters: int, sink, stream=None) -> None:
+    _check(lib().mirng_bench_valu(op, threads, iters, _ptr(sink), _stream(stream)),
+           "bench_valu")

@@ -1,0 +1,352 @@
+// C-ABI entry points of libmirng.so: argument validation, engine state,
+// the plain generate planner and its launches.
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <new>
+
+#include "internal.hpp"
+
+struct mirng_engine_s {
+    int32_t type;
+    // Philox
+    uint32_t key[2];
+    mirng::Pos130 pos;
+    // MRG32k3a
+    uint32_t st[6];
+    uint64_t steps[3];   // informational position, mod 2^192
+};
+
+namespace mirng {
+
+PhiloxTuning &philox_tuning()
+{
+    static PhiloxTuning t;
+    return t;
+}
+
+namespace {
+
+std::mutex g_dev_mu;
+int g_dev_checked[64];   // 0 unknown, 1 ok, -1 unusable
+int g_dev_cus[64];
+
+}  // namespace
+
+hipError_t ensure_device(int *dev_out)
+{
+    int dev = 0;
+    hipError_t err = hipGetDevice(&dev);
+    if (err != hipSuccess) return err;
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    if (g_dev_checked[dev] == 0) {
+        hipDeviceProp_t prop;
+        err = hipGetDeviceProperties(&prop, dev);
+        if (err != hipSuccess) return err;
+        const bool ok = std::strncmp(prop.gcnArchName, "gfx950", 6) == 0;
+        g_dev_checked[dev] = ok ? 1 : -1;
+        g_dev_cus[dev] = prop.multiProcessorCount;
+    }
+    if (g_dev_checked[dev] < 0) return hipErrorInvalidDeviceFunction;
+    if (dev_out) *dev_out = dev;
+    return hipSuccess;
+}
+
+int device_cu_count()
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    return g_dev_cus[dev] > 0 ? g_dev_cus[dev] : 256;
+}
+
+namespace {
+
+bool finite(double x) { return std::isfinite(x); }
+
+// Validates a distribution; returns MIRNG_OK or the error status.
+mirng_status check_dist(const mirng_distribution *d)
+{
+    if (!d) return MIRNG_E_INVALID_ARG;
+    if (d->reserved != 0) return MIRNG_E_INVALID_ARG;
+    switch (d->kind) {
+    case kBits: return MIRNG_OK;
+    case kU32F:
+    case kU64F:
+        if (!finite(d->p0) || !finite(d->p1) || !(d->p0 < d->p1)) return MIRNG_E_INVALID_ARG;
+        return MIRNG_OK;
+    case kGauss:
+        if (!finite(d->p0) || !finite(d->p1) || !(d->p1 > 0.0)) return MIRNG_E_INVALID_ARG;
+        return MIRNG_OK;
+    default: return MIRNG_E_UNSUPPORTED;
+    }
+}
+
+size_t elem_size(int kind) { return kind == kU64F ? 8 : 4; }
+
+bool is_default(const mirng_distribution *d)
+{
+    return d->kind == kBits || (d->p0 == 0.0 && d->p1 == 1.0);
+}
+
+// Largest number of outputs one Philox fill launch takes (slot indices
+// stay below 2^31).
+constexpr uint64_t kMaxPerLaunch = 1ull << 32;
+
+hipError_t philox_plain(const uint32_t key[2], Pos130 p, const mirng_distribution *d,
+                        uint64_t n, char *out, hipStream_t s)
+{
+    const PhiloxTuning &tu = philox_tuning();
+    const int kind = d->kind;
+    const size_t esz = elem_size(kind);
+    const uint32_t epv = (uint32_t)(16 / esz);
+    const uint32_t wpe = kind == kU64F ? 2u : 1u;   // words per element
+    const bool ranged = !is_default(d);
+    while (n > 0) {
+        uint64_t chunk = n < kMaxPerLaunch ? n : kMaxPerLaunch;
+        const uintptr_t addr = (uintptr_t)out;
+        const uint32_t head = (uint32_t)((addr & 15u) / esz);
+        if (kind == kGauss && (head & 1u)) {
+            PhiloxPairs a{};
+            a.k0 = key[0];
+            a.k1 = key[1];
+            a.p_lo = p.l[0];
+            a.p_mid = p.l[1];
+            a.p_top = (uint32_t)p.l[2];
+            a.n = chunk;
+            a.out = (float *)out;
+            a.mean = (float)d->p0;
+            a.sd = (float)d->p1;
+            a.ranged = ranged ? 1 : 0;
+            hipError_t err = launch_philox_pairs(a, s);
+            if (err != hipSuccess) return err;
+        } else {
+            PhiloxFill a{};
+            a.k0 = key[0];
+            a.k1 = key[1];
+            const Pos130 q = pos_sub_u64(p, (uint64_t)head * wpe);
+            // base = floor(q / 4) as 128 bits; phase = q mod 4
+            const uint64_t b_lo = (q.l[0] >> 2) | (q.l[1] << 62);
+            const uint64_t b_hi = (q.l[1] >> 2) | (q.l[2] << 62);
+            a.base[0] = (uint32_t)b_lo;
+            a.base[1] = (uint32_t)(b_lo >> 32);
+            a.base[2] = (uint32_t)b_hi;
+            a.base[3] = (uint32_t)(b_hi >> 32);
+            a.phase = (uint32_t)(q.l[0] & 3u);
+            a.head = head;
+            a.n = chunk;
+            const uint64_t nslots = (head + chunk + epv - 1) / epv;
+            a.nslots = (uint32_t)nslots;
+            const uint64_t waves_target = (uint64_t)device_cu_count() * tu.waves_per_cu;
+            uint64_t iters = (nslots + 64 * waves_target - 1) / (64 * waves_target);
+            if (iters < (uint64_t)tu.min_iters) iters = tu.min_iters;
+            a.slots_per_wave = (uint32_t)(iters * 64);
+            // complete slots: first element >= 0 and last element < chunk
+            const uint64_t lo = head ? 1 : 0;
+            const uint64_t hi = (head + chunk) / epv;   // slots below hi end inside n
+            a.full_lo = (uint32_t)lo;
+            a.full_count = (uint32_t)(hi > lo ? hi - lo : 0);
+            a.out_base = out - (addr & 15u);
+            a.kind = kind;
+            a.ranged = ranged ? 1 : 0;
+            if (kind == kU64F) {
+                a.a64 = d->p0;
+                a.d64 = d->p1 - d->p0;
+            } else if (kind == kGauss) {
+                a.a32 = (float)d->p0;
+                a.d32 = (float)d->p1;
+            } else {
+                a.a32 = (float)d->p0;
+                a.d32 = (float)(d->p1 - d->p0);
+            }
+            hipError_t err = launch_philox_fill(a, s);
+            if (err != hipSuccess) return err;
+        }
+        p = pos_add_u64(p, words_consumed(MIRNG_PHILOX4X32_10, kind, chunk));
+        out += chunk * esz;
+        n -= chunk;
+    }
+    return hipSuccess;
+}
+
+void steps_add(uint64_t steps[3], const uint64_t *limbs, size_t nlimbs)
+{
+    uint64_t carry = 0;
+    for (int i = 0; i < 3; ++i) {
+        const uint64_t add = (size_t)i < nlimbs ? limbs[i] : 0;
+        const uint64_t s1 = steps[i] + add;
+        const uint64_t c1 = s1 < add ? 1 : 0;
+        const uint64_t s2 = s1 + carry;
+        const uint64_t c2 = s2 < carry ? 1 : 0;
+        steps[i] = s2;
+        carry = c1 | c2;
+    }
+}
+
+}  // namespace
+}  // namespace mirng
+
+using namespace mirng;
+
+// Declared in the MRG translation unit.
+namespace mirng {
+hipError_t mrg_plain(const uint32_t st[6], const mirng_distribution *d, uint64_t n,
+                     char *out, hipStream_t s);
+hipError_t mrg_substreams(const uint32_t st[6], const mirng_distribution *d,
+                          uint64_t first, uint64_t count, uint64_t n_each, char *out,
+                          hipStream_t s);
+}  // namespace mirng
+
+extern "C" {
+
+int32_t mirng_abi_version(void) { return MIRNG_ABI_VERSION; }
+
+const char *mirng_status_string(mirng_status s)
+{
+    switch (s) {
+    case MIRNG_OK: return "ok";
+    case MIRNG_E_INVALID_ARG: return "invalid argument";
+    case MIRNG_E_UNSUPPORTED: return "unsupported engine type or distribution";
+    case MIRNG_E_ALLOC: return "allocation failed";
+    case MIRNG_E_LAUNCH: return "kernel launch failed";
+    case MIRNG_E_DEVICE: return "no usable gfx950 device";
+    case MIRNG_E_CAPACITY: return "request exceeds capacity";
+    default: return "unknown status";
+    }
+}
+
+uint64_t mirng_words_consumed(int32_t engine_type, int32_t kind, uint64_t n)
+{
+    return words_consumed(engine_type, kind, n);
+}
+
+mirng_status mirng_engine_create(int32_t type, uint64_t seed, uint64_t offset,
+                                 mirng_engine *out)
+{
+    if (!out) return MIRNG_E_INVALID_ARG;
+    if (type != MIRNG_PHILOX4X32_10 && type != MIRNG_MRG32K3A) return MIRNG_E_UNSUPPORTED;
+    mirng_engine e = new (std::nothrow) mirng_engine_s();
+    if (!e) return MIRNG_E_ALLOC;
+    e->type = type;
+    if (type == MIRNG_PHILOX4X32_10) {
+        e->key[0] = (uint32_t)seed;
+        e->key[1] = (uint32_t)(seed >> 32);
+        e->pos = Pos130{{offset, 0, 0}};
+    } else {
+        mrg_seed_state(seed, e->st);
+        mrg_jump(e->st, &offset, 1);
+        e->steps[0] = offset;
+    }
+    *out = e;
+    return MIRNG_OK;
+}
+
+mirng_status mirng_engine_destroy(mirng_engine e)
+{
+    delete e;
+    return MIRNG_OK;
+}
+
+mirng_status mirng_skip_ahead_multi(mirng_engine e, const uint64_t *limbs, size_t nlimbs)
+{
+    if (!e || nlimbs > 3 || (nlimbs > 0 && !limbs)) return MIRNG_E_INVALID_ARG;
+    if (e->type == MIRNG_PHILOX4X32_10) {
+        e->pos = pos_add(e->pos, limbs, nlimbs);
+    } else {
+        mrg_jump(e->st, limbs, nlimbs);
+        steps_add(e->steps, limbs, nlimbs);
+    }
+    return MIRNG_OK;
+}
+
+mirng_status mirng_skip_ahead(mirng_engine e, uint64_t n)
+{
+    return mirng_skip_ahead_multi(e, &n, 1);
+}
+
+mirng_status mirng_engine_get_state(mirng_engine e, mirng_state *s)
+{
+    if (!e || !s) return MIRNG_E_INVALID_ARG;
+    std::memset(s, 0, sizeof *s);
+    s->engine_type = e->type;
+    if (e->type == MIRNG_PHILOX4X32_10) {
+        s->words[0] = e->key[0];
+        s->words[1] = e->key[1];
+        for (int i = 0; i < 3; ++i) s->pos[i] = e->pos.l[i];
+    } else {
+        for (int i = 0; i < 6; ++i) s->words[i] = e->st[i];
+        for (int i = 0; i < 3; ++i) s->pos[i] = e->steps[i];
+    }
+    return MIRNG_OK;
+}
+
+mirng_status mirng_engine_set_state(mirng_engine e, const mirng_state *s)
+{
+    if (!e || !s || s->engine_type != e->type) return MIRNG_E_INVALID_ARG;
+    if (e->type == MIRNG_PHILOX4X32_10) {
+        if (s->pos[2] > 3) return MIRNG_E_INVALID_ARG;
+        for (int i = 2; i < 6; ++i)
+            if (s->words[i] != 0) return MIRNG_E_INVALID_ARG;
+        e->key[0] = s->words[0];
+        e->key[1] = s->words[1];
+        for (int i = 0; i < 3; ++i) e->pos.l[i] = s->pos[i];
+    } else {
+        for (int i = 0; i < 3; ++i)
+            if (s->words[i] >= kM1 || s->words[3 + i] >= kM2) return MIRNG_E_INVALID_ARG;
+        if (!(s->words[0] | s->words[1] | s->words[2])) return MIRNG_E_INVALID_ARG;
+        if (!(s->words[3] | s->words[4] | s->words[5])) return MIRNG_E_INVALID_ARG;
+        for (int i = 0; i < 6; ++i) e->st[i] = s->words[i];
+        for (int i = 0; i < 3; ++i) e->steps[i] = s->pos[i];
+    }
+    return MIRNG_OK;
+}
+
+mirng_status mirng_generate(mirng_engine e, const mirng_distribution *d, uint64_t n,
+                            void *out, void *stream)
+{
+    if (!e || !d) return MIRNG_E_INVALID_ARG;
+    const mirng_status ds = check_dist(d);
+    if (ds != MIRNG_OK) return ds;
+    if (n == 0) return MIRNG_OK;
+    if (!out) return MIRNG_E_INVALID_ARG;
+    if (((uintptr_t)out) % elem_size(d->kind) != 0) return MIRNG_E_INVALID_ARG;
+    if (ensure_device(nullptr) != hipSuccess) return MIRNG_E_DEVICE;
+    hipStream_t s = (hipStream_t)stream;
+    const uint64_t consumed = words_consumed(e->type, d->kind, n);
+    hipError_t err;
+    if (e->type == MIRNG_PHILOX4X32_10) {
+        const Pos130 p = e->pos;
+        e->pos = pos_add_u64(e->pos, consumed);
+        err = philox_plain(e->key, p, d, n, (char *)out, s);
+    } else {
+        uint32_t st[6];
+        std::memcpy(st, e->st, sizeof st);
+        mrg_jump(e->st, &consumed, 1);
+        steps_add(e->steps, &consumed, 1);
+        err = mrg_plain(st, d, n, (char *)out, s);
+    }
+    return err == hipSuccess ? MIRNG_OK : MIRNG_E_LAUNCH;
+}
+
+mirng_status mirng_generate_substreams(mirng_engine e, const mirng_distribution *d,
+                                       uint64_t first, uint64_t count, uint64_t n_each,
+                                       void *out, void *stream)
+{
+    if (!e || !d) return MIRNG_E_INVALID_ARG;
+    if (e->type != MIRNG_MRG32K3A) return MIRNG_E_UNSUPPORTED;
+    const mirng_status ds = check_dist(d);
+    if (ds != MIRNG_OK) return ds;
+    if (count == 0 || n_each == 0) return MIRNG_OK;
+    if (!out) return MIRNG_E_INVALID_ARG;
+    if (((uintptr_t)out) % elem_size(d->kind) != 0) return MIRNG_E_INVALID_ARG;
+    if (first >= (1ull << 30) || count > (1ull << 30) || first + count > (1ull << 30))
+        return MIRNG_E_INVALID_ARG;
+    if (ensure_device(nullptr) != hipSuccess) return MIRNG_E_DEVICE;
+    hipError_t err = mrg_substreams(e->st, d, first, count, n_each, (char *)out,
+                                    (hipStream_t)stream);
+    return err == hipSuccess ? MIRNG_OK : MIRNG_E_LAUNCH;
+}
+
+}  // extern "C"

@@ -1,0 +1,110 @@
+// Library-internal declarations shared by the host code and the kernel
+// translation units of libmirng.so.  Nothing here is part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "mirng.h"
+
+namespace mirng {
+
+// ------------------------------------------------------------ constants
+// Philox4x32-10 (Salmon et al., SC'11): multipliers and Weyl key bumps.
+constexpr uint32_t kPhiloxM0 = 0xD2511F53u;
+constexpr uint32_t kPhiloxM1 = 0xCD9E8D57u;
+constexpr uint32_t kPhiloxW0 = 0x9E3779B9u;
+constexpr uint32_t kPhiloxW1 = 0xBB67AE85u;
+
+// MRG32k3a (L'Ecuyer 1999): moduli and multipliers.
+constexpr uint64_t kM1 = 4294967087ull;   // 2^32 - 209
+constexpr uint64_t kM2 = 4294944443ull;   // 2^32 - 22853
+constexpr uint64_t kA12 = 1403580ull;     // x1[n] uses  a12 x1[n-2]
+constexpr uint64_t kA13 = 810728ull;      //           - a13 x1[n-3]
+constexpr uint64_t kA21 = 527612ull;      // x2[n] uses  a21 x2[n-1]
+constexpr uint64_t kA23 = 1370589ull;     //           - a23 x2[n-3]
+
+// ------------------------------------------------------------ host math
+// 130-bit Philox word position, little-endian 64-bit limbs, l[2] < 4.
+struct Pos130 {
+    uint64_t l[3];
+};
+
+Pos130 pos_add(Pos130 p, const uint64_t *limbs, size_t nlimbs);
+Pos130 pos_add_u64(Pos130 p, uint64_t n);
+Pos130 pos_sub_u64(Pos130 p, uint64_t n);
+
+// 3x3 matrix modulo m, row-major.
+struct Mat3 {
+    uint32_t a[9];
+};
+
+Mat3 mat_identity();
+Mat3 mat_mul(const Mat3 &x, const Mat3 &y, uint64_t m);
+void mat_vec(const Mat3 &x, const uint32_t v[3], uint64_t m, uint32_t out[3]);
+Mat3 mat_pow_u64(const Mat3 &x, uint64_t n, uint64_t m);
+// Companion matrices of the two components acting on (x[n-3], x[n-2], x[n-1]).
+const Mat3 &mrg_a1();
+const Mat3 &mrg_a2();
+// Jump table A^(2^k), k < 192, for component c (0 or 1).
+const Mat3 &mrg_pow2(int comp, int k);
+// state <- A^n state, n = sum limbs[i] 2^(64 i).
+void mrg_jump(uint32_t st[6], const uint64_t *limbs, size_t nlimbs);
+void mrg_seed_state(uint64_t seed, uint32_t st[6]);
+
+uint64_t words_consumed(int engine_type, int kind, uint64_t n);
+
+// ------------------------------------------------------------ launches
+enum Kind : int32_t { kBits = 1, kU32F = 2, kU64F = 3, kGauss = 4 };
+
+// One Philox fill launch.  The output is viewed as 16-byte slots starting
+// at out_base (16-byte aligned); slot s receives engine words
+// q + 4 s .. q + 4 s + 3, where q = 4 * base + phase.  Element j of slot s is
+// output index s * epv + j - head; only indices in [0, n) are written.
+struct PhiloxFill {
+    uint32_t k0, k1;
+    uint32_t base[4];       // 128-bit block index of q
+    uint32_t phase;         // q mod 4
+    uint32_t head;          // elements of slot 0 before the first output
+    uint64_t n;             // outputs in this launch
+    uint32_t nslots;
+    uint32_t slots_per_wave;
+    uint32_t full_lo;       // slots [full_lo, full_lo + full_count) are complete
+    uint32_t full_count;
+    char *out_base;
+    float a32, d32;         // uniform F32: fma(u, d, a); Gaussian: fma(z, sd, mean)
+    double a64, d64;        // uniform F64
+    int32_t kind;
+    int32_t ranged;         // 0 when the parameters are the defaults
+};
+
+// Gaussian output whose 16-byte slots do not line up with word pairs (the
+// output pointer is 4 mod 8): one thread per pair, element stores.
+struct PhiloxPairs {
+    uint32_t k0, k1;
+    uint64_t p_lo, p_mid;   // word position of pair 0 (130-bit, top in p_top)
+    uint32_t p_top;
+    uint64_t n;
+    float *out;
+    float mean, sd;
+    int32_t ranged;
+};
+
+hipError_t launch_philox_fill(const PhiloxFill &a, hipStream_t s);
+hipError_t launch_philox_pairs(const PhiloxPairs &a, hipStream_t s);
+
+// Launch geometry knobs (plain path); the autotuner may override them.
+struct PhiloxTuning {
+    int block = 256;          // threads per workgroup
+    int waves_per_cu = 32;    // resident-wave target used to size the grid
+    int min_iters = 4;        // minimum 64-slot iterations per wave
+    int nontemporal = 1;      // streaming stores
+};
+PhiloxTuning &philox_tuning();
+
+int device_cu_count();
+hipError_t ensure_device(int *dev);
+
+}  // namespace mirng

@@ -1,0 +1,157 @@
+"""Host-side tests of libmirng.so that launch nothing: every symbol the
+headers declare is exported, engine state and skip-ahead (the library's
+matrix-power jumps) agree with the oracle's polynomial jumps, and argument
+validation returns the documented status without touching the device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2109_01329_amd as mr
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+M1, M2 = 2**32 - 209, 2**32 - 22853
+
+
+@pytest.fixture(scope="module")
+def L():
+    return mr.lib()
+
+
+def _declared_symbols():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", fn)).read()
+            src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+            names |= set(re.findall(r"\b(mirng_\w+)\s*\(", src))
+    return names
+
+
+def test_exports_every_declared_symbol(L):
+    names = _declared_symbols()
+    assert "mirng_generate" in names and "mirng_engine_create" in names
+    for n in sorted(names):
+        assert hasattr(L, n), n
+
+
+def test_abi_version_and_status_strings(L):
+    assert L.mirng_abi_version() == 1
+    for s in range(7):
+        assert L.mirng_status_string(s)
+    assert L.mirng_status_string(99) == b"unknown status"
+
+
+def test_philox_state_from_seed_and_offset():
+    e = mr.Engine(mr.PHILOX4X32_10, 0x1122334455667788, 12345)
+    s = e.get_state()
+    assert (s.words[0], s.words[1]) == (0x55667788, 0x11223344)
+    assert e.position == 12345
+    e.skip_ahead(2**64 + 7)
+    assert e.position == 12345 + 2**64 + 7
+    e.skip_ahead(2**130 - 1)          # wraps modulo 2^130
+    assert e.position == 12345 + 2**64 + 6
+
+
+def test_mrg_create_matches_oracle_jump(orc):
+    g = np.random.default_rng(41)
+    for _ in range(20):
+        seed = int(g.integers(0, 2**64, dtype=np.uint64))
+        off = int(g.integers(0, 2**40, dtype=np.uint64))
+        e = mr.Engine(mr.MRG32K3A, seed, off)
+        s = e.get_state()
+        want = orc.mrg_skip(orc.mrg_seed(seed), off)
+        assert [int(x) for x in s.words] == [int(x) for x in want]
+        assert e.position == off
+
+
+@pytest.mark.parametrize("n", [1, 2**63 + 5, 2**76, 3 * 2**76 + 1, 2**127, 2**191 + 99])
+def test_mrg_skip_multi_matches_oracle(orc, n):
+    e = mr.Engine(mr.MRG32K3A, 7, 0)
+    e.skip_ahead(n)
+    want = orc.mrg_skip(orc.mrg_seed(7), n)
+    assert [int(x) for x in e.get_state().words] == [int(x) for x in want]
+
+
+def test_state_round_trip_and_validation():
+    e = mr.Engine(mr.MRG32K3A, 99, 5)
+    s = e.get_state()
+    f = mr.Engine(mr.MRG32K3A, 1, 0)
+    f.set_state(s)
+    assert list(f.get_state().words) == list(s.words)
+    bad = mr.State.from_buffer_copy(s)
+    bad.words[0] = M1
+    with pytest.raises(mr.MirngError):
+        f.set_state(bad)
+    zero = mr.State.from_buffer_copy(s)
+    zero.words[0] = zero.words[1] = zero.words[2] = 0
+    with pytest.raises(mr.MirngError):
+        f.set_state(zero)
+    p = mr.Engine(mr.PHILOX4X32_10, 3, 0)
+    with pytest.raises(mr.MirngError):
+        p.set_state(s)                    # engine type mismatch
+    ps = p.get_state()
+    ps.pos[2] = 4
+    with pytest.raises(mr.MirngError):
+        p.set_state(ps)
+
+
+def test_words_consumed():
+    assert mr.words_consumed(1, mr.UNIFORM_F64, 5) == 10
+    assert mr.words_consumed(2, mr.UNIFORM_F64, 5) == 5
+    assert mr.words_consumed(1, mr.GAUSSIAN_F32, 5) == 6
+    assert mr.words_consumed(2, mr.BITS_U32, 5) == 5
+    assert mr.words_consumed(1, 77, 5) == 0
+
+
+def _gen(L, e, kind, n, out, p0=0.0, p1=1.0, reserved=0):
+    d = mr.Distribution(kind, reserved, p0, p1)
+    return L.mirng_generate(e.handle, ctypes.byref(d), n, out, None)
+
+
+def test_generate_validation_without_device(L):
+    """Validation happens before any device call and leaves the engine as
+    it was."""
+    e = mr.Engine(mr.PHILOX4X32_10, 1, 10)
+    fake = 0x10000
+    assert _gen(L, e, mr.UNIFORM_F32, 0, None) == 0               # n == 0: no-op
+    assert _gen(L, e, mr.UNIFORM_F32, 8, None) == 1               # NULL out
+    assert _gen(L, e, mr.UNIFORM_F32, 8, fake + 2) == 1           # misaligned F32
+    assert _gen(L, e, mr.UNIFORM_F64, 8, fake + 4) == 1           # misaligned F64
+    assert _gen(L, e, mr.UNIFORM_F32, 8, fake, 1.0, 1.0) == 1     # a >= b
+    assert _gen(L, e, mr.UNIFORM_F32, 8, fake, float("nan"), 1.0) == 1
+    assert _gen(L, e, mr.UNIFORM_F64, 8, fake, 0.0, float("inf")) == 1
+    assert _gen(L, e, mr.GAUSSIAN_F32, 8, fake, 0.0, 0.0) == 1    # stddev <= 0
+    assert _gen(L, e, mr.GAUSSIAN_F32, 8, fake, 0.0, -1.0) == 1
+    assert _gen(L, e, mr.UNIFORM_F32, 8, fake, reserved=1) == 1
+    assert _gen(L, e, 9, 8, fake) == 2                            # unknown kind
+    d = mr.Distribution(mr.UNIFORM_F32, 0, 0.0, 1.0)
+    assert L.mirng_generate(None, ctypes.byref(d), 8, fake, None) == 1
+    assert L.mirng_generate(e.handle, None, 8, fake, None) == 1
+    assert e.position == 10
+
+
+def test_engine_create_validation(L):
+    h = ctypes.c_void_p()
+    assert L.mirng_engine_create(3, 1, 0, ctypes.byref(h)) == 2
+    assert L.mirng_engine_create(1, 1, 0, None) == 1
+    assert L.mirng_engine_destroy(None) == 0
+    lim = (ctypes.c_uint64 * 4)(1, 2, 3, 4)
+    e = mr.Engine(mr.MRG32K3A, 1, 0)
+    before = list(e.get_state().words)
+    assert L.mirng_skip_ahead_multi(e.handle, lim, 4) == 1
+    assert L.mirng_skip_ahead_multi(e.handle, None, 2) == 1
+    assert list(e.get_state().words) == before
+
+
+def test_substream_validation(L):
+    d = mr.Distribution(mr.UNIFORM_F64, 0, 0.0, 1.0)
+    p = mr.Engine(mr.PHILOX4X32_10, 1, 0)
+    assert L.mirng_generate_substreams(p.handle, ctypes.byref(d), 0, 4, 16, 0x10000, None) == 2
+    m = mr.Engine(mr.MRG32K3A, 1, 0)
+    assert L.mirng_generate_substreams(m.handle, ctypes.byref(d), 0, 4, 16, None, None) == 1
+    assert L.mirng_generate_substreams(m.handle, ctypes.byref(d), 2**30, 1, 16, 0x10000,
+                                       None) == 1
+    assert L.mirng_generate_substreams(m.handle, ctypes.byref(d), 0, 0, 16, None, None) == 0

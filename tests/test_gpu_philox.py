@@ -1,0 +1,115 @@
+"""GPU parity of the Philox4x32-10 path against the oracle, through the C ABI:
+bit-exact bits and uniforms, Gaussians within 2 ulp of the FP64 transform,
+at every engine-position phase, output alignment, ragged size, counter
+carry and the 2^130 wrap."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2109_01329_amd as mr
+from tests import gpu_helpers as gh
+
+pytestmark = pytest.mark.gpu
+
+KINDS = [mr.BITS_U32, mr.UNIFORM_F32, mr.UNIFORM_F64, mr.GAUSSIAN_F32]
+
+
+def test_small_case_seed42():
+    """Seed 42, offset 0: 2^20 uniform FP32 and 2^20 bits from engines at the
+    same position, and one engine producing uniforms then bits."""
+    n = 1 << 20
+    e = mr.Engine(mr.PHILOX4X32_10, 42, 0)
+    u, _ = gh.generate(e, mr.UNIFORM_F32, n)
+    gh.assert_match(mr.UNIFORM_F32, u, gh.oracle_philox(42, 0, mr.UNIFORM_F32, n))
+    b_same_engine, _ = gh.generate(e, mr.BITS_U32, n)
+    gh.assert_match(mr.BITS_U32, b_same_engine, gh.oracle_philox(42, n, mr.BITS_U32, n))
+    f = mr.Engine(mr.PHILOX4X32_10, 42, 0)
+    b, _ = gh.generate(f, mr.BITS_U32, n)
+    gh.assert_match(mr.BITS_U32, b, gh.oracle_philox(42, 0, mr.BITS_U32, n))
+    assert e.position == 2 * n
+
+
+POSITIONS = [0, 1, 2, 3, 12345, (1 << 34) - 5, (1 << 66) - 3, (1 << 98) - 1,
+             (1 << 130) - 7]
+SIZES = [1, 2, 3, 5, 17, 255, 4097, 70001]
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_phases_alignments_sizes(kind):
+    esz = mr.ELEM_BYTES[kind]
+    offsets = [0, 4, 8, 12] if esz == 4 else [0, 8]
+    seed = 0x0123456789ABCDEF
+    for pos in POSITIONS:
+        for off in offsets:
+            for n in SIZES:
+                e = mr.Engine(mr.PHILOX4X32_10, seed, 0)
+                e.skip_ahead(pos)
+                got, buf = gh.generate(e, kind, n, off)
+                want = gh.oracle_philox(seed, pos, kind, n)
+                gh.assert_match(kind, got, want)
+                assert gh.guards_intact(buf, off, n * esz), (pos, off, n)
+                assert e.position == (pos + mr.words_consumed(1, kind, n)) % (1 << 130)
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_continuity_across_calls(kind):
+    g = np.random.default_rng(51)
+    for _ in range(6):
+        seed = int(g.integers(0, 2**64, dtype=np.uint64))
+        off = int(g.integers(0, 2**40, dtype=np.uint64))
+        n1 = int(g.integers(1, 5000)) * (2 if kind == mr.GAUSSIAN_F32 else 1)
+        n2 = int(g.integers(1, 5000))
+        e = mr.Engine(mr.PHILOX4X32_10, seed, off)
+        a, _ = gh.generate(e, kind, n1)
+        b, _ = gh.generate(e, kind, n2)
+        f = mr.Engine(mr.PHILOX4X32_10, seed, off)
+        c, _ = gh.generate(f, kind, n1 + n2)
+        gh.assert_match(kind, np.concatenate([a, b]), gh.oracle_philox(seed, off, kind, n1 + n2))
+        if kind != mr.GAUSSIAN_F32:
+            assert np.array_equal(np.concatenate([a, b]).view(np.uint8), c.view(np.uint8))
+
+
+@pytest.mark.parametrize("kind,p0,p1", [
+    (mr.UNIFORM_F32, -3.0, 5.0), (mr.UNIFORM_F32, 1e-3, 2e-3), (mr.UNIFORM_F32, 100.0, 101.5),
+    (mr.UNIFORM_F64, -1.0, 0.0), (mr.UNIFORM_F64, 1e-3, 2e-3),
+    (mr.GAUSSIAN_F32, 2.5, 0.5), (mr.GAUSSIAN_F32, -1.0, 3.0)])
+def test_range_and_moments_parameters(kind, p0, p1):
+    n = 100003
+    for off in (0, 4 if mr.ELEM_BYTES[kind] == 4 else 8):
+        e = mr.Engine(mr.PHILOX4X32_10, 77, 3)
+        got, _ = gh.generate(e, kind, n, off, p0, p1)
+        gh.assert_match(kind, got, gh.oracle_philox(77, 3, kind, n, p0, p1), p0, p1)
+
+
+def test_gaussian_odd_offset_pairs_path():
+    """Output 4 mod 8 bytes: the pair kernel; odd n drops the last z1."""
+    for pos in (0, 1, 2, 3, (1 << 66) - 1):
+        for n in (1, 2, 7, 1000, 65537):
+            e = mr.Engine(mr.PHILOX4X32_10, 5, 0)
+            e.skip_ahead(pos)
+            got, buf = gh.generate(e, mr.GAUSSIAN_F32, n, 4)
+            gh.assert_match(mr.GAUSSIAN_F32, got, gh.oracle_philox(5, pos, mr.GAUSSIAN_F32, n))
+            assert gh.guards_intact(buf, 4, 4 * n)
+
+
+def test_many_seeds_bits():
+    g = np.random.default_rng(52)
+    for _ in range(40):
+        seed = int(g.integers(0, 2**64, dtype=np.uint64))
+        pos = int(g.integers(0, 2**62, dtype=np.uint64)) << int(g.integers(0, 66))
+        n = int(g.integers(1, 20000))
+        e = mr.Engine(mr.PHILOX4X32_10, seed, 0)
+        e.skip_ahead(pos)
+        got, _ = gh.generate(e, mr.BITS_U32, n, 4 * int(g.integers(0, 4)))
+        gh.assert_match(mr.BITS_U32, got, gh.oracle_philox(seed, pos, mr.BITS_U32, n))
+
+
+def test_gaussian_error_distribution():
+    """Worst error of 2^22 Gaussians in ulp of the FP64 transform."""
+    n = 1 << 22
+    e = mr.Engine(mr.PHILOX4X32_10, 2024, 0)
+    got, _ = gh.generate(e, mr.GAUSSIAN_F32, n)
+    want = gh.oracle_philox(2024, 0, mr.GAUSSIAN_F32, n)
+    worst = gh.assert_match(mr.GAUSSIAN_F32, got, want)
+    # in tolerance units (2 ulp): the kernel rounds an FP64 value once
+    assert worst <= 0.5 * 1.02
