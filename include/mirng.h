@@ -179,6 +179,33 @@ mirng_status mirng_generate_substreams(mirng_engine e,
                                        uint64_t n_each, void *out,
                                        void *stream);
 
+/* ------------------------------------------------------ launch configuration */
+
+/* Launch shape of the Philox kernels: the search space of the autotuner.
+ * It changes only speed: every output is the same under every valid shape.
+ * walk 0: each wave owns a contiguous run of 16-byte outputs and the grid
+ *   holds CUs * waves_per_cu waves of work (any kind, any position).
+ * walk 1: a persistent grid of CUs * waves_per_cu resident waves walks the
+ *   output grid-stride, blocks_per_lane Philox blocks per lane per step;
+ *   used where outputs do not straddle Philox blocks (bits and uniform FP32
+ *   at any position, FP64 and Gaussian at even positions), walk 0 elsewhere.
+ * Process-wide; set it while no generate call is being enqueued. */
+typedef struct {
+    int32_t walk;             /* 0 contiguous runs, 1 grid-stride               */
+    int32_t block;            /* threads per workgroup: 64, 128, 256, 512, 1024 */
+    int32_t waves_per_cu;     /* walk 0: 1..4096; walk 1: 1..64                  */
+    int32_t blocks_per_lane;  /* walk 1: 1, 2 or 4 (ignored by walk 0)          */
+    int32_t nontemporal;      /* 0: plain stores, 1: streaming (nt) stores       */
+    int32_t reserved;         /* must be 0 */
+} mirng_philox_config;
+
+/* Copy the current shape out.  c == NULL -> INVALID_ARG. */
+mirng_status mirng_philox_config_get(mirng_philox_config *c);
+
+/* Install a shape.  c == NULL or any field out of range -> INVALID_ARG and
+ * the current shape is kept.  Host-only. */
+mirng_status mirng_philox_config_set(const mirng_philox_config *c);
+
 /* ------------------------------------------------------------------ misc */
 
 /* Static description of a status code (never NULL). */

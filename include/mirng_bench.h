@@ -23,24 +23,24 @@ extern "C" {
 #endif
 
 /* Write `bytes` (a multiple of 16) of a constant pattern to `out` (16-byte
- * aligned device buffer) with one 16-byte store per lane per iteration,
- * in the launch shape of the Philox kernel.  nontemporal != 0 uses
+ * aligned device buffer) with one 16-byte store per lane per step, in the
+ * walk and launch shape the Philox configuration selects.  nontemporal != 0 uses
  * streaming stores.  Errors: NULL out, bytes % 16 != 0 or misaligned out
  * -> INVALID_ARG; launch -> LAUNCH. */
 mirng_status mirng_bench_store(void *out, uint64_t bytes, int32_t nontemporal,
                                void *stream);
 
 /* Evaluate `nblocks` Philox4x32-10 blocks (counter = block index, key =
- * (k0, k1)) in the launch shape of the Philox kernel and XOR-fold them into
- * one word per wave written to `sink` (device, >= nblocks / 64 + 1 words):
- * the generation work without its stores. */
+ * (k0, k1)) on a persistent grid-stride grid and XOR-fold them into one
+ * word per wave written to `sink` (device, at least CUs * 64 words): the
+ * generation work without its stores. */
 mirng_status mirng_bench_philox_nostore(uint64_t nblocks, uint32_t k0, uint32_t k1,
                                         uint32_t *sink, void *stream);
 
 /* Instruction-rate probes: `threads` lanes each run `iters` iterations of
  * 8 independent chains of one operation; the folded result goes to
  * sink[thread].  op: 0 = 32x32->64 integer multiply-add (v_mad_u64_u32),
- * 1 = three-input xor (v_xor3_b32), 2 = FP64 fused multiply-add,
+ * 1 = 32-bit xor, 2 = FP64 fused multiply-add,
  * 3 = FP64 floor, 4 = FP32 fused multiply-add.
  * Operations per call = threads * iters * 8. */
 mirng_status mirng_bench_valu(int32_t op, uint32_t threads, uint32_t iters,

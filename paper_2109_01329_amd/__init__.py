@@ -49,6 +49,15 @@ class Request(ctypes.Structure):
                 ("out", ctypes.c_void_p)]
 
 
+class PhiloxConfig(ctypes.Structure):
+    _fields_ = [("walk", ctypes.c_int32), ("block", ctypes.c_int32),
+                ("waves_per_cu", ctypes.c_int32), ("blocks_per_lane", ctypes.c_int32),
+                ("nontemporal", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
 _lib = None
 
 
@@ -75,6 +84,8 @@ def lib() -> ctypes.CDLL:
         "mirng_generate_substreams": ([E, ctypes.POINTER(Distribution), u64, u64, u64, vp, vp],
                                       ctypes.c_int),
         "mirng_status_string": ([ctypes.c_int], ctypes.c_char_p),
+        "mirng_philox_config_get": ([ctypes.POINTER(PhiloxConfig)], ctypes.c_int),
+        "mirng_philox_config_set": ([ctypes.POINTER(PhiloxConfig)], ctypes.c_int),
         "mirng_abi_version": ([], ctypes.c_int32),
         "mirng_words_consumed": ([ctypes.c_int32, ctypes.c_int32, u64], u64),
         "mirng_bench_store": ([vp, u64, ctypes.c_int32, vp], ctypes.c_int),
@@ -192,6 +203,23 @@ class Engine:
         _check(lib().mirng_generate_substreams(self._h, ctypes.byref(d), first, count, n_each,
                                                _ptr(out), _stream(stream)),
                "generate_substreams")
+
+
+def philox_config() -> PhiloxConfig:
+    c = PhiloxConfig()
+    _check(lib().mirng_philox_config_get(ctypes.byref(c)), "philox_config_get")
+    return c
+
+
+def set_philox_config(c: PhiloxConfig | None = None, **fields) -> PhiloxConfig:
+    """Install a launch shape (fields not given keep their current value);
+    returns the previous shape."""
+    prev = philox_config()
+    new = PhiloxConfig.from_buffer_copy(c if c is not None else prev)
+    for k, v in fields.items():
+        setattr(new, k, int(v))
+    _check(lib().mirng_philox_config_set(ctypes.byref(new)), "philox_config_set")
+    return prev
 
 
 # ------------------------------------------------------------ measurement

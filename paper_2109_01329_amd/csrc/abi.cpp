@@ -20,10 +20,24 @@ struct mirng_engine_s {
 
 namespace mirng {
 
-PhiloxTuning &philox_tuning()
+mirng_philox_config &philox_config()
 {
-    static PhiloxTuning t;
-    return t;
+    // measured on MI355X at n = 2^28 (launch-shape sweeps in the design
+    // notes): contiguous runs, 1024-thread groups, 256 waves of work per CU,
+    // streaming stores
+    static mirng_philox_config c = {0, 1024, 256, 1, 1, 0};
+    return c;
+}
+
+bool philox_config_valid(const mirng_philox_config &c)
+{
+    const bool block_ok = c.block == 64 || c.block == 128 || c.block == 256 ||
+                          c.block == 512 || c.block == 1024;
+    const int wmax = c.walk == 0 ? 4096 : 64;
+    return (c.walk == 0 || c.walk == 1) && block_ok && c.waves_per_cu >= 1 &&
+           c.waves_per_cu <= wmax &&
+           (c.blocks_per_lane == 1 || c.blocks_per_lane == 2 || c.blocks_per_lane == 4) &&
+           (c.nontemporal == 0 || c.nontemporal == 1) && c.reserved == 0;
 }
 
 namespace {
@@ -95,20 +109,74 @@ bool is_default(const mirng_distribution *d)
 // stay below 2^31).
 constexpr uint64_t kMaxPerLaunch = 1ull << 32;
 
+Epilogue make_epilogue(const mirng_distribution *d, int nt)
+{
+    Epilogue ep{};
+    ep.ranged = is_default(d) ? 0 : 1;
+    ep.nt = nt;
+    if (d->kind == kU64F) {
+        ep.a64 = d->p0;
+        ep.d64 = d->p1 - d->p0;
+    } else if (d->kind == kGauss) {
+        ep.a32 = (float)d->p0;
+        ep.d32 = (float)d->p1;
+    } else {
+        ep.a32 = (float)d->p0;
+        ep.d32 = (float)(d->p1 - d->p0);
+    }
+    return ep;
+}
+
+// Words p .. of the engine into n outputs at out: the contiguous-walk
+// kernel, or the grid-stride kernel when it is selected and outputs do not
+// straddle Philox blocks, or the pair kernel for Gaussians whose pairs do
+// not line up with the 16-byte grid.
 hipError_t philox_plain(const uint32_t key[2], Pos130 p, const mirng_distribution *d,
                         uint64_t n, char *out, hipStream_t s)
 {
-    const PhiloxTuning &tu = philox_tuning();
+    const mirng_philox_config tu = philox_config();
     const int kind = d->kind;
     const size_t esz = elem_size(kind);
-    const uint32_t epv = (uint32_t)(16 / esz);
     const uint32_t wpe = kind == kU64F ? 2u : 1u;   // words per element
-    const bool ranged = !is_default(d);
+    const Epilogue ep = make_epilogue(d, tu.nontemporal);
+    const uint64_t cus = (uint64_t)device_cu_count();
     while (n > 0) {
-        uint64_t chunk = n < kMaxPerLaunch ? n : kMaxPerLaunch;
+        const uint64_t chunk = n < kMaxPerLaunch ? n : kMaxPerLaunch;
+        const uint64_t b_lo = (p.l[0] >> 2) | (p.l[1] << 62);   // floor(p / 4), 128 bits
+        const uint64_t b_hi = (p.l[1] >> 2) | (p.l[2] << 62);
+        const bool whole = tu.walk == 1 &&
+                           (kind == kBits || kind == kU32F || (p.l[0] & 1u) == 0);
         const uintptr_t addr = (uintptr_t)out;
-        const uint32_t head = (uint32_t)((addr & 15u) / esz);
-        if (kind == kGauss && (head & 1u)) {
+        hipError_t err;
+        if (whole) {
+            PhiloxBlocks a{};
+            a.k0 = key[0];
+            a.k1 = key[1];
+            a.base[0] = (uint32_t)b_lo;
+            a.base[1] = (uint32_t)(b_lo >> 32);
+            a.base[2] = (uint32_t)b_hi;
+            a.base[3] = (uint32_t)(b_hi >> 32);
+            const uint32_t epb = 4u / wpe;
+            a.head = (uint32_t)(p.l[0] & 3u) / wpe;
+            const uint64_t nblocks = (a.head + chunk + epb - 1) / epb;
+            a.nblocks = (uint32_t)nblocks;
+            const uint64_t lo = a.head ? 1 : 0;
+            const uint64_t hi = (a.head + chunk) / epb;   // blocks below hi end inside n
+            a.full_lo = (uint32_t)lo;
+            a.full_count = (uint32_t)(hi > lo ? hi - lo : 0);
+            a.n = chunk;
+            a.out = out;
+            a.ep = ep;
+            a.kind = kind;
+            a.bpl = (uint32_t)tu.blocks_per_lane;
+            a.block = (uint32_t)tu.block;
+            const uint64_t wpb = (uint64_t)tu.block / 64;
+            const uint64_t steps = (nblocks + 64ull * a.bpl - 1) / (64ull * a.bpl);
+            const uint64_t want = (cus * tu.waves_per_cu + wpb - 1) / wpb;
+            const uint64_t need = (steps + wpb - 1) / wpb;
+            a.groups = (uint32_t)(want < need ? want : need);
+            err = launch_philox_blocks(a, s);
+        } else if (kind == kGauss && ((addr & 15u) / esz) & 1u) {
             PhiloxPairs a{};
             a.k0 = key[0];
             a.k1 = key[1];
@@ -117,53 +185,42 @@ hipError_t philox_plain(const uint32_t key[2], Pos130 p, const mirng_distributio
             a.p_top = (uint32_t)p.l[2];
             a.n = chunk;
             a.out = (float *)out;
-            a.mean = (float)d->p0;
-            a.sd = (float)d->p1;
-            a.ranged = ranged ? 1 : 0;
-            hipError_t err = launch_philox_pairs(a, s);
-            if (err != hipSuccess) return err;
+            a.mean = ep.a32;
+            a.sd = ep.d32;
+            a.ranged = ep.ranged;
+            err = launch_philox_pairs(a, s);
         } else {
+            const uint32_t epv = (uint32_t)(16 / esz);
+            const uint32_t head = (uint32_t)((addr & 15u) / esz);
             PhiloxFill a{};
             a.k0 = key[0];
             a.k1 = key[1];
             const Pos130 q = pos_sub_u64(p, (uint64_t)head * wpe);
-            // base = floor(q / 4) as 128 bits; phase = q mod 4
-            const uint64_t b_lo = (q.l[0] >> 2) | (q.l[1] << 62);
-            const uint64_t b_hi = (q.l[1] >> 2) | (q.l[2] << 62);
-            a.base[0] = (uint32_t)b_lo;
-            a.base[1] = (uint32_t)(b_lo >> 32);
-            a.base[2] = (uint32_t)b_hi;
-            a.base[3] = (uint32_t)(b_hi >> 32);
+            const uint64_t q_lo = (q.l[0] >> 2) | (q.l[1] << 62);
+            const uint64_t q_hi = (q.l[1] >> 2) | (q.l[2] << 62);
+            a.base[0] = (uint32_t)q_lo;
+            a.base[1] = (uint32_t)(q_lo >> 32);
+            a.base[2] = (uint32_t)q_hi;
+            a.base[3] = (uint32_t)(q_hi >> 32);
             a.phase = (uint32_t)(q.l[0] & 3u);
             a.head = head;
             a.n = chunk;
             const uint64_t nslots = (head + chunk + epv - 1) / epv;
             a.nslots = (uint32_t)nslots;
-            const uint64_t waves_target = (uint64_t)device_cu_count() * tu.waves_per_cu;
-            uint64_t iters = (nslots + 64 * waves_target - 1) / (64 * waves_target);
-            if (iters < (uint64_t)tu.min_iters) iters = tu.min_iters;
-            a.slots_per_wave = (uint32_t)(iters * 64);
-            // complete slots: first element >= 0 and last element < chunk
+            const uint64_t waves_target = cus * (uint64_t)(tu.walk == 0 ? tu.waves_per_cu : 256);
+            const uint64_t iters = (nslots + 64 * waves_target - 1) / (64 * waves_target);
+            a.slots_per_wave = (uint32_t)((iters ? iters : 1) * 64);
             const uint64_t lo = head ? 1 : 0;
             const uint64_t hi = (head + chunk) / epv;   // slots below hi end inside n
             a.full_lo = (uint32_t)lo;
             a.full_count = (uint32_t)(hi > lo ? hi - lo : 0);
             a.out_base = out - (addr & 15u);
+            a.ep = ep;
             a.kind = kind;
-            a.ranged = ranged ? 1 : 0;
-            if (kind == kU64F) {
-                a.a64 = d->p0;
-                a.d64 = d->p1 - d->p0;
-            } else if (kind == kGauss) {
-                a.a32 = (float)d->p0;
-                a.d32 = (float)d->p1;
-            } else {
-                a.a32 = (float)d->p0;
-                a.d32 = (float)(d->p1 - d->p0);
-            }
-            hipError_t err = launch_philox_fill(a, s);
-            if (err != hipSuccess) return err;
+            a.block = (uint32_t)(tu.walk == 0 ? tu.block : 1024);
+            err = launch_philox_fill(a, s);
         }
+        if (err != hipSuccess) return err;
         p = pos_add_u64(p, words_consumed(MIRNG_PHILOX4X32_10, kind, chunk));
         out += chunk * esz;
         n -= chunk;
@@ -202,6 +259,20 @@ hipError_t mrg_substreams(const uint32_t st[6], const mirng_distribution *d,
 extern "C" {
 
 int32_t mirng_abi_version(void) { return MIRNG_ABI_VERSION; }
+
+mirng_status mirng_philox_config_get(mirng_philox_config *c)
+{
+    if (!c) return MIRNG_E_INVALID_ARG;
+    *c = philox_config();
+    return MIRNG_OK;
+}
+
+mirng_status mirng_philox_config_set(const mirng_philox_config *c)
+{
+    if (!c || !philox_config_valid(*c)) return MIRNG_E_INVALID_ARG;
+    philox_config() = *c;
+    return MIRNG_OK;
+}
 
 const char *mirng_status_string(mirng_status s)
 {

@@ -59,10 +59,40 @@ uint64_t words_consumed(int engine_type, int kind, uint64_t n);
 // ------------------------------------------------------------ launches
 enum Kind : int32_t { kBits = 1, kU32F = 2, kU64F = 3, kGauss = 4 };
 
-// One Philox fill launch.  The output is viewed as 16-byte slots starting
-// at out_base (16-byte aligned); slot s receives engine words
-// q + 4 s .. q + 4 s + 3, where q = 4 * base + phase.  Element j of slot s is
-// output index s * epv + j - head; only indices in [0, n) are written.
+// Output epilogue parameters shared by the generation kernels.
+struct Epilogue {
+    float a32, d32;         // uniform F32: fma(u, d, a); Gaussian: fma(z, sd, mean)
+    double a64, d64;        // uniform F64: fma(u, d, a)
+    int32_t ranged;         // 0 when the parameters are the defaults
+    int32_t nt;             // streaming stores
+};
+
+// Fast Philox launch: block j (counter base + j) carries words that are
+// whole output elements j * epb - head .. j * epb - head + epb - 1 (epb = 4,
+// or 2 for FP64); it is written with one 16-byte store at its element
+// address.  Valid whenever output elements do not straddle blocks: bits and
+// uniform FP32 at any position, FP64 and Gaussian at even positions.
+struct PhiloxBlocks {
+    uint32_t k0, k1;
+    uint32_t base[4];       // 128-bit counter of block 0
+    uint32_t head;          // elements of block 0 that precede output 0
+    uint32_t nblocks;
+    uint32_t full_lo;       // blocks [full_lo, full_lo + full_count) are complete
+    uint32_t full_count;
+    uint64_t n;             // outputs in this launch
+    char *out;              // output element 0
+    Epilogue ep;
+    int32_t kind;
+    uint32_t bpl;           // blocks per lane per iteration: 1, 2 or 4
+    uint32_t block;         // threads per workgroup
+    uint32_t groups;        // workgroups (persistent grid)
+};
+
+// Contiguous-walk Philox launch (every kind and position).  The output is
+// viewed as 16-byte slots starting at out_base (16-byte aligned); slot s
+// receives engine words q + 4 s .. q + 4 s + 3, where q = 4 * base + phase.
+// Element j of slot s is output index s * epv + j - head; only indices in
+// [0, n) are written.
 struct PhiloxFill {
     uint32_t k0, k1;
     uint32_t base[4];       // 128-bit block index of q
@@ -74,14 +104,13 @@ struct PhiloxFill {
     uint32_t full_lo;       // slots [full_lo, full_lo + full_count) are complete
     uint32_t full_count;
     char *out_base;
-    float a32, d32;         // uniform F32: fma(u, d, a); Gaussian: fma(z, sd, mean)
-    double a64, d64;        // uniform F64
+    Epilogue ep;
     int32_t kind;
-    int32_t ranged;         // 0 when the parameters are the defaults
+    uint32_t block;         // threads per workgroup
 };
 
-// Gaussian output whose 16-byte slots do not line up with word pairs (the
-// output pointer is 4 mod 8): one thread per pair, element stores.
+// Gaussian output whose 16-byte slots do not line up with word pairs (odd
+// position and the output pointer 4 mod 8): one thread per pair.
 struct PhiloxPairs {
     uint32_t k0, k1;
     uint64_t p_lo, p_mid;   // word position of pair 0 (130-bit, top in p_top)
@@ -92,17 +121,14 @@ struct PhiloxPairs {
     int32_t ranged;
 };
 
+hipError_t launch_philox_blocks(const PhiloxBlocks &a, hipStream_t s);
 hipError_t launch_philox_fill(const PhiloxFill &a, hipStream_t s);
 hipError_t launch_philox_pairs(const PhiloxPairs &a, hipStream_t s);
 
-// Launch geometry knobs (plain path); the autotuner may override them.
-struct PhiloxTuning {
-    int block = 256;          // threads per workgroup
-    int waves_per_cu = 32;    // resident-wave target used to size the grid
-    int min_iters = 4;        // minimum 64-slot iterations per wave
-    int nontemporal = 1;      // streaming stores
-};
-PhiloxTuning &philox_tuning();
+// Launch shape of the Philox fill kernel (process-wide, set through the
+// ABI or by the autotuner).
+mirng_philox_config &philox_config();
+bool philox_config_valid(const mirng_philox_config &c);
 
 int device_cu_count();
 hipError_t ensure_device(int *dev);

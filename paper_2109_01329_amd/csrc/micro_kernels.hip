@@ -1,62 +1,56 @@
 // Measurement kernels (ceilings for the generation kernels).
 #include "internal.hpp"
+#include "philox.hpp"
 #include "mirng_bench.h"
 #include "transforms.hpp"
 
 namespace mirng {
 namespace {
 
-__global__ __launch_bounds__(256) void store_kernel(char *out, uint64_t nvec,
-                                                    uint32_t vec_per_wave, int nt)
+// The two walks of the Philox kernels, stores only.  vpw == 0: grid-stride
+// (each wave step covers bpl * 64 consecutive 16-byte vectors, steps strided
+// by the number of waves).  vpw > 0: wave w owns vectors [w vpw, (w+1) vpw)
+// and writes 64 consecutive vectors per step.
+__global__ __launch_bounds__(1024) void store_kernel(char *out, uint64_t nvec, int nt, int bpl,
+                                                     uint32_t vpw)
 {
     const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
     const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    const uint64_t v0 = wave * vec_per_wave;
-    if (v0 >= nvec) return;
-    const uint64_t v1 = v0 + vec_per_wave < nvec ? v0 + vec_per_wave : nvec;
     u32x4 val;
     val.x = 0x3F000000u ^ lane; val.y = (uint32_t)wave; val.z = 0x12345678u; val.w = lane;
-    for (uint64_t v = v0 + lane; v < v1; v += 64) {
-        u32x4 *p = (u32x4 *)(out + v * 16);
-        if (nt) __builtin_nontemporal_store(val, p);
-        else *p = val;
+    uint64_t first, last, stride;
+    const uint64_t per = vpw ? 64ull : 64ull * bpl;
+    if (vpw) {
+        first = wave * vpw;
+        last = first + vpw < nvec ? first + vpw : nvec;
+        stride = 64;
+    } else {
+        first = wave * per;
+        last = nvec;
+        stride = waves * per;
+    }
+    for (uint64_t c = first; c < last; c += stride) {
+        for (uint64_t k = 0; k < per; k += 64) {
+            const uint64_t v = c + k + lane;
+            if (v < last) {
+                u32x4 *q = (u32x4 *)(out + v * 16);
+                if (nt) __builtin_nontemporal_store(val, q);
+                else *q = val;
+            }
+        }
     }
 }
 
-__device__ __forceinline__ u32x4 philox10_bench(uint32_t c0, uint32_t c1, uint32_t c2,
-                                                uint32_t c3, uint32_t k0, uint32_t k1)
-{
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        const uint32_t rk0 = k0 + (uint32_t)r * kPhiloxW0;
-        const uint32_t rk1 = k1 + (uint32_t)r * kPhiloxW1;
-        const uint64_t p0 = (uint64_t)kPhiloxM0 * c0;
-        const uint64_t p1 = (uint64_t)kPhiloxM1 * c2;
-        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ rk0;
-        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ rk1;
-        c1 = (uint32_t)p1;
-        c3 = (uint32_t)p0;
-        c0 = n0;
-        c2 = n2;
-    }
-    u32x4 w;
-    w.x = c0; w.y = c1; w.z = c2; w.w = c3;
-    return w;
-}
-
-__global__ __launch_bounds__(256) void philox_nostore_kernel(uint64_t nblocks,
-                                                             uint32_t blk_per_wave,
-                                                             uint32_t k0, uint32_t k1,
-                                                             uint32_t *sink)
+__global__ __launch_bounds__(1024) void philox_nostore_kernel(uint64_t nblocks, uint32_t k0,
+                                                              uint32_t k1, uint32_t *sink)
 {
     const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
     const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    const uint64_t b0 = wave * blk_per_wave;
-    if (b0 >= nblocks) return;
-    const uint64_t b1 = b0 + blk_per_wave < nblocks ? b0 + blk_per_wave : nblocks;
     uint32_t acc = 0;
-    for (uint64_t b = b0 + lane; b < b1; b += 64) {
-        const u32x4 w = philox10_bench((uint32_t)b, (uint32_t)(b >> 32), 0, 0, k0, k1);
+    for (uint64_t b = wave * 64 + lane; b < nblocks; b += waves * 64) {
+        const u32x4 w = philox10((uint32_t)b, (uint32_t)(b >> 32), 0, 0, k0, k1);
         acc ^= w.x ^ w.y ^ w.z ^ w.w;
     }
     // fold across the wave so only one word per wave is written
@@ -131,23 +125,41 @@ using namespace mirng;
 
 extern "C" {
 
+// Persistent grid of the grid-stride Philox kernel for `units` 16-byte units.
+static uint64_t grid_for(uint64_t units, const mirng_philox_config &tu)
+{
+    const uint64_t wpb = (uint64_t)tu.block / 64;
+    const uint64_t steps = (units + 64ull * tu.blocks_per_lane - 1) / (64ull * tu.blocks_per_lane);
+    const uint64_t want = ((uint64_t)device_cu_count() * tu.waves_per_cu + wpb - 1) / wpb;
+    const uint64_t need = (steps + wpb - 1) / wpb;
+    return want < need ? want : need;
+}
+
 mirng_status mirng_bench_store(void *out, uint64_t bytes, int32_t nontemporal, void *stream)
 {
     if (!out || bytes % 16 || ((uintptr_t)out & 15u)) return MIRNG_E_INVALID_ARG;
     if (bytes == 0) return MIRNG_OK;
     if (ensure_device(nullptr) != hipSuccess) return MIRNG_E_DEVICE;
-    const PhiloxTuning &tu = philox_tuning();
+    const mirng_philox_config tu = philox_config();
     const uint64_t nvec = bytes / 16;
-    const uint64_t waves_target = (uint64_t)device_cu_count() * tu.waves_per_cu;
-    uint64_t iters = (nvec + 64 * waves_target - 1) / (64 * waves_target);
-    if (iters < 1) iters = 1;
-    const uint64_t per_wave = iters * 64;
-    const uint64_t waves = (nvec + per_wave - 1) / per_wave;
-    const uint64_t groups = (waves + 3) / 4;
-    if (groups >= (1ull << 31) || per_wave >= (1ull << 32)) return MIRNG_E_INVALID_ARG;
-    hipLaunchKernelGGL(store_kernel, dim3((uint32_t)groups), dim3(256), 0,
-                       (hipStream_t)stream, (char *)out, nvec, (uint32_t)per_wave,
-                       (int)nontemporal);
+    uint64_t groups;
+    uint32_t vpw = 0;
+    if (tu.walk == 0) {
+        const uint64_t waves_target = (uint64_t)device_cu_count() * tu.waves_per_cu;
+        const uint64_t iters = (nvec + 64 * waves_target - 1) / (64 * waves_target);
+        const uint64_t per_wave = (iters ? iters : 1) * 64;
+        if (per_wave >= (1ull << 32)) return MIRNG_E_INVALID_ARG;
+        vpw = (uint32_t)per_wave;
+        const uint64_t waves = (nvec + per_wave - 1) / per_wave;
+        const uint64_t wpb = (uint64_t)tu.block / 64;
+        groups = (waves + wpb - 1) / wpb;
+    } else {
+        groups = grid_for(nvec, tu);
+    }
+    if (groups >= (1ull << 31)) return MIRNG_E_INVALID_ARG;
+    hipLaunchKernelGGL(store_kernel, dim3((uint32_t)groups), dim3(tu.block), 0,
+                       (hipStream_t)stream, (char *)out, nvec, (int)nontemporal,
+                       (int)tu.blocks_per_lane, vpw);
     return hipGetLastError() == hipSuccess ? MIRNG_OK : MIRNG_E_LAUNCH;
 }
 
@@ -157,16 +169,11 @@ mirng_status mirng_bench_philox_nostore(uint64_t nblocks, uint32_t k0, uint32_t 
     if (!sink) return MIRNG_E_INVALID_ARG;
     if (nblocks == 0) return MIRNG_OK;
     if (ensure_device(nullptr) != hipSuccess) return MIRNG_E_DEVICE;
-    const PhiloxTuning &tu = philox_tuning();
-    const uint64_t waves_target = (uint64_t)device_cu_count() * tu.waves_per_cu;
-    uint64_t iters = (nblocks + 64 * waves_target - 1) / (64 * waves_target);
-    if (iters < 1) iters = 1;
-    const uint64_t per_wave = iters * 64;
-    const uint64_t waves = (nblocks + per_wave - 1) / per_wave;
-    const uint64_t groups = (waves + 3) / 4;
-    if (groups >= (1ull << 31) || per_wave >= (1ull << 32)) return MIRNG_E_INVALID_ARG;
-    hipLaunchKernelGGL(philox_nostore_kernel, dim3((uint32_t)groups), dim3(256), 0,
-                       (hipStream_t)stream, nblocks, (uint32_t)per_wave, k0, k1, sink);
+    mirng_philox_config tu = philox_config();
+    tu.blocks_per_lane = 1;
+    if (tu.waves_per_cu > 64) tu.waves_per_cu = 32;   // resident waves for the walk
+    hipLaunchKernelGGL(philox_nostore_kernel, dim3((uint32_t)grid_for(nblocks, tu)),
+                       dim3(tu.block), 0, (hipStream_t)stream, nblocks, k0, k1, sink);
     return hipGetLastError() == hipSuccess ? MIRNG_OK : MIRNG_E_LAUNCH;
 }
 

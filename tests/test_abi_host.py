@@ -155,3 +155,18 @@ def test_substream_validation(L):
     assert L.mirng_generate_substreams(m.handle, ctypes.byref(d), 2**30, 1, 16, 0x10000,
                                        None) == 1
     assert L.mirng_generate_substreams(m.handle, ctypes.byref(d), 0, 0, 16, None, None) == 0
+
+
+def test_philox_config_validation():
+    c = mr.philox_config()
+    assert c.block in (64, 128, 256, 512, 1024)
+    for bad in (dict(block=100), dict(waves_per_cu=0), dict(walk=1, waves_per_cu=65),
+                dict(walk=0, waves_per_cu=4097), dict(walk=2), dict(blocks_per_lane=3),
+                dict(nontemporal=2), dict(reserved=1)):
+        with pytest.raises(mr.MirngError):
+            mr.set_philox_config(**bad)
+    assert mr.philox_config().as_dict() == c.as_dict()
+    prev = mr.set_philox_config(block=512, waves_per_cu=8)
+    assert mr.philox_config().block == 512
+    mr.set_philox_config(prev)
+    assert mr.philox_config().as_dict() == c.as_dict()

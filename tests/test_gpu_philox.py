@@ -113,3 +113,32 @@ def test_gaussian_error_distribution():
     worst = gh.assert_match(mr.GAUSSIAN_F32, got, want)
     # in tolerance units (2 ulp): the kernel rounds an FP64 value once
     assert worst <= 0.5 * 1.02
+
+
+CONFIGS = [
+    dict(walk=1, block=256, waves_per_cu=4, blocks_per_lane=1, nontemporal=0),
+    dict(walk=1, block=64, waves_per_cu=1, blocks_per_lane=4, nontemporal=1),
+    dict(walk=1, block=1024, waves_per_cu=64, blocks_per_lane=2, nontemporal=0),
+    dict(walk=0, block=128, waves_per_cu=3, blocks_per_lane=2, nontemporal=1),
+    dict(walk=0, block=64, waves_per_cu=1, blocks_per_lane=1, nontemporal=0),
+    dict(walk=0, block=1024, waves_per_cu=4096, blocks_per_lane=1, nontemporal=1),
+]
+
+
+@pytest.mark.parametrize("cfg", CONFIGS)
+def test_outputs_invariant_under_launch_shape(cfg):
+    """Every launch shape gives the oracle's values, on both walks (the
+    grid-stride walk hands FP64 and Gaussian at odd positions to the
+    contiguous walk)."""
+    prev = mr.set_philox_config(**cfg)
+    try:
+        for kind in KINDS:
+            for pos in (0, 1, 2, 3, 2**40 + 5):
+                for off in (0, 4 if mr.ELEM_BYTES[kind] == 4 else 8):
+                    n = 100003
+                    e = mr.Engine(mr.PHILOX4X32_10, 99, pos)
+                    got, buf = gh.generate(e, kind, n, off)
+                    gh.assert_match(kind, got, gh.oracle_philox(99, pos, kind, n))
+                    assert gh.guards_intact(buf, off, n * mr.ELEM_BYTES[kind])
+    finally:
+        mr.set_philox_config(prev)
