@@ -14,6 +14,10 @@ the bulk workload at n = 2^28, MRG32k3a substreams (65536 x 4096 FP64),
 the store-only and no-store ceilings, and the oracle timed on the host
 cores over the same headline workload.
 
+Before the W untimed warmup steps the headline step runs for --prewarm-s
+seconds (default 0.4): the first ~100 launches of a fresh process run ~15%
+slower while clocks ramp; the JSON line reports the pre-warm.
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--quick]
 """
 from __future__ import annotations
@@ -33,10 +37,16 @@ HBM_PEAK_GBS = 8000.0
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=20)
-    p.add_argument("--warmup", type=int, default=5)
+    p.add_argument("--steps", type=int, default=100)
+    p.add_argument("--warmup", type=int, default=10)
+    p.add_argument("--prewarm-s", type=float, default=0.4,
+                   help="seconds of headline launches before the warmup steps, so that the "
+                        "GPU's clocks reach their steady state under this load")
     p.add_argument("--quick", action="store_true", help="headline only")
     p.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
+    p.add_argument("--profile", action="store_true",
+                   help="for rocprofv3: 5 headline generate launches, then 3 device copies of "
+                        "1 GiB (a plain copy kernel of known size for counter calibration)")
     return p.parse_args()
 
 
@@ -104,6 +114,30 @@ def main():
         e = mr.Engine(mr.PHILOX4X32_10, seed, offset)
         e.generate(mr.UNIFORM_F32, n, out, stream=stream)
         return e
+
+    if args.profile:
+        with torch.cuda.stream(stream):
+            for _ in range(5):
+                step()
+            src = torch.empty(n, dtype=torch.float32, device=dev)
+            src.fill_(0.5)
+            for _ in range(3):
+                out.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile": "philox uniform_f32 n=2^28 x5, then 1 GiB copy x3",
+                          "config": mr.philox_config().as_dict()}), flush=True)
+        return
+
+    # clock ramp: the first ~100 launches of a fresh process run ~15% slower
+    t_pre = time.perf_counter()
+    launches = 0
+    while time.perf_counter() - t_pre < args.prewarm_s:
+        step()
+        launches += 1
+        if launches % 8 == 0:
+            stream.synchronize()
+    stream.synchronize()
+    prewarm = {"seconds": round(time.perf_counter() - t_pre, 3), "launches": launches}
 
     with torch.cuda.stream(stream):
         for _ in range(args.warmup):
@@ -205,6 +239,8 @@ def main():
         "write_GBs": round(n * 4 / (ms_per_step * 1e-3) / 1e9, 1),
         "hbm_write_frac": round(n * 4 / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "roofline": roofline,
+        "prewarm": prewarm,
+        "philox_config": mr.philox_config().as_dict(),
     }
     line.update(extra)
     if not args.no_cpu:

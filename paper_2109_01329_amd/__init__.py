@@ -69,6 +69,13 @@ def lib() -> ctypes.CDLL:
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} not found: build it with "
                           "`python -m paper_2109_01329_amd.build`")
+    # Streams and device buffers come from PyTorch, which ships its own HIP
+    # runtime: load it first so that libmirng.so binds to that same runtime
+    # (two runtimes in one process do not share streams or allocations).
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = ctypes.CDLL(LIB_PATH)
     E = ctypes.c_void_p
     vp = ctypes.c_void_p

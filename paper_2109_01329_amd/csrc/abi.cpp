@@ -33,7 +33,7 @@ bool philox_config_valid(const mirng_philox_config &c)
 {
     const bool block_ok = c.block == 64 || c.block == 128 || c.block == 256 ||
                           c.block == 512 || c.block == 1024;
-    const int wmax = c.walk == 0 ? 4096 : 64;
+    const int wmax = c.walk == 1 ? 64 : 4096;
     return (c.walk == 0 || c.walk == 1) && block_ok && c.waves_per_cu >= 1 &&
            c.waves_per_cu <= wmax &&
            (c.blocks_per_lane == 1 || c.blocks_per_lane == 2 || c.blocks_per_lane == 4) &&
@@ -171,7 +171,8 @@ hipError_t philox_plain(const uint32_t key[2], Pos130 p, const mirng_distributio
             a.bpl = (uint32_t)tu.blocks_per_lane;
             a.block = (uint32_t)tu.block;
             const uint64_t wpb = (uint64_t)tu.block / 64;
-            const uint64_t steps = (nblocks + 64ull * a.bpl - 1) / (64ull * a.bpl);
+            const uint64_t per = 64ull * a.bpl;
+            const uint64_t steps = (nblocks + per - 1) / per;
             const uint64_t want = (cus * tu.waves_per_cu + wpb - 1) / wpb;
             const uint64_t need = (steps + wpb - 1) / wpb;
             a.groups = (uint32_t)(want < need ? want : need);

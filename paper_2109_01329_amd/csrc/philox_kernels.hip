@@ -24,8 +24,10 @@
 // accepts dword-aligned vector stores).  No data moves between lanes.
 //
 // On MI355X the contiguous walk with many short-lived waves sustains the
-// higher write rate once the Philox rounds are in the loop (measurements in
-// the design notes); the grid-stride walk is kept for the autotuner.
+// higher write rate once the Philox rounds are in the loop, and 16-byte
+// stores at addresses that are only 4-byte aligned cost about a fifth of
+// the write bandwidth (measurements in the design notes); the grid-stride
+// walk is kept for the autotuner.
 #include "internal.hpp"
 #include "philox.hpp"
 #include "transforms.hpp"
@@ -108,6 +110,9 @@ __device__ __forceinline__ void put(char *p, u32x4 v, uint32_t u, uint32_t full_
 
 // ---------------------------------------------------------------- grid-stride walk
 
+// A wave step covers BPL * 64 consecutive blocks (lane L takes c + 64 k + L,
+// BPL independent Philox chains per lane); steps are strided by the number
+// of waves, so the grid writes one compact window per round of steps.
 template <int KIND, int BPL>
 __global__ __launch_bounds__(1024) void philox_blocks_kernel(PhiloxBlocks a)
 {
@@ -124,10 +129,10 @@ __global__ __launch_bounds__(1024) void philox_blocks_kernel(PhiloxBlocks a)
             w[k] = block_at(a.base, a.k0, a.k1, (uint32_t)c + k * 64u + lane);
 #pragma unroll
         for (int k = 0; k < BPL; ++k) {
-            const uint32_t j = (uint32_t)c + k * 64u + lane;
+            const uint64_t j = c + k * 64u + lane;
             if (j < a.nblocks) {
                 const int64_t e0 = (int64_t)j * EPB - (int64_t)a.head;
-                put<KIND>(a.out + e0 * ESZ, transform<KIND>(a.ep, w[k]), j, a.full_lo,
+                put<KIND>(a.out + e0 * ESZ, transform<KIND>(a.ep, w[k]), (uint32_t)j, a.full_lo,
                           a.full_count, e0, a.n, a.ep.nt);
             }
         }

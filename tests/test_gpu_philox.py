@@ -122,6 +122,7 @@ CONFIGS = [
     dict(walk=0, block=128, waves_per_cu=3, blocks_per_lane=2, nontemporal=1),
     dict(walk=0, block=64, waves_per_cu=1, blocks_per_lane=1, nontemporal=0),
     dict(walk=0, block=1024, waves_per_cu=4096, blocks_per_lane=1, nontemporal=1),
+    dict(walk=1, block=512, waves_per_cu=5, blocks_per_lane=4, nontemporal=1),
 ]
 
 
