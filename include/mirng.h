@@ -179,6 +179,66 @@ mirng_status mirng_generate_substreams(mirng_engine e,
                                        uint64_t n_each, void *out,
                                        void *stream);
 
+/* --------------------------------------------------------------- batching */
+
+/* Batched generation: thousands of independent requests of uneven sizes in
+ * one persistent launch -- the inter-event batching that the paper leaves
+ * for future work for its calorimeter application, whose events each draw
+ * three uniforms per hit (Sec. 5.2, Sec. 6).  A batcher owns a ring of
+ * pinned host staging slots and device tables, reused across calls.
+ * Requests are validated on the device, per request: a request that fails
+ * validation writes nothing and gets a non-OK status (see
+ * mirng_batcher_statuses); the others are unaffected.  Engine types in a
+ * batch: Philox4x32-10 (an MRG32k3a request gets MIRNG_E_UNSUPPORTED). */
+
+typedef struct mirng_batcher_s *mirng_batcher;
+
+/* Launch shape of the batched kernel (the autotuner's search space); only
+ * speed depends on it. */
+typedef struct {
+    int32_t block;          /* threads per workgroup: 64, 128, 256, 512, 1024 */
+    int32_t waves_per_cu;   /* waves of work per CU, 1..4096 */
+    int32_t nontemporal;    /* 0: plain stores, 1: streaming (nt) stores */
+    int32_t reserved;       /* must be 0 */
+} mirng_batch_config;
+
+/* Create a batcher (host-only; device memory is allocated at first use).
+ * out == NULL -> INVALID_ARG; allocation -> ALLOC. */
+mirng_status mirng_batcher_create(mirng_batcher *out);
+
+/* Destroy a batcher after waiting for its outstanding work.  NULL is
+ * accepted and ignored. */
+mirng_status mirng_batcher_destroy(mirng_batcher b);
+
+/* Pinned host array for the next batch of `count` requests, to be filled
+ * in place and passed to mirng_generate_batch (which then copies nothing on
+ * the host).  Waits until the ring slot it hands out is no longer in use by
+ * the device.  NULL arguments -> INVALID_ARG; allocation -> ALLOC. */
+mirng_status mirng_batcher_stage(mirng_batcher b, size_t count, mirng_request **reqs);
+
+/* Enqueue `count` requests as one batch on `stream`: one host-to-device
+ * copy of the request table, a planning kernel (validation, per-request
+ * descriptors, tile prefix) and one persistent generation kernel.  Each
+ * valid request's output equals that of a fresh engine created with its
+ * (type, seed, offset) followed by one mirng_generate call; it does not
+ * depend on the other requests, their order or the launch shape.  reqs may
+ * be the array of the last mirng_batcher_stage call, or any host array
+ * (copied into a staging slot).  count == 0 -> OK; b or reqs NULL ->
+ * INVALID_ARG; count >= 2^31 -> INVALID_ARG; device or launch errors ->
+ * DEVICE or LAUNCH.  Asynchronous: no host synchronisation. */
+mirng_status mirng_generate_batch(mirng_batcher b, const mirng_request *reqs, size_t count,
+                                  void *stream);
+
+/* Per-request status of the most recent batch (mirng_status values), valid
+ * once the stream work of that batch has completed.  count must not exceed
+ * that batch's count -> else INVALID_ARG. */
+mirng_status mirng_batcher_statuses(mirng_batcher b, int32_t *statuses, size_t count);
+
+/* Copy out / install the batched kernel's launch shape.  Out-of-range
+ * fields -> INVALID_ARG, shape kept. */
+mirng_status mirng_batcher_config_get(mirng_batcher b, mirng_batch_config *c);
+mirng_status mirng_batcher_config_set(mirng_batcher b, const mirng_batch_config *c);
+
 /* ------------------------------------------------------ launch configuration */
 
 /* Launch shape of the Philox kernels: the search space of the autotuner.

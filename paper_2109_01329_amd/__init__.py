@@ -58,6 +58,27 @@ class PhiloxConfig(ctypes.Structure):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
 
 
+class BatchConfig(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32),
+                ("nontemporal", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
+# numpy view of mirng_request (64 bytes, same field order and offsets)
+REQUEST_FIELDS = [("engine_type", "<i4"), ("reserved", "<i4"), ("kind", "<i4"),
+                  ("dist_reserved", "<i4"), ("p0", "<f8"), ("p1", "<f8"), ("seed", "<u8"),
+                  ("offset", "<u8"), ("n", "<u8"), ("out", "<u8")]
+
+
+def request_dtype():
+    import numpy as np
+    dt = np.dtype(REQUEST_FIELDS)
+    assert dt.itemsize == ctypes.sizeof(Request) == 64
+    return dt
+
+
 _lib = None
 
 
@@ -94,6 +115,13 @@ def lib() -> ctypes.CDLL:
         "mirng_philox_config_get": ([ctypes.POINTER(PhiloxConfig)], ctypes.c_int),
         "mirng_philox_config_set": ([ctypes.POINTER(PhiloxConfig)], ctypes.c_int),
         "mirng_abi_version": ([], ctypes.c_int32),
+        "mirng_batcher_create": ([ctypes.POINTER(vp)], ctypes.c_int),
+        "mirng_batcher_destroy": ([vp], ctypes.c_int),
+        "mirng_batcher_stage": ([vp, ctypes.c_size_t, ctypes.POINTER(vp)], ctypes.c_int),
+        "mirng_generate_batch": ([vp, vp, ctypes.c_size_t, vp], ctypes.c_int),
+        "mirng_batcher_statuses": ([vp, vp, ctypes.c_size_t], ctypes.c_int),
+        "mirng_batcher_config_get": ([vp, ctypes.POINTER(BatchConfig)], ctypes.c_int),
+        "mirng_batcher_config_set": ([vp, ctypes.POINTER(BatchConfig)], ctypes.c_int),
         "mirng_words_consumed": ([ctypes.c_int32, ctypes.c_int32, u64], u64),
         "mirng_bench_store": ([vp, u64, ctypes.c_int32, vp], ctypes.c_int),
         "mirng_bench_philox_nostore": ([u64, ctypes.c_uint32, ctypes.c_uint32, vp, vp],
@@ -227,6 +255,72 @@ def set_philox_config(c: PhiloxConfig | None = None, **fields) -> PhiloxConfig:
         setattr(new, k, int(v))
     _check(lib().mirng_philox_config_set(ctypes.byref(new)), "philox_config_set")
     return prev
+
+
+class Batcher:
+    """Batched generation of many independent requests in one launch.
+
+    Requests are numpy records of `request_dtype()` (field `out` is a device
+    pointer).  `stage(count)` returns a record array in pinned host memory
+    that `generate` sends without a host copy."""
+
+    def __init__(self):
+        h = ctypes.c_void_p()
+        _check(lib().mirng_batcher_create(ctypes.byref(h)), "batcher_create")
+        self._h = h
+        self._staged = None
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().mirng_batcher_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def config(self) -> BatchConfig:
+        c = BatchConfig()
+        _check(lib().mirng_batcher_config_get(self._h, ctypes.byref(c)), "batcher_config_get")
+        return c
+
+    def set_config(self, c: BatchConfig | None = None, **fields) -> BatchConfig:
+        prev = self.config
+        new = BatchConfig.from_buffer_copy(c if c is not None else prev)
+        for k, v in fields.items():
+            setattr(new, k, int(v))
+        _check(lib().mirng_batcher_config_set(self._h, ctypes.byref(new)), "batcher_config_set")
+        return prev
+
+    def stage(self, count: int):
+        import numpy as np
+        ptr = ctypes.c_void_p()
+        _check(lib().mirng_batcher_stage(self._h, count, ctypes.byref(ptr)), "batcher_stage")
+        buf = (ctypes.c_char * (64 * max(count, 1))).from_address(ptr.value)
+        arr = np.frombuffer(buf, dtype=request_dtype(), count=count)
+        self._staged = arr
+        return arr
+
+    def generate(self, reqs, stream=None) -> None:
+        import numpy as np
+        reqs = np.ascontiguousarray(reqs, dtype=request_dtype())
+        _check(lib().mirng_generate_batch(self._h, reqs.ctypes.data, len(reqs), _stream(stream)),
+               "generate_batch")
+
+    def statuses(self, count: int):
+        import numpy as np
+        out = np.zeros(count, dtype=np.int32)
+        _check(lib().mirng_batcher_statuses(self._h, out.ctypes.data, count), "batcher_statuses")
+        return out
+
+
+def make_requests(count: int):
+    """Zeroed request records (engine, distribution defaults left to fill)."""
+    import numpy as np
+    return np.zeros(count, dtype=request_dtype())
 
 
 # ------------------------------------------------------------ measurement

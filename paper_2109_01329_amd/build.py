@@ -27,6 +27,8 @@ SOURCES = [
     "philox_kernels.hip",
     "mrg_kernels.hip",
     "micro_kernels.hip",
+    "batch.cpp",
+    "batch_kernels.hip",
 ]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -194,18 +194,19 @@ hipError_t philox_plain(const uint32_t key[2], Pos130 p, const mirng_distributio
             const uint32_t epv = (uint32_t)(16 / esz);
             const uint32_t head = (uint32_t)((addr & 15u) / esz);
             PhiloxFill a{};
-            a.k0 = key[0];
-            a.k1 = key[1];
+            SlotRun &r = a.run;
+            r.k0 = key[0];
+            r.k1 = key[1];
             const Pos130 q = pos_sub_u64(p, (uint64_t)head * wpe);
             const uint64_t q_lo = (q.l[0] >> 2) | (q.l[1] << 62);
             const uint64_t q_hi = (q.l[1] >> 2) | (q.l[2] << 62);
-            a.base[0] = (uint32_t)q_lo;
-            a.base[1] = (uint32_t)(q_lo >> 32);
-            a.base[2] = (uint32_t)q_hi;
-            a.base[3] = (uint32_t)(q_hi >> 32);
+            r.base[0] = (uint32_t)q_lo;
+            r.base[1] = (uint32_t)(q_lo >> 32);
+            r.base[2] = (uint32_t)q_hi;
+            r.base[3] = (uint32_t)(q_hi >> 32);
             a.phase = (uint32_t)(q.l[0] & 3u);
-            a.head = head;
-            a.n = chunk;
+            r.head = head;
+            r.n = chunk;
             const uint64_t nslots = (head + chunk + epv - 1) / epv;
             a.nslots = (uint32_t)nslots;
             const uint64_t waves_target = cus * (uint64_t)(tu.walk == 0 ? tu.waves_per_cu : 256);
@@ -213,10 +214,10 @@ hipError_t philox_plain(const uint32_t key[2], Pos130 p, const mirng_distributio
             a.slots_per_wave = (uint32_t)((iters ? iters : 1) * 64);
             const uint64_t lo = head ? 1 : 0;
             const uint64_t hi = (head + chunk) / epv;   // slots below hi end inside n
-            a.full_lo = (uint32_t)lo;
-            a.full_count = (uint32_t)(hi > lo ? hi - lo : 0);
-            a.out_base = out - (addr & 15u);
-            a.ep = ep;
+            r.full_lo = (uint32_t)lo;
+            r.full_count = (uint32_t)(hi > lo ? hi - lo : 0);
+            r.out_base = out - (addr & 15u);
+            r.ep = ep;
             a.kind = kind;
             a.block = (uint32_t)(tu.walk == 0 ? tu.block : 1024);
             err = launch_philox_fill(a, s);

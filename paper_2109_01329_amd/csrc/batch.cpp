@@ -1,0 +1,227 @@
+// Batcher: host side of batched generation.  A ring of staging slots, each
+// with a pinned request table, device tables and a completion event, so
+// that successive batches (on one or several streams) overlap without the
+// host waiting, except when a slot is reused while the device still needs
+// it.  Per batch the host copies the request table into pinned memory (or
+// not at all when the caller filled the staged slot) and enqueues one
+// host-to-device copy, the planning and scan kernels, the generation kernel
+// and the device-to-host copy of the per-request statuses.
+#include <cstring>
+#include <mutex>
+#include <new>
+
+#include "internal.hpp"
+
+namespace {
+
+constexpr int kSlots = 4;
+constexpr size_t kChunk = 1024;
+
+struct Slot {
+    mirng_request *h_reqs = nullptr;   // pinned
+    int32_t *h_status = nullptr;       // pinned
+    size_t cap = 0;
+    size_t count = 0;
+    int dev = -1;
+    bool pending = false;              // `done` recorded and maybe not reached
+    hipEvent_t done = nullptr;
+    mirng_request *d_reqs = nullptr;
+    mirng::BatchDesc *d_desc = nullptr;
+    uint64_t *d_local_end = nullptr;
+    uint64_t *d_chunk_total = nullptr;
+    uint64_t *d_chunk_end = nullptr;
+    uint64_t *d_total = nullptr;
+    int32_t *d_status = nullptr;
+};
+
+void release(Slot &s)
+{
+    if (s.done && s.pending) (void)hipEventSynchronize(s.done);
+    if (s.h_reqs) (void)hipHostFree(s.h_reqs);
+    if (s.h_status) (void)hipHostFree(s.h_status);
+    if (s.d_reqs) (void)hipFree(s.d_reqs);
+    if (s.d_desc) (void)hipFree(s.d_desc);
+    if (s.d_local_end) (void)hipFree(s.d_local_end);
+    if (s.d_chunk_total) (void)hipFree(s.d_chunk_total);
+    if (s.d_chunk_end) (void)hipFree(s.d_chunk_end);
+    if (s.d_total) (void)hipFree(s.d_total);
+    if (s.d_status) (void)hipFree(s.d_status);
+    if (s.done) (void)hipEventDestroy(s.done);
+    s = Slot{};
+}
+
+// Waits until the device no longer uses the slot, then makes room for
+// `count` requests on device `dev`.
+hipError_t prepare(Slot &s, size_t count, int dev)
+{
+    if (s.pending) {
+        hipError_t err = hipEventSynchronize(s.done);
+        if (err != hipSuccess) return err;
+        s.pending = false;
+    }
+    if (s.cap >= count && s.dev == dev) return hipSuccess;
+    release(s);
+    size_t cap = count < 1024 ? 1024 : count;
+    const size_t nchunks = (cap + kChunk - 1) / kChunk;
+    hipError_t err = hipSuccess;
+    auto chk = [&](hipError_t e) { if (err == hipSuccess) err = e; };
+    chk(hipHostMalloc((void **)&s.h_reqs, cap * sizeof(mirng_request), hipHostMallocDefault));
+    chk(hipHostMalloc((void **)&s.h_status, cap * sizeof(int32_t), hipHostMallocDefault));
+    chk(hipMalloc((void **)&s.d_reqs, cap * sizeof(mirng_request)));
+    chk(hipMalloc((void **)&s.d_desc, cap * sizeof(mirng::BatchDesc)));
+    chk(hipMalloc((void **)&s.d_local_end, cap * sizeof(uint64_t)));
+    chk(hipMalloc((void **)&s.d_chunk_total, nchunks * sizeof(uint64_t)));
+    chk(hipMalloc((void **)&s.d_chunk_end, nchunks * sizeof(uint64_t)));
+    chk(hipMalloc((void **)&s.d_total, sizeof(uint64_t)));
+    chk(hipMalloc((void **)&s.d_status, cap * sizeof(int32_t)));
+    chk(hipEventCreateWithFlags(&s.done, hipEventDisableTiming));
+    if (err != hipSuccess) {
+        release(s);
+        return err;
+    }
+    s.cap = cap;
+    s.dev = dev;
+    return hipSuccess;
+}
+
+bool config_valid(const mirng_batch_config &c)
+{
+    const bool block_ok = c.block == 64 || c.block == 128 || c.block == 256 ||
+                          c.block == 512 || c.block == 1024;
+    return block_ok && c.waves_per_cu >= 1 && c.waves_per_cu <= 4096 &&
+           (c.nontemporal == 0 || c.nontemporal == 1) && c.reserved == 0;
+}
+
+}  // namespace
+
+struct mirng_batcher_s {
+    std::mutex mu;
+    Slot slots[kSlots];
+    int next = 0;
+    int last = -1;     // slot of the most recent batch
+    int staged = -1;   // slot handed out by mirng_batcher_stage
+    mirng_batch_config cfg = {1024, 256, 1, 0};
+};
+
+using namespace mirng;
+
+extern "C" {
+
+mirng_status mirng_batcher_create(mirng_batcher *out)
+{
+    if (!out) return MIRNG_E_INVALID_ARG;
+    mirng_batcher b = new (std::nothrow) mirng_batcher_s();
+    if (!b) return MIRNG_E_ALLOC;
+    *out = b;
+    return MIRNG_OK;
+}
+
+mirng_status mirng_batcher_destroy(mirng_batcher b)
+{
+    if (!b) return MIRNG_OK;
+    {
+        std::lock_guard<std::mutex> lk(b->mu);
+        for (Slot &s : b->slots) release(s);
+    }
+    delete b;
+    return MIRNG_OK;
+}
+
+mirng_status mirng_batcher_config_get(mirng_batcher b, mirng_batch_config *c)
+{
+    if (!b || !c) return MIRNG_E_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(b->mu);
+    *c = b->cfg;
+    return MIRNG_OK;
+}
+
+mirng_status mirng_batcher_config_set(mirng_batcher b, const mirng_batch_config *c)
+{
+    if (!b || !c || !config_valid(*c)) return MIRNG_E_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(b->mu);
+    b->cfg = *c;
+    return MIRNG_OK;
+}
+
+mirng_status mirng_batcher_stage(mirng_batcher b, size_t count, mirng_request **reqs)
+{
+    if (!b || !reqs) return MIRNG_E_INVALID_ARG;
+    if (count >= (1ull << 31)) return MIRNG_E_INVALID_ARG;
+    int dev = 0;
+    if (ensure_device(&dev) != hipSuccess) return MIRNG_E_DEVICE;
+    std::lock_guard<std::mutex> lk(b->mu);
+    const int k = b->next;
+    if (prepare(b->slots[k], count, dev) != hipSuccess) return MIRNG_E_ALLOC;
+    b->next = (k + 1) % kSlots;
+    b->staged = k;
+    *reqs = b->slots[k].h_reqs;
+    return MIRNG_OK;
+}
+
+mirng_status mirng_generate_batch(mirng_batcher b, const mirng_request *reqs, size_t count,
+                                  void *stream)
+{
+    if (!b || !reqs) return MIRNG_E_INVALID_ARG;
+    if (count >= (1ull << 31)) return MIRNG_E_INVALID_ARG;
+    if (count == 0) return MIRNG_OK;
+    int dev = 0;
+    if (ensure_device(&dev) != hipSuccess) return MIRNG_E_DEVICE;
+    hipStream_t s = (hipStream_t)stream;
+    std::lock_guard<std::mutex> lk(b->mu);
+    int k;
+    if (b->staged >= 0 && reqs == b->slots[b->staged].h_reqs &&
+        count <= b->slots[b->staged].cap && b->slots[b->staged].dev == dev) {
+        k = b->staged;                                   // filled in place
+    } else {
+        k = b->next;
+        if (prepare(b->slots[k], count, dev) != hipSuccess) return MIRNG_E_ALLOC;
+        b->next = (k + 1) % kSlots;
+        std::memcpy(b->slots[k].h_reqs, reqs, count * sizeof(mirng_request));
+    }
+    b->staged = -1;
+    Slot &sl = b->slots[k];
+    sl.count = count;
+    BatchArgs a{};
+    a.reqs = sl.d_reqs;
+    a.count = (uint32_t)count;
+    a.nchunks = (uint32_t)((count + kChunk - 1) / kChunk);
+    a.desc = sl.d_desc;
+    a.local_end = sl.d_local_end;
+    a.chunk_total = sl.d_chunk_total;
+    a.chunk_end = sl.d_chunk_end;
+    a.total = sl.d_total;
+    a.status = sl.d_status;
+    a.nt = b->cfg.nontemporal;
+    a.block = (uint32_t)b->cfg.block;
+    const uint64_t waves = (uint64_t)device_cu_count() * (uint64_t)b->cfg.waves_per_cu;
+    const uint64_t wpb = (uint64_t)b->cfg.block / 64;
+    a.groups = (uint32_t)((waves + wpb - 1) / wpb);
+    hipError_t err = hipMemcpyAsync(sl.d_reqs, sl.h_reqs, count * sizeof(mirng_request),
+                                    hipMemcpyHostToDevice, s);
+    if (err == hipSuccess) err = launch_batch(a, s);
+    if (err == hipSuccess)
+        err = hipMemcpyAsync(sl.h_status, sl.d_status, count * sizeof(int32_t),
+                             hipMemcpyDeviceToHost, s);
+    if (err == hipSuccess) err = hipEventRecord(sl.done, s);
+    if (err != hipSuccess) return MIRNG_E_LAUNCH;
+    sl.pending = true;
+    b->last = k;
+    return MIRNG_OK;
+}
+
+mirng_status mirng_batcher_statuses(mirng_batcher b, int32_t *statuses, size_t count)
+{
+    if (!b || (!statuses && count)) return MIRNG_E_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(b->mu);
+    if (b->last < 0) return count ? MIRNG_E_INVALID_ARG : MIRNG_OK;
+    Slot &sl = b->slots[b->last];
+    if (count > sl.count) return MIRNG_E_INVALID_ARG;
+    if (sl.pending) {
+        if (hipEventSynchronize(sl.done) != hipSuccess) return MIRNG_E_DEVICE;
+        sl.pending = false;
+    }
+    std::memcpy(statuses, sl.h_status, count * sizeof(int32_t));
+    return MIRNG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,290 @@
+// Batched Philox generation: many independent requests of uneven sizes in
+// one persistent launch (the inter-event batching the paper defers for its
+// calorimeter application, arXiv:2109.01329 Sec. 6).
+//
+// plan:  one thread per request validates it (the ABI's rules), derives
+//        its slot run (as the plain path does on the host), and counts its
+//        tiles of 64 units; each workgroup scans the counts of its 1024
+//        requests.
+// scan:  one workgroup scans the per-chunk totals.
+// main:  a fixed grid of waves; wave w takes a contiguous range of tiles
+//        (tiles of one request are adjacent, requests in table order), finds
+//        the request of its first tile by binary search and walks forward,
+//        running the plain kernel's slot walk on each request segment.
+// Every value depends only on its request and position, never on the
+// tiling, the grid or the neighbouring requests.
+#include "internal.hpp"
+#include "philox.hpp"
+#include "transforms.hpp"
+
+namespace mirng {
+namespace {
+
+constexpr uint32_t kChunk = 1024;
+
+__device__ __forceinline__ bool finite(double x) { return __builtin_isfinite(x); }
+
+// Validation and planning of one request; returns its tile count.
+__device__ uint64_t plan_one(const mirng_request &q, BatchDesc &d, int32_t &st, int nt)
+{
+    st = MIRNG_OK;
+    if (q.engine_type != MIRNG_PHILOX4X32_10) {
+        st = MIRNG_E_UNSUPPORTED;
+        return 0;
+    }
+    const int kind = q.dist.kind;
+    if (q.reserved != 0 || q.dist.reserved != 0) { st = MIRNG_E_INVALID_ARG; return 0; }
+    if (kind < kBits || kind > kGauss) { st = MIRNG_E_UNSUPPORTED; return 0; }
+    const double p0 = q.dist.p0, p1 = q.dist.p1;
+    if ((kind == kU32F || kind == kU64F) && !(finite(p0) && finite(p1) && p0 < p1)) {
+        st = MIRNG_E_INVALID_ARG;
+        return 0;
+    }
+    if (kind == kGauss && !(finite(p0) && finite(p1) && p1 > 0.0)) {
+        st = MIRNG_E_INVALID_ARG;
+        return 0;
+    }
+    if (q.n == 0) return 0;
+    const uint64_t esz = kind == kU64F ? 8 : 4;
+    const uint64_t addr = (uint64_t)(uintptr_t)q.out;
+    if (addr == 0 || addr % esz) { st = MIRNG_E_INVALID_ARG; return 0; }
+    if (q.n >= (1ull << 32)) { st = MIRNG_E_CAPACITY; return 0; }
+
+    Epilogue ep;
+    ep.ranged = (kind == kBits || (p0 == 0.0 && p1 == 1.0)) ? 0 : 1;
+    ep.nt = nt;
+    ep.a64 = 0.0;
+    ep.d64 = 0.0;
+    ep.a32 = 0.0f;
+    ep.d32 = 0.0f;
+    if (kind == kU64F) {
+        ep.a64 = p0;
+        ep.d64 = p1 - p0;
+    } else if (kind == kGauss) {
+        ep.a32 = (float)p0;
+        ep.d32 = (float)p1;
+    } else {
+        ep.a32 = (float)p0;
+        ep.d32 = (float)(p1 - p0);
+    }
+    SlotRun &r = d.run;
+    r.k0 = (uint32_t)q.seed;
+    r.k1 = (uint32_t)(q.seed >> 32);
+    r.n = q.n;
+    r.ep = ep;
+    r.pad = 0;
+    d.kind = (uint32_t)kind;
+    const uint64_t p = q.offset;                 // engine words from the seed state
+    const uint32_t head = (uint32_t)((addr & 15u) / esz);
+    if (kind == kGauss && (head & 1u)) {
+        d.pairs = 1;
+        d.phase = 0;
+        d.nunits = (uint32_t)((q.n + 1) / 2);
+        r.base[0] = (uint32_t)p;
+        r.base[1] = (uint32_t)(p >> 32);
+        r.base[2] = 0;
+        r.base[3] = 0;
+        r.head = 0;
+        r.full_lo = 0;
+        r.full_count = 0;
+        r.out_base = (char *)q.out;
+    } else {
+        const uint32_t wpe = kind == kU64F ? 2u : 1u;
+        const uint32_t epv = (uint32_t)(16 / esz);
+        const uint64_t dq = (uint64_t)head * wpe;
+        // q = p - dq modulo 2^130
+        const uint64_t q_lo = p - dq;
+        const uint64_t q_mid = p >= dq ? 0ull : ~0ull;
+        const uint64_t q_top = p >= dq ? 0ull : 3ull;
+        const uint64_t b_lo = (q_lo >> 2) | (q_mid << 62);
+        const uint64_t b_hi = (q_mid >> 2) | (q_top << 62);
+        r.base[0] = (uint32_t)b_lo;
+        r.base[1] = (uint32_t)(b_lo >> 32);
+        r.base[2] = (uint32_t)b_hi;
+        r.base[3] = (uint32_t)(b_hi >> 32);
+        d.phase = (uint32_t)(q_lo & 3u);
+        d.pairs = 0;
+        r.head = head;
+        d.nunits = (uint32_t)((head + q.n + epv - 1) / epv);
+        const uint64_t lo = head ? 1 : 0;
+        const uint64_t hi = (head + q.n) / epv;
+        r.full_lo = (uint32_t)lo;
+        r.full_count = (uint32_t)(hi > lo ? hi - lo : 0);
+        r.out_base = (char *)q.out - (addr & 15u);
+    }
+    return ((uint64_t)d.nunits + 63) / 64;
+}
+
+// Inclusive scan over a workgroup of kChunk threads (16 waves).
+__device__ uint64_t block_scan(uint64_t v, uint64_t *wsum)
+{
+    const uint32_t lane = threadIdx.x & 63u, wid = threadIdx.x >> 6;
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint64_t t = __shfl_up(v, off);
+        if (lane >= (uint32_t)off) v += t;
+    }
+    if (lane == 63) wsum[wid] = v;
+    __syncthreads();
+    if (wid == 0) {
+        uint64_t w = lane < (blockDim.x >> 6) ? wsum[lane] : 0;
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint64_t t = __shfl_up(w, off);
+            if (lane >= (uint32_t)off) w += t;
+        }
+        if (lane < (blockDim.x >> 6)) wsum[lane] = w;
+    }
+    __syncthreads();
+    if (wid > 0) v += wsum[wid - 1];
+    __syncthreads();
+    return v;
+}
+
+__global__ __launch_bounds__(kChunk) void batch_plan_kernel(BatchArgs a)
+{
+    __shared__ uint64_t wsum[kChunk / 64];
+    const uint32_t r = blockIdx.x * kChunk + threadIdx.x;
+    uint64_t tiles = 0;
+    if (r < a.count) {
+        int32_t st;
+        BatchDesc d;
+        tiles = plan_one(a.reqs[r], d, st, a.nt);
+        a.status[r] = st;
+        if (st != MIRNG_OK || tiles == 0) {
+            d.nunits = 0;
+            tiles = 0;
+        }
+        a.desc[r] = d;
+    }
+    const uint64_t inc = block_scan(tiles, wsum);
+    if (r < a.count) a.local_end[r] = inc;
+    if (threadIdx.x == kChunk - 1) a.chunk_total[blockIdx.x] = inc;
+}
+
+__global__ __launch_bounds__(kChunk) void batch_scan_kernel(BatchArgs a)
+{
+    __shared__ uint64_t wsum[kChunk / 64];
+    __shared__ uint64_t carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (uint32_t c0 = 0; c0 < a.nchunks; c0 += kChunk) {
+        const uint32_t c = c0 + threadIdx.x;
+        const uint64_t v = c < a.nchunks ? a.chunk_total[c] : 0;
+        const uint64_t inc = block_scan(v, wsum) + carry;
+        if (c < a.nchunks) a.chunk_end[c] = inc;
+        __syncthreads();
+        if (threadIdx.x == kChunk - 1) carry = inc;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *a.total = carry;
+}
+
+__device__ __forceinline__ uint32_t uniform(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+}
+
+__device__ __forceinline__ uint64_t uniform64(uint64_t v)
+{
+    return ((uint64_t)uniform((uint32_t)(v >> 32)) << 32) | uniform((uint32_t)v);
+}
+
+// Inclusive tile end of request r.
+__device__ __forceinline__ uint64_t tile_end(const BatchArgs &a, uint32_t r)
+{
+    const uint32_t c = r / kChunk;
+    return a.chunk_end[c] - a.chunk_total[c] + a.local_end[r];
+}
+
+// First request whose inclusive tile end exceeds t.
+__device__ uint32_t find_request(const BatchArgs &a, uint64_t t)
+{
+    uint32_t lo = 0, hi = a.nchunks;             // chunk search
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) / 2;
+        if (a.chunk_end[mid] > t) hi = mid;
+        else lo = mid + 1;
+    }
+    const uint32_t c = lo;
+    const uint64_t base = a.chunk_end[c] - a.chunk_total[c];
+    uint32_t rlo = c * kChunk;
+    uint32_t rhi = min(a.count, rlo + kChunk);
+    while (rlo < rhi) {
+        const uint32_t mid = (rlo + rhi) / 2;
+        if (base + a.local_end[mid] > t) rhi = mid;
+        else rlo = mid + 1;
+    }
+    return rlo;
+}
+
+template <int KIND>
+__device__ __forceinline__ void run_kind(const BatchDesc &d, uint32_t u0, uint32_t span,
+                                         uint32_t lane)
+{
+    switch (d.phase) {
+    case 0: walk_slots<KIND, 0>(d.run, u0, span, lane); break;
+    case 1: walk_slots<KIND, 1>(d.run, u0, span, lane); break;
+    case 2: walk_slots<KIND, 2>(d.run, u0, span, lane); break;
+    default: walk_slots<KIND, 3>(d.run, u0, span, lane); break;
+    }
+}
+
+__device__ void run_segment(const BatchDesc &d, uint32_t u0, uint32_t span, uint32_t lane)
+{
+    if (d.pairs) {
+        const uint64_t p = ((uint64_t)d.run.base[1] << 32) | d.run.base[0];
+        for (uint32_t j = u0 + lane; j < u0 + span; j += 64)
+            emit_pair(d.run.k0, d.run.k1, p, 0, 0, j, d.run.n, (float *)d.run.out_base,
+                      d.run.ep.a32, d.run.ep.d32, d.run.ep.ranged);
+        return;
+    }
+    switch (d.kind) {
+    case kBits: run_kind<kBits>(d, u0, span, lane); break;
+    case kU32F: run_kind<kU32F>(d, u0, span, lane); break;
+    case kU64F: run_kind<kU64F>(d, u0, span, lane); break;
+    default: run_kind<kGauss>(d, u0, span, lane); break;
+    }
+}
+
+__global__ __launch_bounds__(1024) void batch_main_kernel(BatchArgs a)
+{
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
+    const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const uint64_t total = *a.total;
+    const uint64_t per = (total + waves - 1) / waves;
+    uint64_t t = wave * per;
+    const uint64_t t1 = min(t + per, total);
+    if (t >= t1) return;
+    uint32_t r = uniform(find_request(a, t));
+    while (t < t1 && r < a.count) {
+        const BatchDesc &d = a.desc[r];
+        const uint64_t end = uniform64(tile_end(a, r));
+        const uint32_t nunits = uniform(d.nunits);
+        const uint64_t tiles = ((uint64_t)nunits + 63) / 64;
+        if (end > t && tiles) {
+            const uint64_t start = end - tiles;
+            const uint64_t seg = min(t1, end);
+            const uint32_t u0 = (uint32_t)((t - start) * 64);
+            const uint32_t u1 = (uint32_t)min((seg - start) * 64, (uint64_t)nunits);
+            run_segment(d, u0, u1 - u0, lane);
+            t = seg;
+        }
+        ++r;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_batch(const BatchArgs &a, hipStream_t s)
+{
+    hipLaunchKernelGGL(batch_plan_kernel, dim3(a.nchunks), dim3(kChunk), 0, s, a);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL(batch_scan_kernel, dim3(1), dim3(kChunk), 0, s, a);
+    err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL(batch_main_kernel, dim3(a.groups), dim3(a.block), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace mirng

@@ -88,23 +88,30 @@ struct PhiloxBlocks {
     uint32_t groups;        // workgroups (persistent grid)
 };
 
-// Contiguous-walk Philox launch (every kind and position).  The output is
-// viewed as 16-byte slots starting at out_base (16-byte aligned); slot s
-// receives engine words q + 4 s .. q + 4 s + 3, where q = 4 * base + phase.
-// Element j of slot s is output index s * epv + j - head; only indices in
-// [0, n) are written.
-struct PhiloxFill {
+// A run of 16-byte output slots of one Philox request.  Slot s receives
+// engine words q + 4 s .. q + 4 s + 3 with q = 4 * base + phase; element j
+// of slot s is output index s * epv + j - head (epv = 4, or 2 for FP64);
+// only indices in [0, n) are written, slots [full_lo, full_lo + full_count)
+// whole.  out_base (slot 0) is 16-byte aligned.
+struct SlotRun {
     uint32_t k0, k1;
     uint32_t base[4];       // 128-bit block index of q
-    uint32_t phase;         // q mod 4
-    uint32_t head;          // elements of slot 0 before the first output
-    uint64_t n;             // outputs in this launch
-    uint32_t nslots;
-    uint32_t slots_per_wave;
-    uint32_t full_lo;       // slots [full_lo, full_lo + full_count) are complete
+    uint32_t head;
+    uint32_t full_lo;
     uint32_t full_count;
+    uint32_t pad;
+    uint64_t n;
     char *out_base;
     Epilogue ep;
+};
+
+// Contiguous-walk Philox launch (every kind and position): each wave owns
+// slots_per_wave consecutive slots of the run.
+struct PhiloxFill {
+    SlotRun run;
+    uint32_t phase;         // q mod 4
+    uint32_t nslots;
+    uint32_t slots_per_wave;
     int32_t kind;
     uint32_t block;         // threads per workgroup
 };
@@ -120,6 +127,35 @@ struct PhiloxPairs {
     float mean, sd;
     int32_t ranged;
 };
+
+// One Philox request of a batch, as planned on the device.
+struct BatchDesc {
+    SlotRun run;            // pair mode: base[0], base[1] = engine position (64-bit)
+    uint32_t kind;
+    uint32_t phase;         // q mod 4 (slot mode)
+    uint32_t nunits;        // 16-byte slots, or pairs in pair mode
+    uint32_t pairs;         // 1: Gaussian pairs that do not line up with the 16-byte grid
+};
+
+// Device tables of one batch.  Tiles are runs of 64 units of one request;
+// tile prefixes are kept per chunk of 1024 requests plus a prefix over
+// chunks.
+struct BatchArgs {
+    const mirng_request *reqs;
+    uint32_t count;
+    uint32_t nchunks;
+    BatchDesc *desc;
+    uint64_t *local_end;    // inclusive tile prefix inside the request's chunk
+    uint64_t *chunk_total;  // tiles per chunk
+    uint64_t *chunk_end;    // inclusive tile prefix over chunks
+    uint64_t *total;        // tiles of the batch
+    int32_t *status;        // per request
+    int32_t nt;             // streaming stores
+    uint32_t block;         // generation kernel: threads per workgroup
+    uint32_t groups;        // generation kernel: workgroups
+};
+
+hipError_t launch_batch(const BatchArgs &a, hipStream_t s);
 
 hipError_t launch_philox_blocks(const PhiloxBlocks &a, hipStream_t s);
 hipError_t launch_philox_fill(const PhiloxFill &a, hipStream_t s);

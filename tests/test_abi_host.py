@@ -170,3 +170,33 @@ def test_philox_config_validation():
     assert mr.philox_config().block == 512
     mr.set_philox_config(prev)
     assert mr.philox_config().as_dict() == c.as_dict()
+
+
+def test_request_record_layout():
+    import ctypes as ct
+    dt = mr.request_dtype()
+    assert dt.itemsize == 64
+    for name, field in (("engine_type", "engine_type"), ("seed", "seed"), ("offset", "offset"),
+                        ("n", "n"), ("out", "out")):
+        assert dt.fields[name][1] == getattr(mr.Request, field).offset
+    assert dt.fields["kind"][1] == mr.Request.dist.offset
+    assert dt.fields["p0"][1] == mr.Request.dist.offset + mr.Distribution.p0.offset
+
+
+def test_batcher_host_validation(L):
+    b = mr.Batcher()
+    c = b.config
+    assert c.block in (64, 128, 256, 512, 1024)
+    for bad in (dict(block=3), dict(waves_per_cu=0), dict(nontemporal=5), dict(reserved=1)):
+        with pytest.raises(mr.MirngError):
+            b.set_config(**bad)
+    assert b.config.as_dict() == c.as_dict()
+    reqs = mr.make_requests(3)
+    # NULL table, empty batch, oversize count: rejected or accepted without a device
+    assert L.mirng_generate_batch(b._h, None, 3, None) == 1
+    assert L.mirng_generate_batch(b._h, reqs.ctypes.data, 0, None) == 0
+    assert L.mirng_generate_batch(b._h, reqs.ctypes.data, 2**31, None) == 1
+    assert L.mirng_batcher_statuses(b._h, None, 0) == 0
+    assert L.mirng_batcher_statuses(b._h, reqs.ctypes.data, 1) == 1   # no batch yet
+    assert L.mirng_batcher_destroy(None) == 0
+    b.close()

@@ -1,0 +1,199 @@
+"""GPU parity of batched generation: every request of a batch equals the
+oracle (and the plain single-request path, byte for byte), invalid requests
+write nothing and report their status, and outputs do not depend on the
+request order, the launch shape or the ring slot and stream used."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2109_01329_amd as mr
+import synth
+from tests import gpu_helpers as gh
+
+pytestmark = pytest.mark.gpu
+
+KINDS = [mr.BITS_U32, mr.UNIFORM_F32, mr.UNIFORM_F64, mr.GAUSSIAN_F32]
+FILL = 0xA5
+
+
+def _mix(rng, count, max_log10=4.3):
+    """Random Philox requests laid out in one buffer with 64-byte guard gaps
+    and every output alignment the element size allows."""
+    reqs = mr.make_requests(count)
+    layout = []
+    pos = 64
+    for i in range(count):
+        kind = int(rng.choice(KINDS))
+        esz = mr.ELEM_BYTES[kind]
+        n = int(rng.choice([0, 1, 2, 3, 5])) if rng.random() < 0.15 else \
+            int(10 ** rng.uniform(0, max_log10))
+        mis = int(rng.integers(0, 16 // esz)) * esz
+        pos = ((pos + 15) // 16) * 16 + mis
+        seed = int(rng.integers(0, 2**64, dtype=np.uint64))
+        offset = int(rng.integers(0, 2**64, dtype=np.uint64)) if rng.random() < 0.3 else \
+            int(rng.integers(0, 2**40, dtype=np.uint64))
+        if kind in (mr.UNIFORM_F32, mr.UNIFORM_F64) and rng.random() < 0.3:
+            p0, p1 = -2.0, 3.5
+        elif kind == mr.GAUSSIAN_F32 and rng.random() < 0.3:
+            p0, p1 = 1.5, 0.25
+        else:
+            p0, p1 = 0.0, 1.0
+        reqs[i] = (1, 0, kind, 0, p0, p1, seed, offset, n, 0)
+        layout.append((pos, kind, n, seed, offset, p0, p1))
+        pos += n * esz + 64
+    return reqs, layout, pos + 64
+
+
+def _run(reqs, layout, nbytes, batcher=None, stream=None):
+    import torch
+    buf = gh.device_buffer(nbytes)
+    buf.fill_(FILL)
+    base = int(buf.data_ptr())
+    r = reqs.copy()
+    r["out"] = [base + lay[0] for lay in layout]
+    b = batcher or mr.Batcher()
+    b.generate(r, stream=stream)
+    torch.cuda.synchronize()
+    return buf.cpu().numpy(), b.statuses(len(r))
+
+
+def _check_outputs(host, layout, statuses):
+    covered = np.zeros(host.size, dtype=bool)
+    for (pos, kind, n, seed, offset, p0, p1), st in zip(layout, statuses):
+        esz = mr.ELEM_BYTES[kind]
+        if st != 0:
+            continue
+        got = host[pos: pos + n * esz].view(gh.NP_DTYPE[kind])
+        want = gh.oracle_philox(seed, offset, kind, n, p0, p1)
+        gh.assert_match(kind, got, want, p0, p1)
+        covered[pos: pos + n * esz] = True
+    assert np.all(host[~covered] == FILL), "bytes outside the requests were written"
+
+
+def test_batch_mixed_requests_vs_oracle():
+    rng = np.random.default_rng(71)
+    reqs, layout, nbytes = _mix(rng, 400)
+    host, st = _run(reqs, layout, nbytes)
+    assert np.all(st == 0)
+    _check_outputs(host, layout, st)
+
+
+def test_batch_equals_plain_path_bytes():
+    import torch
+    rng = np.random.default_rng(72)
+    reqs, layout, nbytes = _mix(rng, 120)
+    host, st = _run(reqs, layout, nbytes)
+    for pos, kind, n, seed, offset, p0, p1 in layout:
+        if n == 0:
+            continue
+        e = mr.Engine(mr.PHILOX4X32_10, seed, offset)
+        got, _ = gh.generate(e, kind, n, pos % 16, p0, p1)
+        esz = mr.ELEM_BYTES[kind]
+        assert np.array_equal(got.view(np.uint8), host[pos: pos + n * esz])
+
+
+def test_batch_invariant_to_order_and_launch_shape():
+    rng = np.random.default_rng(73)
+    reqs, layout, nbytes = _mix(rng, 300)
+    ref, _ = _run(reqs, layout, nbytes)
+    perm = rng.permutation(len(reqs))
+    b = mr.Batcher()
+    for cfg in (dict(block=64, waves_per_cu=1, nontemporal=0),
+                dict(block=256, waves_per_cu=7, nontemporal=1),
+                dict(block=1024, waves_per_cu=4096, nontemporal=0)):
+        b.set_config(**cfg)
+        host, st = _run(reqs[perm], [layout[i] for i in perm], nbytes, batcher=b)
+        assert np.array_equal(host, ref), cfg
+
+
+def test_batch_invalid_requests_report_and_write_nothing():
+    rng = np.random.default_rng(74)
+    reqs, layout, nbytes = _mix(rng, 60, max_log10=3)
+    bad = {}
+    def setbad(i, field, value, code):
+        reqs[i][field] = value
+        bad[i] = code
+    # pick requests with n > 0 to corrupt
+    idx = [i for i, lay in enumerate(layout) if lay[2] > 4]
+    setbad(idx[0], "kind", 9, 2)                       # unknown distribution
+    setbad(idx[1], "engine_type", 7, 2)                # unknown engine
+    setbad(idx[2], "engine_type", 2, 2)                # MRG32k3a: not in batches
+    setbad(idx[3], "reserved", 1, 1)
+    setbad(idx[4], "dist_reserved", 3, 1)
+    if layout[idx[5]][1] in (mr.UNIFORM_F32, mr.UNIFORM_F64):
+        reqs[idx[5]]["p0"], reqs[idx[5]]["p1"] = 1.0, 1.0
+    else:
+        reqs[idx[5]]["kind"] = mr.GAUSSIAN_F32
+        reqs[idx[5]]["p1"] = -1.0
+    bad[idx[5]] = 1
+    reqs[idx[6]]["p0"] = float("nan")
+    reqs[idx[6]]["kind"] = mr.UNIFORM_F32
+    bad[idx[6]] = 1
+    reqs[idx[7]]["n"] = 1 << 32
+    bad[idx[7]] = 6
+    host, st = _run(reqs, layout, nbytes)
+    for i, code in bad.items():
+        assert st[i] == code, (i, st[i], code)
+    good = [i for i in range(len(layout)) if i not in bad]
+    assert np.all(st[good] == 0)
+    lay2 = list(layout)
+    _check_outputs(host, lay2, [st[i] for i in range(len(layout))])
+
+
+def test_batch_calorimeter_shape():
+    """Event-shaped batch: per event a uniform FP32 request of 3h outputs at
+    position 0 and a Gaussian request of h outputs at position 3h on key
+    (seed32, event id); outputs contiguous per event."""
+    import torch
+    ev = synth.calo_events(n_events=2000)
+    h = ev.hits
+    reqs = mr.make_requests(2 * ev.n_events)
+    sizes = np.stack([3 * h, h], axis=1).reshape(-1)
+    offs = np.concatenate([[0], np.cumsum(sizes * 4)])[:-1]
+    out = torch.empty(int(sizes.sum()), dtype=torch.float32, device="cuda")
+    base = int(out.data_ptr())
+    seeds = (np.arange(ev.n_events, dtype=np.uint64) << np.uint64(32)) | np.uint64(ev.seed32)
+    reqs["engine_type"] = 1
+    reqs["kind"] = np.tile([mr.UNIFORM_F32, mr.GAUSSIAN_F32], ev.n_events)
+    reqs["p0"] = 0.0
+    reqs["p1"] = 1.0
+    reqs["seed"] = np.repeat(seeds, 2)
+    reqs["offset"] = np.stack([np.zeros_like(h), 3 * h], axis=1).reshape(-1)
+    reqs["n"] = sizes
+    reqs["out"] = base + offs
+    b = mr.Batcher()
+    b.generate(reqs)
+    torch.cuda.synchronize()
+    assert np.all(b.statuses(len(reqs)) == 0)
+    host = out.cpu().numpy()
+    rng = np.random.default_rng(75)
+    for e in rng.choice(ev.n_events, 150, replace=False):
+        seed = int(seeds[e])
+        o = int(offs[2 * e]) // 4
+        gh.assert_match(mr.UNIFORM_F32, host[o: o + 3 * h[e]],
+                        gh.oracle_philox(seed, 0, mr.UNIFORM_F32, int(3 * h[e])))
+        g = host[o + 3 * h[e]: o + 4 * h[e]]
+        gh.assert_match(mr.GAUSSIAN_F32, g,
+                        gh.oracle_philox(seed, int(3 * h[e]), mr.GAUSSIAN_F32, int(h[e])))
+
+
+def test_batch_staged_ring_two_streams():
+    import torch
+    rng = np.random.default_rng(76)
+    b = mr.Batcher()
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    jobs = []
+    for k in range(7):                 # more batches than ring slots
+        reqs, layout, nbytes = _mix(rng, 50 + 13 * k, max_log10=3.5)
+        buf = gh.device_buffer(nbytes)
+        buf.fill_(FILL)
+        torch.cuda.synchronize()
+        staged = b.stage(len(reqs))
+        staged[:] = reqs
+        staged["out"] = [int(buf.data_ptr()) + lay[0] for lay in layout]
+        b.generate(staged, stream=streams[k % 2])
+        jobs.append((buf, layout))
+    torch.cuda.synchronize()
+    for buf, layout in jobs:
+        host = buf.cpu().numpy()
+        _check_outputs(host, layout, [0] * len(layout))
