@@ -266,6 +266,29 @@ mirng_status mirng_philox_config_get(mirng_philox_config *c);
  * the current shape is kept.  Host-only. */
 mirng_status mirng_philox_config_set(const mirng_philox_config *c);
 
+/* -------------------------------------------------------------- autotuning */
+
+/* The autotuner times every candidate launch shape on the caller's own
+ * workload and installs the fastest; only speed depends on the shape.  It
+ * runs the workload repeatedly on `stream` (so `out` / the requests' outputs
+ * are overwritten), first for about prewarm_ms milliseconds to bring the
+ * clocks to their loaded state, then `rounds` rounds over the candidates,
+ * each timing `reps` back-to-back launches with HIP events; a candidate's
+ * score is its median round.  It synchronises the stream (host-blocking).
+ * The paper notes that the block size chosen for a kernel matters (256 vs
+ * 1024 threads, Sec. 6) and that per-architecture tuning is future work
+ * (Sec. 7).  Results: the chosen shape (also installed) and its time per
+ * launch in milliseconds; either pointer may be NULL.  Errors: bad
+ * arguments -> INVALID_ARG; device or launch failures -> DEVICE / LAUNCH
+ * (the previous shape is then kept). */
+mirng_status mirng_autotune_philox(int32_t kind, uint64_t n, void *out, void *stream,
+                                   int32_t prewarm_ms, int32_t rounds, int32_t reps,
+                                   mirng_philox_config *best, float *best_ms);
+
+mirng_status mirng_autotune_batch(mirng_batcher b, const mirng_request *reqs, size_t count,
+                                  void *stream, int32_t prewarm_ms, int32_t rounds,
+                                  int32_t reps, mirng_batch_config *best, float *best_ms);
+
 /* ------------------------------------------------------------------ misc */
 
 /* Static description of a status code (never NULL). */

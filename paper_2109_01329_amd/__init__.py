@@ -123,6 +123,12 @@ def lib() -> ctypes.CDLL:
         "mirng_batcher_config_get": ([vp, ctypes.POINTER(BatchConfig)], ctypes.c_int),
         "mirng_batcher_config_set": ([vp, ctypes.POINTER(BatchConfig)], ctypes.c_int),
         "mirng_words_consumed": ([ctypes.c_int32, ctypes.c_int32, u64], u64),
+        "mirng_autotune_philox": ([ctypes.c_int32, u64, vp, vp, ctypes.c_int32, ctypes.c_int32,
+                                   ctypes.c_int32, ctypes.POINTER(PhiloxConfig),
+                                   ctypes.POINTER(ctypes.c_float)], ctypes.c_int),
+        "mirng_autotune_batch": ([vp, vp, ctypes.c_size_t, vp, ctypes.c_int32, ctypes.c_int32,
+                                  ctypes.c_int32, ctypes.POINTER(BatchConfig),
+                                  ctypes.POINTER(ctypes.c_float)], ctypes.c_int),
         "mirng_bench_store": ([vp, u64, ctypes.c_int32, vp], ctypes.c_int),
         "mirng_bench_philox_nostore": ([u64, ctypes.c_uint32, ctypes.c_uint32, vp, vp],
                                        ctypes.c_int),
@@ -257,6 +263,18 @@ def set_philox_config(c: PhiloxConfig | None = None, **fields) -> PhiloxConfig:
     return prev
 
 
+def autotune_philox(kind: int, n: int, out, stream=None, prewarm_ms: int = 300,
+                    rounds: int = 5, reps: int = 10):
+    """Time the candidate Philox launch shapes on `n` outputs of `kind` into
+    `out` (overwritten), install the fastest and return (shape, ms)."""
+    c = PhiloxConfig()
+    ms = ctypes.c_float()
+    _check(lib().mirng_autotune_philox(kind, n, _ptr(out), _stream(stream), prewarm_ms, rounds,
+                                       reps, ctypes.byref(c), ctypes.byref(ms)),
+           "autotune_philox")
+    return c, float(ms.value)
+
+
 class Batcher:
     """Batched generation of many independent requests in one launch.
 
@@ -309,6 +327,19 @@ class Batcher:
         reqs = np.ascontiguousarray(reqs, dtype=request_dtype())
         _check(lib().mirng_generate_batch(self._h, reqs.ctypes.data, len(reqs), _stream(stream)),
                "generate_batch")
+
+    def autotune(self, reqs, stream=None, prewarm_ms: int = 300, rounds: int = 5,
+                 reps: int = 10):
+        """Time the candidate batch launch shapes on this batch (its outputs
+        are overwritten), install the fastest and return (shape, ms)."""
+        import numpy as np
+        reqs = np.ascontiguousarray(reqs, dtype=request_dtype())
+        c = BatchConfig()
+        ms = ctypes.c_float()
+        _check(lib().mirng_autotune_batch(self._h, reqs.ctypes.data, len(reqs), _stream(stream),
+                                          prewarm_ms, rounds, reps, ctypes.byref(c),
+                                          ctypes.byref(ms)), "autotune_batch")
+        return c, float(ms.value)
 
     def statuses(self, count: int):
         import numpy as np

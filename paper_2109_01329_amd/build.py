@@ -29,6 +29,7 @@ SOURCES = [
     "micro_kernels.hip",
     "batch.cpp",
     "batch_kernels.hip",
+    "autotune.cpp",
 ]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -47,7 +48,9 @@ def _compile(src: str) -> str:
     if src.endswith(".hip"):
         cmd = [HIPCC, *COMMON, *DEVICE, "-c", path, "-o", obj]
     else:
-        cmd = [HIPCC, *COMMON, "-D__HIP_PLATFORM_AMD__", "-c", path, "-o", obj]
+        # host-only translation units: plain C++ against the HIP headers
+        cmd = [HIPCC, "-x", "c++", *COMMON, "-I/opt/rocm/include", "-D__HIP_PLATFORM_AMD__",
+               "-c", path, "-o", obj]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{res.stdout}\n{res.stderr}")

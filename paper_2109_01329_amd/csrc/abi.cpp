@@ -129,8 +129,7 @@ Epilogue make_epilogue(const mirng_distribution *d, int nt)
 
 // Words p .. of the engine into n outputs at out: the contiguous-walk
 // kernel, or the grid-stride kernel when it is selected and outputs do not
-// straddle Philox blocks, or the pair kernel for Gaussians whose pairs do
-// not line up with the 16-byte grid.
+// straddle Philox blocks.
 hipError_t philox_plain(const uint32_t key[2], Pos130 p, const mirng_distribution *d,
                         uint64_t n, char *out, hipStream_t s)
 {
@@ -177,22 +176,12 @@ hipError_t philox_plain(const uint32_t key[2], Pos130 p, const mirng_distributio
             const uint64_t need = (steps + wpb - 1) / wpb;
             a.groups = (uint32_t)(want < need ? want : need);
             err = launch_philox_blocks(a, s);
-        } else if (kind == kGauss && ((addr & 15u) / esz) & 1u) {
-            PhiloxPairs a{};
-            a.k0 = key[0];
-            a.k1 = key[1];
-            a.p_lo = p.l[0];
-            a.p_mid = p.l[1];
-            a.p_top = (uint32_t)p.l[2];
-            a.n = chunk;
-            a.out = (float *)out;
-            a.mean = ep.a32;
-            a.sd = ep.d32;
-            a.ranged = ep.ranged;
-            err = launch_philox_pairs(a, s);
         } else {
             const uint32_t epv = (uint32_t)(16 / esz);
-            const uint32_t head = (uint32_t)((addr & 15u) / esz);
+            // Gaussian pairs that would straddle the 16-byte grid: slots of
+            // four outputs start at the output itself (dword-aligned stores)
+            const bool at_out = kind == kGauss && (((addr & 15u) / esz) & 1u);
+            const uint32_t head = at_out ? 0u : (uint32_t)((addr & 15u) / esz);
             PhiloxFill a{};
             SlotRun &r = a.run;
             r.k0 = key[0];
@@ -216,7 +205,7 @@ hipError_t philox_plain(const uint32_t key[2], Pos130 p, const mirng_distributio
             const uint64_t hi = (head + chunk) / epv;   // slots below hi end inside n
             r.full_lo = (uint32_t)lo;
             r.full_count = (uint32_t)(hi > lo ? hi - lo : 0);
-            r.out_base = out - (addr & 15u);
+            r.out_base = at_out ? out : out - (addr & 15u);
             r.ep = ep;
             a.kind = kind;
             a.block = (uint32_t)(tu.walk == 0 ? tu.block : 1024);

@@ -1,11 +1,13 @@
 // Batcher: host side of batched generation.  A ring of staging slots, each
-// with a pinned request table, device tables and a completion event, so
+// with a pinned request table, device tables and completion events, so
 // that successive batches (on one or several streams) overlap without the
 // host waiting, except when a slot is reused while the device still needs
 // it.  Per batch the host copies the request table into pinned memory (or
-// not at all when the caller filled the staged slot) and enqueues one
-// host-to-device copy, the planning and scan kernels, the generation kernel
-// and the device-to-host copy of the per-request statuses.
+// not at all when the caller filled the staged slot), uploads it on the
+// batcher's own copy stream (so the upload overlaps earlier work on the
+// caller's stream), and enqueues on the caller's stream, behind the upload,
+// the planning, scan and mark kernels, the generation kernel and the copy
+// of the per-request statuses back to pinned memory.
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -25,12 +27,16 @@ struct Slot {
     int dev = -1;
     bool pending = false;              // `done` recorded and maybe not reached
     hipEvent_t done = nullptr;
+    hipEvent_t uploaded = nullptr;
+    size_t wave_cap = 0;
     mirng_request *d_reqs = nullptr;
     mirng::BatchDesc *d_desc = nullptr;
     uint64_t *d_local_end = nullptr;
     uint64_t *d_chunk_total = nullptr;
     uint64_t *d_chunk_end = nullptr;
     uint64_t *d_total = nullptr;
+    uint64_t *d_tile_start = nullptr;
+    uint32_t *d_wave_req = nullptr;
     int32_t *d_status = nullptr;
 };
 
@@ -45,21 +51,33 @@ void release(Slot &s)
     if (s.d_chunk_total) (void)hipFree(s.d_chunk_total);
     if (s.d_chunk_end) (void)hipFree(s.d_chunk_end);
     if (s.d_total) (void)hipFree(s.d_total);
+    if (s.d_tile_start) (void)hipFree(s.d_tile_start);
+    if (s.d_wave_req) (void)hipFree(s.d_wave_req);
     if (s.d_status) (void)hipFree(s.d_status);
     if (s.done) (void)hipEventDestroy(s.done);
+    if (s.uploaded) (void)hipEventDestroy(s.uploaded);
     s = Slot{};
 }
 
 // Waits until the device no longer uses the slot, then makes room for
-// `count` requests on device `dev`.
-hipError_t prepare(Slot &s, size_t count, int dev)
+// `count` requests and `waves` generation waves on device `dev`.
+hipError_t prepare(Slot &s, size_t count, size_t waves, int dev)
 {
     if (s.pending) {
         hipError_t err = hipEventSynchronize(s.done);
         if (err != hipSuccess) return err;
         s.pending = false;
     }
-    if (s.cap >= count && s.dev == dev) return hipSuccess;
+    if (s.cap >= count && s.dev == dev) {
+        if (s.wave_cap >= waves) return hipSuccess;
+        if (s.d_wave_req) (void)hipFree(s.d_wave_req);
+        s.d_wave_req = nullptr;
+        s.wave_cap = 0;
+        hipError_t err = hipMalloc((void **)&s.d_wave_req, waves * sizeof(uint32_t));
+        if (err != hipSuccess) return err;
+        s.wave_cap = waves;
+        return hipSuccess;
+    }
     release(s);
     size_t cap = count < 1024 ? 1024 : count;
     const size_t nchunks = (cap + kChunk - 1) / kChunk;
@@ -73,13 +91,17 @@ hipError_t prepare(Slot &s, size_t count, int dev)
     chk(hipMalloc((void **)&s.d_chunk_total, nchunks * sizeof(uint64_t)));
     chk(hipMalloc((void **)&s.d_chunk_end, nchunks * sizeof(uint64_t)));
     chk(hipMalloc((void **)&s.d_total, sizeof(uint64_t)));
+    chk(hipMalloc((void **)&s.d_tile_start, cap * sizeof(uint64_t)));
+    chk(hipMalloc((void **)&s.d_wave_req, waves * sizeof(uint32_t)));
     chk(hipMalloc((void **)&s.d_status, cap * sizeof(int32_t)));
     chk(hipEventCreateWithFlags(&s.done, hipEventDisableTiming));
+    chk(hipEventCreateWithFlags(&s.uploaded, hipEventDisableTiming));
     if (err != hipSuccess) {
         release(s);
         return err;
     }
     s.cap = cap;
+    s.wave_cap = waves;
     s.dev = dev;
     return hipSuccess;
 }
@@ -97,6 +119,8 @@ bool config_valid(const mirng_batch_config &c)
 struct mirng_batcher_s {
     std::mutex mu;
     Slot slots[kSlots];
+    hipStream_t copy = nullptr;        // uploads (default priority)
+    int copy_dev = -1;
     int next = 0;
     int last = -1;     // slot of the most recent batch
     int staged = -1;   // slot handed out by mirng_batcher_stage
@@ -122,6 +146,7 @@ mirng_status mirng_batcher_destroy(mirng_batcher b)
     {
         std::lock_guard<std::mutex> lk(b->mu);
         for (Slot &s : b->slots) release(s);
+        if (b->copy) (void)hipStreamDestroy(b->copy);
     }
     delete b;
     return MIRNG_OK;
@@ -143,6 +168,11 @@ mirng_status mirng_batcher_config_set(mirng_batcher b, const mirng_batch_config 
     return MIRNG_OK;
 }
 
+static size_t grid_waves(const mirng_batch_config &c)
+{
+    return (size_t)device_cu_count() * (size_t)c.waves_per_cu;
+}
+
 mirng_status mirng_batcher_stage(mirng_batcher b, size_t count, mirng_request **reqs)
 {
     if (!b || !reqs) return MIRNG_E_INVALID_ARG;
@@ -151,7 +181,7 @@ mirng_status mirng_batcher_stage(mirng_batcher b, size_t count, mirng_request **
     if (ensure_device(&dev) != hipSuccess) return MIRNG_E_DEVICE;
     std::lock_guard<std::mutex> lk(b->mu);
     const int k = b->next;
-    if (prepare(b->slots[k], count, dev) != hipSuccess) return MIRNG_E_ALLOC;
+    if (prepare(b->slots[k], count, grid_waves(b->cfg), dev) != hipSuccess) return MIRNG_E_ALLOC;
     b->next = (k + 1) % kSlots;
     b->staged = k;
     *reqs = b->slots[k].h_reqs;
@@ -168,13 +198,23 @@ mirng_status mirng_generate_batch(mirng_batcher b, const mirng_request *reqs, si
     if (ensure_device(&dev) != hipSuccess) return MIRNG_E_DEVICE;
     hipStream_t s = (hipStream_t)stream;
     std::lock_guard<std::mutex> lk(b->mu);
+    if (b->copy_dev != dev) {
+        if (b->copy) (void)hipStreamDestroy(b->copy);
+        b->copy = nullptr;
+        if (hipStreamCreateWithFlags(&b->copy, hipStreamNonBlocking) != hipSuccess)
+            return MIRNG_E_DEVICE;
+        b->copy_dev = dev;
+    }
+    const uint64_t wpb = (uint64_t)b->cfg.block / 64;
+    const uint64_t waves = ((grid_waves(b->cfg) + wpb - 1) / wpb) * wpb;
     int k;
     if (b->staged >= 0 && reqs == b->slots[b->staged].h_reqs &&
         count <= b->slots[b->staged].cap && b->slots[b->staged].dev == dev) {
         k = b->staged;                                   // filled in place
+        if (prepare(b->slots[k], count, waves, dev) != hipSuccess) return MIRNG_E_ALLOC;
     } else {
         k = b->next;
-        if (prepare(b->slots[k], count, dev) != hipSuccess) return MIRNG_E_ALLOC;
+        if (prepare(b->slots[k], count, waves, dev) != hipSuccess) return MIRNG_E_ALLOC;
         b->next = (k + 1) % kSlots;
         std::memcpy(b->slots[k].h_reqs, reqs, count * sizeof(mirng_request));
     }
@@ -190,14 +230,17 @@ mirng_status mirng_generate_batch(mirng_batcher b, const mirng_request *reqs, si
     a.chunk_total = sl.d_chunk_total;
     a.chunk_end = sl.d_chunk_end;
     a.total = sl.d_total;
+    a.tile_start = sl.d_tile_start;
+    a.wave_req = sl.d_wave_req;
+    a.waves = (uint32_t)waves;
     a.status = sl.d_status;
     a.nt = b->cfg.nontemporal;
     a.block = (uint32_t)b->cfg.block;
-    const uint64_t waves = (uint64_t)device_cu_count() * (uint64_t)b->cfg.waves_per_cu;
-    const uint64_t wpb = (uint64_t)b->cfg.block / 64;
-    a.groups = (uint32_t)((waves + wpb - 1) / wpb);
+    a.groups = (uint32_t)(waves / wpb);
     hipError_t err = hipMemcpyAsync(sl.d_reqs, sl.h_reqs, count * sizeof(mirng_request),
-                                    hipMemcpyHostToDevice, s);
+                                    hipMemcpyHostToDevice, b->copy);
+    if (err == hipSuccess) err = hipEventRecord(sl.uploaded, b->copy);
+    if (err == hipSuccess) err = hipStreamWaitEvent(s, sl.uploaded, 0);
     if (err == hipSuccess) err = launch_batch(a, s);
     if (err == hipSuccess)
         err = hipMemcpyAsync(sl.h_status, sl.d_status, count * sizeof(int32_t),

@@ -4,13 +4,16 @@
 //
 // plan:  one thread per request validates it (the ABI's rules), derives
 //        its slot run (as the plain path does on the host), and counts its
-//        tiles of 64 units; each workgroup scans the counts of its 1024
+//        tiles of 64 slots; each workgroup scans the counts of its 1024
 //        requests.
 // scan:  one workgroup scans the per-chunk totals.
+// mark:  one thread per request writes the request's first global tile and,
+//        for every wave whose range of ceil(tiles / waves) tiles starts inside
+//        the request, the request index (so no wave has to search).
 // main:  a fixed grid of waves; wave w takes a contiguous range of tiles
-//        (tiles of one request are adjacent, requests in table order), finds
-//        the request of its first tile by binary search and walks forward,
-//        running the plain kernel's slot walk on each request segment.
+//        (tiles of one request are adjacent, requests in table order),
+//        starts at its marked request and walks forward, running the plain
+//        kernel's slot walk on each request segment.
 // Every value depends only on its request and position, never on the
 // tiling, the grid or the neighbouring requests.
 #include "internal.hpp"
@@ -76,21 +79,23 @@ __device__ uint64_t plan_one(const mirng_request &q, BatchDesc &d, int32_t &st, 
     d.kind = (uint32_t)kind;
     const uint64_t p = q.offset;                 // engine words from the seed state
     const uint32_t head = (uint32_t)((addr & 15u) / esz);
+    const uint32_t wpe = kind == kU64F ? 2u : 1u;
+    const uint32_t epv = (uint32_t)(16 / esz);
+    d.pairs = 0;
     if (kind == kGauss && (head & 1u)) {
-        d.pairs = 1;
-        d.phase = 0;
-        d.nunits = (uint32_t)((q.n + 1) / 2);
-        r.base[0] = (uint32_t)p;
-        r.base[1] = (uint32_t)(p >> 32);
+        // pairs would straddle the 16-byte grid: slots of 4 outputs start at
+        // the output itself (dword-aligned 16-byte stores)
+        r.base[0] = (uint32_t)(p >> 2);
+        r.base[1] = (uint32_t)(p >> 34);
         r.base[2] = 0;
         r.base[3] = 0;
+        d.phase = (uint32_t)(p & 3u);
         r.head = 0;
+        d.nunits = (uint32_t)((q.n + 3) / 4);
         r.full_lo = 0;
-        r.full_count = 0;
+        r.full_count = (uint32_t)(q.n / 4);
         r.out_base = (char *)q.out;
     } else {
-        const uint32_t wpe = kind == kU64F ? 2u : 1u;
-        const uint32_t epv = (uint32_t)(16 / esz);
         const uint64_t dq = (uint64_t)head * wpe;
         // q = p - dq modulo 2^130
         const uint64_t q_lo = p - dq;
@@ -103,7 +108,6 @@ __device__ uint64_t plan_one(const mirng_request &q, BatchDesc &d, int32_t &st, 
         r.base[2] = (uint32_t)b_hi;
         r.base[3] = (uint32_t)(b_hi >> 32);
         d.phase = (uint32_t)(q_lo & 3u);
-        d.pairs = 0;
         r.head = head;
         d.nunits = (uint32_t)((head + q.n + epv - 1) / epv);
         const uint64_t lo = head ? 1 : 0;
@@ -188,32 +192,21 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t v)
     return ((uint64_t)uniform((uint32_t)(v >> 32)) << 32) | uniform((uint32_t)v);
 }
 
-// Inclusive tile end of request r.
-__device__ __forceinline__ uint64_t tile_end(const BatchArgs &a, uint32_t r)
+__global__ __launch_bounds__(256) void batch_mark_kernel(BatchArgs a)
 {
+    const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= a.count) return;
     const uint32_t c = r / kChunk;
-    return a.chunk_end[c] - a.chunk_total[c] + a.local_end[r];
-}
-
-// First request whose inclusive tile end exceeds t.
-__device__ uint32_t find_request(const BatchArgs &a, uint64_t t)
-{
-    uint32_t lo = 0, hi = a.nchunks;             // chunk search
-    while (lo < hi) {
-        const uint32_t mid = (lo + hi) / 2;
-        if (a.chunk_end[mid] > t) hi = mid;
-        else lo = mid + 1;
-    }
-    const uint32_t c = lo;
-    const uint64_t base = a.chunk_end[c] - a.chunk_total[c];
-    uint32_t rlo = c * kChunk;
-    uint32_t rhi = min(a.count, rlo + kChunk);
-    while (rlo < rhi) {
-        const uint32_t mid = (rlo + rhi) / 2;
-        if (base + a.local_end[mid] > t) rhi = mid;
-        else rlo = mid + 1;
-    }
-    return rlo;
+    const uint64_t end = a.chunk_end[c] - a.chunk_total[c] + a.local_end[r];
+    const uint64_t tiles = ((uint64_t)a.desc[r].nunits + 63) / 64;
+    const uint64_t start = end - tiles;
+    a.tile_start[r] = start;
+    const uint64_t total = *a.total;
+    const uint64_t per = (total + a.waves - 1) / a.waves;
+    if (tiles == 0 || per == 0) return;
+    // waves w with w * per in [start, end)
+    for (uint64_t w = (start + per - 1) / per; w * per < end && w < a.waves; ++w)
+        a.wave_req[w] = r;
 }
 
 template <int KIND>
@@ -230,13 +223,6 @@ __device__ __forceinline__ void run_kind(const BatchDesc &d, uint32_t u0, uint32
 
 __device__ void run_segment(const BatchDesc &d, uint32_t u0, uint32_t span, uint32_t lane)
 {
-    if (d.pairs) {
-        const uint64_t p = ((uint64_t)d.run.base[1] << 32) | d.run.base[0];
-        for (uint32_t j = u0 + lane; j < u0 + span; j += 64)
-            emit_pair(d.run.k0, d.run.k1, p, 0, 0, j, d.run.n, (float *)d.run.out_base,
-                      d.run.ep.a32, d.run.ep.d32, d.run.ep.ranged);
-        return;
-    }
     switch (d.kind) {
     case kBits: run_kind<kBits>(d, u0, span, lane); break;
     case kU32F: run_kind<kU32F>(d, u0, span, lane); break;
@@ -245,28 +231,37 @@ __device__ void run_segment(const BatchDesc &d, uint32_t u0, uint32_t span, uint
     }
 }
 
+// The descriptor of a (wave-uniform) request, copied into registers so that
+// the slot stores cannot force it to be re-read.
+__device__ __forceinline__ BatchDesc load_desc(const BatchDesc *p)
+{
+    BatchDesc d;
+    const uint32_t *src = (const uint32_t *)p;
+    uint32_t *dst = (uint32_t *)&d;
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(BatchDesc) / 4); ++i) dst[i] = uniform(src[i]);
+    return d;
+}
+
 __global__ __launch_bounds__(1024) void batch_main_kernel(BatchArgs a)
 {
     const uint32_t lane = threadIdx.x & 63u;
-    const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
     const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     const uint64_t total = *a.total;
-    const uint64_t per = (total + waves - 1) / waves;
+    const uint64_t per = (total + a.waves - 1) / a.waves;
     uint64_t t = wave * per;
     const uint64_t t1 = min(t + per, total);
     if (t >= t1) return;
-    uint32_t r = uniform(find_request(a, t));
+    uint32_t r = uniform(a.wave_req[wave]);
     while (t < t1 && r < a.count) {
-        const BatchDesc &d = a.desc[r];
-        const uint64_t end = uniform64(tile_end(a, r));
-        const uint32_t nunits = uniform(d.nunits);
-        const uint64_t tiles = ((uint64_t)nunits + 63) / 64;
-        if (end > t && tiles) {
-            const uint64_t start = end - tiles;
+        const uint64_t start = uniform64(a.tile_start[r]);
+        const uint32_t nunits = uniform(a.desc[r].nunits);
+        const uint64_t end = start + ((uint64_t)nunits + 63) / 64;
+        if (end > t) {
             const uint64_t seg = min(t1, end);
             const uint32_t u0 = (uint32_t)((t - start) * 64);
             const uint32_t u1 = (uint32_t)min((seg - start) * 64, (uint64_t)nunits);
-            run_segment(d, u0, u1 - u0, lane);
+            run_segment(load_desc(&a.desc[r]), u0, u1 - u0, lane);
             t = seg;
         }
         ++r;
@@ -281,6 +276,9 @@ hipError_t launch_batch(const BatchArgs &a, hipStream_t s)
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
     hipLaunchKernelGGL(batch_scan_kernel, dim3(1), dim3(kChunk), 0, s, a);
+    err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL(batch_mark_kernel, dim3((a.count + 255) / 256), dim3(256), 0, s, a);
     err = hipGetLastError();
     if (err != hipSuccess) return err;
     hipLaunchKernelGGL(batch_main_kernel, dim3(a.groups), dim3(a.block), 0, s, a);

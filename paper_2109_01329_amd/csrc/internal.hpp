@@ -92,7 +92,11 @@ struct PhiloxBlocks {
 // engine words q + 4 s .. q + 4 s + 3 with q = 4 * base + phase; element j
 // of slot s is output index s * epv + j - head (epv = 4, or 2 for FP64);
 // only indices in [0, n) are written, slots [full_lo, full_lo + full_count)
-// whole.  out_base (slot 0) is 16-byte aligned.
+// whole.  out_base (slot 0) is 16-byte aligned, except for Gaussian outputs
+// whose word pairs would straddle the 16-byte grid (output 4 mod 8 bytes at
+// an odd position): there slots start at the output itself, head = 0, and
+// the 16-byte stores are only 4-byte aligned (the path is ALU-bound, so
+// their cost does not show).
 struct SlotRun {
     uint32_t k0, k1;
     uint32_t base[4];       // 128-bit block index of q
@@ -116,28 +120,16 @@ struct PhiloxFill {
     uint32_t block;         // threads per workgroup
 };
 
-// Gaussian output whose 16-byte slots do not line up with word pairs (odd
-// position and the output pointer 4 mod 8): one thread per pair.
-struct PhiloxPairs {
-    uint32_t k0, k1;
-    uint64_t p_lo, p_mid;   // word position of pair 0 (130-bit, top in p_top)
-    uint32_t p_top;
-    uint64_t n;
-    float *out;
-    float mean, sd;
-    int32_t ranged;
-};
-
 // One Philox request of a batch, as planned on the device.
 struct BatchDesc {
-    SlotRun run;            // pair mode: base[0], base[1] = engine position (64-bit)
+    SlotRun run;
     uint32_t kind;
-    uint32_t phase;         // q mod 4 (slot mode)
-    uint32_t nunits;        // 16-byte slots, or pairs in pair mode
-    uint32_t pairs;         // 1: Gaussian pairs that do not line up with the 16-byte grid
+    uint32_t phase;         // q mod 4
+    uint32_t nunits;        // 16-byte slots
+    uint32_t pairs;         // unused, 0
 };
 
-// Device tables of one batch.  Tiles are runs of 64 units of one request;
+// Device tables of one batch.  Tiles are runs of 64 slots of one request;
 // tile prefixes are kept per chunk of 1024 requests plus a prefix over
 // chunks.
 struct BatchArgs {
@@ -149,6 +141,9 @@ struct BatchArgs {
     uint64_t *chunk_total;  // tiles per chunk
     uint64_t *chunk_end;    // inclusive tile prefix over chunks
     uint64_t *total;        // tiles of the batch
+    uint64_t *tile_start;   // first tile of each request (global)
+    uint32_t *wave_req;     // request holding the first tile of each wave's range
+    uint32_t waves;         // waves of the generation grid
     int32_t *status;        // per request
     int32_t nt;             // streaming stores
     uint32_t block;         // generation kernel: threads per workgroup
@@ -159,7 +154,6 @@ hipError_t launch_batch(const BatchArgs &a, hipStream_t s);
 
 hipError_t launch_philox_blocks(const PhiloxBlocks &a, hipStream_t s);
 hipError_t launch_philox_fill(const PhiloxFill &a, hipStream_t s);
-hipError_t launch_philox_pairs(const PhiloxPairs &a, hipStream_t s);
 
 // Launch shape of the Philox fill kernel (process-wide, set through the
 // ABI or by the autotuner).

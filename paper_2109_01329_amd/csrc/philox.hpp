@@ -188,40 +188,4 @@ __device__ __forceinline__ void walk_slots(const SlotRun &r, uint32_t s0, uint32
     }
 }
 
-// Gaussian pair j of a request whose engine position (130-bit) of pair 0
-// is (p_lo, p_mid, p_top): words p + 2 j and p + 2 j + 1, from one or two
-// blocks; outputs 2 j and (if < n) 2 j + 1 are stored as single floats.
-__device__ __forceinline__ void emit_pair(uint32_t k0, uint32_t k1, uint64_t p_lo,
-                                          uint64_t p_mid, uint32_t p_top, uint64_t j,
-                                          uint64_t n, float *out, float mean, float sd,
-                                          int ranged)
-{
-    const uint64_t lo = p_lo + 2 * j;
-    const uint64_t c1 = lo < p_lo ? 1u : 0u;
-    const uint64_t mid = p_mid + c1;
-    const uint32_t top = p_top + ((c1 && mid == 0) ? 1u : 0u);
-    const uint64_t b_lo = (lo >> 2) | (mid << 62);
-    const uint64_t b_hi = (mid >> 2) | ((uint64_t)(top & 3u) << 62);
-    const uint32_t base[4] = {(uint32_t)b_lo, (uint32_t)(b_lo >> 32), (uint32_t)b_hi,
-                              (uint32_t)(b_hi >> 32)};
-    const uint32_t lane = (uint32_t)(lo & 3u);
-    const u32x4 w0 = block_at(base, k0, k1, 0);
-    uint32_t wa, wb;
-    if (lane < 3) {
-        wa = w0[lane];
-        wb = w0[lane + 1];
-    } else {
-        wa = w0.w;
-        wb = block_at(base, k0, k1, 1).x;
-    }
-    const f32x2 z = box_muller(wa, wb);
-    float z0 = z.x, z1 = z.y;
-    if (ranged) {
-        z0 = __builtin_fmaf(z0, sd, mean);
-        z1 = __builtin_fmaf(z1, sd, mean);
-    }
-    out[2 * j] = z0;
-    if (2 * j + 1 < n) out[2 * j + 1] = z1;
-}
-
 }  // namespace mirng

@@ -79,16 +79,6 @@ __global__ __launch_bounds__(1024) void philox_fill_kernel(PhiloxFill a)
     walk_slots<KIND, PHASE>(a.run, s0, min(a.slots_per_wave, a.nslots - s0), lane);
 }
 
-// Gaussian pairs whose output does not sit on the 16-byte grid in pair
-// units: one thread per pair, words p + 2 j and p + 2 j + 1.
-__global__ __launch_bounds__(256) void philox_pairs_kernel(PhiloxPairs a)
-{
-    const uint64_t npairs = (a.n + 1) / 2;
-    const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= npairs) return;
-    emit_pair(a.k0, a.k1, a.p_lo, a.p_mid, a.p_top, j, a.n, a.out, a.mean, a.sd, a.ranged);
-}
-
 template <int KIND>
 hipError_t launch_blocks_kind(const PhiloxBlocks &a, hipStream_t s)
 {
@@ -137,14 +127,6 @@ hipError_t launch_philox_fill(const PhiloxFill &a, hipStream_t s)
     case kU64F: return launch_fill_kind<kU64F>(a, grid, block, s);
     default: return launch_fill_kind<kGauss>(a, grid, block, s);
     }
-}
-
-hipError_t launch_philox_pairs(const PhiloxPairs &a, hipStream_t s)
-{
-    const uint64_t npairs = (a.n + 1) / 2;
-    const dim3 grid((uint32_t)((npairs + 255) / 256));
-    hipLaunchKernelGGL(philox_pairs_kernel, grid, dim3(256), 0, s, a);
-    return hipGetLastError();
 }
 
 }  // namespace mirng

@@ -200,3 +200,24 @@ def test_batcher_host_validation(L):
     assert L.mirng_batcher_statuses(b._h, reqs.ctypes.data, 1) == 1   # no batch yet
     assert L.mirng_batcher_destroy(None) == 0
     b.close()
+
+
+def test_autotune_argument_validation(L):
+    c = mr.PhiloxConfig()
+    ms = ctypes.c_float()
+    fake = ctypes.c_void_p(0x10000)
+    assert L.mirng_autotune_philox(9, 16, fake, None, 0, 1, 1, ctypes.byref(c), ctypes.byref(ms)) == 2
+    assert L.mirng_autotune_philox(2, 0, fake, None, 0, 1, 1, None, None) == 1
+    assert L.mirng_autotune_philox(2, 16, None, None, 0, 1, 1, None, None) == 1
+    assert L.mirng_autotune_philox(2, 16, fake, None, -1, 1, 1, None, None) == 1
+    assert L.mirng_autotune_philox(2, 16, fake, None, 0, 0, 1, None, None) == 1
+    assert L.mirng_autotune_philox(2, 16, fake, None, 0, 1, 0, None, None) == 1
+    assert L.mirng_autotune_philox(3, 16, ctypes.c_void_p(0x10004), None, 0, 1, 1, None, None) == 1
+    b = mr.Batcher()
+    reqs = mr.make_requests(2)
+    bc = mr.BatchConfig()
+    assert L.mirng_autotune_batch(None, reqs.ctypes.data, 2, None, 0, 1, 1, None, None) == 1
+    assert L.mirng_autotune_batch(b._h, None, 2, None, 0, 1, 1, None, None) == 1
+    assert L.mirng_autotune_batch(b._h, reqs.ctypes.data, 0, None, 0, 1, 1, None, None) == 1
+    assert L.mirng_autotune_batch(b._h, reqs.ctypes.data, 2, None, 0, 65, 1,
+                                  ctypes.byref(bc), None) == 1

@@ -1,0 +1,47 @@
+"""The autotuner picks a launch shape by timing candidates on the caller's
+workload; the chosen shape is installed and outputs generated with it still
+equal the oracle (a launch shape changes speed only)."""
+import numpy as np
+import pytest
+
+import paper_2109_01329_amd as mr
+from tests import gpu_helpers as gh
+from tests.test_gpu_batch import _mix, _run, _check_outputs
+
+pytestmark = pytest.mark.gpu
+
+
+def test_autotune_philox_installs_a_valid_shape():
+    import torch
+    n = (1 << 20) + 37
+    prev = mr.philox_config()
+    try:
+        buf = torch.empty(n, dtype=torch.float32, device="cuda")
+        cfg, ms = mr.autotune_philox(mr.UNIFORM_F32, n, buf, prewarm_ms=50, rounds=2, reps=3)
+        torch.cuda.synchronize()
+        assert ms > 0.0
+        assert mr.philox_config().as_dict() == cfg.as_dict()
+        e = mr.Engine(mr.PHILOX4X32_10, 0xFEEDFACE12345678, 12345)
+        got, out = gh.generate(e, mr.UNIFORM_F32, n, 4)
+        assert gh.guards_intact(out, 4, n * 4)
+        gh.assert_match(mr.UNIFORM_F32, got, gh.oracle_philox(0xFEEDFACE12345678, 12345,
+                                                               mr.UNIFORM_F32, n))
+    finally:
+        mr.set_philox_config(prev)
+
+
+def test_autotune_batch_keeps_outputs():
+    rng = np.random.default_rng(81)
+    reqs, layout, nbytes = _mix(rng, 200, max_log10=3.5)
+    b = mr.Batcher()
+    import torch
+    buf = gh.device_buffer(nbytes)
+    r = reqs.copy()
+    r["out"] = [int(buf.data_ptr()) + lay[0] for lay in layout]
+    cfg, ms = b.autotune(r, prewarm_ms=50, rounds=2, reps=3)
+    torch.cuda.synchronize()
+    assert ms > 0.0
+    assert b.config.as_dict() == cfg.as_dict()
+    host, st = _run(reqs, layout, nbytes, batcher=b)
+    assert np.all(st == 0)
+    _check_outputs(host, layout, st)
