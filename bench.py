@@ -178,6 +178,77 @@ def calo_batch_leg(mr, synth, torch, stream, dev, reps=20, tune=True, windows=5,
             "batch_over_plain_time": round(ms_pipe / plain_ms, 3)}
 
 
+def serve_leg(mr, synth, torch, dev, cells=None, duration_s=0.25, streams=4,
+              capacity=32 * 10**9, ring_gib=64):
+    """Serving loop under open-loop Poisson arrivals at 1e3, 1e4 and 1e5
+    requests/s for `duration_s` each: sizes floor(10^U(3, 8)), engine and
+    distribution uniform over the 2 x 4 mix, seeds uint64, offsets in
+    [0, 2^40).  Outputs go to a ring of `ring_gib` GiB of device memory
+    (placed in arrival order, 256-byte aligned).  Reports completed
+    throughput, p50/p99 latency (submission to completion) and, when the
+    bulk cells were measured, the plain path's rate on the same mix."""
+    import numpy as np
+    ring_bytes = ring_gib << 30
+    ring = torch.empty(ring_bytes, dtype=torch.uint8, device=dev)
+    base = int(ring.data_ptr())
+
+    def requests(rate, count, k):
+        tr = synth.request_trace(rate, count, k=k)
+        reqs = mr.make_requests(count)
+        reqs["engine_type"] = tr.engine
+        reqs["kind"] = tr.kind
+        reqs["p1"] = 1.0
+        reqs["seed"] = tr.seed
+        reqs["offset"] = tr.offset
+        reqs["n"] = tr.n
+        esz = np.where(tr.kind == mr.UNIFORM_F64, 8, 4).astype(np.int64)
+        size = (tr.n * esz + 255) // 256 * 256
+        out = np.empty(count, dtype=np.uint64)
+        pos = 0
+        for i in range(count):
+            if pos + int(size[i]) > ring_bytes:
+                pos = 0
+            out[i] = base + pos
+            pos += int(size[i])
+        reqs["out"] = out
+        return tr, reqs
+
+    def run(rate, count, k):
+        tr, reqs = requests(rate, count, k)
+        srv = mr.Server(streams=streams, capacity_bytes=capacity, max_batch=65536)
+        _, sub = srv.replay(reqs, tr.arrival_s)
+        srv.drain()
+        st = srv.stats()
+        srv.close()
+        assert np.all(sub == 0) and st["failed"] == 0
+        return tr, st
+
+    run(1e4, 200, 50)                      # warm-up: tables, staging memory
+    res = {}
+    for i, rate in enumerate((1e3, 1e4, 1e5)):
+        count = int(rate * duration_s)
+        tr, st = run(rate, count, 51 + i)
+        samples = int(tr.n.sum())
+        row = {"requests": count, "samples": samples,
+               "offered_Gsamples_s": round(samples / max(tr.arrival_s[-1], 1e-9) / 1e9, 1),
+               "served_Gsamples_s": round(st["samples"] / st["span_s"] / 1e9, 1),
+               "latency_ms": {"p50": round(st["latency_p50_ms"], 3),
+                              "p99": round(st["latency_p99_ms"], 3),
+                              "max": round(st["latency_max_ms"], 3)},
+               "batches": st["batches"], "span_s": round(st["span_s"], 4),
+               "max_inflight_GB": round(st["max_inflight_bytes"] / 1e9, 2)}
+        if cells:
+            t_plain = 0.0
+            for e, kd, n in zip(tr.engine, tr.kind, tr.n):
+                c = cells[f"{synth.ENGINE_NAME[int(e)]}/{synth.KIND_NAME[int(kd)]}"]
+                t_plain += float(n) / (c["Gsamples_s"] * 1e9)
+            row["plain_same_mix_Gsamples_s"] = round(samples / t_plain / 1e9, 1)
+        res[f"{int(rate)}_per_s"] = row
+    del ring
+    return {"streams": streams, "capacity_GB": capacity / 1e9, "duration_s": duration_s,
+            "rates": res}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -327,6 +398,7 @@ def main():
         extra["cells"] = res
         del big, buf
         extra["batched"] = calo_batch_leg(mr, synth, torch, stream, dev)
+        extra["serving"] = serve_leg(mr, synth, torch, dev, cells=res)
 
     line = {
         "metric": "Gsamples/s + HBM write GB/s (% peak), Philox FP32 uniform n=2^28; batched p99 ms",

@@ -188,8 +188,8 @@ mirng_status mirng_generate_substreams(mirng_engine e,
  * pinned host staging slots and device tables, reused across calls.
  * Requests are validated on the device, per request: a request that fails
  * validation writes nothing and gets a non-OK status (see
- * mirng_batcher_statuses); the others are unaffected.  Engine types in a
- * batch: Philox4x32-10 (an MRG32k3a request gets MIRNG_E_UNSUPPORTED). */
+ * mirng_batcher_statuses); the others are unaffected.  Both engine types
+ * may be mixed in one batch. */
 
 typedef struct mirng_batcher_s *mirng_batcher;
 
@@ -218,7 +218,8 @@ mirng_status mirng_batcher_stage(mirng_batcher b, size_t count, mirng_request **
 
 /* Enqueue `count` requests as one batch on `stream`: one host-to-device
  * copy of the request table, a planning kernel (validation, per-request
- * descriptors, tile prefix) and one persistent generation kernel.  Each
+ * descriptors and MRG32k3a start states, tile prefixes) and two persistent
+ * generation kernels (Philox4x32-10 requests, MRG32k3a requests).  Each
  * valid request's output equals that of a fresh engine created with its
  * (type, seed, offset) followed by one mirng_generate call; it does not
  * depend on the other requests, their order or the launch shape.  reqs may
@@ -229,9 +230,10 @@ mirng_status mirng_batcher_stage(mirng_batcher b, size_t count, mirng_request **
 mirng_status mirng_generate_batch(mirng_batcher b, const mirng_request *reqs, size_t count,
                                   void *stream);
 
-/* Per-request status of the most recent batch (mirng_status values), valid
- * once the stream work of that batch has completed.  count must not exceed
- * that batch's count -> else INVALID_ARG. */
+/* Per-request status of the most recent batch (mirng_status values); waits
+ * (host-blocking) until that batch has completed.  count must not exceed
+ * that batch's count -> else INVALID_ARG; no batch yet and count > 0 ->
+ * INVALID_ARG. */
 mirng_status mirng_batcher_statuses(mirng_batcher b, int32_t *statuses, size_t count);
 
 /* Copy out / install the batched kernel's launch shape.  Out-of-range
@@ -265,6 +267,75 @@ mirng_status mirng_philox_config_get(mirng_philox_config *c);
 /* Install a shape.  c == NULL or any field out of range -> INVALID_ARG and
  * the current shape is kept.  Host-only. */
 mirng_status mirng_philox_config_set(const mirng_philox_config *c);
+
+/* ---------------------------------------------------------------- serving */
+
+/* A serving loop over the batched launch: requests arrive one at a time
+ * from any host thread and are answered asynchronously (continuous
+ * batching).  The paper measures time-to-solution of single calls and
+ * notes that many small calls are dominated by per-call overheads (Sec. 6);
+ * a server amortises them by launching whatever has arrived as one batch
+ * whenever one of its S streams is free.
+ *
+ * Admission: requests are admitted in arrival order while the output bytes
+ * of admitted, unfinished requests stay within capacity_bytes; a request
+ * larger than the capacity on its own is refused at submission
+ * (MIRNG_E_CAPACITY).  A batch holds at most max_batch requests.  Each
+ * request is validated by the batched kernel, as in mirng_generate_batch,
+ * and its final status is that request's status.  The caller owns the
+ * output memory and must keep it valid until the request completes. */
+
+typedef struct mirng_server_s *mirng_server;
+
+typedef struct {
+    int32_t streams;            /* S: batches in flight at once, 1..8 */
+    int32_t reserved;           /* must be 0 */
+    uint64_t capacity_bytes;    /* in-flight output bytes, >= 1 */
+    uint64_t max_batch;         /* requests per batch, 1 .. 2^24 */
+} mirng_server_config;
+
+typedef struct {
+    uint64_t submitted;         /* accepted by mirng_server_submit */
+    uint64_t refused;           /* refused at submission (capacity) */
+    uint64_t completed;         /* finished, any status */
+    uint64_t failed;            /* finished with a non-OK status */
+    uint64_t batches;           /* batches launched */
+    uint64_t samples;           /* outputs of completed OK requests */
+    uint64_t bytes;             /* output bytes of completed OK requests */
+    uint64_t max_inflight_bytes;/* high-water mark of admitted, unfinished bytes */
+    double latency_p50_ms;      /* submission to completion, completed requests */
+    double latency_p99_ms;
+    double latency_max_ms;
+    double span_s;              /* first submission to last completion */
+} mirng_server_stats;
+
+/* Start a server on the current device (threads and streams of its own;
+ * streams at the default priority).  NULL arguments or out-of-range
+ * fields -> INVALID_ARG; device -> DEVICE; allocation -> ALLOC. */
+mirng_status mirng_server_create(const mirng_server_config *cfg, mirng_server *out);
+
+/* Finish every accepted request, then stop the server.  NULL is accepted. */
+mirng_status mirng_server_destroy(mirng_server s);
+
+/* Queue one request (copied).  *ticket names it in later calls.  Never
+ * blocks on the device.  Request larger than the capacity -> CAPACITY (no
+ * ticket); NULL arguments -> INVALID_ARG. */
+mirng_status mirng_server_submit(mirng_server s, const mirng_request *req, uint64_t *ticket);
+
+/* Non-blocking: *done = 1 and *status = the request's status once it has
+ * completed, else *done = 0.  Unknown ticket -> INVALID_ARG. */
+mirng_status mirng_server_poll(mirng_server s, uint64_t ticket, int32_t *done, int32_t *status);
+
+/* Block until the request has completed; *status as for poll and, if
+ * latency_ms is not NULL, its submission-to-completion time. */
+mirng_status mirng_server_wait(mirng_server s, uint64_t ticket, int32_t *status,
+                               double *latency_ms);
+
+/* Block until every accepted request has completed. */
+mirng_status mirng_server_drain(mirng_server s);
+
+/* Counters and latency percentiles since creation (waits for nothing). */
+mirng_status mirng_server_stats_get(mirng_server s, mirng_server_stats *out);
 
 /* -------------------------------------------------------------- autotuning */
 

@@ -66,6 +66,24 @@ class BatchConfig(ctypes.Structure):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
 
 
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("streams", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("capacity_bytes", ctypes.c_uint64), ("max_batch", ctypes.c_uint64)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("refused", ctypes.c_uint64),
+                ("completed", ctypes.c_uint64), ("failed", ctypes.c_uint64),
+                ("batches", ctypes.c_uint64), ("samples", ctypes.c_uint64),
+                ("bytes", ctypes.c_uint64), ("max_inflight_bytes", ctypes.c_uint64),
+                ("latency_p50_ms", ctypes.c_double), ("latency_p99_ms", ctypes.c_double),
+                ("latency_max_ms", ctypes.c_double), ("span_s", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {f: (float(getattr(self, f)) if t is ctypes.c_double else int(getattr(self, f)))
+                for f, t in self._fields_}
+
+
 # numpy view of mirng_request (64 bytes, same field order and offsets)
 REQUEST_FIELDS = [("engine_type", "<i4"), ("reserved", "<i4"), ("kind", "<i4"),
                   ("dist_reserved", "<i4"), ("p0", "<f8"), ("p1", "<f8"), ("seed", "<u8"),
@@ -123,6 +141,16 @@ def lib() -> ctypes.CDLL:
         "mirng_batcher_config_get": ([vp, ctypes.POINTER(BatchConfig)], ctypes.c_int),
         "mirng_batcher_config_set": ([vp, ctypes.POINTER(BatchConfig)], ctypes.c_int),
         "mirng_words_consumed": ([ctypes.c_int32, ctypes.c_int32, u64], u64),
+        "mirng_server_create": ([ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)], ctypes.c_int),
+        "mirng_server_destroy": ([vp], ctypes.c_int),
+        "mirng_server_submit": ([vp, vp, ctypes.POINTER(u64)], ctypes.c_int),
+        "mirng_server_poll": ([vp, u64, ctypes.POINTER(ctypes.c_int32),
+                               ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+        "mirng_server_wait": ([vp, u64, ctypes.POINTER(ctypes.c_int32),
+                               ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+        "mirng_server_drain": ([vp], ctypes.c_int),
+        "mirng_server_stats_get": ([vp, ctypes.POINTER(ServerStats)], ctypes.c_int),
+        "mirng_bench_server_replay": ([vp, vp, vp, ctypes.c_size_t, vp, vp], ctypes.c_int),
         "mirng_autotune_philox": ([ctypes.c_int32, u64, vp, vp, ctypes.c_int32, ctypes.c_int32,
                                    ctypes.c_int32, ctypes.POINTER(PhiloxConfig),
                                    ctypes.POINTER(ctypes.c_float)], ctypes.c_int),
@@ -346,6 +374,74 @@ class Batcher:
         out = np.zeros(count, dtype=np.int32)
         _check(lib().mirng_batcher_statuses(self._h, out.ctypes.data, count), "batcher_statuses")
         return out
+
+
+class Server:
+    """Serving loop: requests are submitted one at a time and completed
+    asynchronously by continuous batching over `streams` HIP streams, with
+    at most `capacity_bytes` of admitted, unfinished output."""
+
+    def __init__(self, streams: int = 2, capacity_bytes: int = 32 * 10**9,
+                 max_batch: int = 65536):
+        cfg = ServerConfig(streams, 0, capacity_bytes, max_batch)
+        h = ctypes.c_void_p()
+        _check(lib().mirng_server_create(ctypes.byref(cfg), ctypes.byref(h)), "server_create")
+        self._h = h
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().mirng_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, req) -> int:
+        """Queue one request (a record of `request_dtype()`); returns its ticket."""
+        import numpy as np
+        r = np.ascontiguousarray(np.asarray(req, dtype=request_dtype()).reshape(1))
+        t = ctypes.c_uint64()
+        _check(lib().mirng_server_submit(self._h, r.ctypes.data, ctypes.byref(t)), "server_submit")
+        return int(t.value)
+
+    def poll(self, ticket: int):
+        """(done, status) of a ticket, without blocking."""
+        d, s = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().mirng_server_poll(self._h, ticket, ctypes.byref(d), ctypes.byref(s)),
+               "server_poll")
+        return bool(d.value), int(s.value)
+
+    def wait(self, ticket: int):
+        """Block until the ticket completes; returns (status, latency_ms)."""
+        s, lat = ctypes.c_int32(), ctypes.c_double()
+        _check(lib().mirng_server_wait(self._h, ticket, ctypes.byref(s), ctypes.byref(lat)),
+               "server_wait")
+        return int(s.value), float(lat.value)
+
+    def drain(self) -> None:
+        _check(lib().mirng_server_drain(self._h), "server_drain")
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(lib().mirng_server_stats_get(self._h, ctypes.byref(st)), "server_stats")
+        return st.as_dict()
+
+    def replay(self, reqs, arrival_s):
+        """Submit reqs[i] at arrival_s[i] seconds from now (native open-loop
+        load generator); returns (tickets, submission statuses)."""
+        import numpy as np
+        reqs = np.ascontiguousarray(reqs, dtype=request_dtype())
+        arr = np.ascontiguousarray(arrival_s, dtype=np.float64)
+        assert len(arr) == len(reqs)
+        tickets = np.zeros(len(reqs), dtype=np.uint64)
+        st = np.zeros(len(reqs), dtype=np.int32)
+        _check(lib().mirng_bench_server_replay(self._h, reqs.ctypes.data, arr.ctypes.data,
+                                               len(reqs), tickets.ctypes.data, st.ctypes.data),
+               "server_replay")
+        return tickets, st
 
 
 def make_requests(count: int):

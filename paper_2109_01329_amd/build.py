@@ -30,6 +30,8 @@ SOURCES = [
     "batch.cpp",
     "batch_kernels.hip",
     "autotune.cpp",
+    "scheduler.cpp",
+    "server.cpp",
 ]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

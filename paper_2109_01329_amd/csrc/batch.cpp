@@ -6,8 +6,8 @@
 // not at all when the caller filled the staged slot), uploads it on the
 // batcher's own copy stream (so the upload overlaps earlier work on the
 // caller's stream), and enqueues on the caller's stream, behind the upload,
-// the planning, scan and mark kernels, the generation kernel and the copy
-// of the per-request statuses back to pinned memory.
+// the planning, scan and mark kernels, the two generation kernels (Philox,
+// MRG32k3a) and the copy of the per-request statuses back to pinned memory.
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -36,9 +36,18 @@ struct Slot {
     uint64_t *d_chunk_end = nullptr;
     uint64_t *d_total = nullptr;
     uint64_t *d_tile_start = nullptr;
+    uint64_t *d_mrg_start = nullptr;
     uint32_t *d_wave_req = nullptr;
+    uint32_t *d_grp_req = nullptr;
     int32_t *d_status = nullptr;
 };
+
+// Workgroups of the MRG generation kernel: its 36 KiB of LDS per group let
+// four groups share a CU.
+size_t mrg_groups()
+{
+    return (size_t)mirng::device_cu_count() * 4;
+}
 
 void release(Slot &s)
 {
@@ -52,7 +61,9 @@ void release(Slot &s)
     if (s.d_chunk_end) (void)hipFree(s.d_chunk_end);
     if (s.d_total) (void)hipFree(s.d_total);
     if (s.d_tile_start) (void)hipFree(s.d_tile_start);
+    if (s.d_mrg_start) (void)hipFree(s.d_mrg_start);
     if (s.d_wave_req) (void)hipFree(s.d_wave_req);
+    if (s.d_grp_req) (void)hipFree(s.d_grp_req);
     if (s.d_status) (void)hipFree(s.d_status);
     if (s.done) (void)hipEventDestroy(s.done);
     if (s.uploaded) (void)hipEventDestroy(s.uploaded);
@@ -87,12 +98,14 @@ hipError_t prepare(Slot &s, size_t count, size_t waves, int dev)
     chk(hipHostMalloc((void **)&s.h_status, cap * sizeof(int32_t), hipHostMallocDefault));
     chk(hipMalloc((void **)&s.d_reqs, cap * sizeof(mirng_request)));
     chk(hipMalloc((void **)&s.d_desc, cap * sizeof(mirng::BatchDesc)));
-    chk(hipMalloc((void **)&s.d_local_end, cap * sizeof(uint64_t)));
-    chk(hipMalloc((void **)&s.d_chunk_total, nchunks * sizeof(uint64_t)));
-    chk(hipMalloc((void **)&s.d_chunk_end, nchunks * sizeof(uint64_t)));
-    chk(hipMalloc((void **)&s.d_total, sizeof(uint64_t)));
+    chk(hipMalloc((void **)&s.d_local_end, 2 * cap * sizeof(uint64_t)));
+    chk(hipMalloc((void **)&s.d_chunk_total, 2 * nchunks * sizeof(uint64_t)));
+    chk(hipMalloc((void **)&s.d_chunk_end, 2 * nchunks * sizeof(uint64_t)));
+    chk(hipMalloc((void **)&s.d_total, 2 * sizeof(uint64_t)));
     chk(hipMalloc((void **)&s.d_tile_start, cap * sizeof(uint64_t)));
+    chk(hipMalloc((void **)&s.d_mrg_start, cap * sizeof(uint64_t)));
     chk(hipMalloc((void **)&s.d_wave_req, waves * sizeof(uint32_t)));
+    chk(hipMalloc((void **)&s.d_grp_req, mrg_groups() * sizeof(uint32_t)));
     chk(hipMalloc((void **)&s.d_status, cap * sizeof(int32_t)));
     chk(hipEventCreateWithFlags(&s.done, hipEventDisableTiming));
     chk(hipEventCreateWithFlags(&s.uploaded, hipEventDisableTiming));
@@ -205,6 +218,8 @@ mirng_status mirng_generate_batch(mirng_batcher b, const mirng_request *reqs, si
             return MIRNG_E_DEVICE;
         b->copy_dev = dev;
     }
+    MrgBatchTables tabs;
+    if (mrg_batch_tables(dev, tabs) != hipSuccess) return MIRNG_E_ALLOC;
     const uint64_t wpb = (uint64_t)b->cfg.block / 64;
     const uint64_t waves = ((grid_waves(b->cfg) + wpb - 1) / wpb) * wpb;
     int k;
@@ -231,8 +246,16 @@ mirng_status mirng_generate_batch(mirng_batcher b, const mirng_request *reqs, si
     a.chunk_end = sl.d_chunk_end;
     a.total = sl.d_total;
     a.tile_start = sl.d_tile_start;
+    a.mrg_start = sl.d_mrg_start;
     a.wave_req = sl.d_wave_req;
+    a.grp_req = sl.d_grp_req;
     a.waves = (uint32_t)waves;
+    a.mgroups = (uint32_t)mrg_groups();
+    a.pow2 = tabs.pow2;
+    a.c_tab4 = tabs.c_tab4;
+    a.u_tab4 = tabs.u_tab4;
+    a.c_tab8 = tabs.c_tab8;
+    a.u_tab8 = tabs.u_tab8;
     a.status = sl.d_status;
     a.nt = b->cfg.nontemporal;
     a.block = (uint32_t)b->cfg.block;

@@ -1,22 +1,28 @@
-// Batched Philox generation: many independent requests of uneven sizes in
-// one persistent launch (the inter-event batching the paper defers for its
-// calorimeter application, arXiv:2109.01329 Sec. 6).
+// Batched generation: many independent requests of uneven sizes in two
+// persistent launches, one for Philox4x32-10 and one for MRG32k3a requests
+// (the inter-event batching the paper defers for its calorimeter
+// application, arXiv:2109.01329 Sec. 6).
 //
 // plan:  one thread per request validates it (the ABI's rules), derives
-//        its slot run (as the plain path does on the host), and counts its
-//        tiles of 64 slots; each workgroup scans the counts of its 1024
-//        requests.
+//        its Philox slot run (as the plain path does on the host) or its
+//        MRG32k3a start state (seed state jumped by the offset through the
+//        A^(2^k) table), and counts its Philox tiles of 64 slots or MRG
+//        chunks; each workgroup scans both counts over its 1024 requests.
 // scan:  one workgroup scans the per-chunk totals.
-// mark:  one thread per request writes the request's first global tile and,
-//        for every wave whose range of ceil(tiles / waves) tiles starts inside
-//        the request, the request index (so no wave has to search).
-// main:  a fixed grid of waves; wave w takes a contiguous range of tiles
-//        (tiles of one request are adjacent, requests in table order),
+// mark:  one thread per request writes the request's first global tile
+//        (chunk) and, for every wave (group) whose range of tiles (chunks)
+//        starts inside the request, the request index, so that no wave has
+//        to search.
+// philox main: a fixed grid of waves; wave w takes a contiguous range of
+//        tiles (tiles of one request are adjacent, requests in table order),
 //        starts at its marked request and walks forward, running the plain
 //        kernel's slot walk on each request segment.
+// mrg main: a fixed grid of 256-thread groups, each over a contiguous range
+//        of chunks, running the plain kernel's LDS passes on each chunk.
 // Every value depends only on its request and position, never on the
 // tiling, the grid or the neighbouring requests.
 #include "internal.hpp"
+#include "mrg.hpp"
 #include "philox.hpp"
 #include "transforms.hpp"
 
@@ -27,31 +33,36 @@ constexpr uint32_t kChunk = 1024;
 
 __device__ __forceinline__ bool finite(double x) { return __builtin_isfinite(x); }
 
-// Validation and planning of one request; returns its tile count.
-__device__ uint64_t plan_one(const mirng_request &q, BatchDesc &d, int32_t &st, int nt)
+// Validation and planning of one request: its Philox tiles or MRG chunks.
+__device__ void plan_one(const mirng_request &q, BatchDesc &d, int32_t &st, int nt,
+                         const uint32_t *pow2, uint64_t &tiles, uint64_t &mchunks)
 {
     st = MIRNG_OK;
-    if (q.engine_type != MIRNG_PHILOX4X32_10) {
+    tiles = 0;
+    mchunks = 0;
+    d = BatchDesc{};
+    d.engine = (uint32_t)q.engine_type;
+    if (q.engine_type != MIRNG_PHILOX4X32_10 && q.engine_type != MIRNG_MRG32K3A) {
         st = MIRNG_E_UNSUPPORTED;
-        return 0;
+        return;
     }
     const int kind = q.dist.kind;
-    if (q.reserved != 0 || q.dist.reserved != 0) { st = MIRNG_E_INVALID_ARG; return 0; }
-    if (kind < kBits || kind > kGauss) { st = MIRNG_E_UNSUPPORTED; return 0; }
+    if (q.reserved != 0 || q.dist.reserved != 0) { st = MIRNG_E_INVALID_ARG; return; }
+    if (kind < kBits || kind > kGauss) { st = MIRNG_E_UNSUPPORTED; return; }
     const double p0 = q.dist.p0, p1 = q.dist.p1;
     if ((kind == kU32F || kind == kU64F) && !(finite(p0) && finite(p1) && p0 < p1)) {
         st = MIRNG_E_INVALID_ARG;
-        return 0;
+        return;
     }
     if (kind == kGauss && !(finite(p0) && finite(p1) && p1 > 0.0)) {
         st = MIRNG_E_INVALID_ARG;
-        return 0;
+        return;
     }
-    if (q.n == 0) return 0;
+    if (q.n == 0) return;
     const uint64_t esz = kind == kU64F ? 8 : 4;
     const uint64_t addr = (uint64_t)(uintptr_t)q.out;
-    if (addr == 0 || addr % esz) { st = MIRNG_E_INVALID_ARG; return 0; }
-    if (q.n >= (1ull << 32)) { st = MIRNG_E_CAPACITY; return 0; }
+    if (addr == 0 || addr % esz) { st = MIRNG_E_INVALID_ARG; return; }
+    if (q.n >= (1ull << 32)) { st = MIRNG_E_CAPACITY; return; }
 
     Epilogue ep;
     ep.ranged = (kind == kBits || (p0 == 0.0 && p1 == 1.0)) ? 0 : 1;
@@ -71,17 +82,31 @@ __device__ uint64_t plan_one(const mirng_request &q, BatchDesc &d, int32_t &st, 
         ep.d32 = (float)(p1 - p0);
     }
     SlotRun &r = d.run;
-    r.k0 = (uint32_t)q.seed;
-    r.k1 = (uint32_t)(q.seed >> 32);
     r.n = q.n;
     r.ep = ep;
     r.pad = 0;
     d.kind = (uint32_t)kind;
-    const uint64_t p = q.offset;                 // engine words from the seed state
+    const uint64_t p = q.offset;   // engine words (Philox) or steps (MRG) from the seed state
+
+    if (q.engine_type == MIRNG_MRG32K3A) {
+        uint32_t v[6] = {(uint32_t)((q.seed & 0xFFFFFFFFull) % kM1), 1u, 1u,
+                         (uint32_t)((q.seed >> 32) % kM2), 1u, 1u};
+        for (int k = 0; k < 64; ++k)
+            if ((p >> k) & 1u) apply_mat(pow2 + k * kMatWords, v);
+#pragma unroll
+        for (int i = 0; i < 6; ++i) d.mst[i] = v[i];
+        const uint64_t per = (uint64_t)kMrgThreads * kBatchMrgPasses * (kind == kU64F ? 16 : 32);
+        r.out_base = (char *)q.out;
+        mchunks = (q.n + per - 1) / per;
+        d.mchunks = (uint32_t)mchunks;
+        return;
+    }
+
+    r.k0 = (uint32_t)q.seed;
+    r.k1 = (uint32_t)(q.seed >> 32);
     const uint32_t head = (uint32_t)((addr & 15u) / esz);
     const uint32_t wpe = kind == kU64F ? 2u : 1u;
     const uint32_t epv = (uint32_t)(16 / esz);
-    d.pairs = 0;
     if (kind == kGauss && (head & 1u)) {
         // pairs would straddle the 16-byte grid: slots of 4 outputs start at
         // the output itself (dword-aligned 16-byte stores)
@@ -116,7 +141,7 @@ __device__ uint64_t plan_one(const mirng_request &q, BatchDesc &d, int32_t &st, 
         r.full_count = (uint32_t)(hi > lo ? hi - lo : 0);
         r.out_base = (char *)q.out - (addr & 15u);
     }
-    return ((uint64_t)d.nunits + 63) / 64;
+    tiles = ((uint64_t)d.nunits + 63) / 64;
 }
 
 // Inclusive scan over a workgroup of kChunk threads (16 waves).
@@ -147,39 +172,50 @@ __global__ __launch_bounds__(kChunk) void batch_plan_kernel(BatchArgs a)
 {
     __shared__ uint64_t wsum[kChunk / 64];
     const uint32_t r = blockIdx.x * kChunk + threadIdx.x;
-    uint64_t tiles = 0;
+    uint64_t tiles = 0, mchunks = 0;
     if (r < a.count) {
         int32_t st;
         BatchDesc d;
-        tiles = plan_one(a.reqs[r], d, st, a.nt);
+        plan_one(a.reqs[r], d, st, a.nt, a.pow2, tiles, mchunks);
         a.status[r] = st;
-        if (st != MIRNG_OK || tiles == 0) {
+        if (st != MIRNG_OK) {
             d.nunits = 0;
+            d.mchunks = 0;
             tiles = 0;
+            mchunks = 0;
         }
         a.desc[r] = d;
     }
-    const uint64_t inc = block_scan(tiles, wsum);
-    if (r < a.count) a.local_end[r] = inc;
-    if (threadIdx.x == kChunk - 1) a.chunk_total[blockIdx.x] = inc;
+    const uint64_t inc0 = block_scan(tiles, wsum);
+    const uint64_t inc1 = block_scan(mchunks, wsum);
+    if (r < a.count) {
+        a.local_end[2 * r] = inc0;
+        a.local_end[2 * r + 1] = inc1;
+    }
+    if (threadIdx.x == kChunk - 1) {
+        a.chunk_total[2 * blockIdx.x] = inc0;
+        a.chunk_total[2 * blockIdx.x + 1] = inc1;
+    }
 }
 
 __global__ __launch_bounds__(kChunk) void batch_scan_kernel(BatchArgs a)
 {
     __shared__ uint64_t wsum[kChunk / 64];
-    __shared__ uint64_t carry;
-    if (threadIdx.x == 0) carry = 0;
+    __shared__ uint64_t carry[2];
+    if (threadIdx.x < 2) carry[threadIdx.x] = 0;
     __syncthreads();
     for (uint32_t c0 = 0; c0 < a.nchunks; c0 += kChunk) {
         const uint32_t c = c0 + threadIdx.x;
-        const uint64_t v = c < a.nchunks ? a.chunk_total[c] : 0;
-        const uint64_t inc = block_scan(v, wsum) + carry;
-        if (c < a.nchunks) a.chunk_end[c] = inc;
-        __syncthreads();
-        if (threadIdx.x == kChunk - 1) carry = inc;
-        __syncthreads();
+        for (int j = 0; j < 2; ++j) {
+            const uint64_t v = c < a.nchunks ? a.chunk_total[2 * c + j] : 0;
+            const uint64_t inc = block_scan(v, wsum) + carry[j];
+            if (c < a.nchunks) a.chunk_end[2 * c + j] = inc;
+            __syncthreads();
+            if (threadIdx.x == kChunk - 1) carry[j] = inc;
+            __syncthreads();
+        }
     }
-    if (threadIdx.x == 0) *a.total = carry;
+    if (threadIdx.x < 2) a.total[threadIdx.x] = carry[threadIdx.x];
 }
 
 __device__ __forceinline__ uint32_t uniform(uint32_t v)
@@ -197,16 +233,23 @@ __global__ __launch_bounds__(256) void batch_mark_kernel(BatchArgs a)
     const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= a.count) return;
     const uint32_t c = r / kChunk;
-    const uint64_t end = a.chunk_end[c] - a.chunk_total[c] + a.local_end[r];
     const uint64_t tiles = ((uint64_t)a.desc[r].nunits + 63) / 64;
-    const uint64_t start = end - tiles;
-    a.tile_start[r] = start;
-    const uint64_t total = *a.total;
-    const uint64_t per = (total + a.waves - 1) / a.waves;
-    if (tiles == 0 || per == 0) return;
-    // waves w with w * per in [start, end)
-    for (uint64_t w = (start + per - 1) / per; w * per < end && w < a.waves; ++w)
-        a.wave_req[w] = r;
+    const uint64_t mch = a.desc[r].mchunks;
+    const uint64_t end0 = a.chunk_end[2 * c] - a.chunk_total[2 * c] + a.local_end[2 * r];
+    const uint64_t end1 =
+        a.chunk_end[2 * c + 1] - a.chunk_total[2 * c + 1] + a.local_end[2 * r + 1];
+    const uint64_t start0 = end0 - tiles, start1 = end1 - mch;
+    a.tile_start[r] = start0;
+    a.mrg_start[r] = start1;
+    // waves w with w * per in [start, end); groups likewise for MRG chunks
+    const uint64_t per0 = (a.total[0] + a.waves - 1) / a.waves;
+    if (tiles && per0)
+        for (uint64_t w = (start0 + per0 - 1) / per0; w * per0 < end0 && w < a.waves; ++w)
+            a.wave_req[w] = r;
+    const uint64_t per1 = (a.total[1] + a.mgroups - 1) / a.mgroups;
+    if (mch && per1)
+        for (uint64_t g = (start1 + per1 - 1) / per1; g * per1 < end1 && g < a.mgroups; ++g)
+            a.grp_req[g] = r;
 }
 
 template <int KIND>
@@ -247,7 +290,7 @@ __global__ __launch_bounds__(1024) void batch_main_kernel(BatchArgs a)
 {
     const uint32_t lane = threadIdx.x & 63u;
     const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    const uint64_t total = *a.total;
+    const uint64_t total = a.total[0];
     const uint64_t per = (total + a.waves - 1) / a.waves;
     uint64_t t = wave * per;
     const uint64_t t1 = min(t + per, total);
@@ -268,6 +311,76 @@ __global__ __launch_bounds__(1024) void batch_main_kernel(BatchArgs a)
     }
 }
 
+// One chunk of an MRG request: 256 threads x kBatchMrgPasses passes of L.
+template <int KIND>
+__device__ void mrg_chunk(const BatchDesc &d, uint64_t k, const uint32_t *c_tab,
+                          const uint32_t *u_tab, char *lds, uint32_t *wg_state)
+{
+    using S = MrgShape<KIND>;
+    constexpr uint32_t q = kBatchMrgPasses * S::L;
+    const uint32_t t = threadIdx.x;
+    if (t < 64) {
+        uint32_t v[6];
+#pragma unroll
+        for (int i = 0; i < 6; ++i) v[i] = d.mst[i];
+        for (int dg = 0; dg < kCDigits; ++dg) {
+            const uint32_t digit = (uint32_t)(k >> (6 * dg)) & 63u;
+            if (digit) apply_mat(c_tab + (dg * 64 + digit) * kMatWords, v);
+        }
+        if (t == 0) {
+#pragma unroll
+            for (int i = 0; i < 6; ++i) wg_state[i] = v[i];
+        }
+    }
+    __syncthreads();
+    uint32_t v[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) v[i] = wg_state[i];
+    if (t) apply_mat(u_tab + t * kMatWords, v);
+    MrgState s = mrg_state(v);
+    const uint64_t e_wg = k * kMrgThreads * q;
+    for (uint32_t pass = 0; pass < kBatchMrgPasses; ++pass) {
+        const uint64_t e0 = e_wg + (uint64_t)pass * S::L;
+        if (e0 >= d.run.n) break;   // uniform per group
+        mrg_fill_row<KIND>(s, lds + t * S::ROW, d.run.ep);
+        __syncthreads();
+        mrg_store_pass<KIND>(lds, e0, q, d.run.n, d.run.out_base, d.run.ep.nt);
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kMrgThreads) void batch_mrg_kernel(BatchArgs a)
+{
+    // LDS rows are 144 bytes for every kind (32 x 4 or 16 x 8, plus 16)
+    __shared__ __attribute__((aligned(16))) char lds[kMrgThreads * MrgShape<kU32F>::ROW];
+    __shared__ uint32_t wg_state[6];
+    static_assert(MrgShape<kU64F>::ROW == MrgShape<kU32F>::ROW, "row size");
+    const uint64_t total = a.total[1];
+    const uint64_t per = (total + a.mgroups - 1) / a.mgroups;
+    uint64_t c = (uint64_t)blockIdx.x * per;
+    const uint64_t c1 = min(c + per, total);
+    if (c >= c1) return;
+    uint32_t r = a.grp_req[blockIdx.x];
+    while (c < c1 && r < a.count) {
+        const uint64_t start = a.mrg_start[r];
+        const uint64_t end = start + a.desc[r].mchunks;
+        if (end > c) {
+            const uint64_t seg = min(c1, end);
+            const BatchDesc d = load_desc(&a.desc[r]);
+            for (uint64_t k = c - start; k < seg - start; ++k) {
+                switch (d.kind) {
+                case kBits: mrg_chunk<kBits>(d, k, a.c_tab4, a.u_tab4, lds, wg_state); break;
+                case kU32F: mrg_chunk<kU32F>(d, k, a.c_tab4, a.u_tab4, lds, wg_state); break;
+                case kU64F: mrg_chunk<kU64F>(d, k, a.c_tab8, a.u_tab8, lds, wg_state); break;
+                default: mrg_chunk<kGauss>(d, k, a.c_tab4, a.u_tab4, lds, wg_state); break;
+                }
+            }
+            c = seg;
+        }
+        ++r;
+    }
+}
+
 }  // namespace
 
 hipError_t launch_batch(const BatchArgs &a, hipStream_t s)
@@ -282,6 +395,9 @@ hipError_t launch_batch(const BatchArgs &a, hipStream_t s)
     err = hipGetLastError();
     if (err != hipSuccess) return err;
     hipLaunchKernelGGL(batch_main_kernel, dim3(a.groups), dim3(a.block), 0, s, a);
+    err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL(batch_mrg_kernel, dim3(a.mgroups), dim3(kMrgThreads), 0, s, a);
     return hipGetLastError();
 }
 

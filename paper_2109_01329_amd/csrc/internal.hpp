@@ -120,35 +120,58 @@ struct PhiloxFill {
     uint32_t block;         // threads per workgroup
 };
 
-// One Philox request of a batch, as planned on the device.
+// One request of a batch, as planned on the device.  Philox requests are
+// runs of 16-byte slots cut into tiles of 64 slots (one wave each); MRG32k3a
+// requests are cut into chunks of 256 threads x kBatchMrgSteps steps (one
+// workgroup each).
 struct BatchDesc {
-    SlotRun run;
+    SlotRun run;            // Philox slots; for MRG only n, out_base and ep are used
     uint32_t kind;
-    uint32_t phase;         // q mod 4
-    uint32_t nunits;        // 16-byte slots
-    uint32_t pairs;         // unused, 0
+    uint32_t phase;         // Philox: q mod 4
+    uint32_t nunits;        // Philox: 16-byte slots (0 for MRG)
+    uint32_t engine;        // mirng_engine_type
+    uint32_t mst[6];        // MRG: state after `offset` steps from the seed state
+    uint32_t mchunks;       // MRG: chunks (0 for Philox)
+    uint32_t pad;
 };
 
-// Device tables of one batch.  Tiles are runs of 64 slots of one request;
-// tile prefixes are kept per chunk of 1024 requests plus a prefix over
-// chunks.
+// Steps per MRG thread in a batch chunk: two passes of L (L = 32 outputs,
+// or 16 for FP64).
+constexpr uint32_t kBatchMrgPasses = 2;
+
+// Device tables of one batch.  Philox tiles and MRG chunks are numbered by
+// two inclusive prefixes (entries 2i and 2i + 1 of the prefix arrays), kept
+// per chunk of 1024 requests plus a prefix over chunks.
 struct BatchArgs {
     const mirng_request *reqs;
     uint32_t count;
     uint32_t nchunks;
     BatchDesc *desc;
-    uint64_t *local_end;    // inclusive tile prefix inside the request's chunk
-    uint64_t *chunk_total;  // tiles per chunk
-    uint64_t *chunk_end;    // inclusive tile prefix over chunks
-    uint64_t *total;        // tiles of the batch
-    uint64_t *tile_start;   // first tile of each request (global)
+    uint64_t *local_end;    // [2 count] inclusive prefixes inside the request's chunk
+    uint64_t *chunk_total;  // [2 nchunks] per chunk
+    uint64_t *chunk_end;    // [2 nchunks] inclusive prefixes over chunks
+    uint64_t *total;        // [2] Philox tiles, MRG chunks of the batch
+    uint64_t *tile_start;   // first Philox tile of each request (global)
+    uint64_t *mrg_start;    // first MRG chunk of each request (global)
     uint32_t *wave_req;     // request holding the first tile of each wave's range
-    uint32_t waves;         // waves of the generation grid
+    uint32_t *grp_req;      // request holding the first MRG chunk of each group's range
+    uint32_t waves;         // waves of the Philox generation grid
+    uint32_t mgroups;       // workgroups of the MRG generation grid
     int32_t *status;        // per request
     int32_t nt;             // streaming stores
-    uint32_t block;         // generation kernel: threads per workgroup
-    uint32_t groups;        // generation kernel: workgroups
+    uint32_t block;         // Philox generation kernel: threads per workgroup
+    uint32_t groups;        // Philox generation kernel: workgroups
+    const uint32_t *pow2;   // MRG A^(2^k), k < 64: [k][comp][9]
+    const uint32_t *c_tab4, *u_tab4;   // MRG chunk / thread jumps, 4-byte kinds
+    const uint32_t *c_tab8, *u_tab8;   // MRG chunk / thread jumps, FP64
 };
+
+// Resident MRG jump tables for batches on device `dev`.
+struct MrgBatchTables {
+    const uint32_t *pow2;
+    const uint32_t *c_tab4, *u_tab4, *c_tab8, *u_tab8;
+};
+hipError_t mrg_batch_tables(int dev, MrgBatchTables &t);
 
 hipError_t launch_batch(const BatchArgs &a, hipStream_t s);
 

@@ -1,0 +1,220 @@
+// MRG32k3a device code shared by the plain / substream kernel and the
+// batched kernel (L'Ecuyer, Oper. Res. 1999).
+//
+// A workgroup of kMrgThreads threads produces outputs in passes: thread t
+// runs L consecutive steps of its own sequence into its LDS row, then the
+// group writes the rows back with 16-byte stores on the output's 16-byte
+// grid.  Rows are padded by 16 bytes so that 8 consecutive lanes reading
+// 16 bytes hit distinct banks.
+//
+// The recurrence runs in FP64: all products are below 2^53 and exact, the
+// quotient by m is estimated by a multiply with 1/m biased by -2^-30 so that
+// the floor is never too large, and one conditional subtraction finishes
+// the reduction.  The results are the exact integers of the definition.
+#pragma once
+
+#include "internal.hpp"
+#include "transforms.hpp"
+
+namespace mirng {
+
+constexpr int kMrgThreads = 256;
+constexpr int kMatWords = 18;   // two 3x3 matrices (component 1, component 2)
+constexpr int kCDigits = 4;     // chunk index < 64^4 = 2^24
+
+// x mod m1 for any 64-bit x (2^32 = 209 mod m1).
+__device__ __forceinline__ uint32_t red_m1(uint64_t x)
+{
+    x = (x >> 32) * 209u + (x & 0xFFFFFFFFull);
+    x = (x >> 32) * 209u + (x & 0xFFFFFFFFull);
+    return (uint32_t)(x >= kM1 ? x - kM1 : x);
+}
+
+// x mod m2 for any 64-bit x (2^32 = 22853 mod m2).
+__device__ __forceinline__ uint32_t red_m2(uint64_t x)
+{
+    x = (x >> 32) * 22853u + (x & 0xFFFFFFFFull);
+    x = (x >> 32) * 22853u + (x & 0xFFFFFFFFull);
+    return (uint32_t)(x >= kM2 ? x - kM2 : x);
+}
+
+// v <- M v for both components; M points at 18 words (comp 1 then comp 2).
+__device__ __forceinline__ void apply_mat(const uint32_t *M, uint32_t v[6])
+{
+    uint32_t r[6];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const uint64_t a = red_m1((uint64_t)M[3 * i] * v[0]) +
+                           (uint64_t)red_m1((uint64_t)M[3 * i + 1] * v[1]) +
+                           red_m1((uint64_t)M[3 * i + 2] * v[2]);
+        r[i] = red_m1(a);
+        const uint64_t b = red_m2((uint64_t)M[9 + 3 * i] * v[3]) +
+                           (uint64_t)red_m2((uint64_t)M[9 + 3 * i + 1] * v[4]) +
+                           red_m2((uint64_t)M[9 + 3 * i + 2] * v[5]);
+        r[3 + i] = red_m2(b);
+    }
+#pragma unroll
+    for (int i = 0; i < 6; ++i) v[i] = r[i];
+}
+
+constexpr double kM1d = 4294967087.0;
+constexpr double kM2d = 4294944443.0;
+constexpr double kInvM1 = 1.0 / 4294967087.0;
+constexpr double kInvM2 = 1.0 / 4294944443.0;
+constexpr double kNorm = 1.0 / 4294967088.0;   // 1 / (m1 + 1), rounded once
+
+struct MrgState {
+    double a0, a1, a2;   // x1[n-3], x1[n-2], x1[n-1]
+    double b0, b1, b2;   // x2[n-3], x2[n-2], x2[n-1]
+};
+
+__device__ __forceinline__ MrgState mrg_state(const uint32_t v[6])
+{
+    return MrgState{(double)v[0], (double)v[1], (double)v[2],
+                    (double)v[3], (double)v[4], (double)v[5]};
+}
+
+// One step; returns the combined output y in [1, m1] as an exact double.
+__device__ __forceinline__ double mrg_step(MrgState &s)
+{
+    double p1 = __builtin_fma(1403580.0, s.a1, -810728.0 * s.a0);
+    const double k1 = __builtin_floor(__builtin_fma(p1, kInvM1, -0x1p-30));
+    p1 = __builtin_fma(-k1, kM1d, p1);
+    p1 = (p1 >= kM1d) ? p1 - kM1d : p1;
+    double p2 = __builtin_fma(527612.0, s.b2, -1370589.0 * s.b0);
+    const double k2 = __builtin_floor(__builtin_fma(p2, kInvM2, -0x1p-30));
+    p2 = __builtin_fma(-k2, kM2d, p2);
+    p2 = (p2 >= kM2d) ? p2 - kM2d : p2;
+    s.a0 = s.a1; s.a1 = s.a2; s.a2 = p1;
+    s.b0 = s.b1; s.b1 = s.b2; s.b2 = p2;
+    const double y = p1 - p2;
+    return (p1 <= p2) ? y + kM1d : y;
+}
+
+__device__ __forceinline__ float y_to_u01f(double y)
+{
+    return (float)(__builtin_floor(y * 0x1p-8) * 0x1p-24);
+}
+
+template <int KIND>
+struct MrgShape {
+    static constexpr int ESZ = KIND == kU64F ? 8 : 4;
+    static constexpr int L = 128 / ESZ;          // outputs per thread per pass
+    static constexpr int ROW = L * ESZ + 16;     // padded LDS row, bytes
+    static constexpr int VPR = L * ESZ / 16;     // 16-byte vectors per row
+    static constexpr int EPV = 16 / ESZ;         // elements per vector
+};
+
+// Runs L steps of `s` and writes the L outputs into `row` (16-byte aligned).
+template <int KIND>
+__device__ __forceinline__ void mrg_fill_row(MrgState &s, char *row, const Epilogue &ep)
+{
+    using S = MrgShape<KIND>;
+#pragma unroll
+    for (int l = 0; l < S::L; l += S::EPV) {
+        u32x4 pk;
+        if constexpr (KIND == kBits) {
+            pk.x = (uint32_t)mrg_step(s); pk.y = (uint32_t)mrg_step(s);
+            pk.z = (uint32_t)mrg_step(s); pk.w = (uint32_t)mrg_step(s);
+        } else if constexpr (KIND == kU32F) {
+            f32x4 f;
+            f.x = y_to_u01f(mrg_step(s)); f.y = y_to_u01f(mrg_step(s));
+            f.z = y_to_u01f(mrg_step(s)); f.w = y_to_u01f(mrg_step(s));
+            if (ep.ranged) {
+                f.x = __builtin_fmaf(f.x, ep.d32, ep.a32);
+                f.y = __builtin_fmaf(f.y, ep.d32, ep.a32);
+                f.z = __builtin_fmaf(f.z, ep.d32, ep.a32);
+                f.w = __builtin_fmaf(f.w, ep.d32, ep.a32);
+            }
+            pk = __builtin_bit_cast(u32x4, f);
+        } else if constexpr (KIND == kU64F) {
+            f64x2 d;
+            d.x = mrg_step(s) * kNorm;
+            d.y = mrg_step(s) * kNorm;
+            if (ep.ranged) {
+                d.x = __builtin_fma(d.x, ep.d64, ep.a64);
+                d.y = __builtin_fma(d.y, ep.d64, ep.a64);
+            }
+            pk = __builtin_bit_cast(u32x4, d);
+        } else {
+            const uint32_t w0 = (uint32_t)mrg_step(s);
+            const uint32_t w1 = (uint32_t)mrg_step(s);
+            const uint32_t w2 = (uint32_t)mrg_step(s);
+            const uint32_t w3 = (uint32_t)mrg_step(s);
+            f32x4 f;
+            f.xy = box_muller(w0, w1);
+            f.zw = box_muller(w2, w3);
+            if (ep.ranged) {
+                f.x = __builtin_fmaf(f.x, ep.d32, ep.a32);
+                f.y = __builtin_fmaf(f.y, ep.d32, ep.a32);
+                f.z = __builtin_fmaf(f.z, ep.d32, ep.a32);
+                f.w = __builtin_fmaf(f.w, ep.d32, ep.a32);
+            }
+            pk = __builtin_bit_cast(u32x4, f);
+        }
+        *(u32x4 *)(row + (l / S::EPV) * 16) = pk;
+    }
+}
+
+template <int ESZ>
+__device__ __forceinline__ void put_elem(char *out, uint64_t e, const char *src)
+{
+    if constexpr (ESZ == 4)
+        *(uint32_t *)(out + e * 4) = *(const uint32_t *)src;
+    else
+        *(uint64_t *)(out + e * 8) = *(const uint64_t *)src;
+}
+
+// Writes one pass back to memory.  Row t of `lds` holds the L outputs of
+// elements [e0 + t * stride, + L) of an output array of n elements whose
+// element 0 is at `out` (element-aligned; e0 and stride are multiples of
+// L).  With h = elements between the previous 16-byte boundary and `out`,
+// every row spans VPR vectors of the 16-byte grid when h = 0 and VPR + 1
+// when not; the two end vectors are then shared with other rows and are
+// written element by element, the others with one 16-byte store.
+// Elements at or beyond n are not written.
+template <int KIND>
+__device__ void mrg_store_pass(const char *lds, uint64_t e0, uint64_t stride, uint64_t n,
+                               char *out, int nt)
+{
+    using S = MrgShape<KIND>;
+    constexpr int ESZ = S::ESZ, EPV = S::EPV, VPR = S::VPR, L = S::L;
+    const uint32_t h = (uint32_t)(((uintptr_t)out & 15u) / ESZ);
+    const uint32_t nv = VPR + (h ? 1u : 0u);
+    const uint32_t t = threadIdx.x;
+    for (uint32_t vi = t; vi < (uint32_t)kMrgThreads * nv; vi += kMrgThreads) {
+        const uint32_t row = vi / nv;
+        const uint32_t j = vi - row * nv;
+        const uint64_t r0 = e0 + (uint64_t)row * stride;     // element of row offset 0
+        const char *src = lds + row * S::ROW;
+        // row-local index of the vector's first element (may be negative)
+        const int32_t i0 = (int32_t)(j * EPV) - (int32_t)h;
+        if (r0 + (uint64_t)(i0 + EPV) <= n && i0 >= 0 && i0 + EPV <= L) {
+            char *dst = out + (r0 + (uint64_t)i0) * ESZ;
+            u32x4 val;
+            if (h == 0) {
+                val = *(const u32x4 *)(src + i0 * ESZ);
+            } else if constexpr (ESZ == 4) {
+                const uint32_t *p = (const uint32_t *)(src + i0 * 4);
+                val = u32x4{p[0], p[1], p[2], p[3]};
+            } else {
+                const uint2 *p = (const uint2 *)(src + i0 * 8);
+                const uint2 x = p[0], y = p[1];
+                val = u32x4{x.x, x.y, y.x, y.y};
+            }
+            if (nt)
+                __builtin_nontemporal_store(val, (u32x4 *)dst);
+            else
+                *(u32x4 *)dst = val;
+        } else {
+#pragma unroll
+            for (int k = 0; k < EPV; ++k) {
+                const int32_t i = i0 + k;
+                if (i >= 0 && i < L && r0 + (uint64_t)i < n)
+                    put_elem<ESZ>(out, r0 + (uint64_t)i, src + i * ESZ);
+            }
+        }
+    }
+}
+
+}  // namespace mirng

@@ -8,21 +8,14 @@
 // start state is A^(c 256 q) A^(s 2^76) S, formed from resident tables of
 // base-64 digit powers (at most 4 + 5 matrix-vector products, done by one
 // wave); thread t then applies A^(t q) from a resident table and runs q
-// sequential steps.  Each pass of L steps goes through LDS (rows padded by
-// 16 bytes so 8 consecutive lanes hit distinct banks) and is written back
-// as 128-byte segments, one per thread, with 16-byte stores.
-//
-// The recurrence runs in FP64: all products are below 2^53 and exact, the
-// quotient by m is estimated by a multiply with 1/m biased by -2^-30 so that
-// the floor is never too large, and one conditional subtraction finishes
-// the reduction.  The results are the exact integers of the definition.
+// sequential steps, L at a time through LDS (the shared pass code).
 #include <map>
 #include <mutex>
 #include <utility>
 #include <vector>
 
 #include "internal.hpp"
-#include "transforms.hpp"
+#include "mrg.hpp"
 
 namespace mirng {
 
@@ -31,102 +24,26 @@ struct MrgLaunch {
     uint32_t q;               // steps per thread (multiple of L)
     uint32_t chunks_per_sub;  // workgroups per substream
     uint32_t use_sub;         // 0: plain generate (substream 0 only)
-    uint32_t vec_ok;          // output base is 16-byte aligned
+    uint32_t pad;
     uint64_t n_each;          // outputs per substream
     uint64_t s_first;         // first substream index
     const uint32_t *u_tab;    // A^(t q): [t][comp][9]
     const uint32_t *c_tab;    // A^(k 64^d 256 q): [d][k][comp][9]
     const uint32_t *s_tab;    // A^(k 64^d 2^76): [d][k][comp][9]
     char *out;
-    int32_t ranged;
-    float a32, d32;
-    double a64, d64;
+    Epilogue ep;
 };
 
-constexpr int kThreads = 256;
-constexpr int kCDigits = 4;   // chunk index < 64^4 = 2^24
+constexpr int kThreads = kMrgThreads;
 constexpr int kSDigits = 5;   // substream index < 64^5 = 2^30
-constexpr int kMatWords = 18; // two 3x3 matrices
 
 namespace {
-
-// x mod m1 for any 64-bit x (2^32 = 209 mod m1).
-__device__ __forceinline__ uint32_t red_m1(uint64_t x)
-{
-    x = (x >> 32) * 209u + (x & 0xFFFFFFFFull);
-    x = (x >> 32) * 209u + (x & 0xFFFFFFFFull);
-    return (uint32_t)(x >= kM1 ? x - kM1 : x);
-}
-
-// x mod m2 for any 64-bit x (2^32 = 22853 mod m2).
-__device__ __forceinline__ uint32_t red_m2(uint64_t x)
-{
-    x = (x >> 32) * 22853u + (x & 0xFFFFFFFFull);
-    x = (x >> 32) * 22853u + (x & 0xFFFFFFFFull);
-    return (uint32_t)(x >= kM2 ? x - kM2 : x);
-}
-
-// v <- M v for both components; M points at 18 words (comp 0 then comp 1).
-__device__ __forceinline__ void apply_mat(const uint32_t *M, uint32_t v[6])
-{
-    uint32_t r[6];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        const uint64_t a = red_m1((uint64_t)M[3 * i] * v[0]) +
-                           (uint64_t)red_m1((uint64_t)M[3 * i + 1] * v[1]) +
-                           red_m1((uint64_t)M[3 * i + 2] * v[2]);
-        r[i] = red_m1(a);
-        const uint64_t b = red_m2((uint64_t)M[9 + 3 * i] * v[3]) +
-                           (uint64_t)red_m2((uint64_t)M[9 + 3 * i + 1] * v[4]) +
-                           red_m2((uint64_t)M[9 + 3 * i + 2] * v[5]);
-        r[3 + i] = red_m2(b);
-    }
-#pragma unroll
-    for (int i = 0; i < 6; ++i) v[i] = r[i];
-}
-
-constexpr double kM1d = 4294967087.0;
-constexpr double kM2d = 4294944443.0;
-constexpr double kInvM1 = 1.0 / 4294967087.0;
-constexpr double kInvM2 = 1.0 / 4294944443.0;
-constexpr double kNorm = 1.0 / 4294967088.0;   // 1 / (m1 + 1), rounded once
-
-struct MrgState {
-    double a0, a1, a2;   // x1[n-3], x1[n-2], x1[n-1]
-    double b0, b1, b2;   // x2[n-3], x2[n-2], x2[n-1]
-};
-
-// One step; returns the combined output y in [1, m1] as an exact double.
-__device__ __forceinline__ double mrg_step(MrgState &s)
-{
-    double p1 = __builtin_fma(1403580.0, s.a1, -810728.0 * s.a0);
-    const double k1 = __builtin_floor(__builtin_fma(p1, kInvM1, -0x1p-30));
-    p1 = __builtin_fma(-k1, kM1d, p1);
-    p1 = (p1 >= kM1d) ? p1 - kM1d : p1;
-    double p2 = __builtin_fma(527612.0, s.b2, -1370589.0 * s.b0);
-    const double k2 = __builtin_floor(__builtin_fma(p2, kInvM2, -0x1p-30));
-    p2 = __builtin_fma(-k2, kM2d, p2);
-    p2 = (p2 >= kM2d) ? p2 - kM2d : p2;
-    s.a0 = s.a1; s.a1 = s.a2; s.a2 = p1;
-    s.b0 = s.b1; s.b1 = s.b2; s.b2 = p2;
-    const double y = p1 - p2;
-    return (p1 <= p2) ? y + kM1d : y;
-}
-
-__device__ __forceinline__ float y_to_u01f(double y)
-{
-    return (float)(__builtin_floor(y * 0x1p-8) * 0x1p-24);
-}
 
 template <int KIND>
 __global__ __launch_bounds__(kThreads) void mrg_kernel(MrgLaunch a)
 {
-    constexpr int ESZ = KIND == kU64F ? 8 : 4;
-    constexpr int L = 128 / ESZ;           // outputs per thread per pass
-    constexpr int ROW = L * ESZ + 16;      // padded LDS row, bytes
-    constexpr int VPR = L * ESZ / 16;      // 16-byte vectors per row
-    constexpr int EPV = 16 / ESZ;          // elements per vector
-    __shared__ __attribute__((aligned(16))) char lds[kThreads * ROW];
+    using S = MrgShape<KIND>;
+    __shared__ __attribute__((aligned(16))) char lds[kThreads * S::ROW];
     __shared__ uint32_t wg_state[6];
 
     const uint32_t t = threadIdx.x;
@@ -160,86 +77,19 @@ __global__ __launch_bounds__(kThreads) void mrg_kernel(MrgLaunch a)
 #pragma unroll
     for (int i = 0; i < 6; ++i) v[i] = wg_state[i];
     if (t) apply_mat(a.u_tab + t * kMatWords, v);
-    MrgState s{(double)v[0], (double)v[1], (double)v[2],
-               (double)v[3], (double)v[4], (double)v[5]};
+    MrgState s = mrg_state(v);
 
     const uint64_t e_wg = (uint64_t)c * kThreads * a.q;
-    char *sub_out = a.out + (uint64_t)sub * a.n_each * ESZ;
-    char *row = lds + t * ROW;
-    const uint32_t passes = a.q / L;
+    char *sub_out = a.out + (uint64_t)sub * a.n_each * S::ESZ;
+    char *row = lds + t * S::ROW;
+    const uint32_t passes = a.q / S::L;
 
     for (uint32_t pass = 0; pass < passes; ++pass) {
-        if (e_wg + (uint64_t)pass * L >= a.n_each) break;   // uniform per group
-        // generate L outputs into this thread's LDS row
-#pragma unroll
-        for (int l = 0; l < L; l += EPV) {
-            u32x4 pk;
-            if constexpr (KIND == kBits) {
-                pk.x = (uint32_t)mrg_step(s); pk.y = (uint32_t)mrg_step(s);
-                pk.z = (uint32_t)mrg_step(s); pk.w = (uint32_t)mrg_step(s);
-            } else if constexpr (KIND == kU32F) {
-                f32x4 f;
-                f.x = y_to_u01f(mrg_step(s)); f.y = y_to_u01f(mrg_step(s));
-                f.z = y_to_u01f(mrg_step(s)); f.w = y_to_u01f(mrg_step(s));
-                if (a.ranged) {
-                    f.x = __builtin_fmaf(f.x, a.d32, a.a32);
-                    f.y = __builtin_fmaf(f.y, a.d32, a.a32);
-                    f.z = __builtin_fmaf(f.z, a.d32, a.a32);
-                    f.w = __builtin_fmaf(f.w, a.d32, a.a32);
-                }
-                pk = __builtin_bit_cast(u32x4, f);
-            } else if constexpr (KIND == kU64F) {
-                f64x2 d;
-                d.x = mrg_step(s) * kNorm;
-                d.y = mrg_step(s) * kNorm;
-                if (a.ranged) {
-                    d.x = __builtin_fma(d.x, a.d64, a.a64);
-                    d.y = __builtin_fma(d.y, a.d64, a.a64);
-                }
-                pk = __builtin_bit_cast(u32x4, d);
-            } else {
-                const uint32_t w0 = (uint32_t)mrg_step(s);
-                const uint32_t w1 = (uint32_t)mrg_step(s);
-                const uint32_t w2 = (uint32_t)mrg_step(s);
-                const uint32_t w3 = (uint32_t)mrg_step(s);
-                f32x4 f;
-                f.xy = box_muller(w0, w1);
-                f.zw = box_muller(w2, w3);
-                if (a.ranged) {
-                    f.x = __builtin_fmaf(f.x, a.d32, a.a32);
-                    f.y = __builtin_fmaf(f.y, a.d32, a.a32);
-                    f.z = __builtin_fmaf(f.z, a.d32, a.a32);
-                    f.w = __builtin_fmaf(f.w, a.d32, a.a32);
-                }
-                pk = __builtin_bit_cast(u32x4, f);
-            }
-            *(u32x4 *)(row + (l / EPV) * 16) = pk;
-        }
+        const uint64_t e0 = e_wg + (uint64_t)pass * S::L;
+        if (e0 >= a.n_each) break;   // uniform per group
+        mrg_fill_row<KIND>(s, row, a.ep);
         __syncthreads();
-        // write the group's 256 segments of L outputs back to memory
-        for (uint32_t vi = t; vi < (uint32_t)(kThreads * VPR); vi += kThreads) {
-            const uint32_t seg = vi / VPR;
-            const uint32_t ch = vi - seg * VPR;
-            const uint64_t e = e_wg + (uint64_t)seg * a.q + (uint64_t)pass * L +
-                               (uint64_t)ch * EPV;
-            const u32x4 val = *(const u32x4 *)(lds + seg * ROW + ch * 16);
-            char *dst = sub_out + e * ESZ;
-            if (a.vec_ok && e + EPV <= a.n_each) {
-                __builtin_nontemporal_store(val, (u32x4 *)dst);
-            } else {
-#pragma unroll
-                for (int j = 0; j < EPV; ++j) {
-                    if (e + j < a.n_each) {
-                        if constexpr (ESZ == 4) {
-                            ((uint32_t *)dst)[j] = val[j];
-                        } else {
-                            ((uint64_t *)dst)[j] =
-                                ((uint64_t)val[2 * j + 1] << 32) | val[2 * j];
-                        }
-                    }
-                }
-            }
-        }
+        mrg_store_pass<KIND>(lds, e0, a.q, a.n_each, sub_out, 1);
         __syncthreads();
     }
 }
@@ -375,16 +225,19 @@ hipError_t launch(const MrgLaunch &a, int kind, uint64_t groups, hipStream_t s)
 
 void fill_params(MrgLaunch &a, const mirng_distribution *d)
 {
-    a.ranged = (d->kind == kBits || (d->p0 == 0.0 && d->p1 == 1.0)) ? 0 : 1;
+    Epilogue &e = a.ep;
+    e = Epilogue{};
+    e.ranged = (d->kind == kBits || (d->p0 == 0.0 && d->p1 == 1.0)) ? 0 : 1;
+    e.nt = 1;
     if (d->kind == kU64F) {
-        a.a64 = d->p0;
-        a.d64 = d->p1 - d->p0;
+        e.a64 = d->p0;
+        e.d64 = d->p1 - d->p0;
     } else if (d->kind == kGauss) {
-        a.a32 = (float)d->p0;
-        a.d32 = (float)d->p1;
+        e.a32 = (float)d->p0;
+        e.d32 = (float)d->p1;
     } else {
-        a.a32 = (float)d->p0;
-        a.d32 = (float)(d->p1 - d->p0);
+        e.a32 = (float)d->p0;
+        e.d32 = (float)(d->p1 - d->p0);
     }
 }
 
@@ -410,9 +263,6 @@ hipError_t run(const uint32_t st[6], const mirng_distribution *d, uint64_t s_fir
     const uint64_t chunks = (n_each + per_group - 1) / per_group;
     a.chunks_per_sub = (uint32_t)chunks;
     a.use_sub = use_sub ? 1 : 0;
-    // 16-byte stores need every substream's start on the 16-byte grid
-    const uint64_t esz = d->kind == kU64F ? 8 : 4;
-    a.vec_ok = ((uintptr_t)out & 15u) == 0 && (!use_sub || (n_each * esz) % 16 == 0) ? 1 : 0;
     a.n_each = n_each;
     a.s_first = s_first;
     a.u_tab = tb.u;
@@ -427,7 +277,43 @@ hipError_t run(const uint32_t st[6], const mirng_distribution *d, uint64_t s_fir
     return launch(a, d->kind, groups, s);
 }
 
+std::map<int, uint32_t *> g_pow2_tables;
+
+hipError_t pow2_table(int dev, uint32_t **out)
+{
+    std::lock_guard<std::mutex> lk(g_tab_mu);
+    auto it = g_pow2_tables.find(dev);
+    if (it != g_pow2_tables.end()) {
+        *out = it->second;
+        return hipSuccess;
+    }
+    std::vector<uint32_t> h((size_t)64 * kMatWords);
+    for (int k = 0; k < 64; ++k) put_mat(h, k, mrg_pow2(0, k), mrg_pow2(1, k));
+    uint32_t *ptr = nullptr;
+    hipError_t err = upload(h, &ptr);
+    if (err != hipSuccess) return err;
+    g_pow2_tables[dev] = ptr;
+    *out = ptr;
+    return hipSuccess;
+}
+
 }  // namespace
+
+hipError_t mrg_batch_tables(int dev, MrgBatchTables &t)
+{
+    uint32_t *p2 = nullptr;
+    DeviceTables t4, t8;
+    hipError_t err = pow2_table(dev, &p2);
+    if (err == hipSuccess) err = tables_for(dev, 32 * kBatchMrgPasses, t4);
+    if (err == hipSuccess) err = tables_for(dev, 16 * kBatchMrgPasses, t8);
+    if (err != hipSuccess) return err;
+    t.pow2 = p2;
+    t.c_tab4 = t4.c;
+    t.u_tab4 = t4.u;
+    t.c_tab8 = t8.c;
+    t.u_tab8 = t8.u;
+    return hipSuccess;
+}
 
 hipError_t mrg_plain(const uint32_t st[6], const mirng_distribution *d, uint64_t n,
                      char *out, hipStream_t s)

@@ -139,9 +139,17 @@ __device__ __forceinline__ u32x4 funnel(u32x4 cur, u32x4 nb)
     return w;
 }
 
-__device__ __forceinline__ uint32_t lane_pull(int addr, uint32_t v)
+// Lane i receives lane i + 1's v, lane 63 receives fill63: one DPP move
+// (wave_shl:1, a GFX9-family wavefront shift; the lane that has no source
+// keeps the destination's old value).
+__device__ __forceinline__ uint32_t from_next_lane(uint32_t v, uint32_t fill63)
 {
-    return (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)v);
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)fill63, (int)v, 0x130, 0xF, 0xF, false);
+}
+
+__device__ __forceinline__ uint32_t lane0(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
 }
 
 // The 16 bytes of slot s of a run, stored whole or element by element.
@@ -171,17 +179,15 @@ __device__ __forceinline__ void walk_slots(const SlotRun &r, uint32_t s0, uint32
             if (slot - s0 < span) emit_slot<KIND>(r, slot, w);
         }
     } else {
-        const int next_addr = (int)(((lane + 1u) & 63u) << 2);
         u32x4 cur = block_at(r.base, r.k0, r.k1, s0 + lane);
         for (uint32_t it = 0; it < iters; ++it) {
             const uint32_t slot = s0 + (it << 6) + lane;
             const u32x4 nxt = block_at(r.base, r.k0, r.k1, slot + 64u);
-            // lane 0 offers its next-step block, which lane 63 needs
-            const u32x4 src = (lane == 0) ? nxt : cur;
+            // lane 63 takes lane 0's next-step block
             u32x4 nb;
-            nb.x = lane_pull(next_addr, src.x);
-            if constexpr (PHASE >= 2) nb.y = lane_pull(next_addr, src.y);
-            if constexpr (PHASE >= 3) nb.z = lane_pull(next_addr, src.z);
+            nb.x = from_next_lane(cur.x, lane0(nxt.x));
+            if constexpr (PHASE >= 2) nb.y = from_next_lane(cur.y, lane0(nxt.y));
+            if constexpr (PHASE >= 3) nb.z = from_next_lane(cur.z, lane0(nxt.z));
             if (slot - s0 < span) emit_slot<KIND>(r, slot, funnel<PHASE>(cur, nb));
             cur = nxt;
         }

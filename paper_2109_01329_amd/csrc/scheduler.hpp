@@ -1,0 +1,103 @@
+// Continuous-batching scheduler of the serving loop, independent of HIP so
+// that its policy can be exercised on the host with a simulated executor.
+//
+// Requests wait in arrival order.  A dispatcher thread launches, whenever an
+// executor slot (a stream) is free, every waiting request that fits: in
+// arrival order, while the output bytes of admitted, unfinished requests
+// stay within the capacity, up to max_batch per batch.  A completion thread
+// waits for the oldest batch in flight, records the per-request statuses
+// and completion times, and returns the batch's bytes to the admission
+// budget.
+#pragma once
+
+#include <chrono>
+#include <condition_variable>
+#include <cstdint>
+#include <deque>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "mirng.h"
+
+namespace mirng {
+
+// Runs batches; slot k holds at most one batch at a time.
+class Executor {
+public:
+    virtual ~Executor() = default;
+    virtual int slots() const = 0;
+    // Called once on each scheduler thread before any other call from it.
+    virtual void bind_thread() {}
+    // Enqueue `reqs` as one batch on slot k (asynchronous).
+    virtual mirng_status launch(int slot, const std::vector<mirng_request> &reqs) = 0;
+    // Block until slot k's batch has completed; statuses of its requests.
+    virtual mirng_status wait(int slot, std::vector<int32_t> &statuses) = 0;
+};
+
+// Output bytes of a request as admission counts them.
+uint64_t request_bytes(const mirng_request &r);
+
+class Scheduler {
+public:
+    Scheduler(Executor &ex, uint64_t capacity_bytes, size_t max_batch);
+    ~Scheduler();   // finishes every accepted request, then stops
+    Scheduler(const Scheduler &) = delete;
+    Scheduler &operator=(const Scheduler &) = delete;
+
+    mirng_status submit(const mirng_request &r, uint64_t *ticket);
+    mirng_status poll(uint64_t ticket, int32_t *done, int32_t *status);
+    mirng_status wait(uint64_t ticket, int32_t *status, double *latency_ms);
+    void drain();
+    mirng_server_stats stats();
+    // Batches launched so far, as lists of tickets (for policy tests).
+    std::vector<std::vector<uint64_t>> batch_log();
+
+private:
+    using Clock = std::chrono::steady_clock;
+    struct Ticket {
+        Clock::time_point submitted;
+        Clock::time_point finished;
+        uint64_t bytes = 0;
+        uint64_t n = 0;
+        int32_t status = 0;
+        bool done = false;
+    };
+    struct Waiting {
+        uint64_t ticket;
+        mirng_request req;
+    };
+    struct InFlight {
+        int slot;
+        std::vector<uint64_t> tickets;
+        uint64_t bytes;
+        mirng_status failed = MIRNG_OK;   // launch status
+    };
+
+    void dispatch_loop();
+    void complete_loop();
+
+    Executor &ex_;
+    const uint64_t capacity_;
+    const size_t max_batch_;
+    std::mutex mu_;
+    std::condition_variable cv_;
+    std::deque<Waiting> waiting_;
+    std::deque<InFlight> inflight_;   // launch order
+    std::vector<bool> slot_busy_;
+    std::vector<Ticket> tickets_;
+    std::vector<std::vector<uint64_t>> log_;
+    uint64_t inflight_bytes_ = 0;
+    uint64_t max_inflight_bytes_ = 0;
+    uint64_t refused_ = 0;
+    uint64_t completed_ = 0;
+    int launching_ = 0;               // batches between dequeue and launch
+    bool stop_ = false;
+    bool have_first_ = false;
+    Clock::time_point first_;
+    Clock::time_point last_;
+    std::thread dispatcher_;
+    std::thread completer_;
+};
+
+}  // namespace mirng

@@ -53,6 +53,15 @@ def oracle_mrg(state, kind: int, n: int, p0=None, p1=None):
     return out
 
 
+def oracle_request(engine: int, seed: int, offset: int, kind: int, n: int, p0=None, p1=None):
+    """Outputs of a batch request: engine created from (seed, offset), then
+    n outputs of `kind`."""
+    if engine == mr.PHILOX4X32_10:
+        return oracle_philox(seed, offset, kind, n, p0, p1)
+    state = oracle.mrg_skip(oracle.mrg_seed(seed), offset)
+    return oracle_mrg(state, kind, n, p0, p1)
+
+
 def ulp32(x: np.ndarray) -> np.ndarray:
     ax = np.abs(np.asarray(x, dtype=np.float64))
     e = np.floor(np.log2(np.where(ax > 0, ax, 1.0)))

@@ -1,7 +1,8 @@
-"""GPU parity of batched generation: every request of a batch equals the
-oracle (and the plain single-request path, byte for byte), invalid requests
-write nothing and report their status, and outputs do not depend on the
-request order, the launch shape or the ring slot and stream used."""
+"""GPU parity of batched generation (Philox4x32-10 and MRG32k3a requests
+mixed): every request of a batch equals the oracle (and the plain
+single-request path, byte for byte), invalid requests write nothing and
+report their status, and outputs do not depend on the request order, the
+launch shape or the ring slot and stream used."""
 import numpy as np
 import pytest
 
@@ -16,9 +17,10 @@ KINDS = [mr.BITS_U32, mr.UNIFORM_F32, mr.UNIFORM_F64, mr.GAUSSIAN_F32]
 FILL = 0xA5
 
 
-def _mix(rng, count, max_log10=4.3):
-    """Random Philox requests laid out in one buffer with 64-byte guard gaps
-    and every output alignment the element size allows."""
+def _mix(rng, count, max_log10=4.3, mrg_frac=0.3):
+    """Random requests laid out in one buffer with 64-byte guard gaps and
+    every output alignment the element size allows; a fraction `mrg_frac`
+    of them on MRG32k3a."""
     reqs = mr.make_requests(count)
     layout = []
     pos = 64
@@ -38,8 +40,9 @@ def _mix(rng, count, max_log10=4.3):
             p0, p1 = 1.5, 0.25
         else:
             p0, p1 = 0.0, 1.0
-        reqs[i] = (1, 0, kind, 0, p0, p1, seed, offset, n, 0)
-        layout.append((pos, kind, n, seed, offset, p0, p1))
+        engine = mr.MRG32K3A if rng.random() < mrg_frac else mr.PHILOX4X32_10
+        reqs[i] = (engine, 0, kind, 0, p0, p1, seed, offset, n, 0)
+        layout.append((pos, kind, n, seed, offset, p0, p1, engine))
         pos += n * esz + 64
     return reqs, layout, pos + 64
 
@@ -59,12 +62,12 @@ def _run(reqs, layout, nbytes, batcher=None, stream=None):
 
 def _check_outputs(host, layout, statuses):
     covered = np.zeros(host.size, dtype=bool)
-    for (pos, kind, n, seed, offset, p0, p1), st in zip(layout, statuses):
+    for (pos, kind, n, seed, offset, p0, p1, engine), st in zip(layout, statuses):
         esz = mr.ELEM_BYTES[kind]
         if st != 0:
             continue
         got = host[pos: pos + n * esz].view(gh.NP_DTYPE[kind])
-        want = gh.oracle_philox(seed, offset, kind, n, p0, p1)
+        want = gh.oracle_request(engine, seed, offset, kind, n, p0, p1)
         gh.assert_match(kind, got, want, p0, p1)
         covered[pos: pos + n * esz] = True
     assert np.all(host[~covered] == FILL), "bytes outside the requests were written"
@@ -83,10 +86,10 @@ def test_batch_equals_plain_path_bytes():
     rng = np.random.default_rng(72)
     reqs, layout, nbytes = _mix(rng, 120)
     host, st = _run(reqs, layout, nbytes)
-    for pos, kind, n, seed, offset, p0, p1 in layout:
+    for pos, kind, n, seed, offset, p0, p1, engine in layout:
         if n == 0:
             continue
-        e = mr.Engine(mr.PHILOX4X32_10, seed, offset)
+        e = mr.Engine(engine, seed, offset)
         got, _ = gh.generate(e, kind, n, pos % 16, p0, p1)
         esz = mr.ELEM_BYTES[kind]
         assert np.array_equal(got.view(np.uint8), host[pos: pos + n * esz])
@@ -117,7 +120,7 @@ def test_batch_invalid_requests_report_and_write_nothing():
     idx = [i for i, lay in enumerate(layout) if lay[2] > 4]
     setbad(idx[0], "kind", 9, 2)                       # unknown distribution
     setbad(idx[1], "engine_type", 7, 2)                # unknown engine
-    setbad(idx[2], "engine_type", 2, 2)                # MRG32k3a: not in batches
+    setbad(idx[2], "engine_type", 0, 2)                # no engine
     setbad(idx[3], "reserved", 1, 1)
     setbad(idx[4], "dist_reserved", 3, 1)
     if layout[idx[5]][1] in (mr.UNIFORM_F32, mr.UNIFORM_F64):
@@ -138,6 +141,30 @@ def test_batch_invalid_requests_report_and_write_nothing():
     assert np.all(st[good] == 0)
     lay2 = list(layout)
     _check_outputs(host, lay2, [st[i] for i in range(len(layout))])
+
+
+def test_batch_mrg_chunk_edges():
+    """MRG requests whose sizes straddle chunk and pass boundaries (16384
+    outputs per chunk for 4-byte kinds, 8192 for FP64), at every alignment
+    and with offsets across the 64-bit range."""
+    rng = np.random.default_rng(77)
+    reqs = mr.make_requests(0)
+    sizes = [1, 31, 32, 33, 63, 64, 65, 8191, 8192, 8193, 16383, 16384, 16385, 40000]
+    recs, layout, pos = [], [], 64
+    for n in sizes:
+        for kind in KINDS:
+            esz = mr.ELEM_BYTES[kind]
+            mis = int(rng.integers(0, 16 // esz)) * esz
+            pos = ((pos + 15) // 16) * 16 + mis
+            seed = int(rng.integers(0, 2**64, dtype=np.uint64))
+            offset = int(rng.integers(0, 2**64, dtype=np.uint64))
+            recs.append((mr.MRG32K3A, 0, kind, 0, 0.0, 1.0, seed, offset, n, 0))
+            layout.append((pos, kind, n, seed, offset, 0.0, 1.0, mr.MRG32K3A))
+            pos += n * esz + 64
+    reqs = np.array(recs, dtype=mr.request_dtype())
+    host, st = _run(reqs, layout, pos + 64)
+    assert np.all(st == 0)
+    _check_outputs(host, layout, st)
 
 
 def test_batch_calorimeter_shape():
