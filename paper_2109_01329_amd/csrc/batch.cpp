@@ -6,8 +6,9 @@
 // not at all when the caller filled the staged slot), uploads it on the
 // batcher's own copy stream (so the upload overlaps earlier work on the
 // caller's stream), and enqueues on the caller's stream, behind the upload,
-// the planning, scan and mark kernels, the two generation kernels (Philox,
+// the planning and scan kernels, the two generation kernels (Philox,
 // MRG32k3a) and the copy of the per-request statuses back to pinned memory.
+#include <algorithm>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -18,6 +19,7 @@ namespace {
 
 constexpr int kSlots = 4;
 constexpr size_t kChunk = 1024;
+constexpr size_t kSmallBatch = 8192;   // batches this small get a grid sized to their work
 
 struct Slot {
     mirng_request *h_reqs = nullptr;   // pinned
@@ -28,17 +30,12 @@ struct Slot {
     bool pending = false;              // `done` recorded and maybe not reached
     hipEvent_t done = nullptr;
     hipEvent_t uploaded = nullptr;
-    size_t wave_cap = 0;
     mirng_request *d_reqs = nullptr;
     mirng::BatchDesc *d_desc = nullptr;
     uint64_t *d_local_end = nullptr;
     uint64_t *d_chunk_total = nullptr;
     uint64_t *d_chunk_end = nullptr;
     uint64_t *d_total = nullptr;
-    uint64_t *d_tile_start = nullptr;
-    uint64_t *d_mrg_start = nullptr;
-    uint32_t *d_wave_req = nullptr;
-    uint32_t *d_grp_req = nullptr;
     int32_t *d_status = nullptr;
 };
 
@@ -60,10 +57,6 @@ void release(Slot &s)
     if (s.d_chunk_total) (void)hipFree(s.d_chunk_total);
     if (s.d_chunk_end) (void)hipFree(s.d_chunk_end);
     if (s.d_total) (void)hipFree(s.d_total);
-    if (s.d_tile_start) (void)hipFree(s.d_tile_start);
-    if (s.d_mrg_start) (void)hipFree(s.d_mrg_start);
-    if (s.d_wave_req) (void)hipFree(s.d_wave_req);
-    if (s.d_grp_req) (void)hipFree(s.d_grp_req);
     if (s.d_status) (void)hipFree(s.d_status);
     if (s.done) (void)hipEventDestroy(s.done);
     if (s.uploaded) (void)hipEventDestroy(s.uploaded);
@@ -71,24 +64,15 @@ void release(Slot &s)
 }
 
 // Waits until the device no longer uses the slot, then makes room for
-// `count` requests and `waves` generation waves on device `dev`.
-hipError_t prepare(Slot &s, size_t count, size_t waves, int dev)
+// `count` requests on device `dev`.
+hipError_t prepare(Slot &s, size_t count, int dev)
 {
     if (s.pending) {
         hipError_t err = hipEventSynchronize(s.done);
         if (err != hipSuccess) return err;
         s.pending = false;
     }
-    if (s.cap >= count && s.dev == dev) {
-        if (s.wave_cap >= waves) return hipSuccess;
-        if (s.d_wave_req) (void)hipFree(s.d_wave_req);
-        s.d_wave_req = nullptr;
-        s.wave_cap = 0;
-        hipError_t err = hipMalloc((void **)&s.d_wave_req, waves * sizeof(uint32_t));
-        if (err != hipSuccess) return err;
-        s.wave_cap = waves;
-        return hipSuccess;
-    }
+    if (s.cap >= count && s.dev == dev) return hipSuccess;
     release(s);
     size_t cap = count < 1024 ? 1024 : count;
     const size_t nchunks = (cap + kChunk - 1) / kChunk;
@@ -102,10 +86,6 @@ hipError_t prepare(Slot &s, size_t count, size_t waves, int dev)
     chk(hipMalloc((void **)&s.d_chunk_total, 2 * nchunks * sizeof(uint64_t)));
     chk(hipMalloc((void **)&s.d_chunk_end, 2 * nchunks * sizeof(uint64_t)));
     chk(hipMalloc((void **)&s.d_total, 2 * sizeof(uint64_t)));
-    chk(hipMalloc((void **)&s.d_tile_start, cap * sizeof(uint64_t)));
-    chk(hipMalloc((void **)&s.d_mrg_start, cap * sizeof(uint64_t)));
-    chk(hipMalloc((void **)&s.d_wave_req, waves * sizeof(uint32_t)));
-    chk(hipMalloc((void **)&s.d_grp_req, mrg_groups() * sizeof(uint32_t)));
     chk(hipMalloc((void **)&s.d_status, cap * sizeof(int32_t)));
     chk(hipEventCreateWithFlags(&s.done, hipEventDisableTiming));
     chk(hipEventCreateWithFlags(&s.uploaded, hipEventDisableTiming));
@@ -114,9 +94,29 @@ hipError_t prepare(Slot &s, size_t count, size_t waves, int dev)
         return err;
     }
     s.cap = cap;
-    s.wave_cap = waves;
     s.dev = dev;
     return hipSuccess;
+}
+
+// Upper bounds on the Philox tiles and MRG chunks of a batch from the
+// request sizes alone (the device planning finds the exact counts); they
+// only size the generation grids of small batches.
+void estimate_work(const mirng_request *q, size_t count, uint64_t &tiles, uint64_t &chunks)
+{
+    tiles = 0;
+    chunks = 0;
+    for (size_t i = 0; i < count; ++i) {
+        const uint64_t n = q[i].n;
+        if (n == 0 || n >= (1ull << 32)) continue;
+        const bool f64 = q[i].dist.kind == MIRNG_UNIFORM_F64;
+        if (q[i].engine_type == MIRNG_MRG32K3A) {
+            const uint64_t per = (uint64_t)256 * mirng::kBatchMrgPasses * (f64 ? 16 : 32);
+            chunks += (n + per - 1) / per;
+        } else {
+            const uint64_t units = (n * (f64 ? 2 : 1) + 3) / 4 + 2;
+            tiles += (units + 63) / 64 + 1;
+        }
+    }
 }
 
 bool config_valid(const mirng_batch_config &c)
@@ -139,6 +139,26 @@ struct mirng_batcher_s {
     int staged = -1;   // slot handed out by mirng_batcher_stage
     mirng_batch_config cfg = {1024, 256, 1, 0};
 };
+
+namespace mirng {
+
+hipError_t batcher_reserve(mirng_batcher b, size_t count)
+{
+    int dev = 0;
+    hipError_t err = ensure_device(&dev);
+    if (err != hipSuccess) return err;
+    MrgBatchTables tabs;
+    err = mrg_batch_tables(dev, tabs);
+    if (err != hipSuccess) return err;
+    std::lock_guard<std::mutex> lk(b->mu);
+    for (Slot &s : b->slots) {
+        err = prepare(s, count, dev);
+        if (err != hipSuccess) return err;
+    }
+    return hipSuccess;
+}
+
+}  // namespace mirng
 
 using namespace mirng;
 
@@ -194,7 +214,7 @@ mirng_status mirng_batcher_stage(mirng_batcher b, size_t count, mirng_request **
     if (ensure_device(&dev) != hipSuccess) return MIRNG_E_DEVICE;
     std::lock_guard<std::mutex> lk(b->mu);
     const int k = b->next;
-    if (prepare(b->slots[k], count, grid_waves(b->cfg), dev) != hipSuccess) return MIRNG_E_ALLOC;
+    if (prepare(b->slots[k], count, dev) != hipSuccess) return MIRNG_E_ALLOC;
     b->next = (k + 1) % kSlots;
     b->staged = k;
     *reqs = b->slots[k].h_reqs;
@@ -221,15 +241,25 @@ mirng_status mirng_generate_batch(mirng_batcher b, const mirng_request *reqs, si
     MrgBatchTables tabs;
     if (mrg_batch_tables(dev, tabs) != hipSuccess) return MIRNG_E_ALLOC;
     const uint64_t wpb = (uint64_t)b->cfg.block / 64;
-    const uint64_t waves = ((grid_waves(b->cfg) + wpb - 1) / wpb) * wpb;
+    uint64_t waves = ((grid_waves(b->cfg) + wpb - 1) / wpb) * wpb;
+    uint64_t mgroups = mrg_groups();
+    if (count <= kSmallBatch) {
+        // small batches: no more waves (groups) than about two tiles
+        // (one chunk) of work each
+        uint64_t tiles, chunks;
+        estimate_work(reqs, count, tiles, chunks);
+        const uint64_t want = ((tiles + 1) / 2 + wpb - 1) / wpb * wpb;
+        waves = std::max<uint64_t>(wpb, std::min(waves, want));
+        mgroups = std::max<uint64_t>(1, std::min(mgroups, chunks));
+    }
     int k;
     if (b->staged >= 0 && reqs == b->slots[b->staged].h_reqs &&
         count <= b->slots[b->staged].cap && b->slots[b->staged].dev == dev) {
         k = b->staged;                                   // filled in place
-        if (prepare(b->slots[k], count, waves, dev) != hipSuccess) return MIRNG_E_ALLOC;
+        if (prepare(b->slots[k], count, dev) != hipSuccess) return MIRNG_E_ALLOC;
     } else {
         k = b->next;
-        if (prepare(b->slots[k], count, waves, dev) != hipSuccess) return MIRNG_E_ALLOC;
+        if (prepare(b->slots[k], count, dev) != hipSuccess) return MIRNG_E_ALLOC;
         b->next = (k + 1) % kSlots;
         std::memcpy(b->slots[k].h_reqs, reqs, count * sizeof(mirng_request));
     }
@@ -245,12 +275,8 @@ mirng_status mirng_generate_batch(mirng_batcher b, const mirng_request *reqs, si
     a.chunk_total = sl.d_chunk_total;
     a.chunk_end = sl.d_chunk_end;
     a.total = sl.d_total;
-    a.tile_start = sl.d_tile_start;
-    a.mrg_start = sl.d_mrg_start;
-    a.wave_req = sl.d_wave_req;
-    a.grp_req = sl.d_grp_req;
     a.waves = (uint32_t)waves;
-    a.mgroups = (uint32_t)mrg_groups();
+    a.mgroups = (uint32_t)mgroups;
     a.pow2 = tabs.pow2;
     a.c_tab4 = tabs.c_tab4;
     a.u_tab4 = tabs.u_tab4;

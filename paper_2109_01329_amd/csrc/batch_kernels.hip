@@ -9,16 +9,14 @@
 //        A^(2^k) table), and counts its Philox tiles of 64 slots or MRG
 //        chunks; each workgroup scans both counts over its 1024 requests.
 // scan:  one workgroup scans the per-chunk totals.
-// mark:  one thread per request writes the request's first global tile
-//        (chunk) and, for every wave (group) whose range of tiles (chunks)
-//        starts inside the request, the request index, so that no wave has
-//        to search.
 // philox main: a fixed grid of waves; wave w takes a contiguous range of
 //        tiles (tiles of one request are adjacent, requests in table order),
-//        starts at its marked request and walks forward, running the plain
-//        kernel's slot walk on each request segment.
+//        finds the request holding its first tile by binary search over the
+//        two-level prefix (chunks, then requests) and walks forward, running
+//        the plain kernel's slot walk on each request segment.
 // mrg main: a fixed grid of 256-thread groups, each over a contiguous range
-//        of chunks, running the plain kernel's LDS passes on each chunk.
+//        of chunks found the same way, running the plain kernel's LDS passes
+//        on each chunk.
 // Every value depends only on its request and position, never on the
 // tiling, the grid or the neighbouring requests.
 #include "internal.hpp"
@@ -228,28 +226,35 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t v)
     return ((uint64_t)uniform((uint32_t)(v >> 32)) << 32) | uniform((uint32_t)v);
 }
 
-__global__ __launch_bounds__(256) void batch_mark_kernel(BatchArgs a)
+// Global inclusive prefix (j = 0: Philox tiles, 1: MRG chunks) at the end
+// of request r.
+__device__ __forceinline__ uint64_t prefix_end(const BatchArgs &a, int j, uint32_t r)
 {
-    const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= a.count) return;
     const uint32_t c = r / kChunk;
-    const uint64_t tiles = ((uint64_t)a.desc[r].nunits + 63) / 64;
-    const uint64_t mch = a.desc[r].mchunks;
-    const uint64_t end0 = a.chunk_end[2 * c] - a.chunk_total[2 * c] + a.local_end[2 * r];
-    const uint64_t end1 =
-        a.chunk_end[2 * c + 1] - a.chunk_total[2 * c + 1] + a.local_end[2 * r + 1];
-    const uint64_t start0 = end0 - tiles, start1 = end1 - mch;
-    a.tile_start[r] = start0;
-    a.mrg_start[r] = start1;
-    // waves w with w * per in [start, end); groups likewise for MRG chunks
-    const uint64_t per0 = (a.total[0] + a.waves - 1) / a.waves;
-    if (tiles && per0)
-        for (uint64_t w = (start0 + per0 - 1) / per0; w * per0 < end0 && w < a.waves; ++w)
-            a.wave_req[w] = r;
-    const uint64_t per1 = (a.total[1] + a.mgroups - 1) / a.mgroups;
-    if (mch && per1)
-        for (uint64_t g = (start1 + per1 - 1) / per1; g * per1 < end1 && g < a.mgroups; ++g)
-            a.grp_req[g] = r;
+    return a.chunk_end[2 * c + j] - a.chunk_total[2 * c + j] + a.local_end[2 * r + j];
+}
+
+// The request holding unit T (T below the batch total): the first r whose
+// prefix end exceeds T, by binary search over chunks, then over the
+// requests of that chunk.  Wave-uniform.
+__device__ uint32_t find_request(const BatchArgs &a, int j, uint64_t T)
+{
+    uint32_t lo = 0, hi = a.nchunks;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (a.chunk_end[2 * mid + j] > T) hi = mid;
+        else lo = mid + 1;
+    }
+    const uint32_t c = lo;
+    const uint64_t base = a.chunk_end[2 * c + j] - a.chunk_total[2 * c + j];
+    lo = c * kChunk;
+    hi = min(a.count, lo + kChunk);
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (base + a.local_end[2 * mid + j] > T) hi = mid;
+        else lo = mid + 1;
+    }
+    return lo;
 }
 
 template <int KIND>
@@ -295,11 +300,11 @@ __global__ __launch_bounds__(1024) void batch_main_kernel(BatchArgs a)
     uint64_t t = wave * per;
     const uint64_t t1 = min(t + per, total);
     if (t >= t1) return;
-    uint32_t r = uniform(a.wave_req[wave]);
+    uint32_t r = uniform(find_request(a, 0, t));
     while (t < t1 && r < a.count) {
-        const uint64_t start = uniform64(a.tile_start[r]);
+        const uint64_t end = uniform64(prefix_end(a, 0, r));
         const uint32_t nunits = uniform(a.desc[r].nunits);
-        const uint64_t end = start + ((uint64_t)nunits + 63) / 64;
+        const uint64_t start = end - ((uint64_t)nunits + 63) / 64;
         if (end > t) {
             const uint64_t seg = min(t1, end);
             const uint32_t u0 = (uint32_t)((t - start) * 64);
@@ -360,10 +365,10 @@ __global__ __launch_bounds__(kMrgThreads) void batch_mrg_kernel(BatchArgs a)
     uint64_t c = (uint64_t)blockIdx.x * per;
     const uint64_t c1 = min(c + per, total);
     if (c >= c1) return;
-    uint32_t r = a.grp_req[blockIdx.x];
+    uint32_t r = find_request(a, 1, c);
     while (c < c1 && r < a.count) {
-        const uint64_t start = a.mrg_start[r];
-        const uint64_t end = start + a.desc[r].mchunks;
+        const uint64_t end = prefix_end(a, 1, r);
+        const uint64_t start = end - a.desc[r].mchunks;
         if (end > c) {
             const uint64_t seg = min(c1, end);
             const BatchDesc d = load_desc(&a.desc[r]);
@@ -389,9 +394,6 @@ hipError_t launch_batch(const BatchArgs &a, hipStream_t s)
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
     hipLaunchKernelGGL(batch_scan_kernel, dim3(1), dim3(kChunk), 0, s, a);
-    err = hipGetLastError();
-    if (err != hipSuccess) return err;
-    hipLaunchKernelGGL(batch_mark_kernel, dim3((a.count + 255) / 256), dim3(256), 0, s, a);
     err = hipGetLastError();
     if (err != hipSuccess) return err;
     hipLaunchKernelGGL(batch_main_kernel, dim3(a.groups), dim3(a.block), 0, s, a);

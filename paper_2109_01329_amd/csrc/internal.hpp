@@ -151,10 +151,6 @@ struct BatchArgs {
     uint64_t *chunk_total;  // [2 nchunks] per chunk
     uint64_t *chunk_end;    // [2 nchunks] inclusive prefixes over chunks
     uint64_t *total;        // [2] Philox tiles, MRG chunks of the batch
-    uint64_t *tile_start;   // first Philox tile of each request (global)
-    uint64_t *mrg_start;    // first MRG chunk of each request (global)
-    uint32_t *wave_req;     // request holding the first tile of each wave's range
-    uint32_t *grp_req;      // request holding the first MRG chunk of each group's range
     uint32_t waves;         // waves of the Philox generation grid
     uint32_t mgroups;       // workgroups of the MRG generation grid
     int32_t *status;        // per request
@@ -174,6 +170,9 @@ struct MrgBatchTables {
 hipError_t mrg_batch_tables(int dev, MrgBatchTables &t);
 
 hipError_t launch_batch(const BatchArgs &a, hipStream_t s);
+// Allocates every staging slot of `b` for `count` requests on the current
+// device (so that later batches of up to `count` requests allocate nothing).
+hipError_t batcher_reserve(mirng_batcher b, size_t count);
 
 hipError_t launch_philox_blocks(const PhiloxBlocks &a, hipStream_t s);
 hipError_t launch_philox_fill(const PhiloxFill &a, hipStream_t s);

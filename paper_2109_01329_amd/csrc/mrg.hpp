@@ -8,9 +8,9 @@
 // 16 bytes hit distinct banks.
 //
 // The recurrence runs in FP64: all products are below 2^53 and exact, the
-// quotient by m is estimated by a multiply with 1/m biased by -2^-30 so that
-// the floor is never too large, and one conditional subtraction finishes
-// the reduction.  The results are the exact integers of the definition.
+// quotient by m is rounded to the nearest integer with the 1.5 * 2^52
+// constant, and one conditional addition finishes the reduction.  The
+// results are the exact integers of the definition.
 #pragma once
 
 #include "internal.hpp"
@@ -74,17 +74,26 @@ __device__ __forceinline__ MrgState mrg_state(const uint32_t v[6])
                     (double)v[3], (double)v[4], (double)v[5]};
 }
 
+// Adding 1.5 * 2^52 to a double of magnitude below 2^51 rounds it to an
+// integer (round to nearest even); subtracting it again gives that integer.
+constexpr double kRound = 0x1.8p52;
+
 // One step; returns the combined output y in [1, m1] as an exact double.
+// For each component, p = a x[n-2] - b x[n-3] (or the x2 analogue) is an
+// exact integer below 2^53 in magnitude; k = RN(p * RN(1/m)) is the nearest
+// integer to p / m up to 2e-10, so r = fma(-k, m, p) is exact and lies in
+// (-m, m), and one conditional addition of m gives p mod m.  Only full-rate
+// FP64 adds, multiplies and FMAs are used (no floor).
 __device__ __forceinline__ double mrg_step(MrgState &s)
 {
     double p1 = __builtin_fma(1403580.0, s.a1, -810728.0 * s.a0);
-    const double k1 = __builtin_floor(__builtin_fma(p1, kInvM1, -0x1p-30));
+    const double k1 = __builtin_fma(p1, kInvM1, kRound) - kRound;
     p1 = __builtin_fma(-k1, kM1d, p1);
-    p1 = (p1 >= kM1d) ? p1 - kM1d : p1;
+    p1 = (p1 < 0.0) ? p1 + kM1d : p1;
     double p2 = __builtin_fma(527612.0, s.b2, -1370589.0 * s.b0);
-    const double k2 = __builtin_floor(__builtin_fma(p2, kInvM2, -0x1p-30));
+    const double k2 = __builtin_fma(p2, kInvM2, kRound) - kRound;
     p2 = __builtin_fma(-k2, kM2d, p2);
-    p2 = (p2 >= kM2d) ? p2 - kM2d : p2;
+    p2 = (p2 < 0.0) ? p2 + kM2d : p2;
     s.a0 = s.a1; s.a1 = s.a2; s.a2 = p1;
     s.b0 = s.b1; s.b1 = s.b2; s.b2 = p2;
     const double y = p1 - p2;

@@ -12,6 +12,9 @@
 namespace mirng {
 namespace {
 
+// Requests per batch for which staging memory is allocated up front.
+constexpr size_t kReserve = 4096;
+
 class HipExecutor : public Executor {
 public:
     ~HipExecutor() override { release(); }
@@ -27,6 +30,8 @@ public:
             mirng_batcher b = nullptr;
             if (mirng_batcher_create(&b) != MIRNG_OK) return hipErrorOutOfMemory;
             batchers_.push_back(b);
+            err = batcher_reserve(b, kReserve);
+            if (err != hipSuccess) return err;
         }
         counts_.assign((size_t)streams, 0);
         return hipSuccess;

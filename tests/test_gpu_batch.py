@@ -224,3 +224,28 @@ def test_batch_staged_ring_two_streams():
     for buf, layout in jobs:
         host = buf.cpu().numpy()
         _check_outputs(host, layout, [0] * len(layout))
+
+
+def test_batch_large_requests_among_small():
+    """Two large requests (one per engine, misaligned, odd phase) among many
+    small ones: the generation waves and groups whose ranges start inside a
+    large request find it by search."""
+    rng = np.random.default_rng(78)
+    reqs, layout, nbytes = _mix(rng, 300, max_log10=3.0)
+    big = [(mr.PHILOX4X32_10, mr.UNIFORM_F32, (1 << 22) + 13, 4, 2**40 + 3),
+           (mr.MRG32K3A, mr.UNIFORM_F64, (1 << 21) + 5, 8, 2**50 + 7),
+           (mr.PHILOX4X32_10, mr.GAUSSIAN_F32, (1 << 20) + 1, 12, 2**33 + 1)]
+    recs = list(reqs)
+    lay = list(layout)
+    pos = nbytes
+    for engine, kind, n, mis, offset in big:
+        pos = ((pos + 15) // 16) * 16 + mis
+        seed = int(rng.integers(0, 2**64, dtype=np.uint64))
+        at = int(rng.integers(0, len(recs) + 1))
+        recs.insert(at, (engine, 0, kind, 0, 0.0, 1.0, seed, offset, n, 0))
+        lay.insert(at, (pos, kind, n, seed, offset, 0.0, 1.0, engine))
+        pos += n * mr.ELEM_BYTES[kind] + 64
+    r = np.array(recs, dtype=mr.request_dtype())
+    host, st = _run(r, lay, pos + 64)
+    assert np.all(st == 0)
+    _check_outputs(host, lay, st)
