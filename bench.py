@@ -51,6 +51,12 @@ def parse():
                         "GPU's clocks reach their steady state under this load")
     p.add_argument("--quick", action="store_true", help="headline only")
     p.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
+    p.add_argument("--shape", default=None,
+                   help="block,waves_per_cu,nontemporal: install this Philox launch shape "
+                        "(walk 0) instead of autotuning")
+    p.add_argument("--no-tune", action="store_true",
+                   help="keep the library's default launch shape instead of autotuning it on "
+                        "the headline workload before the timed region")
     p.add_argument("--profile", action="store_true",
                    help="for rocprofv3: 5 headline generate launches, then 3 device copies of "
                         "1 GiB (a plain copy kernel of known size for counter calibration)")
@@ -75,28 +81,53 @@ def time_kernel_calls(fn, reps, stream):
     return sum(ts) / len(ts), ts[len(ts) // 2], ts[int(0.9 * (len(ts) - 1))]
 
 
-def cpu_baseline(seed, offset, n):
+def cpu_baseline(seed, offset, n, cells=None, n_mt=1 << 26, n_st=1 << 22):
     """The oracle over the full headline workload, split into consecutive
-    slices over the host's cores (ctypes releases the GIL)."""
+    slices over the host's cores (ctypes releases the GIL); and, per bulk
+    cell, the oracle on n_mt outputs over all threads and on n_st outputs in
+    one thread (MRG slices start from the oracle's own polynomial jump)."""
     import concurrent.futures
     import oracle
     threads = min(16, os.cpu_count() or 1)
-    step = (n + threads - 1) // threads
     oracle.lib()
 
-    def one(s):
-        m = min(step, n - s)
-        oracle.philox_generate(seed, offset + s, oracle.UNIFORM_F32, m)
-        return m
+    def timed_split(engine, kind, s, o, total, nthreads):
+        step = (total + nthreads - 1) // nthreads
+        step += step % 2                        # Gaussian pairs stay whole
+        wpo = 2 if (engine == oracle.PHILOX and kind == oracle.UNIFORM_F64) else 1
+        start_state = oracle.mrg_skip(oracle.mrg_seed(s), o) if engine == oracle.MRG else None
 
-    t0 = time.perf_counter()
-    with concurrent.futures.ThreadPoolExecutor(max_workers=threads) as ex:
-        done = sum(ex.map(one, range(0, n, step)))
-    dt = time.perf_counter() - t0
-    return {"value": round(done / dt / 1e9, 4), "unit": "Gsamples/s", "cores": threads,
-            "kind": "oracle",
-            "sample": f"full headline workload: {n} Philox4x32-10 uniform FP32 samples "
-                      f"(seed/offset of the bulk draw), {threads} threads, {dt:.2f} s wall"}
+        def one(first):
+            m = min(step, total - first)
+            if engine == oracle.PHILOX:
+                oracle.philox_generate(s, o + first * wpo, kind, m)
+            else:
+                oracle.mrg_generate(oracle.mrg_skip(start_state, first), kind, m)
+            return m
+
+        t0 = time.perf_counter()
+        with concurrent.futures.ThreadPoolExecutor(max_workers=nthreads) as ex:
+            done = sum(ex.map(one, range(0, total, step)))
+        return done, time.perf_counter() - t0
+
+    done, dt = timed_split(oracle.PHILOX, oracle.UNIFORM_F32, seed, offset, n, threads)
+    res = {"value": round(done / dt / 1e9, 4), "unit": "Gsamples/s", "cores": threads,
+           "kind": "oracle",
+           "sample": f"full headline workload: {n} Philox4x32-10 uniform FP32 samples "
+                     f"(seed/offset of the bulk draw), {threads} threads, {dt:.2f} s wall"}
+    if cells:
+        import synth
+        per = {}
+        for engine, kind, s, o in cells:
+            name = f"{synth.ENGINE_NAME[engine]}/{synth.KIND_NAME[kind]}"
+            d1, t1 = timed_split(engine, kind, s, o, n_mt, threads)
+            d2, t2 = timed_split(engine, kind, s, o, n_st, 1)
+            per[name] = {f"Gsamples_s_{threads}_threads": round(d1 / t1 / 1e9, 4),
+                         "Gsamples_s_1_thread": round(d2 / t2 / 1e9, 4)}
+        res["cells"] = per
+        res["cells_sample"] = (f"each bulk cell's seed/offset: {n_mt} outputs over {threads} "
+                               f"threads, {n_st} outputs in 1 thread")
+    return res
 
 
 def calo_requests(mr, synth, torch, dev):
@@ -178,15 +209,17 @@ def calo_batch_leg(mr, synth, torch, stream, dev, reps=20, tune=True, windows=5,
             "batch_over_plain_time": round(ms_pipe / plain_ms, 3)}
 
 
-def serve_leg(mr, synth, torch, dev, cells=None, duration_s=0.25, streams=4,
+def serve_leg(mr, synth, torch, dev, cells=None, counts=(2000, 20000, 20000), streams=4,
               capacity=32 * 10**9, ring_gib=64):
     """Serving loop under open-loop Poisson arrivals at 1e3, 1e4 and 1e5
-    requests/s for `duration_s` each: sizes floor(10^U(3, 8)), engine and
+    requests/s (`counts` requests each): sizes floor(10^U(3, 8)), engine and
     distribution uniform over the 2 x 4 mix, seeds uint64, offsets in
-    [0, 2^40).  Outputs go to a ring of `ring_gib` GiB of device memory
+    [0, 2^40).  Latency runs from each request's scheduled arrival to its
+    completion.  Outputs go to a ring of `ring_gib` GiB of device memory
     (placed in arrival order, 256-byte aligned).  Reports completed
-    throughput, p50/p99 latency (submission to completion) and, when the
-    bulk cells were measured, the plain path's rate on the same mix."""
+    throughput (samples / span), p50/p99 latency overall and by size decade
+    and, when the bulk cells were measured, the plain path's rate on the
+    same mix."""
     import numpy as np
     ring_bytes = ring_gib << 30
     ring = torch.empty(ring_bytes, dtype=torch.uint8, device=dev)
@@ -216,25 +249,35 @@ def serve_leg(mr, synth, torch, dev, cells=None, duration_s=0.25, streams=4,
     def run(rate, count, k):
         tr, reqs = requests(rate, count, k)
         srv = mr.Server(streams=streams, capacity_bytes=capacity, max_batch=65536)
-        _, sub = srv.replay(reqs, tr.arrival_s)
+        tickets, sub = srv.replay(reqs, tr.arrival_s)
         srv.drain()
+        lat = np.array([srv.wait(int(x))[1] for x in tickets])
         st = srv.stats()
         srv.close()
         assert np.all(sub == 0) and st["failed"] == 0
-        return tr, st
+        return tr, st, lat
 
-    run(1e4, 200, 50)                      # warm-up: tables, staging memory
+    def pct(v, q):
+        v = np.sort(v)
+        return float(v[max(0, int(np.ceil(q * len(v))) - 1)])
+
+    run(1e4, 400, 50)                      # warm-up: tables, staging memory
     res = {}
-    for i, rate in enumerate((1e3, 1e4, 1e5)):
-        count = int(rate * duration_s)
-        tr, st = run(rate, count, 51 + i)
+    for i, (rate, count) in enumerate(zip((1e3, 1e4, 1e5), counts)):
+        tr, st, lat = run(rate, count, 51 + i)
         samples = int(tr.n.sum())
+        dec = np.floor(np.log10(tr.n)).astype(int)
+        by_dec = {f"1e{d}": {"requests": int((dec == d).sum()),
+                             "p50": round(pct(lat[dec == d], 0.5), 3),
+                             "p99": round(pct(lat[dec == d], 0.99), 3)}
+                  for d in range(3, 8) if (dec == d).any()}
         row = {"requests": count, "samples": samples,
                "offered_Gsamples_s": round(samples / max(tr.arrival_s[-1], 1e-9) / 1e9, 1),
                "served_Gsamples_s": round(st["samples"] / st["span_s"] / 1e9, 1),
                "latency_ms": {"p50": round(st["latency_p50_ms"], 3),
                               "p99": round(st["latency_p99_ms"], 3),
                               "max": round(st["latency_max_ms"], 3)},
+               "latency_ms_by_size_decade": by_dec,
                "batches": st["batches"], "span_s": round(st["span_s"], 4),
                "max_inflight_GB": round(st["max_inflight_bytes"] / 1e9, 2)}
         if cells:
@@ -242,11 +285,12 @@ def serve_leg(mr, synth, torch, dev, cells=None, duration_s=0.25, streams=4,
             for e, kd, n in zip(tr.engine, tr.kind, tr.n):
                 c = cells[f"{synth.ENGINE_NAME[int(e)]}/{synth.KIND_NAME[int(kd)]}"]
                 t_plain += float(n) / (c["Gsamples_s"] * 1e9)
-            row["plain_same_mix_Gsamples_s"] = round(samples / t_plain / 1e9, 1)
+            plain = samples / t_plain / 1e9
+            row["plain_same_mix_Gsamples_s"] = round(plain, 1)
+            row["served_over_plain"] = round(row["served_Gsamples_s"] / plain, 3)
         res[f"{int(rate)}_per_s"] = row
     del ring
-    return {"streams": streams, "capacity_GB": capacity / 1e9, "duration_s": duration_s,
-            "rates": res}
+    return {"streams": streams, "capacity_GB": capacity / 1e9, "rates": res}
 
 
 def main():
@@ -275,6 +319,11 @@ def main():
         e.generate(mr.UNIFORM_F32, n, out, stream=stream)
         return e
 
+    if args.shape:
+        blk, wpc, nt = (int(x) for x in args.shape.split(","))
+        mr.set_philox_config(walk=0, block=blk, waves_per_cu=wpc, blocks_per_lane=1,
+                             nontemporal=nt)
+
     if args.profile_batch:
         _, reqs, _, total = calo_requests(mr, synth, torch, dev)
         b = mr.Batcher()
@@ -297,6 +346,16 @@ def main():
         print(json.dumps({"profile": "philox uniform_f32 n=2^28 x5, then 1 GiB copy x3",
                           "config": mr.philox_config().as_dict()}), flush=True)
         return
+
+    # launch shape: the library's autotuner on this workload (outside the
+    # timed region; only speed depends on the shape)
+    tuned = None
+    if not args.shape and not args.no_tune:
+        t_tune = time.perf_counter()
+        cfg, tms = mr.autotune_philox(mr.UNIFORM_F32, n, out, stream=stream, prewarm_ms=300,
+                                      rounds=5, reps=10)
+        tuned = {"config": cfg.as_dict(), "ms": round(tms, 4),
+                 "tuning_s": round(time.perf_counter() - t_tune, 3)}
 
     # clock ramp: the first ~100 launches of a fresh process run ~15% slower
     t_pre = time.perf_counter()
@@ -421,10 +480,11 @@ def main():
         "roofline": roofline,
         "prewarm": prewarm,
         "philox_config": mr.philox_config().as_dict(),
+        "autotune": tuned,
     }
     line.update(extra)
     if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(seed, offset, n)
+        line["cpu_baseline"] = cpu_baseline(seed, offset, n, cells=None if args.quick else cells)
     print(json.dumps(line), flush=True)
 
 

@@ -35,7 +35,8 @@ Scheduler::~Scheduler()
     completer_.join();
 }
 
-mirng_status Scheduler::submit(const mirng_request &r, uint64_t *ticket)
+mirng_status Scheduler::submit(const mirng_request &r, uint64_t *ticket,
+                               const Clock::time_point *arrival)
 {
     const uint64_t bytes = request_bytes(r);
     std::lock_guard<std::mutex> lk(mu_);
@@ -45,13 +46,13 @@ mirng_status Scheduler::submit(const mirng_request &r, uint64_t *ticket)
         return MIRNG_E_CAPACITY;
     }
     Ticket t;
-    t.submitted = Clock::now();
+    t.submitted = arrival ? *arrival : Clock::now();
     t.bytes = bytes;
     t.n = r.n;
     const uint64_t id = tickets_.size();
     tickets_.push_back(t);
     waiting_.push_back({id, r});
-    if (!have_first_) {
+    if (!have_first_ || t.submitted < first_) {
         first_ = t.submitted;
         have_first_ = true;
     }

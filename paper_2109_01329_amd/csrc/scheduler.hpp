@@ -40,12 +40,18 @@ uint64_t request_bytes(const mirng_request &r);
 
 class Scheduler {
 public:
+    using Clock = std::chrono::steady_clock;
+
     Scheduler(Executor &ex, uint64_t capacity_bytes, size_t max_batch);
     ~Scheduler();   // finishes every accepted request, then stops
     Scheduler(const Scheduler &) = delete;
     Scheduler &operator=(const Scheduler &) = delete;
 
-    mirng_status submit(const mirng_request &r, uint64_t *ticket);
+    // `arrival` (default: now) is the time latency is measured from; an
+    // open-loop load generator passes the scheduled arrival, so that a late
+    // submission still counts against the latency.
+    mirng_status submit(const mirng_request &r, uint64_t *ticket,
+                        const Clock::time_point *arrival = nullptr);
     mirng_status poll(uint64_t ticket, int32_t *done, int32_t *status);
     mirng_status wait(uint64_t ticket, int32_t *status, double *latency_ms);
     void drain();
@@ -54,7 +60,6 @@ public:
     std::vector<std::vector<uint64_t>> batch_log();
 
 private:
-    using Clock = std::chrono::steady_clock;
     struct Ticket {
         Clock::time_point submitted;
         Clock::time_point finished;

@@ -162,7 +162,7 @@ mirng_status mirng_bench_server_replay(mirng_server s, const mirng_request *reqs
         while (Clock::now() < due) {
         }
         tickets[i] = ~0ull;
-        submit_status[i] = s->sched->submit(reqs[i], &tickets[i]);
+        submit_status[i] = s->sched->submit(reqs[i], &tickets[i], &due);
     }
     return MIRNG_OK;
 }
