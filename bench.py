@@ -293,6 +293,88 @@ def serve_leg(mr, synth, torch, dev, cells=None, counts=(2000, 20000, 20000), st
     return {"streams": streams, "capacity_GB": capacity / 1e9, "rates": res}
 
 
+def tts_leg(mr, torch, iters=100, decades=range(0, 9)):
+    """The paper's RNG burner on this GPU (Sec. 5.1, Sec. 6): per batch size
+    n = 10^0 .. 10^8, `iters` iterations of the whole flow, each timed on
+    the host clock: host and device allocation, generator construction and
+    seeding, Philox4x32-10 uniform FP32 generation, synchronisation, copy of
+    the output to host memory, release.  Run once with this library and once
+    with the installed rocRAND (public host API, as a black box), the
+    vendor-native side of the paper's comparison.  Also the device-only time
+    of the generation call (HIP events).  Reports medians in ms and the
+    ratio TTS_rocrand / TTS_mirng (above 1: this library is faster)."""
+    import ctypes
+    import numpy as np
+    hip = ctypes.CDLL("libamdhip64.so")     # the runtime torch has loaded
+    hip.hipMalloc.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_size_t]
+    hip.hipFree.argtypes = [ctypes.c_void_p]
+    hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+    hip.hipDeviceSynchronize.argtypes = []
+    D2H = 2
+    lib_path = "/opt/rocm/lib/librocrand.so"
+    vendor = ctypes.CDLL(lib_path) if os.path.exists(lib_path) else None
+    if vendor is not None:
+        vendor.rocrand_create_generator.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int]
+        vendor.rocrand_set_seed.argtypes = [ctypes.c_void_p, ctypes.c_ulonglong]
+        vendor.rocrand_generate_uniform.argtypes = [ctypes.c_void_p, ctypes.c_void_p,
+                                                    ctypes.c_size_t]
+        vendor.rocrand_destroy_generator.argtypes = [ctypes.c_void_p]
+    PHILOX_VENDOR = 404                       # ROCRAND_RNG_PSEUDO_PHILOX4_32_10
+
+    def flow_mirng(n):
+        host = np.empty(n, dtype=np.float32)
+        d = ctypes.c_void_p()
+        assert hip.hipMalloc(ctypes.byref(d), n * 4) == 0
+        e = mr.Engine(mr.PHILOX4X32_10, 1234, 0)
+        e.generate(mr.UNIFORM_F32, n, d.value)
+        assert hip.hipMemcpy(host.ctypes.data, d, n * 4, D2H) == 0
+        e.close()
+        hip.hipFree(d)
+        return host
+
+    def flow_vendor(n):
+        host = np.empty(n, dtype=np.float32)
+        d = ctypes.c_void_p()
+        assert hip.hipMalloc(ctypes.byref(d), n * 4) == 0
+        g = ctypes.c_void_p()
+        assert vendor.rocrand_create_generator(ctypes.byref(g), PHILOX_VENDOR) == 0
+        assert vendor.rocrand_set_seed(g, 1234) == 0
+        assert vendor.rocrand_generate_uniform(g, d, n) == 0
+        assert hip.hipMemcpy(host.ctypes.data, d, n * 4, D2H) == 0
+        vendor.rocrand_destroy_generator(g)
+        hip.hipFree(d)
+        return host
+
+    def tts(flow, n):
+        flow(n)
+        ts = []
+        for _ in range(iters if n < 10**7 else max(10, iters // 10)):
+            t0 = time.perf_counter()
+            flow(n)
+            ts.append((time.perf_counter() - t0) * 1e3)
+        return float(np.median(ts)), len(ts)
+
+    def device_only(n):
+        buf = torch.empty(max(n, 1), dtype=torch.float32, device="cuda")
+        s = torch.cuda.current_stream()
+        e = mr.Engine(mr.PHILOX4X32_10, 1234, 0)
+        e.generate(mr.UNIFORM_F32, n, buf, stream=s)
+        return time_kernel_calls(lambda: e.generate(mr.UNIFORM_F32, n, buf, stream=s), 20, s)[1]
+
+    rows = {}
+    for dcd in decades:
+        n = 10 ** dcd
+        ours, k = tts(flow_mirng, n)
+        row = {"tts_ms_mirng": round(ours, 4), "iterations": k,
+               "device_ms_mirng": round(device_only(n), 4)}
+        if vendor is not None:
+            theirs, _ = tts(flow_vendor, n)
+            row["tts_ms_rocrand"] = round(theirs, 4)
+            row["rocrand_over_mirng"] = round(theirs / ours, 3)
+        rows[f"1e{dcd}"] = row
+    return rows
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -458,6 +540,7 @@ def main():
         del big, buf
         extra["batched"] = calo_batch_leg(mr, synth, torch, stream, dev)
         extra["serving"] = serve_leg(mr, synth, torch, dev, cells=res)
+        extra["burner_tts"] = tts_leg(mr, torch)
 
     line = {
         "metric": "Gsamples/s + HBM write GB/s (% peak), Philox FP32 uniform n=2^28; batched p99 ms",
