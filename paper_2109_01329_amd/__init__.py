@@ -291,15 +291,58 @@ def set_philox_config(c: PhiloxConfig | None = None, **fields) -> PhiloxConfig:
     return prev
 
 
+class TuningCache:
+    """Tuned launch shapes in a JSON file, keyed by GPU architecture, engine,
+    distribution and size class (the bit length of the output count), so
+    that a process can reuse a shape timed earlier instead of re-timing."""
+
+    def __init__(self, path: str):
+        import json
+        self.path = path
+        self.entries = {}
+        if os.path.exists(path):
+            with open(path) as f:
+                self.entries = json.load(f)
+
+    def get(self, key: str):
+        return self.entries.get(key)
+
+    def put(self, key: str, value: dict) -> None:
+        import json
+        self.entries[key] = value
+        tmp = self.path + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(self.entries, f, indent=1, sort_keys=True)
+        os.replace(tmp, self.path)
+
+
+def _arch() -> str:
+    import torch
+    return torch.cuda.get_device_properties(torch.cuda.current_device()).gcnArchName.split(":")[0]
+
+
+def size_class(n: int) -> int:
+    return int(n).bit_length()
+
+
 def autotune_philox(kind: int, n: int, out, stream=None, prewarm_ms: int = 300,
-                    rounds: int = 5, reps: int = 10):
+                    rounds: int = 5, reps: int = 10, cache: TuningCache | None = None):
     """Time the candidate Philox launch shapes on `n` outputs of `kind` into
-    `out` (overwritten), install the fastest and return (shape, ms)."""
+    `out` (overwritten), install the fastest and return (shape, ms).  With a
+    cache, a shape stored for the same architecture, kind and size class is
+    installed without timing, and a newly timed one is stored."""
+    key = f"{_arch()}/philox4x32_10/{kind}/{size_class(n)}" if cache is not None else None
+    if key is not None and cache.get(key) is not None:
+        hit = cache.get(key)
+        set_philox_config(**hit["config"])
+        return philox_config(), float(hit["ms"])
     c = PhiloxConfig()
     ms = ctypes.c_float()
     _check(lib().mirng_autotune_philox(kind, n, _ptr(out), _stream(stream), prewarm_ms, rounds,
                                        reps, ctypes.byref(c), ctypes.byref(ms)),
            "autotune_philox")
+    if key is not None:
+        cache.put(key, {"config": c.as_dict(), "ms": float(ms.value)})
     return c, float(ms.value)
 
 
@@ -357,16 +400,28 @@ class Batcher:
                "generate_batch")
 
     def autotune(self, reqs, stream=None, prewarm_ms: int = 300, rounds: int = 5,
-                 reps: int = 10):
+                 reps: int = 10, cache: TuningCache | None = None):
         """Time the candidate batch launch shapes on this batch (its outputs
-        are overwritten), install the fastest and return (shape, ms)."""
+        are overwritten), install the fastest and return (shape, ms).  With a
+        cache, keyed by architecture and the size classes of the request
+        count and of the total output count."""
         import numpy as np
         reqs = np.ascontiguousarray(reqs, dtype=request_dtype())
+        key = None
+        if cache is not None:
+            key = (f"{_arch()}/batch/{size_class(len(reqs))}/"
+                   f"{size_class(int(reqs['n'].sum()))}")
+            hit = cache.get(key)
+            if hit is not None:
+                self.set_config(**hit["config"])
+                return self.config, float(hit["ms"])
         c = BatchConfig()
         ms = ctypes.c_float()
         _check(lib().mirng_autotune_batch(self._h, reqs.ctypes.data, len(reqs), _stream(stream),
                                           prewarm_ms, rounds, reps, ctypes.byref(c),
                                           ctypes.byref(ms)), "autotune_batch")
+        if key is not None:
+            cache.put(key, {"config": c.as_dict(), "ms": float(ms.value)})
         return c, float(ms.value)
 
     def statuses(self, count: int):

@@ -221,3 +221,13 @@ def test_autotune_argument_validation(L):
     assert L.mirng_autotune_batch(b._h, reqs.ctypes.data, 0, None, 0, 1, 1, None, None) == 1
     assert L.mirng_autotune_batch(b._h, reqs.ctypes.data, 2, None, 0, 65, 1,
                                   ctypes.byref(bc), None) == 1
+
+
+def test_tuning_cache_round_trip(tmp_path):
+    path = str(tmp_path / "tune.json")
+    c = mr.TuningCache(path)
+    assert c.get("gfx950/philox4x32_10/2/29") is None
+    c.put("gfx950/philox4x32_10/2/29", {"config": {"walk": 0, "block": 1024}, "ms": 0.17})
+    c2 = mr.TuningCache(path)
+    assert c2.get("gfx950/philox4x32_10/2/29")["ms"] == 0.17
+    assert mr.size_class(1 << 28) == 29 and mr.size_class(1) == 1

@@ -45,3 +45,24 @@ def test_autotune_batch_keeps_outputs():
     host, st = _run(reqs, layout, nbytes, batcher=b)
     assert np.all(st == 0)
     _check_outputs(host, layout, st)
+
+
+def test_autotune_cache_hit_installs_stored_shape(tmp_path):
+    import time
+    import torch
+    n = 1 << 20
+    prev = mr.philox_config()
+    try:
+        cache = mr.TuningCache(str(tmp_path / "tune.json"))
+        buf = torch.empty(n, dtype=torch.float32, device="cuda")
+        cfg, ms = mr.autotune_philox(mr.UNIFORM_F32, n, buf, prewarm_ms=20, rounds=1, reps=2,
+                                     cache=cache)
+        mr.set_philox_config(walk=1, block=256, waves_per_cu=8, blocks_per_lane=1,
+                             nontemporal=0)
+        t0 = time.perf_counter()
+        cfg2, ms2 = mr.autotune_philox(mr.UNIFORM_F32, n, buf, cache=mr.TuningCache(cache.path))
+        assert time.perf_counter() - t0 < 0.2          # no timing loop ran
+        assert cfg2.as_dict() == cfg.as_dict() == mr.philox_config().as_dict()
+        assert ms2 == ms
+    finally:
+        mr.set_philox_config(prev)
