@@ -283,7 +283,10 @@ mirng_status mirng_philox_config_set(const mirng_philox_config *c);
  * (MIRNG_E_CAPACITY).  A batch holds at most max_batch requests.  Each
  * request is validated by the batched kernel, as in mirng_generate_batch,
  * and its final status is that request's status.  The caller owns the
- * output memory and must keep it valid until the request completes. */
+ * output memory and must keep it valid until the request completes.
+ * Tickets (about 64 bytes of host memory each) are kept for the server's
+ * lifetime, so that any ticket can be polled and the statistics cover
+ * every request. */
 
 typedef struct mirng_server_s *mirng_server;
 

@@ -26,9 +26,37 @@ __device__ __forceinline__ double u01d(uint32_t lo, uint32_t hi)
     return __builtin_fma((double)hi, 0x1p-32, (double)(lo >> 11) * 0x1p-53);
 }
 
+// 1/d for d in [1.7, 2.5]: the hardware estimate refined by two Newton
+// steps (each squares the relative error; the result is within a few ulp).
+__device__ __forceinline__ double recip_fast(double d)
+{
+    double r = __builtin_amdgcn_rcp(d);
+    double e = __builtin_fma(-d, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    e = __builtin_fma(-d, r, 1.0);
+    return __builtin_fma(r, e, r);
+}
+
+// sqrt(x) for x in [0, 34] as x * (1 / sqrt(x)): the hardware reciprocal square
+// root of max(x, 2^-100) refined by two Newton steps, so x = 0 gives 0.
+__device__ __forceinline__ double sqrt_fast(double x)
+{
+    const double xs = __builtin_fmax(x, 0x1p-100);
+    const double h = 0.5 * xs;
+    double y = __builtin_amdgcn_rsq(xs);
+    double e = __builtin_fma(-h * y, y, 0.5);
+    y = __builtin_fma(y, e, y);
+    e = __builtin_fma(-h * y, y, 0.5);
+    y = __builtin_fma(y, e, y);
+    return x * y;
+}
+
 // Box-Muller on one word pair.  The radius and the rotation are evaluated
 // in FP64 to about 2^-34 relative error and rounded once to FP32, so each
 // output is within 0.51 ulp of the exact transform of the same two inputs.
+// The one division and the square root use refined hardware estimates
+// (recip_fast, sqrt_fast) instead of the IEEE sequences, whose exactness
+// this accuracy does not need.
 //   ln u1: u1 = 2^e m, m in [sqrt(1/2), sqrt(2)), ln m = 2 atanh(s) with
 //          s = (m - 1)/(m + 1), |s| <= 0.1716, series to s^11.
 //   sin/cos(2 pi u2): 2 u2 = k 2^-23; j = nearest quarter turn; the exact
@@ -43,7 +71,7 @@ __device__ __forceinline__ f32x2 box_muller(uint32_t wa, uint32_t wb)
     m = low ? m * 2.0 : m;
     e = low ? e - 1 : e;
     const double f = m - 1.0;
-    const double s = f / (m + 1.0);
+    const double s = f * recip_fast(m + 1.0);
     const double s2 = s * s;
     double q = 0x1.745d1745d1746p-4;               // 1/11
     q = __builtin_fma(q, s2, 0x1.c71c71c71c71cp-4); // 1/9
@@ -53,7 +81,7 @@ __device__ __forceinline__ f32x2 box_muller(uint32_t wa, uint32_t wb)
     q = __builtin_fma(q, s2, 1.0);
     const double ln_m = 2.0 * s * q;
     const double ln_u1 = __builtin_fma((double)e, 0x1.62e42fefa39efp-1, ln_m);
-    const double r = __builtin_sqrt(-2.0 * ln_u1);
+    const double r = sqrt_fast(-2.0 * ln_u1);
 
     const uint32_t k = wb >> 8;
     const uint32_t j = (k + (1u << 21)) >> 22;     // 0..4
