@@ -60,6 +60,10 @@ def parse():
     p.add_argument("--profile", action="store_true",
                    help="for rocprofv3: 5 headline generate launches, then 3 device copies of "
                         "1 GiB (a plain copy kernel of known size for counter calibration)")
+    p.add_argument("--profile-cells", action="store_true",
+                   help="for rocprofv3 counters: every bulk cell and the substream cell, one "
+                        "warm-up and one measured launch each, then the VALU-rate probe "
+                        "(known instruction count) for calibration")
     p.add_argument("--profile-batch", action="store_true",
                    help="for rocprofv3: the calorimeter batch (default launch shape), 25 "
                         "batches in a row")
@@ -405,6 +409,27 @@ def main():
         blk, wpc, nt = (int(x) for x in args.shape.split(","))
         mr.set_philox_config(walk=0, block=blk, waves_per_cu=wpc, blocks_per_lane=1,
                              nontemporal=nt)
+
+    if args.profile_cells:
+        big = torch.empty(n * 2, dtype=torch.float32, device=dev)
+        order = []
+        for engine, kind, s, o in cells:
+            for _ in range(2):
+                mr.Engine(engine, s, o).generate(kind, n, big, stream=stream)
+            order.append(f"{synth.ENGINE_NAME[engine]}/{synth.KIND_NAME[kind]}")
+        cfg = synth.SUBSTREAMS
+        for _ in range(2):
+            mr.Engine(mr.MRG32K3A, synth.substream_seed(), 0).generate_substreams(
+                mr.UNIFORM_F64, 0, cfg["count"], cfg["per_stream"], big, stream=stream)
+        order.append("mrg32k3a/substreams_65536x4096_f64")
+        vsink = torch.empty(256 * 4096, dtype=torch.int32, device=dev)
+        for _ in range(2):
+            mr.bench_valu(4, 256 * 4096, 256, vsink, stream)
+        order.append("valu probe fma_f32: 1048576 lanes x 256 iterations x 8 FMAs")
+        stream.synchronize()
+        print(json.dumps({"profile": "cells, two launches each (warm-up, measured)",
+                          "order": order, "config": mr.philox_config().as_dict()}), flush=True)
+        return
 
     if args.profile_batch:
         _, reqs, _, total = calo_requests(mr, synth, torch, dev)

@@ -143,3 +143,29 @@ def test_outputs_invariant_under_launch_shape(cfg):
                     assert gh.guards_intact(buf, off, n * mr.ELEM_BYTES[kind])
     finally:
         mr.set_philox_config(prev)
+
+
+AUTOTUNE_CANDIDATES = (
+    [dict(walk=0, block=b, waves_per_cu=w, blocks_per_lane=1, nontemporal=nt)
+     for b in (256, 512, 1024) for w in (64, 128, 256, 512, 1024) for nt in (0, 1)]
+    + [dict(walk=1, block=256, waves_per_cu=8, blocks_per_lane=bpl, nontemporal=0)
+       for bpl in (1, 2)])
+
+
+def test_outputs_invariant_under_every_autotuner_candidate():
+    """The autotuner may install any of its candidate shapes: each gives the
+    oracle's values (uniform FP32 at an odd phase and Gaussians at an even
+    one, misaligned outputs)."""
+    n = 65537
+    want_u = gh.oracle_philox(7, 2**33 + 1, mr.UNIFORM_F32, n)
+    want_g = gh.oracle_philox(7, 2, mr.GAUSSIAN_F32, n)
+    prev = mr.philox_config()
+    try:
+        for cfg in AUTOTUNE_CANDIDATES:
+            mr.set_philox_config(**cfg)
+            got, _ = gh.generate(mr.Engine(mr.PHILOX4X32_10, 7, 2**33 + 1), mr.UNIFORM_F32, n, 4)
+            gh.assert_match(mr.UNIFORM_F32, got, want_u)
+            got, _ = gh.generate(mr.Engine(mr.PHILOX4X32_10, 7, 2), mr.GAUSSIAN_F32, n, 8)
+            gh.assert_match(mr.GAUSSIAN_F32, got, want_g)
+    finally:
+        mr.set_philox_config(prev)
