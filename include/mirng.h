@@ -179,6 +179,18 @@ mirng_status mirng_generate_substreams(mirng_engine e,
                                        uint64_t n_each, void *out,
                                        void *stream);
 
+/* MRG32k3a streams: as mirng_generate_substreams with streams 2^127 steps
+ * apart (L'Ecuyer et al., Oper. Res. 2002: streams of 2^51 substreams of
+ * 2^76 steps).  Stream s starts 2^127 * s steps past the engine's current
+ * state; combine with mirng_skip_ahead_multi (2^76 * j) on a copy of the
+ * engine to reach substream j of a stream.  Same arguments, limits and
+ * errors. */
+mirng_status mirng_generate_streams(mirng_engine e,
+                                    const mirng_distribution *d,
+                                    uint64_t first, uint64_t count,
+                                    uint64_t n_each, void *out,
+                                    void *stream);
+
 /* --------------------------------------------------------------- batching */
 
 /* Batched generation: thousands of independent requests of uneven sizes in

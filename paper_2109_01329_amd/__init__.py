@@ -129,6 +129,8 @@ def lib() -> ctypes.CDLL:
         "mirng_generate": ([E, ctypes.POINTER(Distribution), u64, vp, vp], ctypes.c_int),
         "mirng_generate_substreams": ([E, ctypes.POINTER(Distribution), u64, u64, u64, vp, vp],
                                       ctypes.c_int),
+        "mirng_generate_streams": ([E, ctypes.POINTER(Distribution), u64, u64, u64, vp, vp],
+                                   ctypes.c_int),
         "mirng_status_string": ([ctypes.c_int], ctypes.c_char_p),
         "mirng_philox_config_get": ([ctypes.POINTER(PhiloxConfig)], ctypes.c_int),
         "mirng_philox_config_set": ([ctypes.POINTER(PhiloxConfig)], ctypes.c_int),
@@ -272,6 +274,15 @@ class Engine:
         _check(lib().mirng_generate_substreams(self._h, ctypes.byref(d), first, count, n_each,
                                                _ptr(out), _stream(stream)),
                "generate_substreams")
+
+    def generate_streams(self, kind: int, first: int, count: int, n_each: int, out,
+                         p0: float | None = None, p1: float | None = None,
+                         stream=None) -> None:
+        """As generate_substreams with streams 2^127 steps apart."""
+        d = distribution(kind, p0, p1)
+        _check(lib().mirng_generate_streams(self._h, ctypes.byref(d), first, count, n_each,
+                                            _ptr(out), _stream(stream)),
+               "generate_streams")
 
 
 def philox_config() -> PhiloxConfig:

@@ -242,9 +242,10 @@ using namespace mirng;
 namespace mirng {
 hipError_t mrg_plain(const uint32_t st[6], const mirng_distribution *d, uint64_t n,
                      char *out, hipStream_t s);
+// spacing_log2: 76 (substreams) or 127 (streams), L'Ecuyer et al. 2002.
 hipError_t mrg_substreams(const uint32_t st[6], const mirng_distribution *d,
                           uint64_t first, uint64_t count, uint64_t n_each, char *out,
-                          hipStream_t s);
+                          hipStream_t s, int spacing_log2);
 }  // namespace mirng
 
 extern "C" {
@@ -392,9 +393,10 @@ mirng_status mirng_generate(mirng_engine e, const mirng_distribution *d, uint64_
     return err == hipSuccess ? MIRNG_OK : MIRNG_E_LAUNCH;
 }
 
-mirng_status mirng_generate_substreams(mirng_engine e, const mirng_distribution *d,
-                                       uint64_t first, uint64_t count, uint64_t n_each,
-                                       void *out, void *stream)
+namespace {
+
+mirng_status spaced(mirng_engine e, const mirng_distribution *d, uint64_t first,
+                    uint64_t count, uint64_t n_each, void *out, void *stream, int log2)
 {
     if (!e || !d) return MIRNG_E_INVALID_ARG;
     if (e->type != MIRNG_MRG32K3A) return MIRNG_E_UNSUPPORTED;
@@ -407,8 +409,24 @@ mirng_status mirng_generate_substreams(mirng_engine e, const mirng_distribution 
         return MIRNG_E_INVALID_ARG;
     if (ensure_device(nullptr) != hipSuccess) return MIRNG_E_DEVICE;
     hipError_t err = mrg_substreams(e->st, d, first, count, n_each, (char *)out,
-                                    (hipStream_t)stream);
+                                    (hipStream_t)stream, log2);
     return err == hipSuccess ? MIRNG_OK : MIRNG_E_LAUNCH;
+}
+
+}  // namespace
+
+mirng_status mirng_generate_substreams(mirng_engine e, const mirng_distribution *d,
+                                       uint64_t first, uint64_t count, uint64_t n_each,
+                                       void *out, void *stream)
+{
+    return spaced(e, d, first, count, n_each, out, stream, 76);
+}
+
+mirng_status mirng_generate_streams(mirng_engine e, const mirng_distribution *d,
+                                    uint64_t first, uint64_t count, uint64_t n_each,
+                                    void *out, void *stream)
+{
+    return spaced(e, d, first, count, n_each, out, stream, 127);
 }
 
 }  // extern "C"

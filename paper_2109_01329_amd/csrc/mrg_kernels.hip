@@ -135,7 +135,7 @@ struct DeviceTables {
 
 std::mutex g_tab_mu;
 std::map<std::pair<int, uint32_t>, DeviceTables> g_q_tables;
-std::map<int, uint32_t *> g_sub_tables;
+std::map<std::pair<int, int>, uint32_t *> g_sub_tables;   // (device, log2 spacing)
 
 hipError_t upload(const std::vector<uint32_t> &h, uint32_t **d)
 {
@@ -178,23 +178,22 @@ hipError_t tables_for(int dev, uint32_t q, DeviceTables &out)
     return hipSuccess;
 }
 
-hipError_t substream_table(int dev, uint32_t **out)
+// Digit tables A^(k 64^d 2^e), d < 5, for substreams (e = 76) or streams
+// (e = 127) spaced 2^e steps apart.
+hipError_t spacing_table(int dev, int e, uint32_t **out)
 {
     std::lock_guard<std::mutex> lk(g_tab_mu);
-    auto it = g_sub_tables.find(dev);
+    auto it = g_sub_tables.find({dev, e});
     if (it != g_sub_tables.end()) {
         *out = it->second;
         return hipSuccess;
     }
     std::vector<uint32_t> s((size_t)kSDigits * 64 * kMatWords);
-    for (int d = 0; d < kSDigits; ++d) {
-        const int e = 76 + 6 * d;   // 64^d * 2^76
-        digit_row(s, d, mrg_pow2(0, e), mrg_pow2(1, e));
-    }
+    for (int d = 0; d < kSDigits; ++d) digit_row(s, d, mrg_pow2(0, e + 6 * d), mrg_pow2(1, e + 6 * d));
     uint32_t *ptr = nullptr;
     hipError_t err = upload(s, &ptr);
     if (err != hipSuccess) return err;
-    g_sub_tables[dev] = ptr;
+    g_sub_tables[{dev, e}] = ptr;
     *out = ptr;
     return hipSuccess;
 }
@@ -242,7 +241,7 @@ void fill_params(MrgLaunch &a, const mirng_distribution *d)
 }
 
 hipError_t run(const uint32_t st[6], const mirng_distribution *d, uint64_t s_first,
-               uint64_t nsub, bool use_sub, uint64_t n_each, char *out, hipStream_t s)
+               uint64_t nsub, int spacing_log2, uint64_t n_each, char *out, hipStream_t s)
 {
     int dev = 0;
     hipError_t err = hipGetDevice(&dev);
@@ -251,9 +250,10 @@ hipError_t run(const uint32_t st[6], const mirng_distribution *d, uint64_t s_fir
     DeviceTables tb;
     err = tables_for(dev, q, tb);
     if (err != hipSuccess) return err;
+    const bool use_sub = spacing_log2 > 0;
     uint32_t *stab = nullptr;
     if (use_sub) {
-        err = substream_table(dev, &stab);
+        err = spacing_table(dev, spacing_log2, &stab);
         if (err != hipSuccess) return err;
     }
     MrgLaunch a{};
@@ -318,15 +318,16 @@ hipError_t mrg_batch_tables(int dev, MrgBatchTables &t)
 hipError_t mrg_plain(const uint32_t st[6], const mirng_distribution *d, uint64_t n,
                      char *out, hipStream_t s)
 {
-    return run(st, d, 0, 1, false, n, out, s);
+    return run(st, d, 0, 1, 0, n, out, s);
 }
 
 hipError_t mrg_substreams(const uint32_t st[6], const mirng_distribution *d,
                           uint64_t first, uint64_t count, uint64_t n_each, char *out,
-                          hipStream_t s)
+                          hipStream_t s, int spacing_log2)
 {
     if (first + count > (1ull << (6 * kSDigits))) return hipErrorInvalidValue;
-    return run(st, d, first, count, true, n_each, out, s);
+    if (spacing_log2 != 76 && spacing_log2 != 127) return hipErrorInvalidValue;
+    return run(st, d, first, count, spacing_log2, n_each, out, s);
 }
 
 }  // namespace mirng

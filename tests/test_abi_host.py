@@ -155,6 +155,11 @@ def test_substream_validation(L):
     assert L.mirng_generate_substreams(m.handle, ctypes.byref(d), 2**30, 1, 16, 0x10000,
                                        None) == 1
     assert L.mirng_generate_substreams(m.handle, ctypes.byref(d), 0, 0, 16, None, None) == 0
+    assert L.mirng_generate_streams(p.handle, ctypes.byref(d), 0, 4, 16, 0x10000, None) == 2
+    assert L.mirng_generate_streams(m.handle, ctypes.byref(d), 0, 4, 16, None, None) == 1
+    assert L.mirng_generate_streams(m.handle, ctypes.byref(d), 2**30 - 1, 2, 16, 0x10000,
+                                    None) == 1
+    assert L.mirng_generate_streams(m.handle, ctypes.byref(d), 0, 4, 16, 0x10004, None) == 1
 
 
 def test_philox_config_validation():

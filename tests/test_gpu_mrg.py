@@ -97,3 +97,29 @@ def test_substreams_ragged(kind, first, count, n_each, off):
         st = oracle.mrg_skip(st0, (first + i) << 76)
         gh.assert_match(kind, got[i * n_each:(i + 1) * n_each], gh.oracle_mrg(st, kind, n_each))
     assert gh.guards_intact(buf, off, count * n_each * esz)
+
+
+@pytest.mark.parametrize("kind,first,count,n_each,off", [
+    (mr.UNIFORM_F64, 0, 5, 4097, 8), (mr.BITS_U32, 2**30 - 3, 3, 1000, 4),
+    (mr.GAUSSIAN_F32, 77, 2, 12345, 0)])
+def test_streams_2p127(kind, first, count, n_each, off):
+    """Streams 2^127 steps apart equal the oracle's jump by s * 2^127 (its
+    polynomial method, a different algorithm from the library's tables);
+    substream j of stream s is reached by a further jump of 2^76 j."""
+    esz = mr.ELEM_BYTES[kind]
+    e = mr.Engine(mr.MRG32K3A, 0xDEADBEEF12345678, 31)
+    buf = gh.device_buffer(count * n_each * esz + off + 64)
+    buf.fill_(0xA5)
+    e.generate_streams(kind, first, count, n_each, int(buf.data_ptr()) + off)
+    got = gh.fetch(buf, off, kind, count * n_each)
+    st0 = oracle.mrg_skip(oracle.mrg_seed(0xDEADBEEF12345678), 31)
+    for i in range(count):
+        st = oracle.mrg_skip(st0, (first + i) << 127)
+        gh.assert_match(kind, got[i * n_each:(i + 1) * n_each], gh.oracle_mrg(st, kind, n_each))
+    assert gh.guards_intact(buf, off, count * n_each * esz)
+    # substream 3 of stream `first`: skip 2^127 first + 2^76 3, then plain
+    e2 = mr.Engine(mr.MRG32K3A, 0xDEADBEEF12345678, 31)
+    e2.skip_ahead((first << 127) + (3 << 76))
+    got2, _ = gh.generate(e2, kind, 999)
+    gh.assert_match(kind, got2, gh.oracle_mrg(oracle.mrg_skip(st0, (first << 127) + (3 << 76)),
+                                              kind, 999))
