@@ -85,3 +85,29 @@ def test_bulk_cell(engine, kind, seed, offset):
     if kind == mr.GAUSSIAN_F32:
         assert abs(float(out.double().mean())) < 6 / N**0.5
         assert abs(float(out.double().var()) - 1.0) < 6 * (2 / N) ** 0.5
+
+
+@pytest.mark.parametrize("engine,kind,seed,offset", [
+    (mr.PHILOX4X32_10, mr.UNIFORM_F32, 0x0123456789ABCDEF, 2**40 + 1),
+    (mr.PHILOX4X32_10, mr.GAUSSIAN_F32, 77, 3),
+    (mr.MRG32K3A, mr.BITS_U32, 0xFEDCBA9876543210, 12345)])
+def test_beyond_2p32_outputs(engine, kind, seed, offset):
+    """One generate of 2^32 + 2^20 + 7 outputs (beyond a single Philox launch
+    of 2^32, and 17 GB): windows at the head, across 2^32 and at the tail
+    equal the oracle, and the engine advanced by the words consumed."""
+    import torch
+    n = (1 << 32) + (1 << 20) + 7
+    esz = mr.ELEM_BYTES[kind]
+    buf = torch.empty(n * esz // 4 + 64, dtype=torch.int32, device="cuda")
+    e = mr.Engine(engine, seed, offset)
+    e.generate(kind, n, buf)
+    torch.cuda.synchronize()
+    raw = buf.view(torch.uint8)
+    for start in (0, (1 << 32) - 4098, n - 4096):
+        start -= start % 2
+        m = min(8192, n - start)
+        got = raw[start * esz: (start + m) * esz].cpu().numpy().view(gh.NP_DTYPE[kind])
+        gh.assert_match(kind, got, _expect_window(engine, kind, seed, offset, start, m))
+    assert e.position() == offset + mr.words_consumed(engine, kind, n)
+    del buf, raw
+    torch.cuda.empty_cache()
