@@ -27,7 +27,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-BITS_U32, UNIFORM_F32, UNIFORM_F64, GAUSSIAN_F32 = 1, 2, 3, 4
+BITS_U32, UNIFORM_F32, UNIFORM_F64, GAUSSIAN_F32, GAUSSIAN_F64 = 1, 2, 3, 4, 5
 PHILOX, MRG = 1, 2
 
 _u32p = ctypes.POINTER(ctypes.c_uint32)
@@ -79,6 +79,11 @@ def lib() -> ctypes.CDLL:
         L.orc_box_muller.argtypes = [ctypes.c_uint32, ctypes.c_uint32,
                                      ctypes.POINTER(ctypes.c_double),
                                      ctypes.POINTER(ctypes.c_double)]
+        L.orc_box_muller64.argtypes = [ctypes.c_double, ctypes.c_double,
+                                       ctypes.POINTER(ctypes.c_double),
+                                       ctypes.POINTER(ctypes.c_double)]
+        L.orc_gauss64_uniforms.argtypes = [ctypes.c_int, _u32p, ctypes.POINTER(ctypes.c_double),
+                                           ctypes.POINTER(ctypes.c_double)]
         L.orc_apply.argtypes = [ctypes.c_int, ctypes.c_int, _u32p, ctypes.c_uint64,
                                 ctypes.c_double, ctypes.c_double, ctypes.c_void_p]
         L.orc_words_consumed.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_uint64]
@@ -109,7 +114,7 @@ def _ptr(a: np.ndarray, typ):
 
 
 OUT_DTYPE = {BITS_U32: np.uint32, UNIFORM_F32: np.float32,
-             UNIFORM_F64: np.float64, GAUSSIAN_F32: np.float64}
+             UNIFORM_F64: np.float64, GAUSSIAN_F32: np.float64, GAUSSIAN_F64: np.float64}
 
 PHILOX_POS_MOD = 1 << 130
 
@@ -249,6 +254,23 @@ def box_muller(w_a: int, w_b: int):
     z0, z1 = ctypes.c_double(), ctypes.c_double()
     lib().orc_box_muller(w_a, w_b, ctypes.byref(z0), ctypes.byref(z1))
     return z0.value, z1.value
+
+
+def box_muller64(u1: float, u2: float):
+    """Gaussian FP64 pair from FP64 uniforms (R21)."""
+    z0, z1 = ctypes.c_double(), ctypes.c_double()
+    lib().orc_box_muller64(u1, u2, ctypes.byref(z0), ctypes.byref(z1))
+    return z0.value, z1.value
+
+
+def gauss64_uniforms(engine: int, words) -> tuple:
+    """The (u1, u2) of one Gaussian FP64 pair: four Philox words or two MRG
+    outputs (R21)."""
+    w = np.ascontiguousarray(words, dtype=np.uint32)
+    u1, u2 = ctypes.c_double(), ctypes.c_double()
+    lib().orc_gauss64_uniforms(1 if engine == MRG else 0, _ptr(w, _u32p), ctypes.byref(u1),
+                               ctypes.byref(u2))
+    return u1.value, u2.value
 
 
 def box_muller_factors(words: np.ndarray):

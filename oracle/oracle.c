@@ -284,7 +284,7 @@ void orc_mrg_skip(uint64_t st[6], const uint64_t n[3])
  * Distributions (readings R10-R16).  Kinds match the library's numbering:
  * 1 = raw 32-bit words, 2 = uniform FP32, 3 = uniform FP64,
  * 4 = Gaussian (returned here as the FP64 transform; the library's FP32
- * result must be within 2 ulp of it).
+ * result must be within 2 ulp of it), 5 = Gaussian FP64 (R21).
  * ---------------------------------------------------------------------- */
 
 /* R10: u = (w >> 8) * 2^-24, exact, in [0, 1 - 2^-24]. */
@@ -354,6 +354,35 @@ void orc_box_muller(uint32_t w_a, uint32_t w_b, double *z0, double *z1)
     *z1 = r * s;
 }
 
+/* Gaussian FP64 (R21): Box-Muller ([BM58]) on a pair of FP64 uniforms,
+ * u1 in (0, 1] and u2 in [0, 1), evaluated with libm in FP64:
+ * r = sqrt(-2 ln u1), z0 = r cos(2 pi u2), z1 = r sin(2 pi u2).
+ * Pinned by: mpmath at 50 digits, special cases, moments (tests/). */
+void orc_box_muller64(double u1, double u2, double *z0, double *z1)
+{
+    double r = sqrt(-2.0 * log(u1));
+    double s, c;
+    sincospi_exact(2.0 * u2, &s, &c);
+    *z0 = r * c;
+    *z1 = r * s;
+}
+
+/* The FP64 uniform pair of a Gaussian FP64 output pair (R21).  Philox: four
+ * words; u1 = (v_a + 1) 2^-53 with v_a the 53 bits of (w0, w1) (first word
+ * low, as for uniform FP64), u2 = v_b 2^-53 from (w2, w3).  MRG: two
+ * outputs y_a, y_b; u1 = y_a / (m1 + 1), u2 = y_b / (m1 + 1), each one
+ * multiply by the rounded scale (as for uniform FP64). */
+void orc_gauss64_uniforms(int mrg, const uint32_t *w, double *u1, double *u2)
+{
+    if (mrg) {
+        *u1 = orc_u01_f64_mrg(w[0]);
+        *u2 = orc_u01_f64_mrg(w[1]);
+    } else {
+        *u1 = orc_u01_f64_words(w[0], w[1]) + 0x1p-53;
+        *u2 = orc_u01_f64_words(w[2], w[3]);
+    }
+}
+
 /* Apply a distribution to a word stream (kind numbering above).  For the
  * Philox engine U-F64 takes two words per output; for MRG one (R11).
  * Gaussian pairs use words (2j, 2j+1); odd n discards the last z1 (R14).
@@ -391,18 +420,32 @@ void orc_apply(int kind, int mrg, const uint32_t *w, uint64_t n,
         }
         break;
     }
+    case 5: {
+        /* pair j uses words 4j .. 4j + 3 (Philox) or outputs 2j, 2j + 1 (MRG) */
+        double *o = (double *)out;
+        for (i = 0; i < n; i += 2) {
+            double u1, u2, z0, z1;
+            orc_gauss64_uniforms(mrg, w + (mrg ? i : 2 * i), &u1, &u2);
+            orc_box_muller64(u1, u2, &z0, &z1);
+            o[i] = z0 * p1 + p0;
+            if (i + 1 < n) o[i + 1] = z1 * p1 + p0;
+        }
+        break;
+    }
     default:
         break;
     }
 }
 
 /* Number of engine words (Philox) or steps (MRG) that n outputs consume
- * (R14): U-F64 on Philox takes 2 per output, Gaussian 2 per started pair,
+ * (R14, R21): U-F64 on Philox takes 2 per output, Gaussian FP32 2 per
+ * started pair, Gaussian FP64 4 (Philox) or 2 (MRG) per started pair,
  * everything else 1. */
 uint64_t orc_words_consumed(int kind, int mrg, uint64_t n)
 {
     if (kind == 3) return mrg ? n : 2 * n;
     if (kind == 4) return 2 * ((n + 1) / 2);
+    if (kind == 5) return (mrg ? 2 : 4) * ((n + 1) / 2);
     return n;
 }
 

@@ -174,3 +174,111 @@ def test_gaussian_mean_sd(orc):
     z = orc.philox_generate(3, 0, orc.GAUSSIAN_F32, 64)
     y = orc.philox_generate(3, 0, orc.GAUSSIAN_F32, 64, 2.5, 0.5)
     assert np.array_equal(y, z * 0.5 + 2.5)
+
+
+# ---------------------------------------------------------------- Gaussian FP64 (R21)
+
+def _ulp64(x):
+    x = abs(float(x))
+    if x == 0.0:
+        return 2.0**-1074
+    return 2.0 ** (math.floor(math.log2(x)) - 52)
+
+
+def _bm64_mp(u1, u2):
+    mpmath.mp.dps = 50
+    r = mpmath.sqrt(-2 * mpmath.log(mpmath.mpf(u1)))
+    return r * mpmath.cospi(2 * mpmath.mpf(u2)), r * mpmath.sinpi(2 * mpmath.mpf(u2))
+
+
+def test_box_muller64_vs_mpmath(orc):
+    """The FP64 Gaussian transform is within 4 ulp64 of the exact value of the
+    same two FP64 uniforms (libm log, sqrt and sin/cos after the exact
+    quarter-turn reduction), on random and edge pairs."""
+    g = np.random.default_rng(34)
+    us = [(float(a), float(b)) for a, b in g.random((2000, 2))]
+    us = [(1.0 - a if a < 1.0 else 1.0, b) for a, b in us]     # u1 in (0, 1]
+    edges1 = [2.0**-53, 2.0**-30, 0.5, 1.0 - 2.0**-53, 1.0 - 2.0**-30, 0.3, 0.999]
+    edges2 = [0.0, 2.0**-53, 0.125, 0.25 - 2.0**-53, 0.375, 0.5, 0.75, 1.0 - 2.0**-53]
+    us += [(a, b) for a in edges1 for b in edges2]
+    worst = 0.0
+    for u1, u2 in us:
+        z0, z1 = orc.box_muller64(u1, u2)
+        e0, e1 = _bm64_mp(u1, u2)
+        for z, e in ((z0, e0), (z1, e1)):
+            if e == 0:
+                assert z == 0.0
+                continue
+            worst = max(worst, float(abs(mpmath.mpf(z) - e)) / _ulp64(e))
+    assert worst <= 4.0, worst
+
+
+def test_gauss64_uniforms_from_words(orc):
+    """Philox: u1 = (v_a + 1) 2^-53 from words (w0, w1), u2 = v_b 2^-53 from
+    (w2, w3), first word low; MRG: y / (m1 + 1) for each output."""
+    M1 = 2**32 - 209
+    g = np.random.default_rng(35)
+    for w in g.integers(0, 2**32, (200, 4), dtype=np.uint64):
+        w = [int(x) for x in w]
+        va = ((w[1] << 32) | w[0]) >> 11
+        vb = ((w[3] << 32) | w[2]) >> 11
+        assert orc.gauss64_uniforms(orc.PHILOX, w) == ((va + 1) / 2**53, vb / 2**53)
+        y = [1 + x % M1 for x in w[:2]]
+        u1, u2 = orc.gauss64_uniforms(orc.MRG, y)
+        for u, yy in ((u1, y[0]), (u2, y[1])):
+            mpmath.mp.dps = 40
+            assert abs(mpmath.mpf(u) - mpmath.mpf(yy) / (M1 + 1)) <= mpmath.mpf(2)**-52 * u
+    assert orc.gauss64_uniforms(orc.PHILOX, [0] * 4) == (2.0**-53, 0.0)
+    assert orc.gauss64_uniforms(orc.PHILOX, [0xFFFFFFFF] * 4) == (1.0, 1.0 - 2.0**-53)
+
+
+def test_gaussian64_words_per_pair_and_consumption(orc):
+    """Pair j of a Philox Gaussian FP64 stream uses words 4j .. 4j + 3; MRG
+    outputs 2j, 2j + 1; odd n drops the last z1 (R21)."""
+    assert orc.words_consumed(orc.GAUSSIAN_F64, orc.PHILOX, 5) == 12
+    assert orc.words_consumed(orc.GAUSSIAN_F64, orc.MRG, 5) == 6
+    w = orc.philox_words(11, 6, 16)
+    z = orc.philox_generate(11, 6, orc.GAUSSIAN_F64, 7)
+    for j in range(4):
+        u1, u2 = orc.gauss64_uniforms(orc.PHILOX, w[4 * j: 4 * j + 4])
+        z0, z1 = orc.box_muller64(u1, u2)
+        assert z[2 * j] == z0
+        if 2 * j + 1 < 7:
+            assert z[2 * j + 1] == z1
+    st = orc.mrg_seed(11)
+    y, _ = orc.mrg_words(st, 8)
+    zm, _ = orc.mrg_generate(st, orc.GAUSSIAN_F64, 8)
+    for j in range(4):
+        assert tuple(zm[2 * j: 2 * j + 2]) == orc.box_muller64(
+            *orc.gauss64_uniforms(orc.MRG, y[2 * j: 2 * j + 2]))
+    z8 = orc.philox_generate(11, 6, orc.GAUSSIAN_F64, 8)
+    assert np.array_equal(z, z8[:7])
+
+
+def test_gaussian64_distribution(orc):
+    """2^20 Philox and 2^19 MRG Gaussian FP64 outputs pass a
+    Kolmogorov-Smirnov test against the standard normal (scipy) at the 0.1%
+    level, with the moments of N(0, 1)."""
+    from scipy import stats
+    for z in (orc.philox_generate(2025, 0, orc.GAUSSIAN_F64, 1 << 20),
+              orc.mrg_generate(orc.mrg_seed(2025), orc.GAUSSIAN_F64, 1 << 19)[0]):
+        n = z.size
+        assert stats.kstest(z, "norm").pvalue > 1e-3
+        se = 1 / math.sqrt(n)
+        assert abs(z.mean()) < 5 * se
+        assert abs(z.var() - 1) < 5 * math.sqrt(2) * se
+
+
+def test_gaussian64_special_cases(orc):
+    """u1 = 1 gives +-0; u2 on the axes gives exact axis values; the largest
+    radius is sqrt(-2 ln 2^-53)."""
+    for u2 in (0.0, 0.25, 0.5, 0.75, 0.3):
+        z0, z1 = orc.box_muller64(1.0, u2)
+        assert z0 == 0.0 and z1 == 0.0
+    r = math.sqrt(-2.0 * math.log(0.3))
+    assert orc.box_muller64(0.3, 0.0) == (r, 0.0)
+    assert orc.box_muller64(0.3, 0.25) == (0.0, r)
+    assert orc.box_muller64(0.3, 0.5) == (-r, 0.0)
+    assert orc.box_muller64(0.3, 0.75) == (0.0, -r)
+    z0, _ = orc.box_muller64(2.0**-53, 0.0)
+    assert z0 == math.sqrt(-2.0 * math.log(2.0**-53))
