@@ -98,15 +98,15 @@ def cpu_baseline(seed, offset, n, cells=None, n_mt=1 << 26, n_st=1 << 22):
     def timed_split(engine, kind, s, o, total, nthreads):
         step = (total + nthreads - 1) // nthreads
         step += step % 2                        # Gaussian pairs stay whole
-        wpo = 2 if (engine == oracle.PHILOX and kind == oracle.UNIFORM_F64) else 1
         start_state = oracle.mrg_skip(oracle.mrg_seed(s), o) if engine == oracle.MRG else None
 
         def one(first):
             m = min(step, total - first)
+            skip = oracle.words_consumed(kind, engine, first)
             if engine == oracle.PHILOX:
-                oracle.philox_generate(s, o + first * wpo, kind, m)
+                oracle.philox_generate(s, o + skip, kind, m)
             else:
-                oracle.mrg_generate(oracle.mrg_skip(start_state, first), kind, m)
+                oracle.mrg_generate(oracle.mrg_skip(start_state, skip), kind, m)
             return m
 
         t0 = time.perf_counter()
@@ -413,7 +413,7 @@ def main():
     if args.profile_cells:
         big = torch.empty(n * 2, dtype=torch.float32, device=dev)
         order = []
-        for engine, kind, s, o in cells:
+        for engine, kind, s, o in cells + synth.extra_draws():
             for _ in range(2):
                 mr.Engine(engine, s, o).generate(kind, n, big, stream=stream)
             order.append(f"{synth.ENGINE_NAME[engine]}/{synth.KIND_NAME[kind]}")
@@ -535,7 +535,7 @@ def main():
         # every bulk cell
         res = {}
         big = torch.empty(n * 2, dtype=torch.float32, device=dev)   # 2 GiB
-        for engine, kind, s, o in cells:
+        for engine, kind, s, o in cells + synth.extra_draws():
             name = f"{synth.ENGINE_NAME[engine]}/{synth.KIND_NAME[kind]}"
 
             def gen(engine=engine, kind=kind, s=s, o=o):
@@ -592,7 +592,8 @@ def main():
     }
     line.update(extra)
     if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(seed, offset, n, cells=None if args.quick else cells)
+        line["cpu_baseline"] = cpu_baseline(
+            seed, offset, n, cells=None if args.quick else cells + synth.extra_draws())
     print(json.dumps(line), flush=True)
 
 

@@ -36,10 +36,18 @@
  *     word low) * 2^-53, or y / (m1 + 1) for MRG; Gaussian FP32 = Box-Muller
  *     on word pairs (u1 = ((w_a >> 8) + 1) 2^-24, u2 = (w_b >> 8) 2^-24,
  *     z0 = sqrt(-2 ln u1) cos(2 pi u2), z1 = ... sin(2 pi u2)).
+ *   Gaussian FP64 = Box-Muller in FP64 on FP64 uniform pairs: Philox
+ *     u1 = (v_a + 1) 2^-53, u2 = v_b 2^-53 with v_a, v_b the 53-bit values
+ *     of words (4j, 4j+1) and (4j+2, 4j+3) (first word low); MRG u1, u2 =
+ *     y_a / (m1 + 1), y_b / (m1 + 1) of outputs 2j, 2j+1; results within a
+ *     few ulp of the exact transform.
  *   Range: uniform r = fma(u, RN(b - a), RN(a)) in the output precision;
- *     Gaussian r = fma(z, RN32(stddev), RN32(mean)).
- *   Consumption per call: n words, except uniform FP64 on Philox (2n) and
- *     Gaussian (2 * ceil(n / 2); for odd n the last z1 is dropped).
+ *     Gaussian r = fma(z, RN32(stddev), RN32(mean)); Gaussian FP64
+ *     r = fma(z, stddev, mean).
+ *   Consumption per call: n words, except uniform FP64 on Philox (2n),
+ *     Gaussian FP32 (2 * ceil(n / 2); for odd n the last z1 is dropped) and
+ *     Gaussian FP64 (4 * ceil(n / 2) Philox words or 2 * ceil(n / 2) MRG
+ *     steps).
  */
 #ifndef MIRNG_H
 #define MIRNG_H
@@ -64,7 +72,8 @@ typedef enum {
     MIRNG_BITS_U32 = 1,      /* uint32 out, engine words                     */
     MIRNG_UNIFORM_F32 = 2,   /* float out, [a, b); default (0, 1)            */
     MIRNG_UNIFORM_F64 = 3,   /* double out, [a, b); default (0, 1)           */
-    MIRNG_GAUSSIAN_F32 = 4   /* float out, mean p0, stddev p1; default (0,1) */
+    MIRNG_GAUSSIAN_F32 = 4,  /* float out, mean p0, stddev p1; default (0,1) */
+    MIRNG_GAUSSIAN_F64 = 5   /* double out, mean p0, stddev p1; default (0,1) */
 } mirng_dist_kind;
 
 /* A distribution: kind plus two parameters.  Uniform: p0 = a, p1 = b with

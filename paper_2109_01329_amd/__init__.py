@@ -17,13 +17,13 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmirng.so")
 
 PHILOX4X32_10, MRG32K3A = 1, 2
-BITS_U32, UNIFORM_F32, UNIFORM_F64, GAUSSIAN_F32 = 1, 2, 3, 4
+BITS_U32, UNIFORM_F32, UNIFORM_F64, GAUSSIAN_F32, GAUSSIAN_F64 = 1, 2, 3, 4, 5
 
 STATUS = {0: "MIRNG_OK", 1: "MIRNG_E_INVALID_ARG", 2: "MIRNG_E_UNSUPPORTED",
           3: "MIRNG_E_ALLOC", 4: "MIRNG_E_LAUNCH", 5: "MIRNG_E_DEVICE",
           6: "MIRNG_E_CAPACITY"}
 
-ELEM_BYTES = {BITS_U32: 4, UNIFORM_F32: 4, UNIFORM_F64: 8, GAUSSIAN_F32: 4}
+ELEM_BYTES = {BITS_U32: 4, UNIFORM_F32: 4, UNIFORM_F64: 8, GAUSSIAN_F32: 4, GAUSSIAN_F64: 8}
 
 
 class MirngError(RuntimeError):

@@ -92,13 +92,14 @@ mirng_status check_dist(const mirng_distribution *d)
         if (!finite(d->p0) || !finite(d->p1) || !(d->p0 < d->p1)) return MIRNG_E_INVALID_ARG;
         return MIRNG_OK;
     case kGauss:
+    case kGauss64:
         if (!finite(d->p0) || !finite(d->p1) || !(d->p1 > 0.0)) return MIRNG_E_INVALID_ARG;
         return MIRNG_OK;
     default: return MIRNG_E_UNSUPPORTED;
     }
 }
 
-size_t elem_size(int kind) { return kind == kU64F ? 8 : 4; }
+size_t elem_size(int kind) { return (size_t)elem_bytes(kind); }
 
 bool is_default(const mirng_distribution *d)
 {
@@ -117,6 +118,9 @@ Epilogue make_epilogue(const mirng_distribution *d, int nt)
     if (d->kind == kU64F) {
         ep.a64 = d->p0;
         ep.d64 = d->p1 - d->p0;
+    } else if (d->kind == kGauss64) {
+        ep.a64 = d->p0;
+        ep.d64 = d->p1;
     } else if (d->kind == kGauss) {
         ep.a32 = (float)d->p0;
         ep.d32 = (float)d->p1;
@@ -136,14 +140,14 @@ hipError_t philox_plain(const uint32_t key[2], Pos130 p, const mirng_distributio
     const mirng_philox_config tu = philox_config();
     const int kind = d->kind;
     const size_t esz = elem_size(kind);
-    const uint32_t wpe = kind == kU64F ? 2u : 1u;   // words per element
+    const uint32_t wpe = (uint32_t)philox_words_per_elem(kind);
     const Epilogue ep = make_epilogue(d, tu.nontemporal);
     const uint64_t cus = (uint64_t)device_cu_count();
     while (n > 0) {
         const uint64_t chunk = n < kMaxPerLaunch ? n : kMaxPerLaunch;
         const uint64_t b_lo = (p.l[0] >> 2) | (p.l[1] << 62);   // floor(p / 4), 128 bits
         const uint64_t b_hi = (p.l[1] >> 2) | (p.l[2] << 62);
-        const bool whole = tu.walk == 1 &&
+        const bool whole = tu.walk == 1 && kind != kGauss64 &&
                            (kind == kBits || kind == kU32F || (p.l[0] & 1u) == 0);
         const uintptr_t addr = (uintptr_t)out;
         hipError_t err;
@@ -178,9 +182,10 @@ hipError_t philox_plain(const uint32_t key[2], Pos130 p, const mirng_distributio
             err = launch_philox_blocks(a, s);
         } else {
             const uint32_t epv = (uint32_t)(16 / esz);
-            // Gaussian pairs that would straddle the 16-byte grid: slots of
-            // four outputs start at the output itself (dword-aligned stores)
-            const bool at_out = kind == kGauss && (((addr & 15u) / esz) & 1u);
+            // Gaussian pairs that would straddle the 16-byte grid: slots
+            // (two pairs of FP32, or one pair of FP64) start at the output
+            // itself (16-byte stores at 4- or 8-byte alignment)
+            const bool at_out = paired(kind) && (((addr & 15u) / esz) & 1u);
             const uint32_t head = at_out ? 0u : (uint32_t)((addr & 15u) / esz);
             PhiloxFill a{};
             SlotRun &r = a.run;

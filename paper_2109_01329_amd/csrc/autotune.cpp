@@ -87,9 +87,9 @@ mirng_status mirng_autotune_philox(int32_t kind, uint64_t n, void *out, void *st
                                    int32_t prewarm_ms, int32_t rounds, int32_t reps,
                                    mirng_philox_config *best, float *best_ms)
 {
-    if (kind < kBits || kind > kGauss) return MIRNG_E_UNSUPPORTED;
+    if (kind < kBits || kind > kGauss64) return MIRNG_E_UNSUPPORTED;
     if (!out || n == 0 || !tune_args_ok(prewarm_ms, rounds, reps)) return MIRNG_E_INVALID_ARG;
-    if ((uintptr_t)out % (kind == kU64F ? 8u : 4u)) return MIRNG_E_INVALID_ARG;
+    if ((uintptr_t)out % (uintptr_t)elem_bytes(kind)) return MIRNG_E_INVALID_ARG;
     if (ensure_device(nullptr) != hipSuccess) return MIRNG_E_DEVICE;
     std::vector<mirng_philox_config> cand;
     for (int block : {256, 512, 1024})

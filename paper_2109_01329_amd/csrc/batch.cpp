@@ -108,7 +108,8 @@ void estimate_work(const mirng_request *q, size_t count, uint64_t &tiles, uint64
     for (size_t i = 0; i < count; ++i) {
         const uint64_t n = q[i].n;
         if (n == 0 || n >= (1ull << 32)) continue;
-        const bool f64 = q[i].dist.kind == MIRNG_UNIFORM_F64;
+        const bool f64 = q[i].dist.kind == MIRNG_UNIFORM_F64 ||
+                         q[i].dist.kind == MIRNG_GAUSSIAN_F64;
         if (q[i].engine_type == MIRNG_MRG32K3A) {
             const uint64_t per = (uint64_t)256 * mirng::kBatchMrgPasses * (f64 ? 16 : 32);
             chunks += (n + per - 1) / per;
@@ -242,6 +243,10 @@ mirng_status mirng_generate_batch(mirng_batcher b, const mirng_request *reqs, si
     if (mrg_batch_tables(dev, tabs) != hipSuccess) return MIRNG_E_ALLOC;
     const uint64_t wpb = (uint64_t)b->cfg.block / 64;
     uint64_t waves = ((grid_waves(b->cfg) + wpb - 1) / wpb) * wpb;
+    // Philox Gaussian FP64 requests need the wide generation kernel
+    int32_t wide = 0;
+    for (size_t i = 0; i < count && !wide; ++i)
+        wide = reqs[i].engine_type == MIRNG_PHILOX4X32_10 && reqs[i].dist.kind == MIRNG_GAUSSIAN_F64;
     uint64_t mgroups = mrg_groups();
     if (count <= kSmallBatch) {
         // small batches: no more waves (groups) than about two tiles
@@ -284,6 +289,7 @@ mirng_status mirng_generate_batch(mirng_batcher b, const mirng_request *reqs, si
     a.u_tab8 = tabs.u_tab8;
     a.status = sl.d_status;
     a.nt = b->cfg.nontemporal;
+    a.wide = wide;
     a.block = (uint32_t)b->cfg.block;
     a.groups = (uint32_t)(waves / wpb);
     hipError_t err = hipMemcpyAsync(sl.d_reqs, sl.h_reqs, count * sizeof(mirng_request),

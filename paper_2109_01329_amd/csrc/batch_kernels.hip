@@ -46,18 +46,18 @@ __device__ void plan_one(const mirng_request &q, BatchDesc &d, int32_t &st, int 
     }
     const int kind = q.dist.kind;
     if (q.reserved != 0 || q.dist.reserved != 0) { st = MIRNG_E_INVALID_ARG; return; }
-    if (kind < kBits || kind > kGauss) { st = MIRNG_E_UNSUPPORTED; return; }
+    if (kind < kBits || kind > kGauss64) { st = MIRNG_E_UNSUPPORTED; return; }
     const double p0 = q.dist.p0, p1 = q.dist.p1;
     if ((kind == kU32F || kind == kU64F) && !(finite(p0) && finite(p1) && p0 < p1)) {
         st = MIRNG_E_INVALID_ARG;
         return;
     }
-    if (kind == kGauss && !(finite(p0) && finite(p1) && p1 > 0.0)) {
+    if (paired(kind) && !(finite(p0) && finite(p1) && p1 > 0.0)) {
         st = MIRNG_E_INVALID_ARG;
         return;
     }
     if (q.n == 0) return;
-    const uint64_t esz = kind == kU64F ? 8 : 4;
+    const uint64_t esz = (uint64_t)elem_bytes(kind);
     const uint64_t addr = (uint64_t)(uintptr_t)q.out;
     if (addr == 0 || addr % esz) { st = MIRNG_E_INVALID_ARG; return; }
     if (q.n >= (1ull << 32)) { st = MIRNG_E_CAPACITY; return; }
@@ -72,6 +72,9 @@ __device__ void plan_one(const mirng_request &q, BatchDesc &d, int32_t &st, int 
     if (kind == kU64F) {
         ep.a64 = p0;
         ep.d64 = p1 - p0;
+    } else if (kind == kGauss64) {
+        ep.a64 = p0;
+        ep.d64 = p1;
     } else if (kind == kGauss) {
         ep.a32 = (float)p0;
         ep.d32 = (float)p1;
@@ -93,7 +96,7 @@ __device__ void plan_one(const mirng_request &q, BatchDesc &d, int32_t &st, int 
             if ((p >> k) & 1u) apply_mat(pow2 + k * kMatWords, v);
 #pragma unroll
         for (int i = 0; i < 6; ++i) d.mst[i] = v[i];
-        const uint64_t per = (uint64_t)kMrgThreads * kBatchMrgPasses * (kind == kU64F ? 16 : 32);
+        const uint64_t per = (uint64_t)kMrgThreads * kBatchMrgPasses * (esz == 8 ? 16 : 32);
         r.out_base = (char *)q.out;
         mchunks = (q.n + per - 1) / per;
         d.mchunks = (uint32_t)mchunks;
@@ -103,20 +106,20 @@ __device__ void plan_one(const mirng_request &q, BatchDesc &d, int32_t &st, int 
     r.k0 = (uint32_t)q.seed;
     r.k1 = (uint32_t)(q.seed >> 32);
     const uint32_t head = (uint32_t)((addr & 15u) / esz);
-    const uint32_t wpe = kind == kU64F ? 2u : 1u;
+    const uint32_t wpe = (uint32_t)philox_words_per_elem(kind);
     const uint32_t epv = (uint32_t)(16 / esz);
-    if (kind == kGauss && (head & 1u)) {
-        // pairs would straddle the 16-byte grid: slots of 4 outputs start at
-        // the output itself (dword-aligned 16-byte stores)
+    if (paired(kind) && (head & 1u)) {
+        // pairs would straddle the 16-byte grid: slots (two FP32 pairs or
+        // one FP64 pair) start at the output itself
         r.base[0] = (uint32_t)(p >> 2);
         r.base[1] = (uint32_t)(p >> 34);
         r.base[2] = 0;
         r.base[3] = 0;
         d.phase = (uint32_t)(p & 3u);
         r.head = 0;
-        d.nunits = (uint32_t)((q.n + 3) / 4);
+        d.nunits = (uint32_t)((q.n + epv - 1) / epv);
         r.full_lo = 0;
-        r.full_count = (uint32_t)(q.n / 4);
+        r.full_count = (uint32_t)(q.n / epv);
         r.out_base = (char *)q.out;
     } else {
         const uint64_t dq = (uint64_t)head * wpe;
@@ -269,13 +272,20 @@ __device__ __forceinline__ void run_kind(const BatchDesc &d, uint32_t u0, uint32
     }
 }
 
+// WIDE: the batch holds Philox Gaussian FP64 requests.  Their transform
+// needs many more registers, so batches without them run a kernel that
+// does not contain it (and keeps its occupancy).
+template <bool WIDE>
 __device__ void run_segment(const BatchDesc &d, uint32_t u0, uint32_t span, uint32_t lane)
 {
     switch (d.kind) {
     case kBits: run_kind<kBits>(d, u0, span, lane); break;
     case kU32F: run_kind<kU32F>(d, u0, span, lane); break;
     case kU64F: run_kind<kU64F>(d, u0, span, lane); break;
-    default: run_kind<kGauss>(d, u0, span, lane); break;
+    case kGauss: run_kind<kGauss>(d, u0, span, lane); break;
+    default:
+        if constexpr (WIDE) run_kind<kGauss64>(d, u0, span, lane);
+        break;
     }
 }
 
@@ -291,6 +301,7 @@ __device__ __forceinline__ BatchDesc load_desc(const BatchDesc *p)
     return d;
 }
 
+template <bool WIDE>
 __global__ __launch_bounds__(1024) void batch_main_kernel(BatchArgs a)
 {
     const uint32_t lane = threadIdx.x & 63u;
@@ -309,7 +320,7 @@ __global__ __launch_bounds__(1024) void batch_main_kernel(BatchArgs a)
             const uint64_t seg = min(t1, end);
             const uint32_t u0 = (uint32_t)((t - start) * 64);
             const uint32_t u1 = (uint32_t)min((seg - start) * 64, (uint64_t)nunits);
-            run_segment(load_desc(&a.desc[r]), u0, u1 - u0, lane);
+            run_segment<WIDE>(load_desc(&a.desc[r]), u0, u1 - u0, lane);
             t = seg;
         }
         ++r;
@@ -377,7 +388,8 @@ __global__ __launch_bounds__(kMrgThreads) void batch_mrg_kernel(BatchArgs a)
                 case kBits: mrg_chunk<kBits>(d, k, a.c_tab4, a.u_tab4, lds, wg_state); break;
                 case kU32F: mrg_chunk<kU32F>(d, k, a.c_tab4, a.u_tab4, lds, wg_state); break;
                 case kU64F: mrg_chunk<kU64F>(d, k, a.c_tab8, a.u_tab8, lds, wg_state); break;
-                default: mrg_chunk<kGauss>(d, k, a.c_tab4, a.u_tab4, lds, wg_state); break;
+                case kGauss: mrg_chunk<kGauss>(d, k, a.c_tab4, a.u_tab4, lds, wg_state); break;
+                default: mrg_chunk<kGauss64>(d, k, a.c_tab8, a.u_tab8, lds, wg_state); break;
                 }
             }
             c = seg;
@@ -396,7 +408,10 @@ hipError_t launch_batch(const BatchArgs &a, hipStream_t s)
     hipLaunchKernelGGL(batch_scan_kernel, dim3(1), dim3(kChunk), 0, s, a);
     err = hipGetLastError();
     if (err != hipSuccess) return err;
-    hipLaunchKernelGGL(batch_main_kernel, dim3(a.groups), dim3(a.block), 0, s, a);
+    if (a.wide)
+        hipLaunchKernelGGL(batch_main_kernel<true>, dim3(a.groups), dim3(a.block), 0, s, a);
+    else
+        hipLaunchKernelGGL(batch_main_kernel<false>, dim3(a.groups), dim3(a.block), 0, s, a);
     err = hipGetLastError();
     if (err != hipSuccess) return err;
     hipLaunchKernelGGL(batch_mrg_kernel, dim3(a.mgroups), dim3(kMrgThreads), 0, s, a);

@@ -57,12 +57,18 @@ void mrg_seed_state(uint64_t seed, uint32_t st[6]);
 uint64_t words_consumed(int engine_type, int kind, uint64_t n);
 
 // ------------------------------------------------------------ launches
-enum Kind : int32_t { kBits = 1, kU32F = 2, kU64F = 3, kGauss = 4 };
+enum Kind : int32_t { kBits = 1, kU32F = 2, kU64F = 3, kGauss = 4, kGauss64 = 5 };
+
+// Bytes of one output and engine words (Philox) per output.
+constexpr int elem_bytes(int kind) { return (kind == kU64F || kind == kGauss64) ? 8 : 4; }
+constexpr int philox_words_per_elem(int kind) { return (kind == kU64F || kind == kGauss64) ? 2 : 1; }
+// Kinds whose outputs come in pairs from one Box-Muller transform.
+constexpr bool paired(int kind) { return kind == kGauss || kind == kGauss64; }
 
 // Output epilogue parameters shared by the generation kernels.
 struct Epilogue {
     float a32, d32;         // uniform F32: fma(u, d, a); Gaussian: fma(z, sd, mean)
-    double a64, d64;        // uniform F64: fma(u, d, a)
+    double a64, d64;        // uniform F64: fma(u, d, a); Gaussian F64: fma(z, sd, mean)
     int32_t ranged;         // 0 when the parameters are the defaults
     int32_t nt;             // streaming stores
 };
@@ -157,6 +163,7 @@ struct BatchArgs {
     int32_t nt;             // streaming stores
     uint32_t block;         // Philox generation kernel: threads per workgroup
     uint32_t groups;        // Philox generation kernel: workgroups
+    int32_t wide;           // some Philox request is Gaussian FP64 (host scan)
     const uint32_t *pow2;   // MRG A^(2^k), k < 64: [k][comp][9]
     const uint32_t *c_tab4, *u_tab4;   // MRG chunk / thread jumps, 4-byte kinds
     const uint32_t *c_tab8, *u_tab8;   // MRG chunk / thread jumps, FP64

@@ -107,7 +107,7 @@ __device__ __forceinline__ float y_to_u01f(double y)
 
 template <int KIND>
 struct MrgShape {
-    static constexpr int ESZ = KIND == kU64F ? 8 : 4;
+    static constexpr int ESZ = elem_bytes(KIND);
     static constexpr int L = 128 / ESZ;          // outputs per thread per pass
     static constexpr int ROW = L * ESZ + 16;     // padded LDS row, bytes
     static constexpr int VPR = L * ESZ / 16;     // 16-byte vectors per row
@@ -140,6 +140,15 @@ __device__ __forceinline__ void mrg_fill_row(MrgState &s, char *row, const Epilo
             f64x2 d;
             d.x = mrg_step(s) * kNorm;
             d.y = mrg_step(s) * kNorm;
+            if (ep.ranged) {
+                d.x = __builtin_fma(d.x, ep.d64, ep.a64);
+                d.y = __builtin_fma(d.y, ep.d64, ep.a64);
+            }
+            pk = __builtin_bit_cast(u32x4, d);
+        } else if constexpr (KIND == kGauss64) {
+            const double u1 = mrg_step(s) * kNorm;
+            const double u2 = mrg_step(s) * kNorm;
+            f64x2 d = box_muller64(u1, u2);
             if (ep.ranged) {
                 d.x = __builtin_fma(d.x, ep.d64, ep.a64);
                 d.y = __builtin_fma(d.y, ep.d64, ep.a64);

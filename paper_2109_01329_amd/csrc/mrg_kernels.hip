@@ -203,7 +203,7 @@ hipError_t spacing_table(int dev, int e, uint32_t **out)
 // CU) when the size allows, without leaving half a group idle.
 uint32_t pick_q(int kind, uint64_t n_each, uint64_t nsub)
 {
-    uint32_t q = kind == kU64F ? 16 : 32;
+    uint32_t q = elem_bytes(kind) == 8 ? 16 : 32;   // L outputs per pass
     while (q < 1024 && (uint64_t)kThreads * q * 2048 < n_each * nsub &&
            (uint64_t)kThreads * q * 2 <= n_each)
         q <<= 1;
@@ -217,7 +217,8 @@ hipError_t launch(const MrgLaunch &a, int kind, uint64_t groups, hipStream_t s)
     case kBits: hipLaunchKernelGGL(mrg_kernel<kBits>, grid, block, 0, s, a); break;
     case kU32F: hipLaunchKernelGGL(mrg_kernel<kU32F>, grid, block, 0, s, a); break;
     case kU64F: hipLaunchKernelGGL(mrg_kernel<kU64F>, grid, block, 0, s, a); break;
-    default: hipLaunchKernelGGL(mrg_kernel<kGauss>, grid, block, 0, s, a); break;
+    case kGauss: hipLaunchKernelGGL(mrg_kernel<kGauss>, grid, block, 0, s, a); break;
+    default: hipLaunchKernelGGL(mrg_kernel<kGauss64>, grid, block, 0, s, a); break;
     }
     return hipGetLastError();
 }
@@ -231,6 +232,9 @@ void fill_params(MrgLaunch &a, const mirng_distribution *d)
     if (d->kind == kU64F) {
         e.a64 = d->p0;
         e.d64 = d->p1 - d->p0;
+    } else if (d->kind == kGauss64) {
+        e.a64 = d->p0;
+        e.d64 = d->p1;
     } else if (d->kind == kGauss) {
         e.a32 = (float)d->p0;
         e.d32 = (float)d->p1;

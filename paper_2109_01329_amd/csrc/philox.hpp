@@ -82,6 +82,14 @@ __device__ __forceinline__ u32x4 transform(const Epilogue &ep, u32x4 w)
             d.y = __builtin_fma(d.y, ep.d64, ep.a64);
         }
         v = __builtin_bit_cast(u32x4, d);
+    } else if constexpr (KIND == kGauss64) {
+        // u1 = (v_a + 1) 2^-53 from (w.x, w.y), u2 = v_b 2^-53 from (w.z, w.w)
+        f64x2 d = box_muller64(u01d(w.x, w.y) + 0x1p-53, u01d(w.z, w.w));
+        if (ep.ranged) {
+            d.x = __builtin_fma(d.x, ep.d64, ep.a64);
+            d.y = __builtin_fma(d.y, ep.d64, ep.a64);
+        }
+        v = __builtin_bit_cast(u32x4, d);
     } else {
         f32x4 f;
         f.xy = box_muller(w.x, w.y);
@@ -104,8 +112,8 @@ template <int KIND>
 __device__ __forceinline__ void put(char *p, u32x4 v, uint32_t u, uint32_t full_lo,
                                    uint32_t full_count, int64_t e0, uint64_t n, int nt)
 {
-    constexpr int EPV = (KIND == kU64F) ? 2 : 4;
-    constexpr int ESZ = 16 / EPV;
+    constexpr int EPV = 16 / elem_bytes(KIND);
+    constexpr int ESZ = elem_bytes(KIND);
     if (u - full_lo < full_count) {
         if (nt) __builtin_nontemporal_store(v, (u32x4_a4 *)p);
         else *(u32x4_a4 *)p = v;
@@ -156,7 +164,7 @@ __device__ __forceinline__ uint32_t lane0(uint32_t v)
 template <int KIND>
 __device__ __forceinline__ void emit_slot(const SlotRun &r, uint32_t slot, u32x4 w)
 {
-    constexpr int EPV = (KIND == kU64F) ? 2 : 4;
+    constexpr int EPV = 16 / elem_bytes(KIND);
     const int64_t e0 = (int64_t)slot * EPV - (int64_t)r.head;
     put<KIND>(r.out_base + (uint64_t)slot * 16u, transform<KIND>(r.ep, w), slot, r.full_lo,
               r.full_count, e0, r.n, r.ep.nt);

@@ -111,7 +111,8 @@ hipError_t launch_philox_blocks(const PhiloxBlocks &a, hipStream_t s)
     case kBits: return launch_blocks_kind<kBits>(a, s);
     case kU32F: return launch_blocks_kind<kU32F>(a, s);
     case kU64F: return launch_blocks_kind<kU64F>(a, s);
-    default: return launch_blocks_kind<kGauss>(a, s);
+    case kGauss: return launch_blocks_kind<kGauss>(a, s);
+    default: return hipErrorInvalidValue;   // Gaussian FP64 pairs span whole blocks: fill walk
     }
 }
 
@@ -125,7 +126,8 @@ hipError_t launch_philox_fill(const PhiloxFill &a, hipStream_t s)
     case kBits: return launch_fill_kind<kBits>(a, grid, block, s);
     case kU32F: return launch_fill_kind<kU32F>(a, grid, block, s);
     case kU64F: return launch_fill_kind<kU64F>(a, grid, block, s);
-    default: return launch_fill_kind<kGauss>(a, grid, block, s);
+    case kGauss: return launch_fill_kind<kGauss>(a, grid, block, s);
+    default: return launch_fill_kind<kGauss64>(a, grid, block, s);
     }
 }
 

@@ -11,9 +11,10 @@ namespace mirng {
 uint64_t request_bytes(const mirng_request &r)
 {
     // requests the batched kernel refuses write nothing
-    if (r.dist.kind < MIRNG_BITS_U32 || r.dist.kind > MIRNG_GAUSSIAN_F32) return 0;
+    if (r.dist.kind < MIRNG_BITS_U32 || r.dist.kind > MIRNG_GAUSSIAN_F64) return 0;
     if (r.n >= (1ull << 32)) return 0;
-    return r.n * (r.dist.kind == MIRNG_UNIFORM_F64 ? 8u : 4u);
+    const bool f64 = r.dist.kind == MIRNG_UNIFORM_F64 || r.dist.kind == MIRNG_GAUSSIAN_F64;
+    return r.n * (f64 ? 8u : 4u);
 }
 
 Scheduler::Scheduler(Executor &ex, uint64_t capacity_bytes, size_t max_batch)

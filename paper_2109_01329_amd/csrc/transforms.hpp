@@ -114,4 +114,19 @@ __device__ __forceinline__ f32x2 box_muller(uint32_t wa, uint32_t wb)
     return z;
 }
 
+// Box-Muller in FP64 on a pair of FP64 uniforms u1 in (0, 1], u2 in [0, 1):
+// r = sqrt(-2 ln u1), (z0, z1) = r (cos 2 pi u2, sin 2 pi u2), with the
+// device library's log, IEEE sqrt and sincospi (whose argument reduction is
+// exact, as 2 u2 is).  u1 = 1 gives +-0.
+__device__ __forceinline__ f64x2 box_muller64(double u1, double u2)
+{
+    const double r = __builtin_sqrt(-2.0 * log(u1));
+    double s, c;
+    sincospi(2.0 * u2, &s, &c);
+    f64x2 z;
+    z.x = r * c;
+    z.y = r * s;
+    return z;
+}
+
 }  // namespace mirng

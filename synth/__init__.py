@@ -19,13 +19,14 @@ import numpy as np
 META_SEED = 1329
 
 PHILOX, MRG = 1, 2
-BITS_U32, UNIFORM_F32, UNIFORM_F64, GAUSSIAN_F32 = 1, 2, 3, 4
+BITS_U32, UNIFORM_F32, UNIFORM_F64, GAUSSIAN_F32, GAUSSIAN_F64 = 1, 2, 3, 4, 5
 KINDS = (UNIFORM_F32, UNIFORM_F64, GAUSSIAN_F32, BITS_U32)
 ENGINES = (PHILOX, MRG)
 KIND_NAME = {BITS_U32: "bits_u32", UNIFORM_F32: "uniform_f32",
-             UNIFORM_F64: "uniform_f64", GAUSSIAN_F32: "gaussian_f32"}
+             UNIFORM_F64: "uniform_f64", GAUSSIAN_F32: "gaussian_f32",
+             GAUSSIAN_F64: "gaussian_f64"}
 ENGINE_NAME = {PHILOX: "philox4x32_10", MRG: "mrg32k3a"}
-ELEM_BYTES = {BITS_U32: 4, UNIFORM_F32: 4, UNIFORM_F64: 8, GAUSSIAN_F32: 4}
+ELEM_BYTES = {BITS_U32: 4, UNIFORM_F32: 4, UNIFORM_F64: 8, GAUSSIAN_F32: 4, GAUSSIAN_F64: 8}
 
 
 def rng(k: int) -> np.random.Generator:
@@ -51,6 +52,18 @@ def bulk_draws(count: int = 3):
                 seed = int(g.integers(0, 2**64, dtype=np.uint64))
                 offset = int(g.integers(0, 2**40, dtype=np.uint64))
                 cells.append((engine, kind, seed, offset))
+    return cells
+
+
+def extra_draws():
+    """(engine, kind, seed, offset) cells of the kinds outside the bulk mix
+    (Gaussian FP64), one per engine, drawn like the bulk cells."""
+    g = rng(6)
+    cells = []
+    for engine in ENGINES:
+        seed = int(g.integers(0, 2**64, dtype=np.uint64))
+        offset = int(g.integers(0, 2**40, dtype=np.uint64))
+        cells.append((engine, GAUSSIAN_F64, seed, offset))
     return cells
 
 

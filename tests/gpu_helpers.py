@@ -11,7 +11,8 @@ import oracle
 import paper_2109_01329_amd as mr
 
 NP_DTYPE = {mr.BITS_U32: np.uint32, mr.UNIFORM_F32: np.float32,
-            mr.UNIFORM_F64: np.float64, mr.GAUSSIAN_F32: np.float32}
+            mr.UNIFORM_F64: np.float64, mr.GAUSSIAN_F32: np.float32,
+            mr.GAUSSIAN_F64: np.float64}
 
 
 def device_buffer(nbytes: int):
@@ -90,8 +91,35 @@ def gauss_errors(g: np.ndarray, d: np.ndarray, mean: float = 0.0, sd: float = 1.
     return np.abs(g - d) / tol
 
 
+def ulp64(x: np.ndarray) -> np.ndarray:
+    ax = np.abs(np.asarray(x, dtype=np.float64))
+    e = np.floor(np.log2(np.where(ax > 0, ax, 1.0)))
+    return np.where(ax >= 2.0**-1022, np.ldexp(1.0, (e - 52).astype(np.int64)), 2.0**-1074)
+
+
+def gauss64_errors(g: np.ndarray, d: np.ndarray, mean: float = 0.0, sd: float = 1.0):
+    """Error of FP64 Gaussians g against the oracle's values d, in units of
+    the tolerance: 8 ulp64 of z (both sides evaluate log, sqrt and a
+    sin/cos with exact quarter-turn reduction, each within a few ulp of the
+    exact transform; the oracle is pinned within 4) scaled by |sd|, plus
+    2 ulp64 of the result for the final scaling (fma on the device, multiply
+    and add in the oracle).  z = 0 (u1 = 1) must give exactly the mean."""
+    z = (d - mean) / sd
+    tol = 8.0 * ulp64(z) * abs(sd) + 2.0 * ulp64(d)
+    err = np.abs(g - d)
+    exact = z == 0.0
+    err = np.where(exact, np.where(g == d, 0.0, np.inf), err)
+    return err / np.where(exact, 1.0, tol)
+
+
 def assert_match(kind: int, got: np.ndarray, want: np.ndarray, p0=None, p1=None):
     assert got.shape == want.shape
+    if kind == mr.GAUSSIAN_F64:
+        e = gauss64_errors(got, want, 0.0 if p0 is None else p0, 1.0 if p1 is None else p1)
+        bad = np.nonzero(e > 1.0)[0]
+        assert bad.size == 0, (f"{bad.size} FP64 Gaussians outside tolerance; first at "
+                               f"{bad[:5]}: got {got[bad[:5]]} want {want[bad[:5]]}")
+        return float(e.max()) if e.size else 0.0
     if kind == mr.GAUSSIAN_F32:
         e = gauss_errors(got, want, 0.0 if p0 is None else p0, 1.0 if p1 is None else p1)
         bad = np.nonzero(e > 1.0)[0]

@@ -103,6 +103,13 @@ def test_words_consumed():
     assert mr.words_consumed(2, mr.UNIFORM_F64, 5) == 5
     assert mr.words_consumed(1, mr.GAUSSIAN_F32, 5) == 6
     assert mr.words_consumed(2, mr.BITS_U32, 5) == 5
+    assert mr.words_consumed(1, mr.GAUSSIAN_F64, 5) == 12
+    assert mr.words_consumed(2, mr.GAUSSIAN_F64, 5) == 6
+    import oracle
+    for kind in (1, 2, 3, 4, 5):
+        for engine in (1, 2):
+            for n in (0, 1, 2, 7, 2**40 + 1):
+                assert mr.words_consumed(engine, kind, n) == oracle.words_consumed(kind, engine, n)
     assert mr.words_consumed(1, 77, 5) == 0
 
 
@@ -125,6 +132,10 @@ def test_generate_validation_without_device(L):
     assert _gen(L, e, mr.UNIFORM_F64, 8, fake, 0.0, float("inf")) == 1
     assert _gen(L, e, mr.GAUSSIAN_F32, 8, fake, 0.0, 0.0) == 1    # stddev <= 0
     assert _gen(L, e, mr.GAUSSIAN_F32, 8, fake, 0.0, -1.0) == 1
+    assert _gen(L, e, mr.GAUSSIAN_F64, 8, fake + 4) == 1         # misaligned FP64
+    assert _gen(L, e, mr.GAUSSIAN_F64, 8, fake, 0.0, 0.0) == 1
+    assert _gen(L, e, mr.GAUSSIAN_F64, 8, fake, float("inf"), 1.0) == 1
+    assert _gen(L, e, 6, 8, fake) == 2
     assert _gen(L, e, mr.UNIFORM_F32, 8, fake, reserved=1) == 1
     assert _gen(L, e, 9, 8, fake) == 2                            # unknown kind
     d = mr.Distribution(mr.UNIFORM_F32, 0, 0.0, 1.0)

@@ -11,7 +11,7 @@ from tests import gpu_helpers as gh
 
 pytestmark = pytest.mark.gpu
 
-KINDS = [mr.BITS_U32, mr.UNIFORM_F32, mr.UNIFORM_F64, mr.GAUSSIAN_F32]
+KINDS = [mr.BITS_U32, mr.UNIFORM_F32, mr.UNIFORM_F64, mr.GAUSSIAN_F32, mr.GAUSSIAN_F64]
 
 
 def test_small_case_seed42():
@@ -57,7 +57,8 @@ def test_continuity_across_calls(kind):
     for _ in range(6):
         seed = int(g.integers(0, 2**64, dtype=np.uint64))
         off = int(g.integers(0, 2**40, dtype=np.uint64))
-        n1 = int(g.integers(1, 5000)) * (2 if kind == mr.GAUSSIAN_F32 else 1)
+        paired = kind in (mr.GAUSSIAN_F32, mr.GAUSSIAN_F64)
+        n1 = int(g.integers(1, 5000)) * (2 if paired else 1)
         n2 = int(g.integers(1, 5000))
         e = mr.Engine(mr.PHILOX4X32_10, seed, off)
         a, _ = gh.generate(e, kind, n1)
@@ -72,7 +73,8 @@ def test_continuity_across_calls(kind):
 @pytest.mark.parametrize("kind,p0,p1", [
     (mr.UNIFORM_F32, -3.0, 5.0), (mr.UNIFORM_F32, 1e-3, 2e-3), (mr.UNIFORM_F32, 100.0, 101.5),
     (mr.UNIFORM_F64, -1.0, 0.0), (mr.UNIFORM_F64, 1e-3, 2e-3),
-    (mr.GAUSSIAN_F32, 2.5, 0.5), (mr.GAUSSIAN_F32, -1.0, 3.0)])
+    (mr.GAUSSIAN_F32, 2.5, 0.5), (mr.GAUSSIAN_F32, -1.0, 3.0),
+    (mr.GAUSSIAN_F64, 2.5, 0.5), (mr.GAUSSIAN_F64, -1e3, 1e-3)])
 def test_range_and_moments_parameters(kind, p0, p1):
     n = 100003
     for off in (0, 4 if mr.ELEM_BYTES[kind] == 4 else 8):
@@ -90,6 +92,28 @@ def test_gaussian_odd_offset_pairs_path():
             got, buf = gh.generate(e, mr.GAUSSIAN_F32, n, 4)
             gh.assert_match(mr.GAUSSIAN_F32, got, gh.oracle_philox(5, pos, mr.GAUSSIAN_F32, n))
             assert gh.guards_intact(buf, 4, 4 * n)
+
+
+def test_gaussian64_misaligned_pairs_path():
+    """FP64 Gaussians at an output 8 mod 16 bytes (the pair would straddle
+    the 16-byte grid): slots anchored at the output; odd n drops the last
+    z1; every word phase."""
+    for pos in (0, 1, 2, 3, (1 << 66) - 1):
+        for n in (1, 2, 7, 1000, 65537):
+            e = mr.Engine(mr.PHILOX4X32_10, 6, 0)
+            e.skip_ahead(pos)
+            got, buf = gh.generate(e, mr.GAUSSIAN_F64, n, 8)
+            gh.assert_match(mr.GAUSSIAN_F64, got, gh.oracle_philox(6, pos, mr.GAUSSIAN_F64, n))
+            assert gh.guards_intact(buf, 8, 8 * n)
+
+
+def test_gaussian64_error_distribution():
+    """Worst error of 2^20 FP64 Gaussians in units of the tolerance."""
+    n = 1 << 20
+    e = mr.Engine(mr.PHILOX4X32_10, 2025, 0)
+    got, _ = gh.generate(e, mr.GAUSSIAN_F64, n)
+    worst = gh.assert_match(mr.GAUSSIAN_F64, got, gh.oracle_philox(2025, 0, mr.GAUSSIAN_F64, n))
+    print(f"worst FP64 Gaussian error: {worst:.3f} of the tolerance")
 
 
 def test_many_seeds_bits():
