@@ -108,6 +108,6 @@ def test_beyond_2p32_outputs(engine, kind, seed, offset):
         m = min(8192, n - start)
         got = raw[start * esz: (start + m) * esz].cpu().numpy().view(gh.NP_DTYPE[kind])
         gh.assert_match(kind, got, _expect_window(engine, kind, seed, offset, start, m))
-    assert e.position() == offset + mr.words_consumed(engine, kind, n)
+    assert e.position == offset + mr.words_consumed(engine, kind, n)
     del buf, raw
     torch.cuda.empty_cache()
