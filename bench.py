@@ -35,10 +35,11 @@ HBM_PEAK_GBS = 8000.0
 
 
 # HBM bytes per launch of the headline kernel from rocprofv3 counters:
-# WRITE_SIZE 1048576 KiB x 1.0 + FETCH_SIZE 21.5 KiB x 2.0, each scaled by
-# what the same counter reads for a plain 1 GiB device copy (WRITE 1048576
-# KiB, FETCH 524300.5 KiB).  Reset to None whenever the kernel changes.
-TRAFFIC_PER_LAUNCH = 1073741824 + 44032
+# WRITE_SIZE 1048576 KiB x 1.0 + FETCH_SIZE 26.94 KiB (median of five
+# launches) x 2.0, each scaled by what the same counter reads for a plain
+# 1 GiB device copy (WRITE 1048576 KiB, FETCH 524300 KiB).  Reset to None
+# whenever the kernel changes.
+TRAFFIC_PER_LAUNCH = 1073741824 + 55168
 
 
 def parse():
