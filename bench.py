@@ -71,6 +71,23 @@ def parse():
     return p.parse_args()
 
 
+def time_region(fn, reps, stream, warm=3):
+    """Average duration (ms) of `fn()` in steady state: `warm` untimed calls,
+    then `reps` back-to-back calls between two HIP events on `stream`.  (A
+    launch that follows an idle gap runs faster while the last-level cache
+    absorbs part of its writes; back-to-back calls pay for that.)"""
+    import torch
+    for _ in range(warm):
+        fn()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(reps):
+        fn()
+    b.record(stream)
+    stream.synchronize()
+    return a.elapsed_time(b) / reps
+
+
 def time_kernel_calls(fn, reps, stream):
     """Average duration (ms) of `fn()` over `reps` calls, each bracketed by
     HIP events recorded on `stream` (the stream the kernels run on)."""
@@ -185,7 +202,7 @@ def calo_batch_leg(mr, synth, torch, stream, dev, reps=20, tune=True, windows=5,
         wins.append((time.perf_counter() - t0) * 1e3 / per_window)
     wins.sort()
     ms_pipe = wins[len(wins) // 2]
-    gpu_ms = time_kernel_calls(lambda: b.generate(reqs, stream=stream), reps, stream)[0]
+    gpu_ms = time_region(lambda: b.generate(reqs, stream=stream), reps, stream)
     lat = []
     for _ in range(reps):
         t1 = time.perf_counter()
@@ -201,7 +218,7 @@ def calo_batch_leg(mr, synth, torch, stream, dev, reps=20, tune=True, windows=5,
         mr.Engine(mr.PHILOX4X32_10, 43, 0).generate(mr.GAUSSIAN_F32, n_g, out, stream=stream)
 
     plain()
-    plain_ms = time_kernel_calls(plain, reps, stream)[0]
+    plain_ms = time_region(plain, reps, stream)
     return {"events": ev.n_events, "requests": len(reqs), "samples": total,
             "bytes": total * 4, "config": b.config.as_dict(), "autotune": tuned,
             "ms_per_batch_pipelined": round(ms_pipe, 4),
@@ -461,7 +478,7 @@ def main():
     if not args.shape and not args.no_tune:
         t_tune = time.perf_counter()
         cfg, tms = mr.autotune_philox(mr.UNIFORM_F32, n, out, stream=stream, prewarm_ms=300,
-                                      rounds=5, reps=10)
+                                      rounds=3, reps=30)
         tuned = {"config": cfg.as_dict(), "ms": round(tms, 4),
                  "tuning_s": round(time.perf_counter() - t_tune, 3)}
 
@@ -513,13 +530,15 @@ def main():
     if not args.quick:
         # ceilings on the same GPU
         buf = torch.empty(n * 4, dtype=torch.uint8, device=dev)
-        st_ms = time_kernel_calls(lambda: mr.bench_store(buf, n * 4, True, stream), 20, stream)[0]
-        st2_ms = time_kernel_calls(lambda: mr.bench_store(buf, n * 4, False, stream), 20,
-                                   stream)[0]
+        st_ms = time_region(lambda: mr.bench_store(buf, n * 4, True, stream), 30, stream)
+        st2_ms = time_region(lambda: mr.bench_store(buf, n * 4, False, stream), 30, stream)
         sink = torch.empty(n // 4 // 64 + 64, dtype=torch.int32, device=dev)
         ns_ms = time_kernel_calls(lambda: mr.bench_philox_nostore(n // 4, sink, stream=stream),
                                   20, stream)[0]
+        with torch.cuda.stream(stream):
+            fill_ms = time_region(lambda: buf.zero_(), 30, stream)
         extra["ceilings"] = {
+            "runtime_fill_GBs": round(n * 4 / (fill_ms * 1e-3) / 1e9, 1),
             "store_only_nt_GBs": round(n * 4 / (st_ms * 1e-3) / 1e9, 1),
             "store_only_GBs": round(n * 4 / (st2_ms * 1e-3) / 1e9, 1),
             "philox_nostore_Gsamples_s": round(n / (ns_ms * 1e-3) / 1e9, 1),
@@ -543,7 +562,7 @@ def main():
                 mr.Engine(engine, s, o).generate(kind, n, big, stream=stream)
 
             gen()
-            ms = time_kernel_calls(gen, 10, stream)[0]
+            ms = time_region(gen, 20, stream)
             nbytes = n * synth.ELEM_BYTES[kind]
             res[name] = {"ms": round(ms, 4), "Gsamples_s": round(n / (ms * 1e-3) / 1e9, 1),
                          "GBs": round(nbytes / (ms * 1e-3) / 1e9, 1),
@@ -556,7 +575,7 @@ def main():
                                   stream=stream)
 
         subs()
-        ms = time_kernel_calls(subs, 10, stream)[0]
+        ms = time_region(subs, 20, stream)
         tot = cfg["count"] * cfg["per_stream"]
         res["mrg32k3a/substreams_65536x4096_f64"] = {
             "ms": round(ms, 4), "Gsamples_s": round(tot / (ms * 1e-3) / 1e9, 1),

@@ -2,6 +2,9 @@
 // HIP events and installs the fastest.  Candidates are measured in
 // interleaved rounds after a pre-warm, so that clock ramp-up and drift do
 // not favour whichever shape runs first; the score is the median round.
+// Each measurement follows a few untimed launches of the same shape, so
+// that it sees the steady state of back-to-back launches (a launch after
+// an idle gap runs faster while the last-level cache absorbs its writes).
 #include <algorithm>
 #include <chrono>
 #include <functional>
@@ -10,6 +13,8 @@
 #include "internal.hpp"
 
 namespace {
+
+constexpr int kWarm = 3;   // untimed launches before each measurement
 
 // Time `reps` back-to-back calls of run(); ms per call, or < 0 on error.
 float time_reps(const std::function<mirng_status()> &run, hipStream_t s, int reps,
@@ -47,7 +52,7 @@ int tune(size_t count, const std::function<void(size_t)> &apply,
     for (int r = 0; ok && r < rounds; ++r) {
         for (size_t i = 0; ok && i < count; ++i) {
             apply(i);
-            ok = time_reps(run, s, 1, a, b) >= 0.0f;     // first launch after a change
+            for (int w = 0; ok && w < kWarm; ++w) ok = run() == MIRNG_OK;   // untimed
             const float ms = ok ? time_reps(run, s, reps, a, b) : -1.0f;
             ok = ms >= 0.0f;
             t[i].push_back(ms);
