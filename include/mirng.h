@@ -272,12 +272,17 @@ mirng_status mirng_batcher_config_set(mirng_batcher b, const mirng_batch_config 
  *   output grid-stride, blocks_per_lane Philox blocks per lane per step;
  *   used where outputs do not straddle Philox blocks (bits and uniform FP32
  *   at any position, FP64 and Gaussian at even positions), walk 0 elsewhere.
+ * walk 2: each wave writes blocks_per_lane independent chunks of 64
+ *   16-byte outputs (63 when the position is not a multiple of 4 on the
+ *   16-byte grid; the last lane then only supplies words to its neighbour);
+ *   the grid size follows from n (any kind, any position).
  * Process-wide; set it while no generate call is being enqueued. */
 typedef struct {
-    int32_t walk;             /* 0 contiguous runs, 1 grid-stride               */
+    int32_t walk;             /* 0 contiguous runs, 1 grid-stride, 2 chunks      */
     int32_t block;            /* threads per workgroup: 64, 128, 256, 512, 1024 */
-    int32_t waves_per_cu;     /* walk 0: 1..4096; walk 1: 1..64                  */
-    int32_t blocks_per_lane;  /* walk 1: 1, 2 or 4 (ignored by walk 0)          */
+    int32_t waves_per_cu;     /* walk 0: 1..4096; walk 1: 1..64; walk 2: 1..4096, unused */
+    int32_t blocks_per_lane;  /* walk 1: blocks per lane per step; walk 2: chunks
+                                 per wave; 1, 2 or 4 (ignored by walk 0)           */
     int32_t nontemporal;      /* 0: plain stores, 1: streaming (nt) stores       */
     int32_t reserved;         /* must be 0 */
 } mirng_philox_config;

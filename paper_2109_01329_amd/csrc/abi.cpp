@@ -34,7 +34,7 @@ bool philox_config_valid(const mirng_philox_config &c)
     const bool block_ok = c.block == 64 || c.block == 128 || c.block == 256 ||
                           c.block == 512 || c.block == 1024;
     const int wmax = c.walk == 1 ? 64 : 4096;
-    return (c.walk == 0 || c.walk == 1) && block_ok && c.waves_per_cu >= 1 &&
+    return (c.walk == 0 || c.walk == 1 || c.walk == 2) && block_ok && c.waves_per_cu >= 1 &&
            c.waves_per_cu <= wmax &&
            (c.blocks_per_lane == 1 || c.blocks_per_lane == 2 || c.blocks_per_lane == 4) &&
            (c.nontemporal == 0 || c.nontemporal == 1) && c.reserved == 0;
@@ -203,9 +203,17 @@ hipError_t philox_plain(const uint32_t key[2], Pos130 p, const mirng_distributio
             r.n = chunk;
             const uint64_t nslots = (head + chunk + epv - 1) / epv;
             a.nslots = (uint32_t)nslots;
-            const uint64_t waves_target = cus * (uint64_t)(tu.walk == 0 ? tu.waves_per_cu : 256);
-            const uint64_t iters = (nslots + 64 * waves_target - 1) / (64 * waves_target);
-            a.slots_per_wave = (uint32_t)((iters ? iters : 1) * 64);
+            if (tu.walk == 2) {
+                a.iters = (uint32_t)tu.blocks_per_lane;
+                const bool split = a.phase && splittable(kind, (int)a.phase);
+                a.slots_per_wave = a.iters * (a.phase && !split ? 63u : 64u);
+            } else {
+                const uint64_t waves_target =
+                    cus * (uint64_t)(tu.walk == 0 ? tu.waves_per_cu : 256);
+                const uint64_t iters = (nslots + 64 * waves_target - 1) / (64 * waves_target);
+                a.slots_per_wave = (uint32_t)((iters ? iters : 1) * 64);
+                a.iters = 0;
+            }
             const uint64_t lo = head ? 1 : 0;
             const uint64_t hi = (head + chunk) / epv;   // slots below hi end inside n
             r.full_lo = (uint32_t)lo;
@@ -213,7 +221,7 @@ hipError_t philox_plain(const uint32_t key[2], Pos130 p, const mirng_distributio
             r.out_base = at_out ? out : out - (addr & 15u);
             r.ep = ep;
             a.kind = kind;
-            a.block = (uint32_t)(tu.walk == 0 ? tu.block : 1024);
+            a.block = (uint32_t)(tu.walk == 1 ? 1024 : tu.block);
             err = launch_philox_fill(a, s);
         }
         if (err != hipSuccess) return err;

@@ -144,10 +144,11 @@ mirng_status mirng_bench_store(void *out, uint64_t bytes, int32_t nontemporal, v
     const uint64_t nvec = bytes / 16;
     uint64_t groups;
     uint32_t vpw = 0;
-    if (tu.walk == 0) {
+    if (tu.walk == 0 || tu.walk == 2) {
         const uint64_t waves_target = (uint64_t)device_cu_count() * tu.waves_per_cu;
         const uint64_t iters = (nvec + 64 * waves_target - 1) / (64 * waves_target);
-        const uint64_t per_wave = (iters ? iters : 1) * 64;
+        const uint64_t per_wave = tu.walk == 2 ? 64ull * tu.blocks_per_lane
+                                               : (iters ? iters : 1) * 64;
         if (per_wave >= (1ull << 32)) return MIRNG_E_INVALID_ARG;
         vpw = (uint32_t)per_wave;
         const uint64_t waves = (nvec + per_wave - 1) / per_wave;

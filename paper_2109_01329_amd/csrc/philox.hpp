@@ -202,4 +202,97 @@ __device__ __forceinline__ void walk_slots(const SlotRun &r, uint32_t s0, uint32
     }
 }
 
+// Elements [jlo, jhi) of slot `slot` (those inside the output), from the
+// words w of which only the ones these elements use need be valid.
+template <int KIND>
+__device__ __forceinline__ void emit_part(const SlotRun &r, uint32_t slot, u32x4 w, int jlo,
+                                          int jhi)
+{
+    constexpr int ESZ = elem_bytes(KIND);
+    constexpr int EPV = 16 / ESZ;
+    const u32x4 v = transform<KIND>(r.ep, w);
+    const int64_t e0 = (int64_t)slot * EPV - (int64_t)r.head;
+    char *p = r.out_base + (uint64_t)slot * 16u;
+#pragma unroll
+    for (int j = 0; j < EPV; ++j) {
+        const int64_t e = e0 + j;
+        if (j >= jlo && j < jhi && e >= 0 && e < (int64_t)r.n) {
+            if constexpr (ESZ == 4)
+                ((uint32_t *)p)[j] = v[j];
+            else
+                ((uint64_t *)p)[j] = ((uint64_t)v[2 * j + 1] << 32) | v[2 * j];
+        }
+    }
+}
+
+// Split chunks (PHASE != 0, splittable kinds): a wave writes ITERS chunks of
+// 64 slots at 64-slot boundaries.  Lanes 0..62 take the words they lack
+// from lane L + 1; lane 63 writes only the elements of its slot that come
+// from its own block, and lane 0 writes the rest of the slot before its
+// chunk (the head of its own block), so every block is evaluated once and
+// every store stays on the chunk's 1 KiB grid.  The grid covers one chunk
+// past the last slot, whose lane 0 completes that slot.  `span` counts the
+// wave's slots inside the run, nslots the run's slots.
+template <int KIND, int PHASE, int ITERS>
+__device__ __forceinline__ void walk_split(const SlotRun &r, uint32_t s0, uint32_t span,
+                                           uint32_t nslots, uint32_t lane)
+{
+    constexpr int TAIL = (4 - PHASE) / philox_words_per_elem(KIND);   // elements from block s
+    constexpr int EPV = 16 / elem_bytes(KIND);
+    u32x4 b[ITERS];
+#pragma unroll
+    for (int it = 0; it < ITERS; ++it) b[it] = block_at(r.base, r.k0, r.k1, s0 + it * 64u + lane);
+#pragma unroll
+    for (int it = 0; it < ITERS; ++it) {
+        const uint32_t off = it * 64u + lane;
+        const uint32_t c0 = s0 + it * 64u;                // first slot of this chunk
+        u32x4 nb;
+        nb.x = from_next_lane(b[it].x, 0u);
+        if constexpr (PHASE >= 2) nb.y = from_next_lane(b[it].y, 0u);
+        if constexpr (PHASE >= 3) nb.z = from_next_lane(b[it].z, 0u);
+        const u32x4 w = funnel<PHASE>(b[it], nb);
+        if (off < span) {
+            if (lane < 63u)
+                emit_slot<KIND>(r, s0 + off, w);
+            else
+                emit_part<KIND>(r, s0 + off, w, 0, TAIL);
+        }
+        if (lane == 0u && c0 > 0u && c0 - 1u < nslots)
+            emit_part<KIND>(r, c0 - 1u, funnel<PHASE>(b[it], b[it]), TAIL, EPV);
+    }
+}
+
+// Chunked walk: a wave writes ITERS consecutive chunks of S slots, S = 64
+// for PHASE 0 and 63 otherwise.  For PHASE != 0 lane L's slot takes its
+// missing words from lane L + 1's block, and lane 63 only evaluates the
+// block whose head lane 62 needs (it stores nothing), so chunks are
+// independent: all ITERS blocks of a lane are evaluated together (ILP) and
+// a wave needs no look-ahead across chunks.  Short runs of whole chunks per
+// wave keep the waves in flight on one compact, moving window of memory.
+// Must be called by whole waves.
+template <int KIND, int PHASE, int ITERS>
+__device__ __forceinline__ void walk_chunks(const SlotRun &r, uint32_t s0, uint32_t span,
+                                            uint32_t lane)
+{
+    constexpr uint32_t S = PHASE ? 63u : 64u;
+    u32x4 b[ITERS];
+#pragma unroll
+    for (int it = 0; it < ITERS; ++it) b[it] = block_at(r.base, r.k0, r.k1, s0 + it * S + lane);
+#pragma unroll
+    for (int it = 0; it < ITERS; ++it) {
+        const uint32_t off = it * S + lane;
+        u32x4 w;
+        if constexpr (PHASE == 0) {
+            w = b[it];
+        } else {
+            u32x4 nb;
+            nb.x = from_next_lane(b[it].x, 0u);
+            if constexpr (PHASE >= 2) nb.y = from_next_lane(b[it].y, 0u);
+            if constexpr (PHASE >= 3) nb.z = from_next_lane(b[it].z, 0u);
+            w = funnel<PHASE>(b[it], nb);
+        }
+        if (lane < S && off < span) emit_slot<KIND>(r, s0 + off, w);
+    }
+}
+
 }  // namespace mirng

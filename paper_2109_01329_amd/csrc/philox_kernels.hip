@@ -10,10 +10,15 @@
 // evaluates the Philox block of slot s0 + 64 i + L, so a wave writes 1 KiB
 // contiguously per step.  When the engine position is not a multiple of 4
 // relative to the 16-byte grid, slot s needs the tail of block b and the
-// head of block b + 1: lane L takes those words from lane L + 1
-// (ds_bpermute), and lane 63 from lane 0 of the wave's next step, which is
-// computed one step ahead; the extra block per run is 1/steps.  All stores
-// stay 16-byte aligned.
+// head of block b + 1: lane L takes those words from lane L + 1 (one DPP
+// wavefront shift), and lane 63 from lane 0 of the wave's next step, which
+// is computed one step ahead; the extra block per run is 1/steps.  All
+// stores stay 16-byte aligned.
+//
+// Chunked walk (philox_chunk_kernel).  As the contiguous walk, but each
+// wave writes only 1, 2 or 4 chunks of 64 slots (63 at odd phases, where
+// lane 63 just supplies its block's head to lane 62), evaluated together.
+// Many waves of 1-4 KiB keep the in-flight stores on one compact window.
 //
 // Grid-stride walk (philox_blocks_kernel, selectable).  Whenever outputs do
 // not straddle Philox blocks (bits and uniform FP32 at any position; FP64
@@ -79,6 +84,50 @@ __global__ __launch_bounds__(1024) void philox_fill_kernel(PhiloxFill a)
     walk_slots<KIND, PHASE>(a.run, s0, min(a.slots_per_wave, a.nslots - s0), lane);
 }
 
+// ---------------------------------------------------------------- chunked walk
+
+template <int KIND, int PHASE, int ITERS>
+__global__ __launch_bounds__(1024) void philox_chunk_kernel(PhiloxFill a)
+{
+    constexpr bool SPLIT = PHASE != 0 && splittable(KIND, PHASE);
+    constexpr uint32_t PER = (PHASE && !SPLIT ? 63u : 64u) * ITERS;   // slots per wave
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const uint64_t first = wave * PER;
+    if constexpr (SPLIT) {
+        // the grid covers one chunk past the run (see walk_split)
+        if (first > a.nslots) return;
+        const uint32_t s0 = (uint32_t)first;
+        walk_split<KIND, PHASE, ITERS>(a.run, s0, min(PER, a.nslots - s0), a.nslots, lane);
+    } else {
+        if (first >= a.nslots) return;
+        const uint32_t s0 = (uint32_t)first;
+        walk_chunks<KIND, PHASE, ITERS>(a.run, s0, min(PER, a.nslots - s0), lane);
+    }
+}
+
+template <int KIND, int PHASE>
+void launch_chunk_phase(const PhiloxFill &a, dim3 grid, dim3 block, hipStream_t s)
+{
+    switch (a.iters) {
+    case 4: hipLaunchKernelGGL((philox_chunk_kernel<KIND, PHASE, 4>), grid, block, 0, s, a); break;
+    case 2: hipLaunchKernelGGL((philox_chunk_kernel<KIND, PHASE, 2>), grid, block, 0, s, a); break;
+    default: hipLaunchKernelGGL((philox_chunk_kernel<KIND, PHASE, 1>), grid, block, 0, s, a); break;
+    }
+}
+
+template <int KIND>
+hipError_t launch_chunk_kind(const PhiloxFill &a, dim3 grid, dim3 block, hipStream_t s)
+{
+    switch (a.phase) {
+    case 0: launch_chunk_phase<KIND, 0>(a, grid, block, s); break;
+    case 1: launch_chunk_phase<KIND, 1>(a, grid, block, s); break;
+    case 2: launch_chunk_phase<KIND, 2>(a, grid, block, s); break;
+    default: launch_chunk_phase<KIND, 3>(a, grid, block, s); break;
+    }
+    return hipGetLastError();
+}
+
 template <int KIND>
 hipError_t launch_blocks_kind(const PhiloxBlocks &a, hipStream_t s)
 {
@@ -119,9 +168,22 @@ hipError_t launch_philox_blocks(const PhiloxBlocks &a, hipStream_t s)
 hipError_t launch_philox_fill(const PhiloxFill &a, hipStream_t s)
 {
     const uint32_t waves_per_block = a.block / 64u;
-    const uint64_t waves = ((uint64_t)a.nslots + a.slots_per_wave - 1) / a.slots_per_wave;
+    // split chunks need one chunk past the run (its lane 0 completes the
+    // run's last slot)
+    const uint64_t cover = (uint64_t)a.nslots +
+                           (a.iters && a.phase && splittable(a.kind, (int)a.phase) ? 1u : 0u);
+    const uint64_t waves = (cover + a.slots_per_wave - 1) / a.slots_per_wave;
     const dim3 grid((uint32_t)((waves + waves_per_block - 1) / waves_per_block));
     const dim3 block(a.block);
+    if (a.iters) {
+        switch (a.kind) {
+        case kBits: return launch_chunk_kind<kBits>(a, grid, block, s);
+        case kU32F: return launch_chunk_kind<kU32F>(a, grid, block, s);
+        case kU64F: return launch_chunk_kind<kU64F>(a, grid, block, s);
+        case kGauss: return launch_chunk_kind<kGauss>(a, grid, block, s);
+        default: return launch_chunk_kind<kGauss64>(a, grid, block, s);
+        }
+    }
     switch (a.kind) {
     case kBits: return launch_fill_kind<kBits>(a, grid, block, s);
     case kU32F: return launch_fill_kind<kU32F>(a, grid, block, s);
