@@ -280,7 +280,7 @@ mirng_status mirng_batcher_config_set(mirng_batcher b, const mirng_batch_config 
 typedef struct {
     int32_t walk;             /* 0 contiguous runs, 1 grid-stride, 2 chunks      */
     int32_t block;            /* threads per workgroup: 64, 128, 256, 512, 1024 */
-    int32_t waves_per_cu;     /* walk 0: 1..4096; walk 1: 1..64; walk 2: 1..4096, unused */
+    int32_t waves_per_cu;     /* 1..4096 (walk 1: waves in the grid; walk 2: unused) */
     int32_t blocks_per_lane;  /* walk 1: blocks per lane per step; walk 2: chunks
                                  per wave; 1, 2 or 4 (ignored by walk 0)           */
     int32_t nontemporal;      /* 0: plain stores, 1: streaming (nt) stores       */

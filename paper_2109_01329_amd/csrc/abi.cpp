@@ -33,7 +33,7 @@ bool philox_config_valid(const mirng_philox_config &c)
 {
     const bool block_ok = c.block == 64 || c.block == 128 || c.block == 256 ||
                           c.block == 512 || c.block == 1024;
-    const int wmax = c.walk == 1 ? 64 : 4096;
+    const int wmax = 4096;
     return (c.walk == 0 || c.walk == 1 || c.walk == 2) && block_ok && c.waves_per_cu >= 1 &&
            c.waves_per_cu <= wmax &&
            (c.blocks_per_lane == 1 || c.blocks_per_lane == 2 || c.blocks_per_lane == 4) &&
