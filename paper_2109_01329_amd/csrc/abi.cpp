@@ -205,8 +205,7 @@ hipError_t philox_plain(const uint32_t key[2], Pos130 p, const mirng_distributio
             a.nslots = (uint32_t)nslots;
             if (tu.walk == 2) {
                 a.iters = (uint32_t)tu.blocks_per_lane;
-                const bool split = a.phase && splittable(kind, (int)a.phase);
-                a.slots_per_wave = a.iters * (a.phase && !split ? 63u : 64u);
+                a.slots_per_wave = a.iters * (a.phase ? 63u : 64u);
             } else {
                 const uint64_t waves_target =
                     cus * (uint64_t)(tu.walk == 0 ? tu.waves_per_cu : 256);

@@ -64,15 +64,6 @@ constexpr int elem_bytes(int kind) { return (kind == kU64F || kind == kGauss64) 
 constexpr int philox_words_per_elem(int kind) { return (kind == kU64F || kind == kGauss64) ? 2 : 1; }
 // Kinds whose outputs come in pairs from one Box-Muller transform.
 constexpr bool paired(int kind) { return kind == kGauss || kind == kGauss64; }
-// At word phase p (slot s = words p .. p + 3 of blocks s and s + 1), no
-// output element (or Box-Muller pair) of a slot takes words from both
-// blocks: the slot can be written in two parts, by the lanes holding the
-// two blocks.
-constexpr bool splittable(int kind, int phase)
-{
-    return phase == 0 || kind == kBits || kind == kU32F ||
-           (phase == 2 && (kind == kU64F || kind == kGauss));
-}
 
 // Output epilogue parameters shared by the generation kernels.
 struct Epilogue {

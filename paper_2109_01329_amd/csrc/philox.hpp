@@ -202,87 +202,6 @@ __device__ __forceinline__ void walk_slots(const SlotRun &r, uint32_t s0, uint32
     }
 }
 
-// Elements [JLO, JHI) of slot `slot`, from the words w of which only the
-// ones these elements use need be valid: one store of (JHI - JLO) elements
-// when they all lie inside the output, else element by element.
-template <int KIND, int JLO, int JHI>
-__device__ __forceinline__ void emit_part(const SlotRun &r, uint32_t slot, u32x4 w)
-{
-    constexpr int ESZ = elem_bytes(KIND);
-    constexpr int EPV = 16 / ESZ;
-    constexpr int WORDS = (JHI - JLO) * ESZ / 4;
-    const u32x4 v = transform<KIND>(r.ep, w);
-    const int64_t e0 = (int64_t)slot * EPV - (int64_t)r.head;
-    char *p = r.out_base + (uint64_t)slot * 16u + JLO * ESZ;
-    const uint32_t *src = (const uint32_t *)&v + JLO * ESZ / 4;
-    if (e0 + JLO >= 0 && e0 + JHI <= (int64_t)r.n) {
-        if constexpr (WORDS == 1) {
-            *(uint32_t *)p = src[0];
-        } else if constexpr (WORDS == 2) {
-            *(uint2 *)p = make_uint2(src[0], src[1]);
-        } else {
-            *(uint3 *)p = make_uint3(src[0], src[1], src[2]);
-        }
-        return;
-    }
-#pragma unroll
-    for (int j = JLO; j < JHI; ++j) {
-        const int64_t e = e0 + j;
-        if (e >= 0 && e < (int64_t)r.n) {
-            if constexpr (ESZ == 4)
-                ((uint32_t *)(r.out_base + (uint64_t)slot * 16u))[j] = v[j];
-            else
-                ((uint64_t *)(r.out_base + (uint64_t)slot * 16u))[j] =
-                    ((uint64_t)v[2 * j + 1] << 32) | v[2 * j];
-        }
-    }
-}
-
-// Split runs (PHASE != 0, splittable kinds): a wave writes ITERS chunks of
-// 64 slots at 64-slot boundaries.  Inside the wave, slot s takes the words
-// it lacks from lane L + 1, and lane 63 of a chunk from lane 0 of the next
-// chunk, as in the contiguous walk.  The wave's last slot is written in two
-// parts: its lane 63 stores the elements that come from its own block, and
-// lane 0 of the following wave stores the rest (the head of that wave's
-// first block).  Every block is evaluated once, and all full stores stay on
-// the run's 1 KiB grid.  The grid covers one wave past the run, whose lane 0
-// completes the run's last slot.  `span` counts the wave's slots inside the
-// run, nslots the run's slots.
-template <int KIND, int PHASE, int ITERS>
-__device__ __forceinline__ void walk_split(const SlotRun &r, uint32_t s0, uint32_t span,
-                                           uint32_t nslots, uint32_t lane)
-{
-    constexpr int TAIL = (4 - PHASE) / philox_words_per_elem(KIND);   // elements from block s
-    constexpr int EPV = 16 / elem_bytes(KIND);
-    u32x4 b[ITERS];
-#pragma unroll
-    for (int it = 0; it < ITERS; ++it) b[it] = block_at(r.base, r.k0, r.k1, s0 + it * 64u + lane);
-    if (lane == 0u && s0 > 0u && s0 - 1u < nslots)
-        emit_part<KIND, TAIL, EPV>(r, s0 - 1u, funnel<PHASE>(b[0], b[0]));
-#pragma unroll
-    for (int it = 0; it < ITERS; ++it) {
-        const uint32_t off = it * 64u + lane;
-        // lane 63 takes lane 0's block of the next chunk (none after the last)
-        u32x4 nb;
-        if (it + 1 < ITERS) {
-            nb.x = from_next_lane(b[it].x, lane0(b[it + 1].x));
-            if constexpr (PHASE >= 2) nb.y = from_next_lane(b[it].y, lane0(b[it + 1].y));
-            if constexpr (PHASE >= 3) nb.z = from_next_lane(b[it].z, lane0(b[it + 1].z));
-        } else {
-            nb.x = from_next_lane(b[it].x, 0u);
-            if constexpr (PHASE >= 2) nb.y = from_next_lane(b[it].y, 0u);
-            if constexpr (PHASE >= 3) nb.z = from_next_lane(b[it].z, 0u);
-        }
-        const u32x4 w = funnel<PHASE>(b[it], nb);
-        if (off < span) {
-            if (it + 1 < ITERS || lane < 63u)
-                emit_slot<KIND>(r, s0 + off, w);
-            else
-                emit_part<KIND, 0, TAIL>(r, s0 + off, w);
-        }
-    }
-}
-
 // Chunked walk: a wave writes ITERS consecutive chunks of S slots, S = 64
 // for PHASE 0 and 63 otherwise.  For PHASE != 0 lane L's slot takes its
 // missing words from lane L + 1's block, and lane 63 only evaluates the

@@ -89,21 +89,13 @@ __global__ __launch_bounds__(1024) void philox_fill_kernel(PhiloxFill a)
 template <int KIND, int PHASE, int ITERS>
 __global__ __launch_bounds__(1024) void philox_chunk_kernel(PhiloxFill a)
 {
-    constexpr bool SPLIT = PHASE != 0 && splittable(KIND, PHASE);
-    constexpr uint32_t PER = (PHASE && !SPLIT ? 63u : 64u) * ITERS;   // slots per wave
+    constexpr uint32_t PER = (PHASE ? 63u : 64u) * ITERS;   // slots per wave
     const uint32_t lane = threadIdx.x & 63u;
     const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     const uint64_t first = wave * PER;
-    if constexpr (SPLIT) {
-        // the grid covers one chunk past the run (see walk_split)
-        if (first > a.nslots) return;
-        const uint32_t s0 = (uint32_t)first;
-        walk_split<KIND, PHASE, ITERS>(a.run, s0, min(PER, a.nslots - s0), a.nslots, lane);
-    } else {
-        if (first >= a.nslots) return;
-        const uint32_t s0 = (uint32_t)first;
-        walk_chunks<KIND, PHASE, ITERS>(a.run, s0, min(PER, a.nslots - s0), lane);
-    }
+    if (first >= a.nslots) return;
+    const uint32_t s0 = (uint32_t)first;
+    walk_chunks<KIND, PHASE, ITERS>(a.run, s0, min(PER, a.nslots - s0), lane);
 }
 
 template <int KIND, int PHASE>
@@ -168,11 +160,7 @@ hipError_t launch_philox_blocks(const PhiloxBlocks &a, hipStream_t s)
 hipError_t launch_philox_fill(const PhiloxFill &a, hipStream_t s)
 {
     const uint32_t waves_per_block = a.block / 64u;
-    // split chunks need one chunk past the run (its lane 0 completes the
-    // run's last slot)
-    const uint64_t cover = (uint64_t)a.nslots +
-                           (a.iters && a.phase && splittable(a.kind, (int)a.phase) ? 1u : 0u);
-    const uint64_t waves = (cover + a.slots_per_wave - 1) / a.slots_per_wave;
+    const uint64_t waves = ((uint64_t)a.nslots + a.slots_per_wave - 1) / a.slots_per_wave;
     const dim3 grid((uint32_t)((waves + waves_per_block - 1) / waves_per_block));
     const dim3 block(a.block);
     if (a.iters) {
