@@ -53,8 +53,8 @@ def parse():
     p.add_argument("--quick", action="store_true", help="headline only")
     p.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
     p.add_argument("--shape", default=None,
-                   help="block,waves_per_cu,nontemporal: install this Philox launch shape "
-                        "(walk 0) instead of autotuning")
+                   help="walk,block,waves_per_cu,blocks_per_lane,nontemporal: install this "
+                        "Philox launch shape instead of autotuning")
     p.add_argument("--no-tune", action="store_true",
                    help="keep the library's default launch shape instead of autotuning it on "
                         "the headline workload before the timed region")
@@ -424,8 +424,8 @@ def main():
         return e
 
     if args.shape:
-        blk, wpc, nt = (int(x) for x in args.shape.split(","))
-        mr.set_philox_config(walk=0, block=blk, waves_per_cu=wpc, blocks_per_lane=1,
+        walk, blk, wpc, bpl, nt = (int(x) for x in args.shape.split(","))
+        mr.set_philox_config(walk=walk, block=blk, waves_per_cu=wpc, blocks_per_lane=bpl,
                              nontemporal=nt)
 
     if args.profile_cells:
