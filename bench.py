@@ -41,6 +41,8 @@ HBM_PEAK_GBS = 8000.0
 # (WRITE 1048576 KiB, FETCH 524300 KiB).  Reset to None whenever the kernel
 # changes.
 TRAFFIC_PER_LAUNCH = 1073741824 + 43008
+TRAFFIC_SHAPE = {"walk": 0, "block": 1024, "waves_per_cu": 256, "blocks_per_lane": 1,
+                 "nontemporal": 1, "reserved": 0}
 
 
 def parse():
@@ -520,7 +522,8 @@ def main():
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": TRAFFIC_PER_LAUNCH,
+                "traffic": (TRAFFIC_PER_LAUNCH
+                            if mr.philox_config().as_dict() == TRAFFIC_SHAPE else None),
                 "kernel": "philox_fill_kernel<uniform_f32>",
                 "kernel_ms": {"avg": round(avg_ms, 4),
                               "bracketed_avg": round(b_avg, 4), "bracketed_median": round(b_med, 4),
