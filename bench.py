@@ -234,6 +234,46 @@ def calo_batch_leg(mr, synth, torch, stream, dev, reps=20, tune=True, windows=5,
             "batch_over_plain_time": round(ms_pipe / plain_ms, 3)}
 
 
+def scenario_leg(mr, synth, torch, stream, dev):
+    """FastCaloSim-shaped event batches (the paper's Sec. 5.2 scenarios):
+    single-electron events (10^4 events of 4000-6500 hits) and ttbar events
+    (500 events of 600-800 times as many hits), three uniform FP32 per hit,
+    one Philox request per event on key (42, event id), outputs contiguous
+    per event.  Each scenario is one batched launch, timed in steady state,
+    against the plain path generating the same total in one launch."""
+    import numpy as np
+    res = {}
+    for name, reps in (("single_electron", 20), ("ttbar", 5)):
+        sc = synth.calo_scenario(name)
+        sizes = sc.uniforms.astype(np.uint64)
+        total = int(sizes.sum())
+        out = torch.empty(total, dtype=torch.float32, device=dev)
+        offs = np.concatenate([[0], np.cumsum(sizes * 4)])[:-1].astype(np.uint64)
+        reqs = mr.make_requests(sc.n_events)
+        reqs["engine_type"] = mr.PHILOX4X32_10
+        reqs["kind"] = mr.UNIFORM_F32
+        reqs["p1"] = 1.0
+        reqs["seed"] = (np.arange(sc.n_events, dtype=np.uint64) << np.uint64(32)) | \
+            np.uint64(sc.seed32)
+        reqs["n"] = sizes
+        reqs["out"] = np.uint64(out.data_ptr()) + offs
+        b = mr.Batcher()
+        b.generate(reqs, stream=stream)
+        batch_ms = time_region(lambda: b.generate(reqs, stream=stream), reps, stream)
+        assert np.all(b.statuses(sc.n_events) == 0)
+        e = mr.Engine(mr.PHILOX4X32_10, 42, 0)
+        plain_ms = time_region(lambda: e.generate(mr.UNIFORM_F32, total, out, stream=stream),
+                               reps, stream)
+        res[name] = {"events": sc.n_events, "samples": total, "bytes": total * 4,
+                     "batch_ms": round(batch_ms, 4),
+                     "batch_GBs": round(total * 4 / (batch_ms * 1e-3) / 1e9, 1),
+                     "plain_ms": round(plain_ms, 4),
+                     "batch_over_plain_time": round(batch_ms / plain_ms, 3)}
+        b.close()
+        del out
+    return res
+
+
 def serve_leg(mr, synth, torch, dev, cells=None, counts=(2000, 20000, 20000), streams=4,
               capacity=32 * 10**9, ring_gib=64):
     """Serving loop under open-loop Poisson arrivals at 1e3, 1e4 and 1e5
@@ -588,6 +628,7 @@ def main():
         extra["cells"] = res
         del big, buf
         extra["batched"] = calo_batch_leg(mr, synth, torch, stream, dev)
+        extra["fastcalosim_scenarios"] = scenario_leg(mr, synth, torch, stream, dev)
         extra["serving"] = serve_leg(mr, synth, torch, dev, cells=res)
         extra["burner_tts"] = tts_leg(mr, torch)
 

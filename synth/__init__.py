@@ -101,6 +101,39 @@ def calo_events(n_events: int = 20000, median: float = 2000.0,
     return EventBatch(hits=h)
 
 
+# --- FastCaloSim-shaped scenarios (Sec. 5.2 of the paper) ------------------
+@dataclasses.dataclass
+class CaloScenario:
+    name: str
+    hits: np.ndarray          # hits per event
+    seed32: int = 42
+
+    @property
+    def n_events(self) -> int:
+        return int(self.hits.size)
+
+    @property
+    def uniforms(self) -> np.ndarray:
+        """Three uniforms per hit, per event."""
+        return 3 * self.hits
+
+
+def calo_scenario(name: str, n_events: int | None = None, k: int = 7) -> CaloScenario:
+    """Single-electron events: 4000-6500 hits each (10^4 events, as in the
+    paper's results); ttbar events: 600-800 times as many hits (500
+    events).  Hit counts uniform over those ranges."""
+    g = rng(k)
+    if name == "single_electron":
+        n = 10000 if n_events is None else n_events
+        hits = g.integers(4000, 6501, n)
+    elif name == "ttbar":
+        n = 500 if n_events is None else n_events
+        hits = (g.integers(4000, 6501, n) * g.uniform(600.0, 800.0, n)).astype(np.int64)
+    else:
+        raise ValueError(name)
+    return CaloScenario(name, hits.astype(np.int64))
+
+
 # --- served request trace ------------------------------------------------
 @dataclasses.dataclass
 class Trace:

@@ -249,3 +249,39 @@ def test_batch_large_requests_among_small():
     host, st = _run(r, lay, pos + 64)
     assert np.all(st == 0)
     _check_outputs(host, lay, st)
+
+
+@pytest.mark.parametrize("name,events", [("single_electron", 400), ("ttbar", 3)])
+def test_batch_fastcalosim_scenarios(name, events):
+    """The paper's FastCaloSim scenarios as one batch each: three uniform
+    FP32 per hit on key (42, event id).  Single-electron events are checked
+    whole; ttbar events (tens of millions of samples each) at their head,
+    middle and tail."""
+    import torch
+    sc = synth.calo_scenario(name, n_events=events)
+    sizes = sc.uniforms.astype(np.uint64)
+    total = int(sizes.sum())
+    out = torch.empty(total, dtype=torch.float32, device="cuda")
+    offs = np.concatenate([[0], np.cumsum(sizes)])[:-1].astype(np.int64)
+    reqs = mr.make_requests(events)
+    seeds = (np.arange(events, dtype=np.uint64) << np.uint64(32)) | np.uint64(sc.seed32)
+    reqs["engine_type"] = mr.PHILOX4X32_10
+    reqs["kind"] = mr.UNIFORM_F32
+    reqs["p1"] = 1.0
+    reqs["seed"] = seeds
+    reqs["n"] = sizes
+    reqs["out"] = np.uint64(out.data_ptr()) + offs.astype(np.uint64) * np.uint64(4)
+    b = mr.Batcher()
+    b.generate(reqs)
+    torch.cuda.synchronize()
+    assert np.all(b.statuses(events) == 0)
+    for e in range(events):
+        n, o = int(sizes[e]), int(offs[e])
+        if name == "single_electron":
+            wins = [(0, n)]
+        else:
+            wins = [(0, 4096), (n // 2 - 2048, 4096), (n - 4096, 4096)]
+        for s, m in wins:
+            got = out[o + s: o + s + m].cpu().numpy()
+            gh.assert_match(mr.UNIFORM_F32, got,
+                            gh.oracle_philox(int(seeds[e]), s, mr.UNIFORM_F32, m))
