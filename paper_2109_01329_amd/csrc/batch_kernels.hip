@@ -237,27 +237,41 @@ __device__ __forceinline__ uint64_t prefix_end(const BatchArgs &a, int j, uint32
     return a.chunk_end[2 * c + j] - a.chunk_total[2 * c + j] + a.local_end[2 * r + j];
 }
 
-// The request holding unit T (T below the batch total): the first r whose
-// prefix end exceeds T, by binary search over chunks, then over the
-// requests of that chunk.  Wave-uniform.
-__device__ uint32_t find_request(const BatchArgs &a, int j, uint64_t T)
+// First index i in [lo, hi) with v(i) > T, for v non-decreasing and
+// v(hi - 1) > T: a 64-ary search.  Every lane probes one of 64 evenly spaced
+// positions at once and a ballot keeps the bracket, so each round shrinks
+// the range 64-fold (about 3 dependent loads for 10^4 requests instead of
+// 14).  Called by whole waves; wave-uniform result.
+template <typename V>
+__device__ __forceinline__ uint32_t search64(uint32_t lo, uint32_t hi, uint64_t T, V v)
 {
-    uint32_t lo = 0, hi = a.nchunks;
-    while (lo < hi) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (a.chunk_end[2 * mid + j] > T) hi = mid;
-        else lo = mid + 1;
-    }
-    const uint32_t c = lo;
-    const uint64_t base = a.chunk_end[2 * c + j] - a.chunk_total[2 * c + j];
-    lo = c * kChunk;
-    hi = min(a.count, lo + kChunk);
-    while (lo < hi) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (base + a.local_end[2 * mid + j] > T) hi = mid;
-        else lo = mid + 1;
+    const uint32_t lane = threadIdx.x & 63u;
+    while (hi - lo > 1u) {
+        const uint32_t n = hi - lo;
+        const uint32_t step = (n + 63u) / 64u;
+        const uint32_t p = lo + lane * step;
+        const bool above = p >= hi || v(p) > T;
+        const uint64_t mask = __builtin_amdgcn_ballot_w64(above);
+        const uint32_t f = mask ? (uint32_t)__builtin_ctzll(mask) : 64u;
+        const uint32_t nlo = f == 0u ? lo : lo + (f - 1u) * step + 1u;
+        const uint32_t nhi = f == 64u ? hi : min(hi, lo + f * step + 1u);
+        lo = nlo;
+        hi = nhi;
     }
     return lo;
+}
+
+// The request holding unit T (T below the batch total): the first r whose
+// prefix end exceeds T, searched over chunks, then over the requests of
+// that chunk.  Called by whole waves.
+__device__ uint32_t find_request(const BatchArgs &a, int j, uint64_t T)
+{
+    const uint32_t c = search64(0u, a.nchunks, T,
+                                [&](uint32_t i) { return a.chunk_end[2 * i + j]; });
+    const uint64_t base = a.chunk_end[2 * c + j] - a.chunk_total[2 * c + j];
+    const uint32_t lo = c * kChunk;
+    const uint32_t hi = min(a.count, lo + kChunk);
+    return search64(lo, hi, T, [&](uint32_t i) { return base + a.local_end[2 * i + j]; });
 }
 
 template <int KIND>
