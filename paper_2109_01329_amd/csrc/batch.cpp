@@ -3,11 +3,12 @@
 // that successive batches (on one or several streams) overlap without the
 // host waiting, except when a slot is reused while the device still needs
 // it.  Per batch the host copies the request table into pinned memory (or
-// not at all when the caller filled the staged slot), uploads it on the
-// batcher's own copy stream (so the upload overlaps earlier work on the
-// caller's stream), and enqueues on the caller's stream, behind the upload,
-// the planning and scan kernels, the two generation kernels (Philox,
-// MRG32k3a) and the copy of the per-request statuses back to pinned memory.
+// not at all when the caller filled the staged slot) and enqueues on the
+// batcher's own stream the upload, the planning kernel (and the scan kernel
+// past 64 chunks) and the copy of the per-request statuses back to pinned
+// memory; these overlap the generation of earlier batches.  The caller's
+// stream waits for them and runs the generation kernels (Philox, MRG32k3a)
+// that have work.
 #include <algorithm>
 #include <cstring>
 #include <mutex>
@@ -29,7 +30,7 @@ struct Slot {
     int dev = -1;
     bool pending = false;              // `done` recorded and maybe not reached
     hipEvent_t done = nullptr;
-    hipEvent_t uploaded = nullptr;
+    hipEvent_t planned = nullptr;      // upload, planning and status copy done
     mirng_request *d_reqs = nullptr;
     mirng::BatchDesc *d_desc = nullptr;
     uint64_t *d_local_end = nullptr;
@@ -59,7 +60,7 @@ void release(Slot &s)
     if (s.d_total) (void)hipFree(s.d_total);
     if (s.d_status) (void)hipFree(s.d_status);
     if (s.done) (void)hipEventDestroy(s.done);
-    if (s.uploaded) (void)hipEventDestroy(s.uploaded);
+    if (s.planned) (void)hipEventDestroy(s.planned);
     s = Slot{};
 }
 
@@ -88,7 +89,7 @@ hipError_t prepare(Slot &s, size_t count, int dev)
     chk(hipMalloc((void **)&s.d_total, 2 * sizeof(uint64_t)));
     chk(hipMalloc((void **)&s.d_status, cap * sizeof(int32_t)));
     chk(hipEventCreateWithFlags(&s.done, hipEventDisableTiming));
-    chk(hipEventCreateWithFlags(&s.uploaded, hipEventDisableTiming));
+    chk(hipEventCreateWithFlags(&s.planned, hipEventDisableTiming));
     if (err != hipSuccess) {
         release(s);
         return err;
@@ -133,7 +134,7 @@ bool config_valid(const mirng_batch_config &c)
 struct mirng_batcher_s {
     std::mutex mu;
     Slot slots[kSlots];
-    hipStream_t copy = nullptr;        // uploads (default priority)
+    hipStream_t copy = nullptr;        // uploads and planning (default priority)
     int copy_dev = -1;
     int next = 0;
     int last = -1;     // slot of the most recent batch
@@ -243,10 +244,15 @@ mirng_status mirng_generate_batch(mirng_batcher b, const mirng_request *reqs, si
     if (mrg_batch_tables(dev, tabs) != hipSuccess) return MIRNG_E_ALLOC;
     const uint64_t wpb = (uint64_t)b->cfg.block / 64;
     uint64_t waves = ((grid_waves(b->cfg) + wpb - 1) / wpb) * wpb;
-    // Philox Gaussian FP64 requests need the wide generation kernel
-    int32_t wide = 0;
-    for (size_t i = 0; i < count && !wide; ++i)
-        wide = reqs[i].engine_type == MIRNG_PHILOX4X32_10 && reqs[i].dist.kind == MIRNG_GAUSSIAN_F64;
+    // which generation kernels can have work: Philox requests (Gaussian
+    // FP64 ones need the wide kernel), MRG32k3a requests
+    int32_t wide = 0, philox = 0, mrg = 0;
+    for (size_t i = 0; i < count && !(wide && mrg); ++i) {
+        const bool ph = reqs[i].engine_type == MIRNG_PHILOX4X32_10;
+        philox |= ph;
+        mrg |= reqs[i].engine_type == MIRNG_MRG32K3A;
+        wide |= ph && reqs[i].dist.kind == MIRNG_GAUSSIAN_F64;
+    }
     uint64_t mgroups = mrg_groups();
     if (count <= kSmallBatch) {
         // small batches: no more waves (groups) than about two tiles
@@ -290,16 +296,22 @@ mirng_status mirng_generate_batch(mirng_batcher b, const mirng_request *reqs, si
     a.status = sl.d_status;
     a.nt = b->cfg.nontemporal;
     a.wide = wide;
+    a.philox = philox;
+    a.mrg = mrg;
     a.block = (uint32_t)b->cfg.block;
     a.groups = (uint32_t)(waves / wpb);
+    // upload, planning and the status copy run on the batcher's own stream,
+    // where they overlap the generation of the batches before this one; the
+    // caller's stream waits for them, then generates
     hipError_t err = hipMemcpyAsync(sl.d_reqs, sl.h_reqs, count * sizeof(mirng_request),
                                     hipMemcpyHostToDevice, b->copy);
-    if (err == hipSuccess) err = hipEventRecord(sl.uploaded, b->copy);
-    if (err == hipSuccess) err = hipStreamWaitEvent(s, sl.uploaded, 0);
-    if (err == hipSuccess) err = launch_batch(a, s);
+    if (err == hipSuccess) err = launch_batch_plan(a, b->copy);
     if (err == hipSuccess)
         err = hipMemcpyAsync(sl.h_status, sl.d_status, count * sizeof(int32_t),
-                             hipMemcpyDeviceToHost, s);
+                             hipMemcpyDeviceToHost, b->copy);
+    if (err == hipSuccess) err = hipEventRecord(sl.planned, b->copy);
+    if (err == hipSuccess) err = hipStreamWaitEvent(s, sl.planned, 0);
+    if (err == hipSuccess) err = launch_batch_generate(a, s);
     if (err == hipSuccess) err = hipEventRecord(sl.done, s);
     if (err != hipSuccess) return MIRNG_E_LAUNCH;
     sl.pending = true;

@@ -8,10 +8,12 @@
 //        MRG32k3a start state (seed state jumped by the offset through the
 //        A^(2^k) table), and counts its Philox tiles of 64 slots or MRG
 //        chunks; each workgroup scans both counts over its 1024 requests.
-// scan:  one workgroup scans the per-chunk totals.
+// scan:  one workgroup scans the per-chunk totals (only for batches of more
+//        than 64 chunks; smaller ones are scanned by every generating wave in
+//        registers).
 // philox main: a fixed grid of waves; wave w takes a contiguous range of
 //        tiles (tiles of one request are adjacent, requests in table order),
-//        finds the request holding its first tile by binary search over the
+//        finds the request holding its first tile by a 64-ary search over the
 //        two-level prefix (chunks, then requests) and walks forward, running
 //        the plain kernel's slot walk on each request segment.
 // mrg main: a fixed grid of 256-thread groups, each over a contiguous range
@@ -169,6 +171,26 @@ __device__ uint64_t block_scan(uint64_t v, uint64_t *wsum)
     return v;
 }
 
+// The whole 64-byte request in one round of four 16-byte loads (field by
+// field, the validation's early exits would fetch it in six dependent
+// rounds).
+__device__ __forceinline__ mirng_request load_request(const mirng_request *p)
+{
+    static_assert(sizeof(mirng_request) == 64, "request layout");
+    const uint4 *src = reinterpret_cast<const uint4 *>(p);
+    uint4 w[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) w[i] = src[i];
+    // keeps the compiler from sinking each load into the branch that first
+    // needs it
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        asm volatile("" : "+v"(w[i].x), "+v"(w[i].y), "+v"(w[i].z), "+v"(w[i].w));
+    mirng_request q;
+    __builtin_memcpy(&q, w, sizeof(q));
+    return q;
+}
+
 __global__ __launch_bounds__(kChunk) void batch_plan_kernel(BatchArgs a)
 {
     __shared__ uint64_t wsum[kChunk / 64];
@@ -177,7 +199,8 @@ __global__ __launch_bounds__(kChunk) void batch_plan_kernel(BatchArgs a)
     if (r < a.count) {
         int32_t st;
         BatchDesc d;
-        plan_one(a.reqs[r], d, st, a.nt, a.pow2, tiles, mchunks);
+        const mirng_request q = load_request(&a.reqs[r]);
+        plan_one(q, d, st, a.nt, a.pow2, tiles, mchunks);
         a.status[r] = st;
         if (st != MIRNG_OK) {
             d.nunits = 0;
@@ -229,12 +252,59 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t v)
     return ((uint64_t)uniform((uint32_t)(v >> 32)) << 32) | uniform((uint32_t)v);
 }
 
-// Global inclusive prefix (j = 0: Philox tiles, 1: MRG chunks) at the end
-// of request r.
-__device__ __forceinline__ uint64_t prefix_end(const BatchArgs &a, int j, uint32_t r)
+__device__ __forceinline__ uint64_t readlane64(uint64_t v, uint32_t l)
 {
-    const uint32_t c = r / kChunk;
-    return a.chunk_end[2 * c + j] - a.chunk_total[2 * c + j] + a.local_end[2 * r + j];
+    return ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(v >> 32), (int)l) << 32) |
+           (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, (int)l);
+}
+
+// Inclusive scan across the 64 lanes of a wave.
+__device__ __forceinline__ uint64_t wave_scan(uint64_t v)
+{
+    const uint32_t lane = threadIdx.x & 63u;
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint64_t t = __shfl_up(v, off);
+        if (lane >= (uint32_t)off) v += t;
+    }
+    return v;
+}
+
+// Most chunks whose prefix a wave keeps in registers (one per lane).
+constexpr uint32_t kWaveChunks = 64;
+
+// The chunk-level prefix of count j (0: Philox tiles, 1: MRG chunks) as one
+// wave sees it.  Up to 64 chunks the wave scans the chunk totals itself
+// (lane c holds chunk c: one round of loads, and no scan kernel); beyond
+// that the scan kernel's prefixes are read from memory.
+struct ChunkPrefix {
+    uint64_t inc = 0;     // in registers: prefix through chunk (lane)
+    uint64_t excl = 0;    // in registers: prefix before chunk (lane)
+    uint64_t total = 0;   // wave-uniform batch total
+    bool regs = false;
+};
+
+__device__ ChunkPrefix chunk_prefix(const BatchArgs &a, int j)
+{
+    ChunkPrefix p;
+    p.regs = a.nchunks <= kWaveChunks;
+    if (p.regs) {
+        const uint32_t lane = threadIdx.x & 63u;
+        const uint64_t v = lane < a.nchunks ? a.chunk_total[2 * lane + j] : 0;
+        p.inc = wave_scan(v);
+        p.excl = p.inc - v;
+        p.total = readlane64(p.inc, 63);
+    } else {
+        p.total = uniform64(a.total[j]);
+    }
+    return p;
+}
+
+// Prefix before chunk c (wave-uniform).
+__device__ __forceinline__ uint64_t chunk_base(const BatchArgs &a, int j, const ChunkPrefix &p,
+                                               uint32_t c)
+{
+    if (p.regs) return readlane64(p.excl, c);
+    return uniform64(a.chunk_end[2 * c + j] - a.chunk_total[2 * c + j]);
 }
 
 // First index i in [lo, hi) with v(i) > T, for v non-decreasing and
@@ -261,17 +331,27 @@ __device__ __forceinline__ uint32_t search64(uint32_t lo, uint32_t hi, uint64_t 
     return lo;
 }
 
-// The request holding unit T (T below the batch total): the first r whose
-// prefix end exceeds T, searched over chunks, then over the requests of
-// that chunk.  Called by whole waves.
-__device__ uint32_t find_request(const BatchArgs &a, int j, uint64_t T)
+// The chunk holding unit T (T below the batch total): the first chunk
+// whose prefix end exceeds T.  Called by whole waves.
+__device__ uint32_t find_chunk(const BatchArgs &a, int j, const ChunkPrefix &p, uint64_t T)
 {
-    const uint32_t c = search64(0u, a.nchunks, T,
-                                [&](uint32_t i) { return a.chunk_end[2 * i + j]; });
-    const uint64_t base = a.chunk_end[2 * c + j] - a.chunk_total[2 * c + j];
+    if (p.regs) {
+        // lanes past the last chunk hold the total, which exceeds T
+        const uint64_t m = __builtin_amdgcn_ballot_w64(p.inc > T);
+        return uniform((uint32_t)__builtin_ctzll(m));
+    }
+    return uniform(search64(0u, a.nchunks, T,
+                            [&](uint32_t i) { return a.chunk_end[2 * i + j]; }));
+}
+
+// The request of chunk c (prefix `base` before it) holding unit T.
+__device__ __forceinline__ uint32_t find_in_chunk(const BatchArgs &a, int j, uint32_t c,
+                                                  uint64_t base, uint64_t T)
+{
     const uint32_t lo = c * kChunk;
     const uint32_t hi = min(a.count, lo + kChunk);
-    return search64(lo, hi, T, [&](uint32_t i) { return base + a.local_end[2 * i + j]; });
+    return uniform(search64(lo, hi, T,
+                            [&](uint32_t i) { return base + a.local_end[2 * i + j]; }));
 }
 
 template <int KIND>
@@ -320,21 +400,28 @@ __global__ __launch_bounds__(1024) void batch_main_kernel(BatchArgs a)
 {
     const uint32_t lane = threadIdx.x & 63u;
     const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    const uint64_t total = a.total[0];
-    const uint64_t per = (total + a.waves - 1) / a.waves;
+    const ChunkPrefix p = chunk_prefix(a, 0);
+    const uint64_t per = (p.total + a.waves - 1) / a.waves;
     uint64_t t = wave * per;
-    const uint64_t t1 = min(t + per, total);
+    const uint64_t t1 = min(t + per, p.total);
     if (t >= t1) return;
-    uint32_t r = uniform(find_request(a, 0, t));
+    uint32_t c = find_chunk(a, 0, p, t);
+    uint64_t base = chunk_base(a, 0, p, c);
+    uint32_t r = find_in_chunk(a, 0, c, base, t);
     while (t < t1 && r < a.count) {
-        const uint64_t end = uniform64(prefix_end(a, 0, r));
-        const uint32_t nunits = uniform(a.desc[r].nunits);
-        const uint64_t start = end - ((uint64_t)nunits + 63) / 64;
+        if (r / kChunk != c) {
+            c = r / kChunk;
+            base = chunk_base(a, 0, p, c);
+        }
+        // the descriptor and the prefix end in one round of loads
+        const BatchDesc d = load_desc(&a.desc[r]);
+        const uint64_t end = base + uniform64(a.local_end[2 * r]);
+        const uint64_t start = end - ((uint64_t)d.nunits + 63) / 64;
         if (end > t) {
             const uint64_t seg = min(t1, end);
             const uint32_t u0 = (uint32_t)((t - start) * 64);
-            const uint32_t u1 = (uint32_t)min((seg - start) * 64, (uint64_t)nunits);
-            run_segment<WIDE>(load_desc(&a.desc[r]), u0, u1 - u0, lane);
+            const uint32_t u1 = (uint32_t)min((seg - start) * 64, (uint64_t)d.nunits);
+            run_segment<WIDE>(d, u0, u1 - u0, lane);
             t = seg;
         }
         ++r;
@@ -385,18 +472,24 @@ __global__ __launch_bounds__(kMrgThreads) void batch_mrg_kernel(BatchArgs a)
     __shared__ __attribute__((aligned(16))) char lds[kMrgThreads * MrgShape<kU32F>::ROW];
     __shared__ uint32_t wg_state[6];
     static_assert(MrgShape<kU64F>::ROW == MrgShape<kU32F>::ROW, "row size");
-    const uint64_t total = a.total[1];
-    const uint64_t per = (total + a.mgroups - 1) / a.mgroups;
+    const ChunkPrefix p = chunk_prefix(a, 1);
+    const uint64_t per = (p.total + a.mgroups - 1) / a.mgroups;
     uint64_t c = (uint64_t)blockIdx.x * per;
-    const uint64_t c1 = min(c + per, total);
+    const uint64_t c1 = min(c + per, p.total);
     if (c >= c1) return;
-    uint32_t r = find_request(a, 1, c);
+    uint32_t rc = find_chunk(a, 1, p, c);
+    uint64_t base = chunk_base(a, 1, p, rc);
+    uint32_t r = find_in_chunk(a, 1, rc, base, c);
     while (c < c1 && r < a.count) {
-        const uint64_t end = prefix_end(a, 1, r);
-        const uint64_t start = end - a.desc[r].mchunks;
+        if (r / kChunk != rc) {
+            rc = r / kChunk;
+            base = chunk_base(a, 1, p, rc);
+        }
+        const BatchDesc d = load_desc(&a.desc[r]);
+        const uint64_t end = base + uniform64(a.local_end[2 * r + 1]);
+        const uint64_t start = end - d.mchunks;
         if (end > c) {
             const uint64_t seg = min(c1, end);
-            const BatchDesc d = load_desc(&a.desc[r]);
             for (uint64_t k = c - start; k < seg - start; ++k) {
                 switch (d.kind) {
                 case kBits: mrg_chunk<kBits>(d, k, a.c_tab4, a.u_tab4, lds, wg_state); break;
@@ -414,22 +507,31 @@ __global__ __launch_bounds__(kMrgThreads) void batch_mrg_kernel(BatchArgs a)
 
 }  // namespace
 
-hipError_t launch_batch(const BatchArgs &a, hipStream_t s)
+hipError_t launch_batch_plan(const BatchArgs &a, hipStream_t s)
 {
     hipLaunchKernelGGL(batch_plan_kernel, dim3(a.nchunks), dim3(kChunk), 0, s, a);
     hipError_t err = hipGetLastError();
-    if (err != hipSuccess) return err;
+    if (err != hipSuccess || a.nchunks <= kWaveChunks) return err;
     hipLaunchKernelGGL(batch_scan_kernel, dim3(1), dim3(kChunk), 0, s, a);
-    err = hipGetLastError();
-    if (err != hipSuccess) return err;
-    if (a.wide)
-        hipLaunchKernelGGL(batch_main_kernel<true>, dim3(a.groups), dim3(a.block), 0, s, a);
-    else
-        hipLaunchKernelGGL(batch_main_kernel<false>, dim3(a.groups), dim3(a.block), 0, s, a);
-    err = hipGetLastError();
-    if (err != hipSuccess) return err;
-    hipLaunchKernelGGL(batch_mrg_kernel, dim3(a.mgroups), dim3(kMrgThreads), 0, s, a);
     return hipGetLastError();
+}
+
+hipError_t launch_batch_generate(const BatchArgs &a, hipStream_t s)
+{
+    hipError_t err = hipSuccess;
+    if (a.philox) {
+        if (a.wide)
+            hipLaunchKernelGGL(batch_main_kernel<true>, dim3(a.groups), dim3(a.block), 0, s, a);
+        else
+            hipLaunchKernelGGL(batch_main_kernel<false>, dim3(a.groups), dim3(a.block), 0, s, a);
+        err = hipGetLastError();
+        if (err != hipSuccess) return err;
+    }
+    if (a.mrg) {
+        hipLaunchKernelGGL(batch_mrg_kernel, dim3(a.mgroups), dim3(kMrgThreads), 0, s, a);
+        err = hipGetLastError();
+    }
+    return err;
 }
 
 }  // namespace mirng

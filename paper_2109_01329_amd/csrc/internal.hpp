@@ -165,6 +165,8 @@ struct BatchArgs {
     uint32_t block;         // Philox generation kernel: threads per workgroup
     uint32_t groups;        // Philox generation kernel: workgroups
     int32_t wide;           // some Philox request is Gaussian FP64 (host scan)
+    int32_t philox;         // some request names Philox4x32-10 (host scan)
+    int32_t mrg;            // some request names MRG32k3a (host scan)
     const uint32_t *pow2;   // MRG A^(2^k), k < 64: [k][comp][9]
     const uint32_t *c_tab4, *u_tab4;   // MRG chunk / thread jumps, 4-byte kinds
     const uint32_t *c_tab8, *u_tab8;   // MRG chunk / thread jumps, FP64
@@ -177,7 +179,11 @@ struct MrgBatchTables {
 };
 hipError_t mrg_batch_tables(int dev, MrgBatchTables &t);
 
-hipError_t launch_batch(const BatchArgs &a, hipStream_t s);
+// Planning (validation, per-request plans, prefix sums) of a batch, then its
+// generation kernels; the second may run on another stream once the first
+// has completed.
+hipError_t launch_batch_plan(const BatchArgs &a, hipStream_t s);
+hipError_t launch_batch_generate(const BatchArgs &a, hipStream_t s);
 // Allocates every staging slot of `b` for `count` requests on the current
 // device (so that later batches of up to `count` requests allocate nothing).
 hipError_t batcher_reserve(mirng_batcher b, size_t count);

@@ -81,6 +81,17 @@ def test_batch_mixed_requests_vs_oracle():
     _check_outputs(host, layout, st)
 
 
+@pytest.mark.parametrize("count", [65536, 70001])
+def test_batch_many_small_requests(count):
+    """Batches of exactly 64 chunks of 1024 requests (every wave keeps the
+    chunk prefix in registers) and of more (the scan kernel's prefixes)."""
+    rng = np.random.default_rng(count)
+    reqs, layout, nbytes = _mix(rng, count, max_log10=1.6)
+    host, st = _run(reqs, layout, nbytes)
+    assert np.all(st == 0)
+    _check_outputs(host, layout, st)
+
+
 def test_batch_equals_plain_path_bytes():
     import torch
     rng = np.random.default_rng(72)
