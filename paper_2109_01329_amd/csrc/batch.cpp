@@ -20,7 +20,8 @@ namespace {
 
 constexpr int kSlots = 4;
 constexpr size_t kChunk = 1024;
-constexpr size_t kSmallBatch = 8192;   // batches this small get a grid sized to their work
+constexpr uint64_t kMrgChunksPerGroup = 8;   // MRG chunks per group in large batches
+constexpr uint64_t kMaxMrgGroups = 1u << 24;
 
 struct Slot {
     mirng_request *h_reqs = nullptr;   // pinned
@@ -40,11 +41,11 @@ struct Slot {
     int32_t *d_status = nullptr;
 };
 
-// Workgroups of the MRG generation kernel: its 36 KiB of LDS per group let
-// four groups share a CU.
-size_t mrg_groups()
+// Resident workgroups of the MRG generation kernel: its 36 KiB of LDS per
+// group let four groups share a CU.
+uint64_t mrg_groups()
 {
-    return (size_t)mirng::device_cu_count() * 4;
+    return (uint64_t)mirng::device_cu_count() * 4;
 }
 
 void release(Slot &s)
@@ -99,26 +100,38 @@ hipError_t prepare(Slot &s, size_t count, int dev)
     return hipSuccess;
 }
 
-// Upper bounds on the Philox tiles and MRG chunks of a batch from the
-// request sizes alone (the device planning finds the exact counts); they
-// only size the generation grids of small batches.
-void estimate_work(const mirng_request *q, size_t count, uint64_t &tiles, uint64_t &chunks)
+// What a batch holds, from one pass over its requests: upper bounds on its
+// Philox tiles and MRG chunks (the device planning finds the exact counts;
+// these only size the generation grids) and which generation kernels can
+// have work.
+struct Work {
+    uint64_t tiles = 0, chunks = 0;
+    int32_t philox = 0, mrg = 0;
+    int32_t wide = 0;   // a Philox Gaussian FP64 request: the wide kernel
+};
+
+Work scan_requests(const mirng_request *q, size_t count)
 {
-    tiles = 0;
-    chunks = 0;
+    Work w;
     for (size_t i = 0; i < count; ++i) {
+        const bool ph = q[i].engine_type == MIRNG_PHILOX4X32_10;
+        const bool mg = q[i].engine_type == MIRNG_MRG32K3A;
+        w.philox |= ph;
+        w.mrg |= mg;
+        w.wide |= ph && q[i].dist.kind == MIRNG_GAUSSIAN_F64;
         const uint64_t n = q[i].n;
         if (n == 0 || n >= (1ull << 32)) continue;
         const bool f64 = q[i].dist.kind == MIRNG_UNIFORM_F64 ||
                          q[i].dist.kind == MIRNG_GAUSSIAN_F64;
-        if (q[i].engine_type == MIRNG_MRG32K3A) {
+        if (mg) {
             const uint64_t per = (uint64_t)256 * mirng::kBatchMrgPasses * (f64 ? 16 : 32);
-            chunks += (n + per - 1) / per;
-        } else {
+            w.chunks += (n + per - 1) / per;
+        } else if (ph) {
             const uint64_t units = (n * (f64 ? 2 : 1) + 3) / 4 + 2;
-            tiles += (units + 63) / 64 + 1;
+            w.tiles += (units + 63) / 64 + 1;
         }
     }
+    return w;
 }
 
 bool config_valid(const mirng_batch_config &c)
@@ -244,25 +257,19 @@ mirng_status mirng_generate_batch(mirng_batcher b, const mirng_request *reqs, si
     if (mrg_batch_tables(dev, tabs) != hipSuccess) return MIRNG_E_ALLOC;
     const uint64_t wpb = (uint64_t)b->cfg.block / 64;
     uint64_t waves = ((grid_waves(b->cfg) + wpb - 1) / wpb) * wpb;
-    // which generation kernels can have work: Philox requests (Gaussian
-    // FP64 ones need the wide kernel), MRG32k3a requests
-    int32_t wide = 0, philox = 0, mrg = 0;
-    for (size_t i = 0; i < count && !(wide && mrg); ++i) {
-        const bool ph = reqs[i].engine_type == MIRNG_PHILOX4X32_10;
-        philox |= ph;
-        mrg |= reqs[i].engine_type == MIRNG_MRG32K3A;
-        wide |= ph && reqs[i].dist.kind == MIRNG_GAUSSIAN_F64;
-    }
-    uint64_t mgroups = mrg_groups();
-    if (count <= kSmallBatch) {
-        // small batches: no more waves (groups) than about two tiles
-        // (one chunk) of work each
-        uint64_t tiles, chunks;
-        estimate_work(reqs, count, tiles, chunks);
-        const uint64_t want = ((tiles + 1) / 2 + wpb - 1) / wpb * wpb;
-        waves = std::max<uint64_t>(wpb, std::min(waves, want));
-        mgroups = std::max<uint64_t>(1, std::min(mgroups, chunks));
-    }
+    const Work w = scan_requests(reqs, count);
+    // Philox: no more waves than about two tiles of work each
+    const uint64_t want = ((w.tiles + 1) / 2 + wpb - 1) / wpb * wpb;
+    waves = std::max<uint64_t>(wpb, std::min(waves, want));
+    // MRG: a chunk per group while that fills the resident groups, then
+    // kMrgChunksPerGroup per group.  Chunks of different kinds cost
+    // different times; many short groups let the hardware dispatcher
+    // balance them where a few long ones would wait on the slowest.
+    const uint64_t resident = mrg_groups();
+    const uint64_t mgroups = std::min<uint64_t>(
+        kMaxMrgGroups,
+        std::max<uint64_t>(1, std::max(std::min(w.chunks, resident),
+                                       (w.chunks + kMrgChunksPerGroup - 1) / kMrgChunksPerGroup)));
     int k;
     if (b->staged >= 0 && reqs == b->slots[b->staged].h_reqs &&
         count <= b->slots[b->staged].cap && b->slots[b->staged].dev == dev) {
@@ -295,9 +302,9 @@ mirng_status mirng_generate_batch(mirng_batcher b, const mirng_request *reqs, si
     a.u_tab8 = tabs.u_tab8;
     a.status = sl.d_status;
     a.nt = b->cfg.nontemporal;
-    a.wide = wide;
-    a.philox = philox;
-    a.mrg = mrg;
+    a.wide = w.wide;
+    a.philox = w.philox;
+    a.mrg = w.mrg;
     a.block = (uint32_t)b->cfg.block;
     a.groups = (uint32_t)(waves / wpb);
     // upload, planning and the status copy run on the batcher's own stream,
