@@ -219,6 +219,9 @@ class Engine:
     """An engine (Philox4x32-10 or MRG32k3a) at a position in its stream."""
 
     def __init__(self, engine_type: int, seed: int, offset: int = 0):
+        if not 0 <= offset < 2**64:
+            raise ValueError("offset must lie in [0, 2^64); reach larger positions with "
+                             "skip_ahead")
         h = ctypes.c_void_p()
         _check(lib().mirng_engine_create(engine_type, seed & (2**64 - 1), offset,
                                          ctypes.byref(h)), "engine_create")

@@ -41,10 +41,15 @@ __device__ __forceinline__ u32x4 philox10(uint32_t c0, uint32_t c1, uint32_t c2,
     return w;
 }
 
-// Block base + j as a 128-bit counter.
+// Block base + j as a 128-bit counter.  NC: the caller has checked that
+// base[0] + j does not carry out of the low word, so the three upper words
+// are the base's own (wave-uniform: the first round's product of the upper
+// pair is then loop-invariant).
+template <bool NC = false>
 __device__ __forceinline__ u32x4 block_at(const uint32_t base[4], uint32_t k0, uint32_t k1,
                                           uint32_t j)
 {
+    if constexpr (NC) return philox10(base[0] + j, base[1], base[2], base[3], k0, k1);
     const uint64_t lo0 = ((uint64_t)base[1] << 32) | base[0];
     const uint64_t hi0 = ((uint64_t)base[3] << 32) | base[2];
     const uint64_t lo = lo0 + j;
@@ -56,8 +61,18 @@ __device__ __forceinline__ u32x4 block_at(const uint32_t base[4], uint32_t k0, u
 // 16 bytes at a 4-byte-aligned address (one global_store_dwordx4 on gfx950).
 typedef uint32_t u32x4_a4 __attribute__((ext_vector_type(4), aligned(4)));
 
+// Whether the range (or mean / sd) step applies: RANGED 0 never, 1 always,
+// 2 as the epilogue says.  Kernels that know it per launch pass 0 or 1, so
+// the loop holds no select between both results.
+template <int RANGED>
+__device__ __forceinline__ bool ranged(const Epilogue &ep)
+{
+    if constexpr (RANGED == 2) return ep.ranged != 0;
+    else return RANGED != 0;
+}
+
 // Four words -> the 16 bytes they become.
-template <int KIND>
+template <int KIND, int RANGED = 2>
 __device__ __forceinline__ u32x4 transform(const Epilogue &ep, u32x4 w)
 {
     u32x4 v;
@@ -66,7 +81,7 @@ __device__ __forceinline__ u32x4 transform(const Epilogue &ep, u32x4 w)
     } else if constexpr (KIND == kU32F) {
         f32x4 f;
         f.x = u01f(w.x); f.y = u01f(w.y); f.z = u01f(w.z); f.w = u01f(w.w);
-        if (ep.ranged) {
+        if (ranged<RANGED>(ep)) {
             f.x = __builtin_fmaf(f.x, ep.d32, ep.a32);
             f.y = __builtin_fmaf(f.y, ep.d32, ep.a32);
             f.z = __builtin_fmaf(f.z, ep.d32, ep.a32);
@@ -77,7 +92,7 @@ __device__ __forceinline__ u32x4 transform(const Epilogue &ep, u32x4 w)
         f64x2 d;
         d.x = u01d(w.x, w.y);
         d.y = u01d(w.z, w.w);
-        if (ep.ranged) {
+        if (ranged<RANGED>(ep)) {
             d.x = __builtin_fma(d.x, ep.d64, ep.a64);
             d.y = __builtin_fma(d.y, ep.d64, ep.a64);
         }
@@ -85,7 +100,7 @@ __device__ __forceinline__ u32x4 transform(const Epilogue &ep, u32x4 w)
     } else if constexpr (KIND == kGauss64) {
         // u1 = (v_a + 1) 2^-53 from (w.x, w.y), u2 = v_b 2^-53 from (w.z, w.w)
         f64x2 d = box_muller64(u01d(w.x, w.y) + 0x1p-53, u01d(w.z, w.w));
-        if (ep.ranged) {
+        if (ranged<RANGED>(ep)) {
             d.x = __builtin_fma(d.x, ep.d64, ep.a64);
             d.y = __builtin_fma(d.y, ep.d64, ep.a64);
         }
@@ -94,7 +109,7 @@ __device__ __forceinline__ u32x4 transform(const Epilogue &ep, u32x4 w)
         f32x4 f;
         f.xy = box_muller(w.x, w.y);
         f.zw = box_muller(w.z, w.w);
-        if (ep.ranged) {
+        if (ranged<RANGED>(ep)) {
             f.x = __builtin_fmaf(f.x, ep.d32, ep.a32);
             f.y = __builtin_fmaf(f.y, ep.d32, ep.a32);
             f.z = __builtin_fmaf(f.z, ep.d32, ep.a32);
@@ -161,13 +176,20 @@ __device__ __forceinline__ uint32_t lane0(uint32_t v)
 }
 
 // The 16 bytes of slot s of a run, stored whole or element by element.
-template <int KIND>
+template <int KIND, int RANGED = 2>
 __device__ __forceinline__ void emit_slot(const SlotRun &r, uint32_t slot, u32x4 w)
 {
     constexpr int EPV = 16 / elem_bytes(KIND);
     const int64_t e0 = (int64_t)slot * EPV - (int64_t)r.head;
-    put<KIND>(r.out_base + (uint64_t)slot * 16u, transform<KIND>(r.ep, w), slot, r.full_lo,
-              r.full_count, e0, r.n, r.ep.nt);
+    put<KIND>(r.out_base + (uint64_t)slot * 16u, transform<KIND, RANGED>(r.ep, w), slot,
+              r.full_lo, r.full_count, e0, r.n, r.ep.nt);
+}
+
+// Whether the blocks base + j, j <= s0 + jmax, stay clear of a carry out of
+// the counter's low word (wave-uniform).
+__device__ __forceinline__ bool no_carry(const SlotRun &r, uint32_t s0, uint64_t jmax)
+{
+    return (uint64_t)r.base[0] + s0 + jmax < (1ull << 32);
 }
 
 // One wave writes slots [s0, s0 + span) of a run, 64 consecutive slots per
@@ -175,31 +197,42 @@ __device__ __forceinline__ void emit_slot(const SlotRun &r, uint32_t slot, u32x4
 // tail of block base + s and the head of block base + s + 1: lane L takes
 // those words from lane L + 1 and lane 63 from lane 0 of the next step,
 // which is evaluated one step ahead.  Must be called by whole waves.
-template <int KIND, int PHASE>
-__device__ __forceinline__ void walk_slots(const SlotRun &r, uint32_t s0, uint32_t span,
-                                           uint32_t lane)
+template <int KIND, int PHASE, int RANGED, bool NC>
+__device__ __forceinline__ void walk_slots_body(const SlotRun &r, uint32_t s0, uint32_t span,
+                                                uint32_t lane, uint32_t iters)
 {
-    const uint32_t iters = (span + 63u) >> 6;
     if constexpr (PHASE == 0) {
         for (uint32_t it = 0; it < iters; ++it) {
             const uint32_t slot = s0 + (it << 6) + lane;
-            const u32x4 w = block_at(r.base, r.k0, r.k1, slot);
-            if (slot - s0 < span) emit_slot<KIND>(r, slot, w);
+            const u32x4 w = block_at<NC>(r.base, r.k0, r.k1, slot);
+            if (slot - s0 < span) emit_slot<KIND, RANGED>(r, slot, w);
         }
     } else {
-        u32x4 cur = block_at(r.base, r.k0, r.k1, s0 + lane);
+        u32x4 cur = block_at<NC>(r.base, r.k0, r.k1, s0 + lane);
         for (uint32_t it = 0; it < iters; ++it) {
             const uint32_t slot = s0 + (it << 6) + lane;
-            const u32x4 nxt = block_at(r.base, r.k0, r.k1, slot + 64u);
+            const u32x4 nxt = block_at<NC>(r.base, r.k0, r.k1, slot + 64u);
             // lane 63 takes lane 0's next-step block
             u32x4 nb;
             nb.x = from_next_lane(cur.x, lane0(nxt.x));
             if constexpr (PHASE >= 2) nb.y = from_next_lane(cur.y, lane0(nxt.y));
             if constexpr (PHASE >= 3) nb.z = from_next_lane(cur.z, lane0(nxt.z));
-            if (slot - s0 < span) emit_slot<KIND>(r, slot, funnel<PHASE>(cur, nb));
+            if (slot - s0 < span) emit_slot<KIND, RANGED>(r, slot, funnel<PHASE>(cur, nb));
             cur = nxt;
         }
     }
+}
+
+template <int KIND, int PHASE, int RANGED = 2>
+__device__ __forceinline__ void walk_slots(const SlotRun &r, uint32_t s0, uint32_t span,
+                                           uint32_t lane)
+{
+    const uint32_t iters = (span + 63u) >> 6;
+    // the last block evaluated is the look-ahead of the last step
+    if (no_carry(r, s0, ((uint64_t)iters << 6) + 63u))
+        walk_slots_body<KIND, PHASE, RANGED, true>(r, s0, span, lane, iters);
+    else
+        walk_slots_body<KIND, PHASE, RANGED, false>(r, s0, span, lane, iters);
 }
 
 // Chunked walk: a wave writes ITERS consecutive chunks of S slots, S = 64
@@ -210,14 +243,15 @@ __device__ __forceinline__ void walk_slots(const SlotRun &r, uint32_t s0, uint32
 // a wave needs no look-ahead across chunks.  Short runs of whole chunks per
 // wave keep the waves in flight on one compact, moving window of memory.
 // Must be called by whole waves.
-template <int KIND, int PHASE, int ITERS>
-__device__ __forceinline__ void walk_chunks(const SlotRun &r, uint32_t s0, uint32_t span,
-                                            uint32_t lane)
+template <int KIND, int PHASE, int ITERS, int RANGED, bool NC>
+__device__ __forceinline__ void walk_chunks_body(const SlotRun &r, uint32_t s0, uint32_t span,
+                                                 uint32_t lane)
 {
     constexpr uint32_t S = PHASE ? 63u : 64u;
     u32x4 b[ITERS];
 #pragma unroll
-    for (int it = 0; it < ITERS; ++it) b[it] = block_at(r.base, r.k0, r.k1, s0 + it * S + lane);
+    for (int it = 0; it < ITERS; ++it)
+        b[it] = block_at<NC>(r.base, r.k0, r.k1, s0 + it * S + lane);
 #pragma unroll
     for (int it = 0; it < ITERS; ++it) {
         const uint32_t off = it * S + lane;
@@ -231,8 +265,19 @@ __device__ __forceinline__ void walk_chunks(const SlotRun &r, uint32_t s0, uint3
             if constexpr (PHASE >= 3) nb.z = from_next_lane(b[it].z, 0u);
             w = funnel<PHASE>(b[it], nb);
         }
-        if (lane < S && off < span) emit_slot<KIND>(r, s0 + off, w);
+        if (lane < S && off < span) emit_slot<KIND, RANGED>(r, s0 + off, w);
     }
+}
+
+template <int KIND, int PHASE, int ITERS, int RANGED = 2>
+__device__ __forceinline__ void walk_chunks(const SlotRun &r, uint32_t s0, uint32_t span,
+                                            uint32_t lane)
+{
+    constexpr uint32_t S = PHASE ? 63u : 64u;
+    if (no_carry(r, s0, (ITERS - 1) * S + 63u))
+        walk_chunks_body<KIND, PHASE, ITERS, RANGED, true>(r, s0, span, lane);
+    else
+        walk_chunks_body<KIND, PHASE, ITERS, RANGED, false>(r, s0, span, lane);
 }
 
 }  // namespace mirng

@@ -81,7 +81,11 @@ __global__ __launch_bounds__(1024) void philox_fill_kernel(PhiloxFill a)
     const uint64_t first = (uint64_t)wave * a.slots_per_wave;
     if (first >= a.nslots) return;
     const uint32_t s0 = (uint32_t)first;
-    walk_slots<KIND, PHASE>(a.run, s0, min(a.slots_per_wave, a.nslots - s0), lane);
+    const uint32_t span = min(a.slots_per_wave, a.nslots - s0);
+    if (KIND != kBits && a.run.ep.ranged)
+        walk_slots<KIND, PHASE, 1>(a.run, s0, span, lane);
+    else
+        walk_slots<KIND, PHASE, 0>(a.run, s0, span, lane);
 }
 
 // ---------------------------------------------------------------- chunked walk
@@ -95,7 +99,11 @@ __global__ __launch_bounds__(1024) void philox_chunk_kernel(PhiloxFill a)
     const uint64_t first = wave * PER;
     if (first >= a.nslots) return;
     const uint32_t s0 = (uint32_t)first;
-    walk_chunks<KIND, PHASE, ITERS>(a.run, s0, min(PER, a.nslots - s0), lane);
+    const uint32_t span = min(PER, a.nslots - s0);
+    if (KIND != kBits && a.run.ep.ranged)
+        walk_chunks<KIND, PHASE, ITERS, 1>(a.run, s0, span, lane);
+    else
+        walk_chunks<KIND, PHASE, ITERS, 0>(a.run, s0, span, lane);
 }
 
 template <int KIND, int PHASE>

@@ -155,6 +155,10 @@ def test_engine_create_validation(L):
     assert L.mirng_skip_ahead_multi(e.handle, lim, 4) == 1
     assert L.mirng_skip_ahead_multi(e.handle, None, 2) == 1
     assert list(e.get_state().words) == before
+    # the binding refuses offsets its 64-bit argument would truncate
+    for bad in (-1, 2**64, 2**66 + 3):
+        with pytest.raises(ValueError):
+            mr.Engine(mr.PHILOX4X32_10, 1, bad)
 
 
 def test_substream_validation(L):

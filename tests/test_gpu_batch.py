@@ -92,6 +92,30 @@ def test_batch_many_small_requests(count):
     _check_outputs(host, layout, st)
 
 
+def test_batch_counter_carries():
+    """Philox requests whose blocks cross a carry out of the counter's low
+    word part-way through (a request's 64-bit offset reaches no higher
+    carry), and requests at the top of the offset range."""
+    positions = [((1 << 32) - 3000) * 4 + 1, ((1 << 32) - 2) * 4, 5 * (1 << 34) - 4 * 2000 + 3,
+                 (1 << 64) - 4 * 3000 + 2]
+    reqs = mr.make_requests(len(positions) * len(KINDS))
+    layout = []
+    pos = 64
+    i = 0
+    for kind in KINDS:
+        esz = mr.ELEM_BYTES[kind]
+        for j, off in enumerate(positions):
+            n = 20001 + 7 * j
+            pos = ((pos + 15) // 16) * 16 + (j % (16 // esz)) * esz
+            reqs[i] = (mr.PHILOX4X32_10, 0, kind, 0, 0.0, 1.0, 1234 + i, off, n, 0)
+            layout.append((pos, kind, n, 1234 + i, off, 0.0, 1.0, mr.PHILOX4X32_10))
+            pos += n * esz + 64
+            i += 1
+    host, st = _run(reqs, layout, pos + 64)
+    assert np.all(st == 0)
+    _check_outputs(host, layout, st)
+
+
 def test_batch_equals_plain_path_bytes():
     import torch
     rng = np.random.default_rng(72)

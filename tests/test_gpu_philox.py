@@ -29,8 +29,12 @@ def test_small_case_seed42():
     assert e.position == 2 * n
 
 
+# Counter carries: out of the low word ((1 << 34) - 5, and mid-run at
+# block 2^32 - 3000), out of the low half ((1 << 66) - 3, and mid-run), out
+# of the third word, and the 2^130 wrap.
+CARRY_POSITIONS = [((1 << 32) - 3000) * 4 + 1, (1 << 66) - 4 * 3000 + 2]
 POSITIONS = [0, 1, 2, 3, 12345, (1 << 34) - 5, (1 << 66) - 3, (1 << 98) - 1,
-             (1 << 130) - 7]
+             (1 << 130) - 7] + CARRY_POSITIONS
 SIZES = [1, 2, 3, 5, 17, 255, 4097, 70001]
 
 
@@ -161,10 +165,11 @@ def test_outputs_invariant_under_launch_shape(cfg):
     prev = mr.set_philox_config(**cfg)
     try:
         for kind in KINDS:
-            for pos in (0, 1, 2, 3, 2**40 + 5):
+            for pos in (0, 1, 2, 3, 2**40 + 5, *CARRY_POSITIONS):
                 for off in (0, 4 if mr.ELEM_BYTES[kind] == 4 else 8):
                     n = 100003
-                    e = mr.Engine(mr.PHILOX4X32_10, 99, pos)
+                    e = mr.Engine(mr.PHILOX4X32_10, 99, 0)
+                    e.skip_ahead(pos)
                     got, buf = gh.generate(e, kind, n, off)
                     gh.assert_match(kind, got, gh.oracle_philox(99, pos, kind, n))
                     assert gh.guards_intact(buf, off, n * mr.ELEM_BYTES[kind])
