@@ -34,14 +34,14 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
-# HBM bytes per launch of the headline kernel (walk 0, 1024-thread groups,
-# 256 waves per CU, streaming stores) from rocprofv3 counters: WRITE_SIZE
-# 1048576 KiB x 1.0 + FETCH_SIZE 21.0 KiB (median of five launches) x 2.0,
+# HBM bytes per launch of the headline kernel (walk 0, 256-thread groups,
+# 1024 waves per CU, streaming stores) from rocprofv3 counters: WRITE_SIZE
+# 1048576 KiB x 1.0 + FETCH_SIZE 43.75 KiB (median of five launches) x 2.0,
 # each scaled by what the same counter reads for a plain 1 GiB device copy
 # (WRITE 1048576 KiB, FETCH 524300 KiB).  Reset to None whenever the kernel
 # changes.
-TRAFFIC_PER_LAUNCH = 1073741824 + 43008
-TRAFFIC_SHAPE = {"walk": 0, "block": 1024, "waves_per_cu": 256, "blocks_per_lane": 1,
+TRAFFIC_PER_LAUNCH = 1073741824 + 89600
+TRAFFIC_SHAPE = {"walk": 0, "block": 256, "waves_per_cu": 1024, "blocks_per_lane": 1,
                  "nontemporal": 1, "reserved": 0}
 
 
