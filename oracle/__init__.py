@@ -28,6 +28,7 @@ _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 BITS_U32, UNIFORM_F32, UNIFORM_F64, GAUSSIAN_F32, GAUSSIAN_F64 = 1, 2, 3, 4, 5
+UNIFORM_I32, GAUSSIAN_ICDF_F32, GAUSSIAN_ICDF_F64 = 6, 7, 8
 PHILOX, MRG = 1, 2
 
 _u32p = ctypes.POINTER(ctypes.c_uint32)
@@ -84,6 +85,12 @@ def lib() -> ctypes.CDLL:
                                        ctypes.POINTER(ctypes.c_double)]
         L.orc_gauss64_uniforms.argtypes = [ctypes.c_int, _u32p, ctypes.POINTER(ctypes.c_double),
                                            ctypes.POINTER(ctypes.c_double)]
+        L.orc_uniform_i32.argtypes = [ctypes.c_uint32, ctypes.c_double, ctypes.c_double]
+        L.orc_uniform_i32.restype = ctypes.c_int32
+        L.orc_normal_quantile.argtypes = [ctypes.c_double]
+        L.orc_normal_quantile.restype = ctypes.c_double
+        L.orc_icdf_uniform.argtypes = [ctypes.c_int, ctypes.c_int, _u32p]
+        L.orc_icdf_uniform.restype = ctypes.c_double
         L.orc_apply.argtypes = [ctypes.c_int, ctypes.c_int, _u32p, ctypes.c_uint64,
                                 ctypes.c_double, ctypes.c_double, ctypes.c_void_p]
         L.orc_words_consumed.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_uint64]
@@ -114,7 +121,9 @@ def _ptr(a: np.ndarray, typ):
 
 
 OUT_DTYPE = {BITS_U32: np.uint32, UNIFORM_F32: np.float32,
-             UNIFORM_F64: np.float64, GAUSSIAN_F32: np.float64, GAUSSIAN_F64: np.float64}
+             UNIFORM_F64: np.float64, GAUSSIAN_F32: np.float64, GAUSSIAN_F64: np.float64,
+             UNIFORM_I32: np.int32, GAUSSIAN_ICDF_F32: np.float64,
+             GAUSSIAN_ICDF_F64: np.float64}
 
 PHILOX_POS_MOD = 1 << 130
 
@@ -173,6 +182,8 @@ def apply(kind: int, engine: int, words: np.ndarray, n: int,
 
 
 def default_params(kind: int):
+    if kind == UNIFORM_I32:
+        return (0.0, float(2**31))
     return (0.0, 1.0)
 
 
@@ -284,3 +295,19 @@ def box_muller_factors(words: np.ndarray):
     L.orc_box_muller_factors.argtypes = [_u32p, ctypes.c_uint64, dp, dp, dp]
     L.orc_box_muller_factors(_ptr(w, _u32p), n, _ptr(r, dp), _ptr(s, dp), _ptr(c, dp))
     return r, s, c
+
+
+def uniform_i32(w: int, a: float, b: float) -> int:
+    """R23: a + floor(w (b - a) / 2^32) in exact integer arithmetic."""
+    return int(lib().orc_uniform_i32(w, a, b))
+
+
+def normal_quantile(u: float) -> float:
+    """R24: the z with Phi(z) = u, by bisection on erf / erfc."""
+    return float(lib().orc_normal_quantile(u))
+
+
+def icdf_uniform(kind: int, engine: int, words) -> float:
+    """R24: the uniform in (0, 1) behind one inverse-CDF Gaussian output."""
+    w = np.ascontiguousarray(words, dtype=np.uint32)
+    return float(lib().orc_icdf_uniform(kind, 1 if engine == MRG else 0, _ptr(w, _u32p)))

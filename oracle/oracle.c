@@ -284,7 +284,10 @@ void orc_mrg_skip(uint64_t st[6], const uint64_t n[3])
  * Distributions (readings R10-R16).  Kinds match the library's numbering:
  * 1 = raw 32-bit words, 2 = uniform FP32, 3 = uniform FP64,
  * 4 = Gaussian (returned here as the FP64 transform; the library's FP32
- * result must be within 2 ulp of it), 5 = Gaussian FP64 (R21).
+ * result must be within 2 ulp of it), 5 = Gaussian FP64 (R21),
+ * 6 = uniform int32 on [a, b) (R23), 7 = Gaussian FP32 by the inverse
+ * normal CDF, 8 = Gaussian FP64 by the inverse normal CDF (R24; both
+ * returned as the FP64 transform).
  * ---------------------------------------------------------------------- */
 
 /* R10: u = (w >> 8) * 2^-24, exact, in [0, 1 - 2^-24]. */
@@ -383,10 +386,86 @@ void orc_gauss64_uniforms(int mrg, const uint32_t *w, double *u1, double *u2)
     }
 }
 
+/* R23: uniform integer on [a, b), -2^31 <= a < b <= 2^31: the word read as
+ * the fraction w / 2^32, scaled by r = b - a and floored, all in exact
+ * integer arithmetic: a + floor(w r / 2^32).
+ * Pinned by: exhaustive counts over all 2^32 words for small r (each value
+ * gets floor or ceil of 2^32 / r words), brute force over small words,
+ * the extremes of the range (tests/). */
+int32_t orc_uniform_i32(uint32_t w, double a, double b)
+{
+    const int64_t ia = (int64_t)a, ib = (int64_t)b;
+    const uint64_t r = (uint64_t)(ib - ia);                 /* 1 .. 2^32 */
+    const uint64_t k = (uint64_t)(((u128)w * r) >> 32);     /* 0 .. r - 1 */
+    return (int32_t)(ia + (int64_t)k);
+}
+
+/* Standard normal quantile z = Phi^{-1}(u), u in (0, 1), by its definition:
+ * the z with Phi(z) = u (R24).  With q = min(u, 1 - u) (1 - u is exact for
+ * u >= 1/2) and t = |z| >= 0:
+ *   q > 1/4:  erf(t / sqrt 2) = 1 - 2q   (exact right-hand side);
+ *   q <= 1/4: erfc(t / sqrt 2) = 2q      (exact right-hand side),
+ * so each side is a monotone function of t evaluated where libm is
+ * accurate.  t is found by bisection over the bit patterns of non-negative
+ * doubles (ordered like the doubles themselves) down to two neighbours,
+ * keeping the one whose function value is closer; z = -t for u < 1/2.
+ * Pinned by: mpmath's erfinv at 50 digits, the symmetry
+ * Phi^{-1}(1 - u) = -Phi^{-1}(u), known quantiles, scipy's ndtri (tests/). */
+static double quantile_side(double t, int center)
+{
+    const double x = t * M_SQRT1_2;
+    return center ? erf(x) : erfc(x);
+}
+
+double orc_normal_quantile(double u)
+{
+    if (u == 0.5) return 0.0;
+    const double q = u < 0.5 ? u : 1.0 - u;
+    const int center = q > 0.25;
+    const double target = center ? 1.0 - 2.0 * q : 2.0 * q;
+    /* erf rises with t, erfc falls; search [0, 40] (erfc(40 / sqrt 2) is 0) */
+    uint64_t lo, hi;
+    double d = 0.0;
+    memcpy(&lo, &d, 8);
+    d = 40.0;
+    memcpy(&hi, &d, 8);
+    while (hi - lo > 1) {
+        const uint64_t mid = lo + (hi - lo) / 2;
+        double t;
+        memcpy(&t, &mid, 8);
+        const double f = quantile_side(t, center);
+        const int below = center ? (f < target) : (f > target);
+        if (below) lo = mid;
+        else hi = mid;
+    }
+    double tl, th;
+    memcpy(&tl, &lo, 8);
+    memcpy(&th, &hi, 8);
+    const double el = fabs(quantile_side(tl, center) - target);
+    const double eh = fabs(quantile_side(th, center) - target);
+    const double t = el <= eh ? tl : th;
+    return u < 0.5 ? -t : t;
+}
+
+/* The uniform behind an inverse-CDF Gaussian (R24), strictly inside (0, 1):
+ * FP32 kind: u = ((w >> 8) + 1/2) 2^-24 from one word (Philox word or MRG
+ * output).  FP64 kind, Philox: with v the 53 bits of (w0, w1) as for
+ * uniform FP64, u = (floor(v / 2) + 1/2) 2^-52 (53 significant bits,
+ * exact); MRG: u = y / (m1 + 1) as for uniform FP64, which is never 0 or
+ * 1. */
+double orc_icdf_uniform(int kind, int mrg, const uint32_t *w)
+{
+    if (kind == 7) return ((double)(w[0] >> 8) + 0.5) * 0x1p-24;
+    if (mrg) return orc_u01_f64_mrg(w[0]);
+    const uint64_t v = (((uint64_t)w[1] << 32) | (uint64_t)w[0]) >> 11;
+    return ((double)(v >> 1) + 0.5) * 0x1p-52;
+}
+
 /* Apply a distribution to a word stream (kind numbering above).  For the
  * Philox engine U-F64 takes two words per output; for MRG one (R11).
  * Gaussian pairs use words (2j, 2j+1); odd n discards the last z1 (R14).
  * Output arrays: kind 1 -> uint32, 2 -> float, 3 -> double, 4 -> double
+ * (z * stddev + mean in FP64), 5 -> double, 6 -> int32, 7 and 8 -> double
  * (z * stddev + mean in FP64). */
 void orc_apply(int kind, int mrg, const uint32_t *w, uint64_t n,
                double p0, double p1, void *out)
@@ -432,18 +511,34 @@ void orc_apply(int kind, int mrg, const uint32_t *w, uint64_t n,
         }
         break;
     }
+    case 6: {
+        int32_t *o = (int32_t *)out;
+        for (i = 0; i < n; ++i) o[i] = orc_uniform_i32(w[i], p0, p1);
+        break;
+    }
+    case 7:
+    case 8: {
+        /* FP64 on Philox: words 2i, 2i + 1; otherwise word i */
+        double *o = (double *)out;
+        const int step = (kind == 8 && !mrg) ? 2 : 1;
+        for (i = 0; i < n; ++i) {
+            const double z = orc_normal_quantile(orc_icdf_uniform(kind, mrg, w + step * i));
+            o[i] = z * p1 + p0;
+        }
+        break;
+    }
     default:
         break;
     }
 }
 
 /* Number of engine words (Philox) or steps (MRG) that n outputs consume
- * (R14, R21): U-F64 on Philox takes 2 per output, Gaussian FP32 2 per
- * started pair, Gaussian FP64 4 (Philox) or 2 (MRG) per started pair,
- * everything else 1. */
+ * (R14, R21, R24): U-F64 and inverse-CDF Gaussian FP64 on Philox take 2
+ * per output, Gaussian FP32 2 per started pair, Gaussian FP64 4 (Philox)
+ * or 2 (MRG) per started pair, everything else 1. */
 uint64_t orc_words_consumed(int kind, int mrg, uint64_t n)
 {
-    if (kind == 3) return mrg ? n : 2 * n;
+    if (kind == 3 || kind == 8) return mrg ? n : 2 * n;
     if (kind == 4) return 2 * ((n + 1) / 2);
     if (kind == 5) return (mrg ? 2 : 4) * ((n + 1) / 2);
     return n;
