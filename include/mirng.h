@@ -41,13 +41,22 @@
  *     of words (4j, 4j+1) and (4j+2, 4j+3) (first word low); MRG u1, u2 =
  *     y_a / (m1 + 1), y_b / (m1 + 1) of outputs 2j, 2j+1; results within a
  *     few ulp of the exact transform.
+ *   Uniform int32 on [a, b) = a + floor(w (b - a) / 2^32), exact, with w
+ *     the engine word (Philox) or y (MRG).
+ *   Inverse-CDF Gaussians (the oneMKL "icdf" method, Sec. 4.1 of the
+ *     paper): z = Phi^-1(u) evaluated in FP64 with u strictly inside
+ *     (0, 1): FP32 kind u = ((w >> 8) + 1/2) 2^-24 from one word (or y);
+ *     FP64 kind, Philox u = (floor(v / 2) + 1/2) 2^-52 with v the 53-bit
+ *     value of two words as for uniform FP64, MRG u = y / (m1 + 1).  The
+ *     FP32 kind rounds z to FP32.  Results lie within a few ulp of the
+ *     exact quantile.
  *   Range: uniform r = fma(u, RN(b - a), RN(a)) in the output precision;
  *     Gaussian r = fma(z, RN32(stddev), RN32(mean)); Gaussian FP64
- *     r = fma(z, stddev, mean).
- *   Consumption per call: n words, except uniform FP64 on Philox (2n),
- *     Gaussian FP32 (2 * ceil(n / 2); for odd n the last z1 is dropped) and
- *     Gaussian FP64 (4 * ceil(n / 2) Philox words or 2 * ceil(n / 2) MRG
- *     steps).
+ *     r = fma(z, stddev, mean) (both methods).
+ *   Consumption per call: n words, except uniform FP64 and inverse-CDF
+ *     Gaussian FP64 on Philox (2n), Gaussian FP32 (2 * ceil(n / 2); for odd
+ *     n the last z1 is dropped) and Gaussian FP64 (4 * ceil(n / 2) Philox
+ *     words or 2 * ceil(n / 2) MRG steps).
  */
 #ifndef MIRNG_H
 #define MIRNG_H
@@ -73,12 +82,16 @@ typedef enum {
     MIRNG_UNIFORM_F32 = 2,   /* float out, [a, b); default (0, 1)            */
     MIRNG_UNIFORM_F64 = 3,   /* double out, [a, b); default (0, 1)           */
     MIRNG_GAUSSIAN_F32 = 4,  /* float out, mean p0, stddev p1; default (0,1) */
-    MIRNG_GAUSSIAN_F64 = 5   /* double out, mean p0, stddev p1; default (0,1) */
+    MIRNG_GAUSSIAN_F64 = 5,  /* double out, mean p0, stddev p1; default (0,1) */
+    MIRNG_UNIFORM_I32 = 6,   /* int32 out, [a, b), integers a = p0, b = p1   */
+    MIRNG_GAUSSIAN_ICDF_F32 = 7,  /* float out, inverse CDF; mean p0, sd p1   */
+    MIRNG_GAUSSIAN_ICDF_F64 = 8   /* double out, inverse CDF; mean p0, sd p1  */
 } mirng_dist_kind;
 
 /* A distribution: kind plus two parameters.  Uniform: p0 = a, p1 = b with
- * a < b, both finite.  Gaussian: p0 = mean (finite), p1 = stddev (finite,
- * > 0).  Bits: parameters ignored. */
+ * a < b, both finite.  Uniform int32: a and b integers with
+ * -2^31 <= a < b <= 2^31.  Gaussian (either method): p0 = mean (finite),
+ * p1 = stddev (finite, > 0).  Bits: parameters ignored. */
 typedef struct {
     int32_t kind;       /* a mirng_dist_kind */
     int32_t reserved;   /* must be 0 */

@@ -18,12 +18,14 @@ LIB_PATH = os.path.join(_HERE, "libmirng.so")
 
 PHILOX4X32_10, MRG32K3A = 1, 2
 BITS_U32, UNIFORM_F32, UNIFORM_F64, GAUSSIAN_F32, GAUSSIAN_F64 = 1, 2, 3, 4, 5
+UNIFORM_I32, GAUSSIAN_ICDF_F32, GAUSSIAN_ICDF_F64 = 6, 7, 8
 
 STATUS = {0: "MIRNG_OK", 1: "MIRNG_E_INVALID_ARG", 2: "MIRNG_E_UNSUPPORTED",
           3: "MIRNG_E_ALLOC", 4: "MIRNG_E_LAUNCH", 5: "MIRNG_E_DEVICE",
           6: "MIRNG_E_CAPACITY"}
 
-ELEM_BYTES = {BITS_U32: 4, UNIFORM_F32: 4, UNIFORM_F64: 8, GAUSSIAN_F32: 4, GAUSSIAN_F64: 8}
+ELEM_BYTES = {BITS_U32: 4, UNIFORM_F32: 4, UNIFORM_F64: 8, GAUSSIAN_F32: 4, GAUSSIAN_F64: 8,
+              UNIFORM_I32: 4, GAUSSIAN_ICDF_F32: 4, GAUSSIAN_ICDF_F64: 8}
 
 
 class MirngError(RuntimeError):
@@ -207,11 +209,18 @@ def words_consumed(engine_type: int, kind: int, n: int) -> int:
     return int(lib().mirng_words_consumed(engine_type, kind, n))
 
 
+def default_params(kind: int) -> tuple:
+    """Parameters used when none are given: (0, 1) (the unit range, or mean
+    0 and stddev 1), and [0, 2^31) for uniform int32."""
+    return (0.0, float(2**31)) if kind == UNIFORM_I32 else (0.0, 1.0)
+
+
 def distribution(kind: int, p0: float | None = None, p1: float | None = None) -> Distribution:
+    d0, d1 = default_params(kind)
     if p0 is None:
-        p0 = 0.0
+        p0 = d0
     if p1 is None:
-        p1 = 1.0
+        p1 = d1
     return Distribution(kind, 0, float(p0), float(p1))
 
 

@@ -85,26 +85,10 @@ mirng_status check_dist(const mirng_distribution *d)
 {
     if (!d) return MIRNG_E_INVALID_ARG;
     if (d->reserved != 0) return MIRNG_E_INVALID_ARG;
-    switch (d->kind) {
-    case kBits: return MIRNG_OK;
-    case kU32F:
-    case kU64F:
-        if (!finite(d->p0) || !finite(d->p1) || !(d->p0 < d->p1)) return MIRNG_E_INVALID_ARG;
-        return MIRNG_OK;
-    case kGauss:
-    case kGauss64:
-        if (!finite(d->p0) || !finite(d->p1) || !(d->p1 > 0.0)) return MIRNG_E_INVALID_ARG;
-        return MIRNG_OK;
-    default: return MIRNG_E_UNSUPPORTED;
-    }
+    return (mirng_status)check_params(d->kind, d->p0, d->p1);
 }
 
 size_t elem_size(int kind) { return (size_t)elem_bytes(kind); }
-
-bool is_default(const mirng_distribution *d)
-{
-    return d->kind == kBits || (d->p0 == 0.0 && d->p1 == 1.0);
-}
 
 // Largest number of outputs one Philox fill launch takes (slot indices
 // stay below 2^31).
@@ -112,23 +96,7 @@ constexpr uint64_t kMaxPerLaunch = 1ull << 32;
 
 Epilogue make_epilogue(const mirng_distribution *d, int nt)
 {
-    Epilogue ep{};
-    ep.ranged = is_default(d) ? 0 : 1;
-    ep.nt = nt;
-    if (d->kind == kU64F) {
-        ep.a64 = d->p0;
-        ep.d64 = d->p1 - d->p0;
-    } else if (d->kind == kGauss64) {
-        ep.a64 = d->p0;
-        ep.d64 = d->p1;
-    } else if (d->kind == kGauss) {
-        ep.a32 = (float)d->p0;
-        ep.d32 = (float)d->p1;
-    } else {
-        ep.a32 = (float)d->p0;
-        ep.d32 = (float)(d->p1 - d->p0);
-    }
-    return ep;
+    return epilogue_of(d->kind, d->p0, d->p1, nt);
 }
 
 // Words p .. of the engine into n outputs at out: the contiguous-walk
@@ -147,8 +115,12 @@ hipError_t philox_plain(const uint32_t key[2], Pos130 p, const mirng_distributio
         const uint64_t chunk = n < kMaxPerLaunch ? n : kMaxPerLaunch;
         const uint64_t b_lo = (p.l[0] >> 2) | (p.l[1] << 62);   // floor(p / 4), 128 bits
         const uint64_t b_hi = (p.l[1] >> 2) | (p.l[2] << 62);
+        // one word per output (and no pairs): any position; two words per
+        // output or per pair: even positions; FP64 Gaussian pairs (four
+        // words): never
+        const bool one_word = wpe == 1 && !paired(kind);
         const bool whole = tu.walk == 1 && kind != kGauss64 &&
-                           (kind == kBits || kind == kU32F || (p.l[0] & 1u) == 0);
+                           (one_word || (p.l[0] & 1u) == 0);
         const uintptr_t addr = (uintptr_t)out;
         hipError_t err;
         if (whole) {

@@ -107,8 +107,16 @@ hipError_t prepare(Slot &s, size_t count, int dev)
 struct Work {
     uint64_t tiles = 0, chunks = 0;
     int32_t philox = 0, mrg = 0;
-    int32_t wide = 0;   // a Philox Gaussian FP64 request: the wide kernel
+    int32_t wide = 0;   // a Philox request only the wide kernel holds
 };
+
+// Philox kinds whose transforms need many registers (FP64 Box-Muller, the
+// inverse-CDF Gaussians) live in a separate generation kernel.
+bool wide_kind(int kind)
+{
+    return kind == MIRNG_GAUSSIAN_F64 || kind == MIRNG_GAUSSIAN_ICDF_F32 ||
+           kind == MIRNG_GAUSSIAN_ICDF_F64;
+}
 
 Work scan_requests(const mirng_request *q, size_t count)
 {
@@ -118,11 +126,12 @@ Work scan_requests(const mirng_request *q, size_t count)
         const bool mg = q[i].engine_type == MIRNG_MRG32K3A;
         w.philox |= ph;
         w.mrg |= mg;
-        w.wide |= ph && q[i].dist.kind == MIRNG_GAUSSIAN_F64;
+        w.wide |= ph && wide_kind(q[i].dist.kind);
         const uint64_t n = q[i].n;
         if (n == 0 || n >= (1ull << 32)) continue;
         const bool f64 = q[i].dist.kind == MIRNG_UNIFORM_F64 ||
-                         q[i].dist.kind == MIRNG_GAUSSIAN_F64;
+                         q[i].dist.kind == MIRNG_GAUSSIAN_F64 ||
+                         q[i].dist.kind == MIRNG_GAUSSIAN_ICDF_F64;
         if (mg) {
             const uint64_t per = (uint64_t)256 * mirng::kBatchMrgPasses * (f64 ? 16 : 32);
             w.chunks += (n + per - 1) / per;

@@ -31,8 +31,6 @@ namespace {
 
 constexpr uint32_t kChunk = 1024;
 
-__device__ __forceinline__ bool finite(double x) { return __builtin_isfinite(x); }
-
 // Validation and planning of one request: its Philox tiles or MRG chunks.
 __device__ void plan_one(const mirng_request &q, BatchDesc &d, int32_t &st, int nt,
                          const uint32_t *pow2, uint64_t &tiles, uint64_t &mchunks)
@@ -48,42 +46,16 @@ __device__ void plan_one(const mirng_request &q, BatchDesc &d, int32_t &st, int 
     }
     const int kind = q.dist.kind;
     if (q.reserved != 0 || q.dist.reserved != 0) { st = MIRNG_E_INVALID_ARG; return; }
-    if (kind < kBits || kind > kGauss64) { st = MIRNG_E_UNSUPPORTED; return; }
     const double p0 = q.dist.p0, p1 = q.dist.p1;
-    if ((kind == kU32F || kind == kU64F) && !(finite(p0) && finite(p1) && p0 < p1)) {
-        st = MIRNG_E_INVALID_ARG;
-        return;
-    }
-    if (paired(kind) && !(finite(p0) && finite(p1) && p1 > 0.0)) {
-        st = MIRNG_E_INVALID_ARG;
-        return;
-    }
+    st = check_params(kind, p0, p1);
+    if (st != MIRNG_OK) return;
     if (q.n == 0) return;
     const uint64_t esz = (uint64_t)elem_bytes(kind);
     const uint64_t addr = (uint64_t)(uintptr_t)q.out;
     if (addr == 0 || addr % esz) { st = MIRNG_E_INVALID_ARG; return; }
     if (q.n >= (1ull << 32)) { st = MIRNG_E_CAPACITY; return; }
 
-    Epilogue ep;
-    ep.ranged = (kind == kBits || (p0 == 0.0 && p1 == 1.0)) ? 0 : 1;
-    ep.nt = nt;
-    ep.a64 = 0.0;
-    ep.d64 = 0.0;
-    ep.a32 = 0.0f;
-    ep.d32 = 0.0f;
-    if (kind == kU64F) {
-        ep.a64 = p0;
-        ep.d64 = p1 - p0;
-    } else if (kind == kGauss64) {
-        ep.a64 = p0;
-        ep.d64 = p1;
-    } else if (kind == kGauss) {
-        ep.a32 = (float)p0;
-        ep.d32 = (float)p1;
-    } else {
-        ep.a32 = (float)p0;
-        ep.d32 = (float)(p1 - p0);
-    }
+    const Epilogue ep = epilogue_of(kind, p0, p1, nt);
     SlotRun &r = d.run;
     r.n = q.n;
     r.ep = ep;
@@ -366,9 +338,9 @@ __device__ __forceinline__ void run_kind(const BatchDesc &d, uint32_t u0, uint32
     }
 }
 
-// WIDE: the batch holds Philox Gaussian FP64 requests.  Their transform
-// needs many more registers, so batches without them run a kernel that
-// does not contain it (and keeps its occupancy).
+// WIDE: the batch holds Philox Gaussian FP64 or inverse-CDF Gaussian
+// requests.  Their transforms need many more registers, so batches without
+// them run a kernel that does not contain them (and keeps its occupancy).
 template <bool WIDE>
 __device__ void run_segment(const BatchDesc &d, uint32_t u0, uint32_t span, uint32_t lane)
 {
@@ -377,8 +349,15 @@ __device__ void run_segment(const BatchDesc &d, uint32_t u0, uint32_t span, uint
     case kU32F: run_kind<kU32F>(d, u0, span, lane); break;
     case kU64F: run_kind<kU64F>(d, u0, span, lane); break;
     case kGauss: run_kind<kGauss>(d, u0, span, lane); break;
+    case kI32: run_kind<kI32>(d, u0, span, lane); break;
     default:
-        if constexpr (WIDE) run_kind<kGauss64>(d, u0, span, lane);
+        if constexpr (WIDE) {
+            switch (d.kind) {
+            case kGauss64: run_kind<kGauss64>(d, u0, span, lane); break;
+            case kIcdf: run_kind<kIcdf>(d, u0, span, lane); break;
+            default: run_kind<kIcdf64>(d, u0, span, lane); break;
+            }
+        }
         break;
     }
 }
@@ -496,7 +475,10 @@ __global__ __launch_bounds__(kMrgThreads) void batch_mrg_kernel(BatchArgs a)
                 case kU32F: mrg_chunk<kU32F>(d, k, a.c_tab4, a.u_tab4, lds, wg_state); break;
                 case kU64F: mrg_chunk<kU64F>(d, k, a.c_tab8, a.u_tab8, lds, wg_state); break;
                 case kGauss: mrg_chunk<kGauss>(d, k, a.c_tab4, a.u_tab4, lds, wg_state); break;
-                default: mrg_chunk<kGauss64>(d, k, a.c_tab8, a.u_tab8, lds, wg_state); break;
+                case kGauss64: mrg_chunk<kGauss64>(d, k, a.c_tab8, a.u_tab8, lds, wg_state); break;
+                case kI32: mrg_chunk<kI32>(d, k, a.c_tab4, a.u_tab4, lds, wg_state); break;
+                case kIcdf: mrg_chunk<kIcdf>(d, k, a.c_tab4, a.u_tab4, lds, wg_state); break;
+                default: mrg_chunk<kIcdf64>(d, k, a.c_tab8, a.u_tab8, lds, wg_state); break;
                 }
             }
             c = seg;

@@ -150,8 +150,11 @@ uint64_t words_consumed(int engine_type, int kind, uint64_t n)
 {
     switch (kind) {
     case kBits:
-    case kU32F: return n;
-    case kU64F: return engine_type == MIRNG_PHILOX4X32_10 ? 2 * n : n;
+    case kU32F:
+    case kI32:
+    case kIcdf: return n;
+    case kU64F:
+    case kIcdf64: return engine_type == MIRNG_PHILOX4X32_10 ? 2 * n : n;
     case kGauss: return 2 * ((n + 1) / 2);
     case kGauss64: return (engine_type == MIRNG_PHILOX4X32_10 ? 4 : 2) * ((n + 1) / 2);
     default: return 0;

@@ -57,13 +57,21 @@ void mrg_seed_state(uint64_t seed, uint32_t st[6]);
 uint64_t words_consumed(int engine_type, int kind, uint64_t n);
 
 // ------------------------------------------------------------ launches
-enum Kind : int32_t { kBits = 1, kU32F = 2, kU64F = 3, kGauss = 4, kGauss64 = 5 };
+enum Kind : int32_t {
+    kBits = 1, kU32F = 2, kU64F = 3, kGauss = 4, kGauss64 = 5,
+    kI32 = 6, kIcdf = 7, kIcdf64 = 8
+};
 
 // Bytes of one output and engine words (Philox) per output.
-constexpr int elem_bytes(int kind) { return (kind == kU64F || kind == kGauss64) ? 8 : 4; }
-constexpr int philox_words_per_elem(int kind) { return (kind == kU64F || kind == kGauss64) ? 2 : 1; }
+constexpr int elem_bytes(int kind)
+{
+    return (kind == kU64F || kind == kGauss64 || kind == kIcdf64) ? 8 : 4;
+}
+constexpr int philox_words_per_elem(int kind) { return elem_bytes(kind) == 8 ? 2 : 1; }
 // Kinds whose outputs come in pairs from one Box-Muller transform.
 constexpr bool paired(int kind) { return kind == kGauss || kind == kGauss64; }
+// Kinds with a range (or mean / sd) step that the defaults make a no-op.
+constexpr bool has_range_step(int kind) { return kind != kBits && kind != kI32; }
 
 // Output epilogue parameters shared by the generation kernels.
 struct Epilogue {
@@ -71,7 +79,64 @@ struct Epilogue {
     double a64, d64;        // uniform F64: fma(u, d, a); Gaussian F64: fma(z, sd, mean)
     int32_t ranged;         // 0 when the parameters are the defaults
     int32_t nt;             // streaming stores
+    int32_t ia;             // uniform int32: a
+    uint32_t irm1;          // uniform int32: b - a - 1
 };
+
+// The parameter rules of each kind (the ABI's): MIRNG_OK,
+// MIRNG_E_INVALID_ARG or MIRNG_E_UNSUPPORTED.  Host and device.
+__host__ __device__ inline int32_t check_params(int kind, double p0, double p1)
+{
+    const bool fin = __builtin_isfinite(p0) && __builtin_isfinite(p1);
+    switch (kind) {
+    case kBits: return MIRNG_OK;
+    case kU32F:
+    case kU64F: return (fin && p0 < p1) ? MIRNG_OK : MIRNG_E_INVALID_ARG;
+    case kGauss:
+    case kGauss64:
+    case kIcdf:
+    case kIcdf64: return (fin && p1 > 0.0) ? MIRNG_OK : MIRNG_E_INVALID_ARG;
+    case kI32:
+        return (fin && p0 == __builtin_floor(p0) && p1 == __builtin_floor(p1) &&
+                p0 >= -2147483648.0 && p1 <= 2147483648.0 && p0 < p1)
+                   ? MIRNG_OK
+                   : MIRNG_E_INVALID_ARG;
+    default: return MIRNG_E_UNSUPPORTED;
+    }
+}
+
+// The epilogue of a valid (kind, p0, p1).  Host and device.
+__host__ __device__ inline Epilogue epilogue_of(int kind, double p0, double p1, int nt)
+{
+    Epilogue ep{};
+    ep.ranged = (!has_range_step(kind) || (p0 == 0.0 && p1 == 1.0)) ? 0 : 1;
+    ep.nt = nt;
+    switch (kind) {
+    case kU64F:
+        ep.a64 = p0;
+        ep.d64 = p1 - p0;
+        break;
+    case kGauss64:
+    case kIcdf64:
+        ep.a64 = p0;
+        ep.d64 = p1;
+        break;
+    case kGauss:
+    case kIcdf:
+        ep.a32 = (float)p0;
+        ep.d32 = (float)p1;
+        break;
+    case kI32:
+        ep.ia = (int32_t)(int64_t)p0;
+        ep.irm1 = (uint32_t)((int64_t)p1 - (int64_t)p0 - 1);
+        break;
+    default:
+        ep.a32 = (float)p0;
+        ep.d32 = (float)(p1 - p0);
+        break;
+    }
+    return ep;
+}
 
 // Fast Philox launch: block j (counter base + j) carries words that are
 // whole output elements j * epb - head .. j * epb - head + epb - 1 (epb = 4,

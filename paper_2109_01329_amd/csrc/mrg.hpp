@@ -115,10 +115,27 @@ struct MrgShape {
 };
 
 // Runs L steps of `s` and writes the L outputs into `row` (16-byte aligned).
+// The inverse-CDF kinds evaluate one quantile at a time (a rolled loop) so
+// that the registers of one quantile suffice.
 template <int KIND>
 __device__ __forceinline__ void mrg_fill_row(MrgState &s, char *row, const Epilogue &ep)
 {
     using S = MrgShape<KIND>;
+    if constexpr (KIND == kIcdf || KIND == kIcdf64) {
+#pragma unroll 1
+        for (int l = 0; l < S::L; ++l) {
+            if constexpr (KIND == kIcdf) {
+                float f = icdf_f32((uint32_t)mrg_step(s));
+                if (ep.ranged) f = __builtin_fmaf(f, ep.d32, ep.a32);
+                *(float *)(row + l * 4) = f;
+            } else {
+                // u = y / (m1 + 1) as for uniform FP64: never 0 or 1
+                double d = normal_quantile(mrg_step(s) * kNorm);
+                if (ep.ranged) d = __builtin_fma(d, ep.d64, ep.a64);
+                *(double *)(row + l * 8) = d;
+            }
+        }
+    } else {
 #pragma unroll
     for (int l = 0; l < S::L; l += S::EPV) {
         u32x4 pk;
@@ -154,7 +171,13 @@ __device__ __forceinline__ void mrg_fill_row(MrgState &s, char *row, const Epilo
                 d.y = __builtin_fma(d.y, ep.d64, ep.a64);
             }
             pk = __builtin_bit_cast(u32x4, d);
+        } else if constexpr (KIND == kI32) {
+            pk.x = uniform_i32((uint32_t)mrg_step(s), ep.ia, ep.irm1);
+            pk.y = uniform_i32((uint32_t)mrg_step(s), ep.ia, ep.irm1);
+            pk.z = uniform_i32((uint32_t)mrg_step(s), ep.ia, ep.irm1);
+            pk.w = uniform_i32((uint32_t)mrg_step(s), ep.ia, ep.irm1);
         } else {
+            static_assert(KIND == kGauss, "unknown kind");
             const uint32_t w0 = (uint32_t)mrg_step(s);
             const uint32_t w1 = (uint32_t)mrg_step(s);
             const uint32_t w2 = (uint32_t)mrg_step(s);
@@ -171,6 +194,7 @@ __device__ __forceinline__ void mrg_fill_row(MrgState &s, char *row, const Epilo
             pk = __builtin_bit_cast(u32x4, f);
         }
         *(u32x4 *)(row + (l / S::EPV) * 16) = pk;
+    }
     }
 }
 

@@ -218,30 +218,18 @@ hipError_t launch(const MrgLaunch &a, int kind, uint64_t groups, hipStream_t s)
     case kU32F: hipLaunchKernelGGL(mrg_kernel<kU32F>, grid, block, 0, s, a); break;
     case kU64F: hipLaunchKernelGGL(mrg_kernel<kU64F>, grid, block, 0, s, a); break;
     case kGauss: hipLaunchKernelGGL(mrg_kernel<kGauss>, grid, block, 0, s, a); break;
-    default: hipLaunchKernelGGL(mrg_kernel<kGauss64>, grid, block, 0, s, a); break;
+    case kGauss64: hipLaunchKernelGGL(mrg_kernel<kGauss64>, grid, block, 0, s, a); break;
+    case kI32: hipLaunchKernelGGL(mrg_kernel<kI32>, grid, block, 0, s, a); break;
+    case kIcdf: hipLaunchKernelGGL(mrg_kernel<kIcdf>, grid, block, 0, s, a); break;
+    case kIcdf64: hipLaunchKernelGGL(mrg_kernel<kIcdf64>, grid, block, 0, s, a); break;
+    default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
 void fill_params(MrgLaunch &a, const mirng_distribution *d)
 {
-    Epilogue &e = a.ep;
-    e = Epilogue{};
-    e.ranged = (d->kind == kBits || (d->p0 == 0.0 && d->p1 == 1.0)) ? 0 : 1;
-    e.nt = 1;
-    if (d->kind == kU64F) {
-        e.a64 = d->p0;
-        e.d64 = d->p1 - d->p0;
-    } else if (d->kind == kGauss64) {
-        e.a64 = d->p0;
-        e.d64 = d->p1;
-    } else if (d->kind == kGauss) {
-        e.a32 = (float)d->p0;
-        e.d32 = (float)d->p1;
-    } else {
-        e.a32 = (float)d->p0;
-        e.d32 = (float)(d->p1 - d->p0);
-    }
+    a.ep = epilogue_of(d->kind, d->p0, d->p1, 1);
 }
 
 hipError_t run(const uint32_t st[6], const mirng_distribution *d, uint64_t s_first,

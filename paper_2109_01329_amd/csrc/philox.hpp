@@ -105,7 +105,29 @@ __device__ __forceinline__ u32x4 transform(const Epilogue &ep, u32x4 w)
             d.y = __builtin_fma(d.y, ep.d64, ep.a64);
         }
         v = __builtin_bit_cast(u32x4, d);
+    } else if constexpr (KIND == kI32) {
+        v.x = uniform_i32(w.x, ep.ia, ep.irm1);
+        v.y = uniform_i32(w.y, ep.ia, ep.irm1);
+        v.z = uniform_i32(w.z, ep.ia, ep.irm1);
+        v.w = uniform_i32(w.w, ep.ia, ep.irm1);
+    } else if constexpr (KIND == kIcdf) {
+        f32x4 f = icdf4_f32(w);
+        if (ranged<RANGED>(ep)) {
+            f.x = __builtin_fmaf(f.x, ep.d32, ep.a32);
+            f.y = __builtin_fmaf(f.y, ep.d32, ep.a32);
+            f.z = __builtin_fmaf(f.z, ep.d32, ep.a32);
+            f.w = __builtin_fmaf(f.w, ep.d32, ep.a32);
+        }
+        v = __builtin_bit_cast(u32x4, f);
+    } else if constexpr (KIND == kIcdf64) {
+        f64x2 d = icdf2_f64(w);
+        if (ranged<RANGED>(ep)) {
+            d.x = __builtin_fma(d.x, ep.d64, ep.a64);
+            d.y = __builtin_fma(d.y, ep.d64, ep.a64);
+        }
+        v = __builtin_bit_cast(u32x4, d);
     } else {
+        static_assert(KIND == kGauss, "unknown kind");
         f32x4 f;
         f.xy = box_muller(w.x, w.y);
         f.zw = box_muller(w.z, w.w);

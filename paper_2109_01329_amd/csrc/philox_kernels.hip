@@ -48,7 +48,7 @@ namespace {
 template <int KIND, int BPL>
 __global__ __launch_bounds__(1024) void philox_blocks_kernel(PhiloxBlocks a)
 {
-    constexpr int EPB = (KIND == kU64F) ? 2 : 4;      // elements per block
+    constexpr int EPB = 16 / elem_bytes(KIND);        // elements per block
     constexpr int ESZ = 16 / EPB;
     constexpr uint32_t PER = 64u * BPL;               // blocks per wave step
     const uint32_t lane = threadIdx.x & 63u;
@@ -82,7 +82,7 @@ __global__ __launch_bounds__(1024) void philox_fill_kernel(PhiloxFill a)
     if (first >= a.nslots) return;
     const uint32_t s0 = (uint32_t)first;
     const uint32_t span = min(a.slots_per_wave, a.nslots - s0);
-    if (KIND != kBits && a.run.ep.ranged)
+    if (has_range_step(KIND) && a.run.ep.ranged)
         walk_slots<KIND, PHASE, 1>(a.run, s0, span, lane);
     else
         walk_slots<KIND, PHASE, 0>(a.run, s0, span, lane);
@@ -100,7 +100,7 @@ __global__ __launch_bounds__(1024) void philox_chunk_kernel(PhiloxFill a)
     if (first >= a.nslots) return;
     const uint32_t s0 = (uint32_t)first;
     const uint32_t span = min(PER, a.nslots - s0);
-    if (KIND != kBits && a.run.ep.ranged)
+    if (has_range_step(KIND) && a.run.ep.ranged)
         walk_chunks<KIND, PHASE, ITERS, 1>(a.run, s0, span, lane);
     else
         walk_chunks<KIND, PHASE, ITERS, 0>(a.run, s0, span, lane);
@@ -161,6 +161,9 @@ hipError_t launch_philox_blocks(const PhiloxBlocks &a, hipStream_t s)
     case kU32F: return launch_blocks_kind<kU32F>(a, s);
     case kU64F: return launch_blocks_kind<kU64F>(a, s);
     case kGauss: return launch_blocks_kind<kGauss>(a, s);
+    case kI32: return launch_blocks_kind<kI32>(a, s);
+    case kIcdf: return launch_blocks_kind<kIcdf>(a, s);
+    case kIcdf64: return launch_blocks_kind<kIcdf64>(a, s);
     default: return hipErrorInvalidValue;   // Gaussian FP64 pairs span whole blocks: fill walk
     }
 }
@@ -177,7 +180,11 @@ hipError_t launch_philox_fill(const PhiloxFill &a, hipStream_t s)
         case kU32F: return launch_chunk_kind<kU32F>(a, grid, block, s);
         case kU64F: return launch_chunk_kind<kU64F>(a, grid, block, s);
         case kGauss: return launch_chunk_kind<kGauss>(a, grid, block, s);
-        default: return launch_chunk_kind<kGauss64>(a, grid, block, s);
+        case kGauss64: return launch_chunk_kind<kGauss64>(a, grid, block, s);
+        case kI32: return launch_chunk_kind<kI32>(a, grid, block, s);
+        case kIcdf: return launch_chunk_kind<kIcdf>(a, grid, block, s);
+        case kIcdf64: return launch_chunk_kind<kIcdf64>(a, grid, block, s);
+        default: return hipErrorInvalidValue;
         }
     }
     switch (a.kind) {
@@ -185,7 +192,11 @@ hipError_t launch_philox_fill(const PhiloxFill &a, hipStream_t s)
     case kU32F: return launch_fill_kind<kU32F>(a, grid, block, s);
     case kU64F: return launch_fill_kind<kU64F>(a, grid, block, s);
     case kGauss: return launch_fill_kind<kGauss>(a, grid, block, s);
-    default: return launch_fill_kind<kGauss64>(a, grid, block, s);
+    case kGauss64: return launch_fill_kind<kGauss64>(a, grid, block, s);
+    case kI32: return launch_fill_kind<kI32>(a, grid, block, s);
+    case kIcdf: return launch_fill_kind<kIcdf>(a, grid, block, s);
+    case kIcdf64: return launch_fill_kind<kIcdf64>(a, grid, block, s);
+    default: return hipErrorInvalidValue;
     }
 }
 

@@ -11,9 +11,10 @@ namespace mirng {
 uint64_t request_bytes(const mirng_request &r)
 {
     // requests the batched kernel refuses write nothing
-    if (r.dist.kind < MIRNG_BITS_U32 || r.dist.kind > MIRNG_GAUSSIAN_F64) return 0;
+    if (r.dist.kind < MIRNG_BITS_U32 || r.dist.kind > MIRNG_GAUSSIAN_ICDF_F64) return 0;
     if (r.n >= (1ull << 32)) return 0;
-    const bool f64 = r.dist.kind == MIRNG_UNIFORM_F64 || r.dist.kind == MIRNG_GAUSSIAN_F64;
+    const bool f64 = r.dist.kind == MIRNG_UNIFORM_F64 || r.dist.kind == MIRNG_GAUSSIAN_F64 ||
+                     r.dist.kind == MIRNG_GAUSSIAN_ICDF_F64;
     return r.n * (f64 ? 8u : 4u);
 }
 

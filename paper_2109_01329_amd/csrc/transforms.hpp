@@ -1,6 +1,8 @@
 // Device-side output transforms shared by the Philox and MRG32k3a kernels
 // (library-internal).  Conventions: uniform FP32 = (w >> 8) 2^-24; uniform
-// FP64 from two Philox words = 53 bits * 2^-53; Box-Muller on a word pair.
+// FP64 from two Philox words = 53 bits * 2^-53; Box-Muller on a word pair;
+// uniform int32 by an exact multiply-high; inverse-CDF Gaussians on
+// uniforms strictly inside (0, 1).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -127,6 +129,122 @@ __device__ __forceinline__ f64x2 box_muller64(double u1, double u2)
     z.x = r * c;
     z.y = r * s;
     return z;
+}
+
+// Uniform int32 on [a, b): a + floor(w r / 2^32) with r = irm1 + 1 in
+// [1, 2^32]; w r = w irm1 + w < 2^64, so one 32 x 32 + 32 multiply-add
+// gives it exactly.  The sum wraps like the int32 it stands for.
+__device__ __forceinline__ uint32_t uniform_i32(uint32_t w, int32_t ia, uint32_t irm1)
+{
+    const uint64_t p = (uint64_t)w * irm1 + w;
+    return (uint32_t)ia + (uint32_t)(p >> 32);
+}
+
+// Coefficients of Wichura's algorithm AS 241 (PPND16; Applied Statistics
+// 37(3), 1988): numerator and denominator polynomials of degree 7, lowest
+// order first, for the central region (A / B), the near tails (C / D) and
+// the far tails (E / F).  Kept in constant memory: read as scalar operands
+// they cost no vector registers (FP64 literals would each need two).
+static __constant__ double kPpnd16[6][8] = {
+    {3.387132872796366608, 133.14166789178437745, 1971.5909503065514427,
+     13731.693765509461125, 45921.953931549871457, 67265.770927008700853,
+     33430.575583588128105, 2509.0809287301226727},
+    {1.0, 42.313330701600911252, 687.1870074920579083, 5394.1960214247511077,
+     21213.794301586595867, 39307.89580009271061, 28729.085735721942674,
+     5226.495278852545925},
+    {1.42343711074968357734, 4.6303378461565452959, 5.7694972214606914055,
+     3.64784832476320460504, 1.27045825245236838258, 0.24178072517745061177,
+     0.0227238449892691845833, 7.7454501427834140764e-4},
+    {1.0, 2.05319162663775882187, 1.6763848301838038494, 0.68976733498510000455,
+     0.14810397642748007459, 0.0151986665636164571966, 5.475938084995344946e-4,
+     1.05075007164441684324e-9},
+    {6.6579046435011037772, 5.4637849111641143699, 1.7848265399172913358,
+     0.29656057182850489123, 0.026532189526576123093, 0.0012426609473880784386,
+     2.71155556874348757815e-5, 2.01033439929228813265e-7},
+    {1.0, 0.59983220655588793769, 0.13692988092273580531, 0.0148753612908506148525,
+     7.868691311456132591e-4, 1.8463183175100546818e-5, 1.4215117583164458887e-7,
+     2.04426310338993978564e-15}};
+
+// Polynomial j of the table at x by Horner's rule with fused multiply-adds.
+__device__ __forceinline__ double ppnd16_poly(int j, double x)
+{
+    double r = kPpnd16[j][7];
+#pragma unroll
+    for (int k = 6; k >= 0; --k) r = __builtin_fma(r, x, kPpnd16[j][k]);
+    return r;
+}
+
+// Standard normal quantile Phi^-1(u), u in (0, 1), in FP64 by AS 241,
+// whose rational approximations have relative error near 1e-16.  Central
+// region |u - 1/2| <= 0.425: z = q A(r) / B(r), q = u - 1/2 (exact),
+// r = 0.180625 - q^2.  Tails: r = sqrt(-ln min(u, 1 - u)), then
+// C(r - 1.6) / D(r - 1.6) for r <= 5 and E(r - 5) / F(r - 5) beyond, with
+// the sign of q.  (The device library's quantile is several times larger
+// and spills registers when inlined into the generation loops.)
+__device__ __forceinline__ double normal_quantile(double u)
+{
+    const double q = u - 0.5;
+    if (__builtin_fabs(q) <= 0.425) {
+        const double r = __builtin_fma(-q, q, 0.180625);
+        return q * ppnd16_poly(0, r) / ppnd16_poly(1, r);
+    }
+    const double t = q < 0.0 ? u : 1.0 - u;
+    double r = __builtin_sqrt(-log(t));
+    double z;
+    if (r <= 5.0) {
+        r -= 1.6;
+        z = ppnd16_poly(2, r) / ppnd16_poly(3, r);
+    } else {
+        r -= 5.0;
+        z = ppnd16_poly(4, r) / ppnd16_poly(5, r);
+    }
+    return q < 0.0 ? -z : z;
+}
+
+// Inverse-CDF Gaussian from one word: u = ((w >> 8) + 1/2) 2^-24 (exact in
+// FP64, strictly inside (0, 1)), z = Phi^-1(u) in FP64, rounded once to
+// FP32.
+__device__ __forceinline__ float icdf_f32(uint32_t w)
+{
+    const double u = ((double)(w >> 8) + 0.5) * 0x1p-24;
+    return (float)normal_quantile(u);
+}
+
+// Four inverse-CDF Gaussians, one quantile at a time (a rolled loop that
+// rotates the words through one lane of the vector), so that the registers
+// of one quantile suffice.
+__device__ __forceinline__ f32x4 icdf4_f32(u32x4 w)
+{
+    f32x4 f = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll 1
+    for (int j = 0; j < 4; ++j) {
+        const float z = icdf_f32(w.x);
+        w = u32x4{w.y, w.z, w.w, w.x};
+        f = f32x4{f.y, f.z, f.w, z};
+    }
+    return f;
+}
+
+// The FP64 uniform of an inverse-CDF Gaussian from two Philox words: with
+// v the 53-bit value of (hi:lo) as for uniform FP64,
+// u = (floor(v / 2) + 1/2) 2^-52 (53 significant bits, exact).
+__device__ __forceinline__ double icdf_u64(uint32_t lo, uint32_t hi)
+{
+    const uint64_t v = (((uint64_t)hi << 32) | lo) >> 12;
+    return ((double)v + 0.5) * 0x1p-52;
+}
+
+// Two FP64 inverse-CDF Gaussians from four Philox words, one at a time.
+__device__ __forceinline__ f64x2 icdf2_f64(u32x4 w)
+{
+    f64x2 d = {0.0, 0.0};
+#pragma unroll 1
+    for (int j = 0; j < 2; ++j) {
+        const double z = normal_quantile(icdf_u64(w.x, w.y));
+        w = u32x4{w.z, w.w, w.x, w.y};
+        d = f64x2{d.y, z};
+    }
+    return d;
 }
 
 }  // namespace mirng

@@ -20,13 +20,17 @@ META_SEED = 1329
 
 PHILOX, MRG = 1, 2
 BITS_U32, UNIFORM_F32, UNIFORM_F64, GAUSSIAN_F32, GAUSSIAN_F64 = 1, 2, 3, 4, 5
+UNIFORM_I32, GAUSSIAN_ICDF_F32, GAUSSIAN_ICDF_F64 = 6, 7, 8
 KINDS = (UNIFORM_F32, UNIFORM_F64, GAUSSIAN_F32, BITS_U32)
+EXTRA_KINDS = (GAUSSIAN_F64, UNIFORM_I32, GAUSSIAN_ICDF_F32, GAUSSIAN_ICDF_F64)
 ENGINES = (PHILOX, MRG)
 KIND_NAME = {BITS_U32: "bits_u32", UNIFORM_F32: "uniform_f32",
              UNIFORM_F64: "uniform_f64", GAUSSIAN_F32: "gaussian_f32",
-             GAUSSIAN_F64: "gaussian_f64"}
+             GAUSSIAN_F64: "gaussian_f64", UNIFORM_I32: "uniform_i32",
+             GAUSSIAN_ICDF_F32: "gaussian_icdf_f32", GAUSSIAN_ICDF_F64: "gaussian_icdf_f64"}
 ENGINE_NAME = {PHILOX: "philox4x32_10", MRG: "mrg32k3a"}
-ELEM_BYTES = {BITS_U32: 4, UNIFORM_F32: 4, UNIFORM_F64: 8, GAUSSIAN_F32: 4, GAUSSIAN_F64: 8}
+ELEM_BYTES = {BITS_U32: 4, UNIFORM_F32: 4, UNIFORM_F64: 8, GAUSSIAN_F32: 4, GAUSSIAN_F64: 8,
+              UNIFORM_I32: 4, GAUSSIAN_ICDF_F32: 4, GAUSSIAN_ICDF_F64: 8}
 
 
 def rng(k: int) -> np.random.Generator:
@@ -57,13 +61,17 @@ def bulk_draws(count: int = 3):
 
 def extra_draws():
     """(engine, kind, seed, offset) cells of the kinds outside the bulk mix
-    (Gaussian FP64), one per engine, drawn like the bulk cells."""
-    g = rng(6)
+    (Gaussian FP64, uniform int32, inverse-CDF Gaussians), one per engine
+    and kind, drawn like the bulk cells (meta-seed 6 for Gaussian FP64,
+    8 for the others)."""
     cells = []
-    for engine in ENGINES:
-        seed = int(g.integers(0, 2**64, dtype=np.uint64))
-        offset = int(g.integers(0, 2**40, dtype=np.uint64))
-        cells.append((engine, GAUSSIAN_F64, seed, offset))
+    for k, kinds in ((6, (GAUSSIAN_F64,)), (8, EXTRA_KINDS[1:])):
+        g = rng(k)
+        for kind in kinds:
+            for engine in ENGINES:
+                seed = int(g.integers(0, 2**64, dtype=np.uint64))
+                offset = int(g.integers(0, 2**40, dtype=np.uint64))
+                cells.append((engine, kind, seed, offset))
     return cells
 
 

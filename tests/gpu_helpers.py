@@ -12,7 +12,8 @@ import paper_2109_01329_amd as mr
 
 NP_DTYPE = {mr.BITS_U32: np.uint32, mr.UNIFORM_F32: np.float32,
             mr.UNIFORM_F64: np.float64, mr.GAUSSIAN_F32: np.float32,
-            mr.GAUSSIAN_F64: np.float64}
+            mr.GAUSSIAN_F64: np.float64, mr.UNIFORM_I32: np.int32,
+            mr.GAUSSIAN_ICDF_F32: np.float32, mr.GAUSSIAN_ICDF_F64: np.float64}
 
 
 def device_buffer(nbytes: int):
@@ -114,13 +115,13 @@ def gauss64_errors(g: np.ndarray, d: np.ndarray, mean: float = 0.0, sd: float = 
 
 def assert_match(kind: int, got: np.ndarray, want: np.ndarray, p0=None, p1=None):
     assert got.shape == want.shape
-    if kind == mr.GAUSSIAN_F64:
+    if kind in (mr.GAUSSIAN_F64, mr.GAUSSIAN_ICDF_F64):
         e = gauss64_errors(got, want, 0.0 if p0 is None else p0, 1.0 if p1 is None else p1)
         bad = np.nonzero(e > 1.0)[0]
         assert bad.size == 0, (f"{bad.size} FP64 Gaussians outside tolerance; first at "
                                f"{bad[:5]}: got {got[bad[:5]]} want {want[bad[:5]]}")
         return float(e.max()) if e.size else 0.0
-    if kind == mr.GAUSSIAN_F32:
+    if kind in (mr.GAUSSIAN_F32, mr.GAUSSIAN_ICDF_F32):
         e = gauss_errors(got, want, 0.0 if p0 is None else p0, 1.0 if p1 is None else p1)
         bad = np.nonzero(e > 1.0)[0]
         assert bad.size == 0, (f"{bad.size} Gaussians outside tolerance; first at {bad[:5]}: "

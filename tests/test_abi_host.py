@@ -105,8 +105,12 @@ def test_words_consumed():
     assert mr.words_consumed(2, mr.BITS_U32, 5) == 5
     assert mr.words_consumed(1, mr.GAUSSIAN_F64, 5) == 12
     assert mr.words_consumed(2, mr.GAUSSIAN_F64, 5) == 6
+    assert mr.words_consumed(1, mr.UNIFORM_I32, 5) == 5
+    assert mr.words_consumed(1, mr.GAUSSIAN_ICDF_F32, 5) == 5
+    assert mr.words_consumed(1, mr.GAUSSIAN_ICDF_F64, 5) == 10
+    assert mr.words_consumed(2, mr.GAUSSIAN_ICDF_F64, 5) == 5
     import oracle
-    for kind in (1, 2, 3, 4, 5):
+    for kind in (1, 2, 3, 4, 5, 6, 7, 8):
         for engine in (1, 2):
             for n in (0, 1, 2, 7, 2**40 + 1):
                 assert mr.words_consumed(engine, kind, n) == oracle.words_consumed(kind, engine, n)
@@ -135,9 +139,22 @@ def test_generate_validation_without_device(L):
     assert _gen(L, e, mr.GAUSSIAN_F64, 8, fake + 4) == 1         # misaligned FP64
     assert _gen(L, e, mr.GAUSSIAN_F64, 8, fake, 0.0, 0.0) == 1
     assert _gen(L, e, mr.GAUSSIAN_F64, 8, fake, float("inf"), 1.0) == 1
-    assert _gen(L, e, 6, 8, fake) == 2
+    # uniform int32: integers with -2^31 <= a < b <= 2^31
+    i32 = mr.UNIFORM_I32
+    assert _gen(L, e, i32, 8, fake + 2, 0.0, 10.0) == 1            # misaligned int32
+    assert _gen(L, e, i32, 8, fake, 0.5, 10.0) == 1                # not an integer
+    assert _gen(L, e, i32, 8, fake, 0.0, 10.25) == 1
+    assert _gen(L, e, i32, 8, fake, 5.0, 5.0) == 1                 # a >= b
+    assert _gen(L, e, i32, 8, fake, -2.0**31 - 1, 0.0) == 1        # below int32
+    assert _gen(L, e, i32, 8, fake, 0.0, 2.0**31 + 1) == 1         # above int32 + 1
+    assert _gen(L, e, i32, 8, fake, float("nan"), 1.0) == 1
+    # inverse-CDF Gaussians: stddev > 0, finite
+    assert _gen(L, e, mr.GAUSSIAN_ICDF_F32, 8, fake, 0.0, 0.0) == 1
+    assert _gen(L, e, mr.GAUSSIAN_ICDF_F64, 8, fake, float("inf"), 1.0) == 1
+    assert _gen(L, e, mr.GAUSSIAN_ICDF_F64, 8, fake + 4) == 1     # misaligned FP64
     assert _gen(L, e, mr.UNIFORM_F32, 8, fake, reserved=1) == 1
     assert _gen(L, e, 9, 8, fake) == 2                            # unknown kind
+    assert _gen(L, e, 0, 8, fake) == 2
     d = mr.Distribution(mr.UNIFORM_F32, 0, 0.0, 1.0)
     assert L.mirng_generate(None, ctypes.byref(d), 8, fake, None) == 1
     assert L.mirng_generate(e.handle, None, 8, fake, None) == 1

@@ -13,7 +13,9 @@ from tests import gpu_helpers as gh
 
 pytestmark = pytest.mark.gpu
 
-KINDS = [mr.BITS_U32, mr.UNIFORM_F32, mr.UNIFORM_F64, mr.GAUSSIAN_F32, mr.GAUSSIAN_F64]
+KINDS = [mr.BITS_U32, mr.UNIFORM_F32, mr.UNIFORM_F64, mr.GAUSSIAN_F32, mr.GAUSSIAN_F64,
+         mr.UNIFORM_I32, mr.GAUSSIAN_ICDF_F32, mr.GAUSSIAN_ICDF_F64]
+GAUSSIANS = (mr.GAUSSIAN_F32, mr.GAUSSIAN_F64, mr.GAUSSIAN_ICDF_F32, mr.GAUSSIAN_ICDF_F64)
 FILL = 0xA5
 
 
@@ -36,8 +38,11 @@ def _mix(rng, count, max_log10=4.3, mrg_frac=0.3):
             int(rng.integers(0, 2**40, dtype=np.uint64))
         if kind in (mr.UNIFORM_F32, mr.UNIFORM_F64) and rng.random() < 0.3:
             p0, p1 = -2.0, 3.5
-        elif kind in (mr.GAUSSIAN_F32, mr.GAUSSIAN_F64) and rng.random() < 0.3:
+        elif kind in GAUSSIANS and rng.random() < 0.3:
             p0, p1 = 1.5, 0.25
+        elif kind == mr.UNIFORM_I32:
+            lo = int(rng.integers(-2**31, 2**31 - 1))
+            p0, p1 = float(lo), float(rng.integers(lo + 1, 2**31 + 1))
         else:
             p0, p1 = 0.0, 1.0
         engine = mr.MRG32K3A if rng.random() < mrg_frac else mr.PHILOX4X32_10

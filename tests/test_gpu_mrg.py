@@ -10,7 +10,8 @@ from tests import gpu_helpers as gh
 
 pytestmark = pytest.mark.gpu
 
-KINDS = [mr.BITS_U32, mr.UNIFORM_F32, mr.UNIFORM_F64, mr.GAUSSIAN_F32, mr.GAUSSIAN_F64]
+KINDS = [mr.BITS_U32, mr.UNIFORM_F32, mr.UNIFORM_F64, mr.GAUSSIAN_F32, mr.GAUSSIAN_F64,
+         mr.UNIFORM_I32, mr.GAUSSIAN_ICDF_F32, mr.GAUSSIAN_ICDF_F64]
 SIZES = [1, 3, 16, 31, 33, 1000, 8191, 8193, 65537, (1 << 20) + 3]
 
 
@@ -43,7 +44,9 @@ def test_continuity(kind):
 
 def test_range_parameters():
     for kind, p0, p1 in [(mr.UNIFORM_F32, -2.0, 7.0), (mr.UNIFORM_F64, 10.0, 10.5),
-                         (mr.GAUSSIAN_F32, 1.0, 2.0), (mr.GAUSSIAN_F64, -4.0, 0.25)]:
+                         (mr.GAUSSIAN_F32, 1.0, 2.0), (mr.GAUSSIAN_F64, -4.0, 0.25),
+                         (mr.UNIFORM_I32, -7.0, 1000.0), (mr.UNIFORM_I32, -2.0**31, 2.0**31),
+                         (mr.GAUSSIAN_ICDF_F32, 1.0, 2.0), (mr.GAUSSIAN_ICDF_F64, -4.0, 0.25)]:
         e = mr.Engine(mr.MRG32K3A, 5, 5)
         got, _ = gh.generate(e, kind, 40001, 0, p0, p1)
         st = oracle.mrg_skip(oracle.mrg_seed(5), 5)

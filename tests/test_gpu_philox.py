@@ -11,7 +11,8 @@ from tests import gpu_helpers as gh
 
 pytestmark = pytest.mark.gpu
 
-KINDS = [mr.BITS_U32, mr.UNIFORM_F32, mr.UNIFORM_F64, mr.GAUSSIAN_F32, mr.GAUSSIAN_F64]
+KINDS = [mr.BITS_U32, mr.UNIFORM_F32, mr.UNIFORM_F64, mr.GAUSSIAN_F32, mr.GAUSSIAN_F64,
+         mr.UNIFORM_I32, mr.GAUSSIAN_ICDF_F32, mr.GAUSSIAN_ICDF_F64]
 
 
 def test_small_case_seed42():
@@ -78,7 +79,11 @@ def test_continuity_across_calls(kind):
     (mr.UNIFORM_F32, -3.0, 5.0), (mr.UNIFORM_F32, 1e-3, 2e-3), (mr.UNIFORM_F32, 100.0, 101.5),
     (mr.UNIFORM_F64, -1.0, 0.0), (mr.UNIFORM_F64, 1e-3, 2e-3),
     (mr.GAUSSIAN_F32, 2.5, 0.5), (mr.GAUSSIAN_F32, -1.0, 3.0),
-    (mr.GAUSSIAN_F64, 2.5, 0.5), (mr.GAUSSIAN_F64, -1e3, 1e-3)])
+    (mr.GAUSSIAN_F64, 2.5, 0.5), (mr.GAUSSIAN_F64, -1e3, 1e-3),
+    (mr.UNIFORM_I32, -5.0, 7.0), (mr.UNIFORM_I32, -2.0**31, 2.0**31), (mr.UNIFORM_I32, 0.0, 1.0),
+    (mr.UNIFORM_I32, 1000.0, 2.0**31), (mr.UNIFORM_I32, -2.0**31, -2.0**31 + 3),
+    (mr.GAUSSIAN_ICDF_F32, 2.5, 0.5), (mr.GAUSSIAN_ICDF_F32, -1.0, 3.0),
+    (mr.GAUSSIAN_ICDF_F64, 2.5, 0.5), (mr.GAUSSIAN_ICDF_F64, -1e3, 1e-3)])
 def test_range_and_moments_parameters(kind, p0, p1):
     n = 100003
     for off in (0, 4 if mr.ELEM_BYTES[kind] == 4 else 8):
@@ -157,6 +162,18 @@ CONFIGS = [
 ]
 
 
+_ORACLE_CACHE = {}
+
+
+def _oracle_cached(seed, pos, kind, n):
+    """The oracle's outputs, computed once per (seed, pos, kind, n) across
+    the launch shapes (they do not depend on it)."""
+    key = (seed, pos, kind, n)
+    if key not in _ORACLE_CACHE:
+        _ORACLE_CACHE[key] = gh.oracle_philox(seed, pos, kind, n)
+    return _ORACLE_CACHE[key]
+
+
 @pytest.mark.parametrize("cfg", CONFIGS)
 def test_outputs_invariant_under_launch_shape(cfg):
     """Every launch shape gives the oracle's values, on both walks (the
@@ -171,7 +188,7 @@ def test_outputs_invariant_under_launch_shape(cfg):
                     e = mr.Engine(mr.PHILOX4X32_10, 99, 0)
                     e.skip_ahead(pos)
                     got, buf = gh.generate(e, kind, n, off)
-                    gh.assert_match(kind, got, gh.oracle_philox(99, pos, kind, n))
+                    gh.assert_match(kind, got, _oracle_cached(99, pos, kind, n))
                     assert gh.guards_intact(buf, off, n * mr.ELEM_BYTES[kind])
     finally:
         mr.set_philox_config(prev)
