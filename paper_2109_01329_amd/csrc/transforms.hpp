@@ -28,7 +28,7 @@ __device__ __forceinline__ double u01d(uint32_t lo, uint32_t hi)
     return __builtin_fma((double)hi, 0x1p-32, (double)(lo >> 11) * 0x1p-53);
 }
 
-// 1/d for d in [1.7, 2.5]: the hardware estimate refined by two Newton
+// 1/d for positive normal d: the hardware estimate refined by two Newton
 // steps (each squares the relative error; the result is within a few ulp).
 __device__ __forceinline__ double recip_fast(double d)
 {
@@ -53,6 +53,29 @@ __device__ __forceinline__ double sqrt_fast(double x)
     return x * y;
 }
 
+// ln x for positive normal x, to about 2^-34 relative error: x = 2^e m with
+// m in [sqrt(1/2), sqrt(2)), ln m = 2 atanh(s), s = (m - 1)/(m + 1),
+// |s| <= 0.1716, series to s^11, plus e ln 2.
+__device__ __forceinline__ double ln_fast(double x)
+{
+    int e;
+    double m = __builtin_frexp(x, &e);             // [0.5, 1)
+    const bool low = m < 0x1.6a09e667f3bcdp-1;     // sqrt(1/2)
+    m = low ? m * 2.0 : m;
+    e = low ? e - 1 : e;
+    const double f = m - 1.0;
+    const double s = f * recip_fast(m + 1.0);
+    const double s2 = s * s;
+    double q = 0x1.745d1745d1746p-4;               // 1/11
+    q = __builtin_fma(q, s2, 0x1.c71c71c71c71cp-4); // 1/9
+    q = __builtin_fma(q, s2, 0x1.2492492492492p-3); // 1/7
+    q = __builtin_fma(q, s2, 0x1.999999999999ap-3); // 1/5
+    q = __builtin_fma(q, s2, 0x1.5555555555555p-2); // 1/3
+    q = __builtin_fma(q, s2, 1.0);
+    const double ln_m = 2.0 * s * q;
+    return __builtin_fma((double)e, 0x1.62e42fefa39efp-1, ln_m);
+}
+
 // Box-Muller on one word pair.  The radius and the rotation are evaluated
 // in FP64 to about 2^-34 relative error and rounded once to FP32, so each
 // output is within 0.51 ulp of the exact transform of the same two inputs.
@@ -67,23 +90,7 @@ __device__ __forceinline__ double sqrt_fast(double x)
 __device__ __forceinline__ f32x2 box_muller(uint32_t wa, uint32_t wb)
 {
     const double u1 = (double)((wa >> 8) + 1u) * 0x1p-24;
-    int e;
-    double m = __builtin_frexp(u1, &e);            // [0.5, 1)
-    const bool low = m < 0x1.6a09e667f3bcdp-1;     // sqrt(1/2)
-    m = low ? m * 2.0 : m;
-    e = low ? e - 1 : e;
-    const double f = m - 1.0;
-    const double s = f * recip_fast(m + 1.0);
-    const double s2 = s * s;
-    double q = 0x1.745d1745d1746p-4;               // 1/11
-    q = __builtin_fma(q, s2, 0x1.c71c71c71c71cp-4); // 1/9
-    q = __builtin_fma(q, s2, 0x1.2492492492492p-3); // 1/7
-    q = __builtin_fma(q, s2, 0x1.999999999999ap-3); // 1/5
-    q = __builtin_fma(q, s2, 0x1.5555555555555p-2); // 1/3
-    q = __builtin_fma(q, s2, 1.0);
-    const double ln_m = 2.0 * s * q;
-    const double ln_u1 = __builtin_fma((double)e, 0x1.62e42fefa39efp-1, ln_m);
-    const double r = sqrt_fast(-2.0 * ln_u1);
+    const double r = sqrt_fast(-2.0 * ln_fast(u1));
 
     const uint32_t k = wb >> 8;
     const uint32_t j = (k + (1u << 21)) >> 22;     // 0..4
@@ -174,6 +181,30 @@ __device__ __forceinline__ double ppnd16_poly(int j, double x)
     return r;
 }
 
+// Phi^-1(u) by AS 241 (as normal_quantile below) for FP32 outputs: the
+// tail's logarithm, square root and both divisions use the refined
+// estimates above (ln_fast, sqrt_fast for -ln t <= 34, recip_fast), so z
+// carries about 1e-10 relative error before its one rounding to FP32.
+__device__ __forceinline__ double normal_quantile_f32(double u)
+{
+    const double q = u - 0.5;
+    if (__builtin_fabs(q) <= 0.425) {
+        const double r = __builtin_fma(-q, q, 0.180625);
+        return q * ppnd16_poly(0, r) * recip_fast(ppnd16_poly(1, r));
+    }
+    const double t = q < 0.0 ? u : 1.0 - u;
+    double r = sqrt_fast(-ln_fast(t));
+    double z;
+    if (r <= 5.0) {
+        r -= 1.6;
+        z = ppnd16_poly(2, r) * recip_fast(ppnd16_poly(3, r));
+    } else {
+        r -= 5.0;
+        z = ppnd16_poly(4, r) * recip_fast(ppnd16_poly(5, r));
+    }
+    return q < 0.0 ? -z : z;
+}
+
 // Standard normal quantile Phi^-1(u), u in (0, 1), in FP64 by AS 241,
 // whose rational approximations have relative error near 1e-16.  Central
 // region |u - 1/2| <= 0.425: z = q A(r) / B(r), q = u - 1/2 (exact),
@@ -202,12 +233,12 @@ __device__ __forceinline__ double normal_quantile(double u)
 }
 
 // Inverse-CDF Gaussian from one word: u = ((w >> 8) + 1/2) 2^-24 (exact in
-// FP64, strictly inside (0, 1)), z = Phi^-1(u) in FP64, rounded once to
-// FP32.
+// FP64, strictly inside (0, 1); -ln t <= 25 ln 2), z = Phi^-1(u) in FP64,
+// rounded once to FP32.
 __device__ __forceinline__ float icdf_f32(uint32_t w)
 {
     const double u = ((double)(w >> 8) + 0.5) * 0x1p-24;
-    return (float)normal_quantile(u);
+    return (float)normal_quantile_f32(u);
 }
 
 // Four inverse-CDF Gaussians, one quantile at a time (a rolled loop that
