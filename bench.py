@@ -71,7 +71,9 @@ def parse():
     p.add_argument("--profile-batch", action="store_true",
                    help="for rocprofv3: the calorimeter batch (default launch shape), 25 "
                         "batches in a row")
-    p.add_argument("--profile-scenario", default=None, choices=("single_electron", "ttbar"),
+    p.add_argument("--profile-scenario", default=None,
+                   choices=("single_electron", "ttbar", "single_electron_min200k",
+                            "single_electron_soa"),
                    help="for rocprofv3: one FastCaloSim-shaped scenario (default launch "
                         "shape), 25 batches in a row, then 5 plain launches of the same total")
     return p.parse_args()
@@ -242,22 +244,21 @@ def calo_batch_leg(mr, synth, torch, stream, dev, reps=20, tune=True, windows=5,
 
 
 def scenario_requests(mr, sc, torch, dev):
-    """One Philox uniform FP32 request per event of scenario `sc`: three
-    uniforms per hit on key (seed32, event id), outputs contiguous per event
-    in one device buffer.  Returns (requests, buffer, total samples)."""
+    """The Philox uniform FP32 requests of scenario `sc` (its own request
+    description: per event, or per event and quantity), with outputs in one
+    device buffer.  Returns (requests, buffer, total samples)."""
     import numpy as np
-    sizes = sc.uniforms.astype(np.uint64)
+    seeds, offsets, sizes, first = sc.requests()
     total = int(sizes.sum())
     out = torch.empty(total, dtype=torch.float32, device=dev)
-    offs = np.concatenate([[0], np.cumsum(sizes * 4)])[:-1].astype(np.uint64)
-    reqs = mr.make_requests(sc.n_events)
+    reqs = mr.make_requests(sizes.size)
     reqs["engine_type"] = mr.PHILOX4X32_10
     reqs["kind"] = mr.UNIFORM_F32
     reqs["p1"] = 1.0
-    reqs["seed"] = (np.arange(sc.n_events, dtype=np.uint64) << np.uint64(32)) | \
-        np.uint64(sc.seed32)
+    reqs["seed"] = seeds
+    reqs["offset"] = offsets
     reqs["n"] = sizes
-    reqs["out"] = np.uint64(out.data_ptr()) + offs
+    reqs["out"] = np.uint64(out.data_ptr()) + first * np.uint64(4)
     return reqs, out, total
 
 
@@ -266,22 +267,26 @@ def scenario_leg(mr, synth, torch, stream, dev):
     single-electron events (10^4 events of 4000-6500 hits) and ttbar events
     (500 events of 600-800 times as many hits), three uniform FP32 per hit,
     one Philox request per event on key (42, event id), outputs contiguous
-    per event.  Each scenario is one batch (launch shape autotuned on it
+    per event; and two single-electron variants: at least 200,000 uniforms
+    per event, and one request per event and quantity into three arrays
+    (SoA).  Each scenario is one batch (launch shape autotuned on it
     first), timed in steady state, against the plain path generating the
     same total in one launch."""
     import numpy as np
     res = {}
-    for name, reps in (("single_electron", 20), ("ttbar", 5)):
+    for name, reps in (("single_electron", 20), ("ttbar", 5), ("single_electron_min200k", 10),
+                       ("single_electron_soa", 20)):
         sc = synth.calo_scenario(name)
         reqs, out, total = scenario_requests(mr, sc, torch, dev)
         b = mr.Batcher()
         cfg, _ = b.autotune(reqs, stream=stream, prewarm_ms=200, rounds=3, reps=5)
         batch_ms = time_region(lambda: b.generate(reqs, stream=stream), reps, stream)
-        assert np.all(b.statuses(sc.n_events) == 0)
+        assert np.all(b.statuses(reqs.size) == 0)
         e = mr.Engine(mr.PHILOX4X32_10, 42, 0)
         plain_ms = time_region(lambda: e.generate(mr.UNIFORM_F32, total, out, stream=stream),
                                reps, stream)
-        res[name] = {"events": sc.n_events, "samples": total, "bytes": total * 4,
+        res[name] = {"events": sc.n_events, "requests": int(reqs.size), "samples": total,
+                     "bytes": total * 4,
                      "batch_config": cfg.as_dict(),
                      "batch_ms": round(batch_ms, 4),
                      "batch_GBs": round(total * 4 / (batch_ms * 1e-3) / 1e9, 1),
@@ -531,8 +536,8 @@ def main():
         for _ in range(5):
             e.generate(mr.UNIFORM_F32, total, out, stream=stream)
         stream.synchronize()
-        assert np.all(b.statuses(sc.n_events) == 0)
-        print(json.dumps({"profile": f"{sc.name} batch ({sc.n_events} requests, {total} "
+        assert np.all(b.statuses(reqs.size) == 0)
+        print(json.dumps({"profile": f"{sc.name} batch ({reqs.size} requests, {total} "
                                      "samples) x25, then plain x5",
                           "config": b.config.as_dict()}), flush=True)
         return

@@ -8,7 +8,8 @@
 // past 64 chunks) and the copy of the per-request statuses back to pinned
 // memory; these overlap the generation of earlier batches.  The caller's
 // stream waits for them and runs the generation kernels (Philox, MRG32k3a)
-// that have work.
+// that have work; with both, the MRG kernel runs on a side stream beside
+// the Philox kernel and the caller's stream joins it.
 #include <algorithm>
 #include <cstring>
 #include <mutex>
@@ -32,6 +33,7 @@ struct Slot {
     bool pending = false;              // `done` recorded and maybe not reached
     hipEvent_t done = nullptr;
     hipEvent_t planned = nullptr;      // upload, planning and status copy done
+    hipEvent_t mrg_done = nullptr;     // MRG generation done (its own stream)
     mirng_request *d_reqs = nullptr;
     mirng::BatchDesc *d_desc = nullptr;
     uint64_t *d_local_end = nullptr;
@@ -62,6 +64,7 @@ void release(Slot &s)
     if (s.d_status) (void)hipFree(s.d_status);
     if (s.done) (void)hipEventDestroy(s.done);
     if (s.planned) (void)hipEventDestroy(s.planned);
+    if (s.mrg_done) (void)hipEventDestroy(s.mrg_done);
     s = Slot{};
 }
 
@@ -91,6 +94,7 @@ hipError_t prepare(Slot &s, size_t count, int dev)
     chk(hipMalloc((void **)&s.d_status, cap * sizeof(int32_t)));
     chk(hipEventCreateWithFlags(&s.done, hipEventDisableTiming));
     chk(hipEventCreateWithFlags(&s.planned, hipEventDisableTiming));
+    chk(hipEventCreateWithFlags(&s.mrg_done, hipEventDisableTiming));
     if (err != hipSuccess) {
         release(s);
         return err;
@@ -108,6 +112,7 @@ struct Work {
     uint64_t tiles = 0, chunks = 0;
     int32_t philox = 0, mrg = 0;
     int32_t wide = 0;   // a Philox request only the wide kernel holds
+    int32_t mrg_wide = 0;   // an MRG request only the wide MRG kernel holds
 };
 
 // Philox kinds whose transforms need many registers (FP64 Box-Muller, the
@@ -127,6 +132,8 @@ Work scan_requests(const mirng_request *q, size_t count)
         w.philox |= ph;
         w.mrg |= mg;
         w.wide |= ph && wide_kind(q[i].dist.kind);
+        w.mrg_wide |= mg && (q[i].dist.kind == MIRNG_GAUSSIAN_ICDF_F32 ||
+                             q[i].dist.kind == MIRNG_GAUSSIAN_ICDF_F64);
         const uint64_t n = q[i].n;
         if (n == 0 || n >= (1ull << 32)) continue;
         const bool f64 = q[i].dist.kind == MIRNG_UNIFORM_F64 ||
@@ -157,6 +164,7 @@ struct mirng_batcher_s {
     std::mutex mu;
     Slot slots[kSlots];
     hipStream_t copy = nullptr;        // uploads and planning (default priority)
+    hipStream_t side = nullptr;        // MRG generation beside Philox (default priority)
     int copy_dev = -1;
     int next = 0;
     int last = -1;     // slot of the most recent batch
@@ -204,6 +212,7 @@ mirng_status mirng_batcher_destroy(mirng_batcher b)
         std::lock_guard<std::mutex> lk(b->mu);
         for (Slot &s : b->slots) release(s);
         if (b->copy) (void)hipStreamDestroy(b->copy);
+        if (b->side) (void)hipStreamDestroy(b->side);
     }
     delete b;
     return MIRNG_OK;
@@ -257,8 +266,12 @@ mirng_status mirng_generate_batch(mirng_batcher b, const mirng_request *reqs, si
     std::lock_guard<std::mutex> lk(b->mu);
     if (b->copy_dev != dev) {
         if (b->copy) (void)hipStreamDestroy(b->copy);
+        if (b->side) (void)hipStreamDestroy(b->side);
         b->copy = nullptr;
-        if (hipStreamCreateWithFlags(&b->copy, hipStreamNonBlocking) != hipSuccess)
+        b->side = nullptr;
+        b->copy_dev = -1;
+        if (hipStreamCreateWithFlags(&b->copy, hipStreamNonBlocking) != hipSuccess ||
+            hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking) != hipSuccess)
             return MIRNG_E_DEVICE;
         b->copy_dev = dev;
     }
@@ -314,6 +327,7 @@ mirng_status mirng_generate_batch(mirng_batcher b, const mirng_request *reqs, si
     a.wide = w.wide;
     a.philox = w.philox;
     a.mrg = w.mrg;
+    a.mrg_wide = w.mrg_wide;
     a.block = (uint32_t)b->cfg.block;
     a.groups = (uint32_t)(waves / wpb);
     // upload, planning and the status copy run on the batcher's own stream,
@@ -327,7 +341,21 @@ mirng_status mirng_generate_batch(mirng_batcher b, const mirng_request *reqs, si
                              hipMemcpyDeviceToHost, b->copy);
     if (err == hipSuccess) err = hipEventRecord(sl.planned, b->copy);
     if (err == hipSuccess) err = hipStreamWaitEvent(s, sl.planned, 0);
-    if (err == hipSuccess) err = launch_batch_generate(a, s);
+    if (a.philox && a.mrg) {
+        // both engines: the MRG kernel (VALU-bound) runs on the side stream
+        // beside the Philox kernel (bound by HBM writes), and the caller's
+        // stream joins it before the batch counts as done
+        BatchArgs ph = a, mg = a;
+        ph.mrg = 0;
+        mg.philox = 0;
+        if (err == hipSuccess) err = hipStreamWaitEvent(b->side, sl.planned, 0);
+        if (err == hipSuccess) err = launch_batch_generate(mg, b->side);
+        if (err == hipSuccess) err = hipEventRecord(sl.mrg_done, b->side);
+        if (err == hipSuccess) err = launch_batch_generate(ph, s);
+        if (err == hipSuccess) err = hipStreamWaitEvent(s, sl.mrg_done, 0);
+    } else if (err == hipSuccess) {
+        err = launch_batch_generate(a, s);
+    }
     if (err == hipSuccess) err = hipEventRecord(sl.done, s);
     if (err != hipSuccess) return MIRNG_E_LAUNCH;
     sl.pending = true;

@@ -374,8 +374,12 @@ __device__ __forceinline__ BatchDesc load_desc(const BatchDesc *p)
     return d;
 }
 
+// Groups of the wide kernel hold at most 256 threads, which lets it use up
+// to 512 registers per lane instead of spilling past 128.
+constexpr uint32_t kWideBlock = 256;
+
 template <bool WIDE>
-__global__ __launch_bounds__(1024) void batch_main_kernel(BatchArgs a)
+__global__ __launch_bounds__(WIDE ? kWideBlock : 1024) void batch_main_kernel(BatchArgs a)
 {
     const uint32_t lane = threadIdx.x & 63u;
     const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
@@ -445,6 +449,9 @@ __device__ void mrg_chunk(const BatchDesc &d, uint64_t k, const uint32_t *c_tab,
     }
 }
 
+// WIDE: the batch holds MRG inverse-CDF requests, whose transforms need
+// about twice the registers of the others (halving the resident groups).
+template <bool WIDE>
 __global__ __launch_bounds__(kMrgThreads) void batch_mrg_kernel(BatchArgs a)
 {
     // LDS rows are 144 bytes for every kind (32 x 4 or 16 x 8, plus 16)
@@ -477,8 +484,14 @@ __global__ __launch_bounds__(kMrgThreads) void batch_mrg_kernel(BatchArgs a)
                 case kGauss: mrg_chunk<kGauss>(d, k, a.c_tab4, a.u_tab4, lds, wg_state); break;
                 case kGauss64: mrg_chunk<kGauss64>(d, k, a.c_tab8, a.u_tab8, lds, wg_state); break;
                 case kI32: mrg_chunk<kI32>(d, k, a.c_tab4, a.u_tab4, lds, wg_state); break;
-                case kIcdf: mrg_chunk<kIcdf>(d, k, a.c_tab4, a.u_tab4, lds, wg_state); break;
-                default: mrg_chunk<kIcdf64>(d, k, a.c_tab8, a.u_tab8, lds, wg_state); break;
+                default:
+                    if constexpr (WIDE) {
+                        if (d.kind == kIcdf)
+                            mrg_chunk<kIcdf>(d, k, a.c_tab4, a.u_tab4, lds, wg_state);
+                        else
+                            mrg_chunk<kIcdf64>(d, k, a.c_tab8, a.u_tab8, lds, wg_state);
+                    }
+                    break;
                 }
             }
             c = seg;
@@ -502,15 +515,24 @@ hipError_t launch_batch_generate(const BatchArgs &a, hipStream_t s)
 {
     hipError_t err = hipSuccess;
     if (a.philox) {
-        if (a.wide)
-            hipLaunchKernelGGL(batch_main_kernel<true>, dim3(a.groups), dim3(a.block), 0, s, a);
-        else
+        if (a.wide) {
+            // same waves in groups of at most kWideBlock threads; waves past
+            // a.waves find no tiles and return
+            const uint32_t blk = a.block < kWideBlock ? a.block : kWideBlock;
+            const uint32_t wpb = blk / 64u;
+            const uint32_t groups = (a.waves + wpb - 1u) / wpb;
+            hipLaunchKernelGGL(batch_main_kernel<true>, dim3(groups), dim3(blk), 0, s, a);
+        } else
             hipLaunchKernelGGL(batch_main_kernel<false>, dim3(a.groups), dim3(a.block), 0, s, a);
         err = hipGetLastError();
         if (err != hipSuccess) return err;
     }
     if (a.mrg) {
-        hipLaunchKernelGGL(batch_mrg_kernel, dim3(a.mgroups), dim3(kMrgThreads), 0, s, a);
+        if (a.mrg_wide)
+            hipLaunchKernelGGL(batch_mrg_kernel<true>, dim3(a.mgroups), dim3(kMrgThreads), 0, s, a);
+        else
+            hipLaunchKernelGGL(batch_mrg_kernel<false>, dim3(a.mgroups), dim3(kMrgThreads), 0, s,
+                               a);
         err = hipGetLastError();
     }
     return err;

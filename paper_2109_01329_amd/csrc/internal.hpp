@@ -232,6 +232,7 @@ struct BatchArgs {
     int32_t wide;           // some Philox request is Gaussian FP64 (host scan)
     int32_t philox;         // some request names Philox4x32-10 (host scan)
     int32_t mrg;            // some request names MRG32k3a (host scan)
+    int32_t mrg_wide;       // some MRG32k3a request is an inverse-CDF Gaussian
     const uint32_t *pow2;   // MRG A^(2^k), k < 64: [k][comp][9]
     const uint32_t *c_tab4, *u_tab4;   // MRG chunk / thread jumps, 4-byte kinds
     const uint32_t *c_tab8, *u_tab8;   // MRG chunk / thread jumps, FP64

@@ -115,6 +115,9 @@ class CaloScenario:
     name: str
     hits: np.ndarray          # hits per event
     seed32: int = 42
+    min_per_event: int = 0    # least uniforms an event draws (the paper's 200,000 variant)
+    layout: str = "aos"       # "aos": one request per event, a hit's 3 uniforms adjacent;
+                              # "soa": one request per event and quantity, 3 arrays
 
     @property
     def n_events(self) -> int:
@@ -122,16 +125,41 @@ class CaloScenario:
 
     @property
     def uniforms(self) -> np.ndarray:
-        """Three uniforms per hit, per event."""
-        return 3 * self.hits
+        """Uniforms per event: three per hit, at least min_per_event."""
+        return np.maximum(3 * self.hits, self.min_per_event)
+
+    def requests(self):
+        """One Philox uniform FP32 request per row, on the event's key
+        (event << 32) | seed32: (seed, offset in words, n, first output
+        element).  AoS: one request per event at offset 0, outputs
+        contiguous per event.  SoA: quantity q of event e is h_e outputs at
+        offset q h_e, stored in array q (elements [q H, (q + 1) H), H the
+        total hits) at that event's place among the events."""
+        e = np.arange(self.n_events, dtype=np.uint64)
+        seeds = (e << np.uint64(32)) | np.uint64(self.seed32)
+        if self.layout == "aos":
+            n = self.uniforms.astype(np.uint64)
+            first = np.concatenate([[0], np.cumsum(n)])[:-1].astype(np.uint64)
+            return seeds, np.zeros_like(n), n, first
+        h = self.hits.astype(np.uint64)
+        total = np.uint64(h.sum())
+        place = np.concatenate([[0], np.cumsum(h)])[:-1].astype(np.uint64)
+        rows = [(seeds, np.uint64(q) * h, h, np.uint64(q) * total + place) for q in range(3)]
+        return tuple(np.stack([r[i] for r in rows], axis=1).reshape(-1) for i in range(4))
+
+
+SCENARIOS = ("single_electron", "ttbar", "single_electron_min200k", "single_electron_soa")
 
 
 def calo_scenario(name: str, n_events: int | None = None, k: int = 7) -> CaloScenario:
     """Single-electron events: 4000-6500 hits each (10^4 events, as in the
     paper's results); ttbar events: 600-800 times as many hits (500
-    events).  Hit counts uniform over those ranges."""
+    events).  Hit counts uniform over those ranges.  Variants of the
+    single-electron shape: every event draws at least 200,000 uniforms
+    (the paper's stated minimum), or the three quantities of a hit go to
+    three separate arrays (SoA)."""
     g = rng(k)
-    if name == "single_electron":
+    if name.startswith("single_electron"):
         n = 10000 if n_events is None else n_events
         hits = g.integers(4000, 6501, n)
     elif name == "ttbar":
@@ -139,7 +167,14 @@ def calo_scenario(name: str, n_events: int | None = None, k: int = 7) -> CaloSce
         hits = (g.integers(4000, 6501, n) * g.uniform(600.0, 800.0, n)).astype(np.int64)
     else:
         raise ValueError(name)
-    return CaloScenario(name, hits.astype(np.int64))
+    sc = CaloScenario(name, hits.astype(np.int64))
+    if name == "single_electron_min200k":
+        sc.min_per_event = 200000
+    elif name == "single_electron_soa":
+        sc.layout = "soa"
+    elif name != "single_electron" and name != "ttbar":
+        raise ValueError(name)
+    return sc
 
 
 # --- served request trace ------------------------------------------------

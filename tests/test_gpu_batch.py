@@ -291,37 +291,47 @@ def test_batch_large_requests_among_small():
     _check_outputs(host, lay, st)
 
 
-@pytest.mark.parametrize("name,events", [("single_electron", 400), ("ttbar", 3)])
+@pytest.mark.parametrize("name,events", [("single_electron", 400), ("ttbar", 3),
+                                         ("single_electron_min200k", 40),
+                                         ("single_electron_soa", 300)])
 def test_batch_fastcalosim_scenarios(name, events):
     """The paper's FastCaloSim scenarios as one batch each: three uniform
-    FP32 per hit on key (42, event id).  Single-electron events are checked
-    whole; ttbar events (tens of millions of samples each) at their head,
-    middle and tail."""
+    FP32 per hit on key (42, event id); the variants draw at least 200,000
+    per event, or one request per quantity into three arrays.  Requests of
+    up to 200,000 outputs are checked whole; ttbar events (tens of millions
+    of samples each) at their head, middle and tail."""
     import torch
     sc = synth.calo_scenario(name, n_events=events)
-    sizes = sc.uniforms.astype(np.uint64)
+    seeds, offsets, sizes, first = sc.requests()
     total = int(sizes.sum())
     out = torch.empty(total, dtype=torch.float32, device="cuda")
-    offs = np.concatenate([[0], np.cumsum(sizes)])[:-1].astype(np.int64)
-    reqs = mr.make_requests(events)
-    seeds = (np.arange(events, dtype=np.uint64) << np.uint64(32)) | np.uint64(sc.seed32)
+    reqs = mr.make_requests(sizes.size)
     reqs["engine_type"] = mr.PHILOX4X32_10
     reqs["kind"] = mr.UNIFORM_F32
     reqs["p1"] = 1.0
     reqs["seed"] = seeds
+    reqs["offset"] = offsets
     reqs["n"] = sizes
-    reqs["out"] = np.uint64(out.data_ptr()) + offs.astype(np.uint64) * np.uint64(4)
+    reqs["out"] = np.uint64(out.data_ptr()) + first * np.uint64(4)
     b = mr.Batcher()
     b.generate(reqs)
     torch.cuda.synchronize()
-    assert np.all(b.statuses(events) == 0)
-    for e in range(events):
-        n, o = int(sizes[e]), int(offs[e])
-        if name == "single_electron":
-            wins = [(0, n)]
-        else:
-            wins = [(0, 4096), (n // 2 - 2048, 4096), (n - 4096, 4096)]
+    assert np.all(b.statuses(sizes.size) == 0)
+    host = out.cpu().numpy()
+    covered = 0
+    for r in range(sizes.size):
+        n, o, f = int(sizes[r]), int(offsets[r]), int(first[r])
+        wins = [(0, n)] if n <= 200000 else [(0, 4096), (n // 2 - 2048, 4096), (n - 4096, 4096)]
         for s, m in wins:
-            got = out[o + s: o + s + m].cpu().numpy()
-            gh.assert_match(mr.UNIFORM_F32, got,
-                            gh.oracle_philox(int(seeds[e]), s, mr.UNIFORM_F32, m))
+            gh.assert_match(mr.UNIFORM_F32, host[f + s: f + s + m],
+                            gh.oracle_philox(int(seeds[r]), o + s, mr.UNIFORM_F32, m))
+        covered += n
+    assert covered == total
+    if sc.layout == "soa":
+        # quantity q of event e is the event's stream from word q h_e on
+        e, h = 1, int(sc.hits[1])
+        place = int(sc.hits[:1].sum())
+        allw = gh.oracle_philox(int(seeds[3]), 0, mr.UNIFORM_F32, 3 * h)
+        for q in range(3):
+            start = q * int(sc.hits.sum()) + place
+            gh.assert_match(mr.UNIFORM_F32, host[start: start + h], allw[q * h:(q + 1) * h])
