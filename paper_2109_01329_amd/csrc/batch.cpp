@@ -41,6 +41,8 @@ struct Slot {
     uint64_t *d_chunk_end = nullptr;
     uint64_t *d_total = nullptr;
     int32_t *d_status = nullptr;
+    uint32_t *d_wave_start = nullptr;  // [wave_cap]
+    size_t wave_cap = 0;
 };
 
 // Resident workgroups of the MRG generation kernel: its 36 KiB of LDS per
@@ -62,10 +64,24 @@ void release(Slot &s)
     if (s.d_chunk_end) (void)hipFree(s.d_chunk_end);
     if (s.d_total) (void)hipFree(s.d_total);
     if (s.d_status) (void)hipFree(s.d_status);
+    if (s.d_wave_start) (void)hipFree(s.d_wave_start);
     if (s.done) (void)hipEventDestroy(s.done);
     if (s.planned) (void)hipEventDestroy(s.planned);
     if (s.mrg_done) (void)hipEventDestroy(s.mrg_done);
     s = Slot{};
+}
+
+// Room for the start table of `waves` Philox waves in a slot that the
+// device no longer uses (after prepare).
+hipError_t ensure_waves(Slot &s, size_t waves)
+{
+    if (s.wave_cap >= waves) return hipSuccess;
+    if (s.d_wave_start) (void)hipFree(s.d_wave_start);
+    s.d_wave_start = nullptr;
+    s.wave_cap = 0;
+    hipError_t err = hipMalloc((void **)&s.d_wave_start, waves * sizeof(uint32_t));
+    if (err == hipSuccess) s.wave_cap = waves;
+    return err;
 }
 
 // Waits until the device no longer uses the slot, then makes room for
@@ -174,6 +190,14 @@ struct mirng_batcher_s {
 
 namespace mirng {
 
+// Waves of the Philox generation grid for launch shape c (whole groups).
+size_t grid_waves(const mirng_batch_config &c)
+{
+    const size_t wpb = (size_t)c.block / 64;
+    const size_t w = (size_t)device_cu_count() * (size_t)c.waves_per_cu;
+    return (w + wpb - 1) / wpb * wpb;
+}
+
 hipError_t batcher_reserve(mirng_batcher b, size_t count)
 {
     int dev = 0;
@@ -185,6 +209,7 @@ hipError_t batcher_reserve(mirng_batcher b, size_t count)
     std::lock_guard<std::mutex> lk(b->mu);
     for (Slot &s : b->slots) {
         err = prepare(s, count, dev);
+        if (err == hipSuccess) err = ensure_waves(s, grid_waves(b->cfg));
         if (err != hipSuccess) return err;
     }
     return hipSuccess;
@@ -234,10 +259,6 @@ mirng_status mirng_batcher_config_set(mirng_batcher b, const mirng_batch_config 
     return MIRNG_OK;
 }
 
-static size_t grid_waves(const mirng_batch_config &c)
-{
-    return (size_t)device_cu_count() * (size_t)c.waves_per_cu;
-}
 
 mirng_status mirng_batcher_stage(mirng_batcher b, size_t count, mirng_request **reqs)
 {
@@ -278,7 +299,7 @@ mirng_status mirng_generate_batch(mirng_batcher b, const mirng_request *reqs, si
     MrgBatchTables tabs;
     if (mrg_batch_tables(dev, tabs) != hipSuccess) return MIRNG_E_ALLOC;
     const uint64_t wpb = (uint64_t)b->cfg.block / 64;
-    uint64_t waves = ((grid_waves(b->cfg) + wpb - 1) / wpb) * wpb;
+    uint64_t waves = grid_waves(b->cfg);
     const Work w = scan_requests(reqs, count);
     // Philox: no more waves than about two tiles of work each
     const uint64_t want = ((w.tiles + 1) / 2 + wpb - 1) / wpb * wpb;
@@ -306,6 +327,7 @@ mirng_status mirng_generate_batch(mirng_batcher b, const mirng_request *reqs, si
     b->staged = -1;
     Slot &sl = b->slots[k];
     sl.count = count;
+    if (ensure_waves(sl, waves) != hipSuccess) return MIRNG_E_ALLOC;
     BatchArgs a{};
     a.reqs = sl.d_reqs;
     a.count = (uint32_t)count;
@@ -316,6 +338,7 @@ mirng_status mirng_generate_batch(mirng_batcher b, const mirng_request *reqs, si
     a.chunk_end = sl.d_chunk_end;
     a.total = sl.d_total;
     a.waves = (uint32_t)waves;
+    a.wave_start = sl.d_wave_start;
     a.mgroups = (uint32_t)mgroups;
     a.pow2 = tabs.pow2;
     a.c_tab4 = tabs.c_tab4;

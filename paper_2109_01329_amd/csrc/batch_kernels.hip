@@ -11,11 +11,13 @@
 // scan:  one workgroup scans the per-chunk totals (only for batches of more
 //        than 64 chunks; smaller ones are scanned by every generating wave in
 //        registers).
+// start: one thread per Philox wave finds the request holding the wave's
+//        first tile (a table read by the generating waves).
 // philox main: a fixed grid of waves; wave w takes a contiguous range of
 //        tiles (tiles of one request are adjacent, requests in table order),
-//        finds the request holding its first tile by a 64-ary search over the
-//        two-level prefix (chunks, then requests) and walks forward, running
-//        the plain kernel's slot walk on each request segment.
+//        reads the request holding its first tile from the start table and
+//        walks forward, running the plain kernel's slot walk on each request
+//        segment.
 // mrg main: a fixed grid of 256-thread groups, each over a contiguous range
 //        of chunks found the same way, running the plain kernel's LDS passes
 //        on each chunk.
@@ -326,6 +328,67 @@ __device__ __forceinline__ uint32_t find_in_chunk(const BatchArgs &a, int j, uin
                             [&](uint32_t i) { return base + a.local_end[2 * i + j]; }));
 }
 
+// Wave start table, filled during planning: for wave w of the Philox
+// grid, the request holding its first tile w * ceil(T / W) (count when the
+// wave has no tiles).  One thread per wave, each with its own
+// lower-bound searches (over the chunk prefix, then over the chunk's
+// requests); generating waves then start with one load instead of a search.
+__global__ __launch_bounds__(256) void batch_start_kernel(BatchArgs a)
+{
+    const uint32_t w = blockIdx.x * 256u + threadIdx.x;
+    const ChunkPrefix p = chunk_prefix(a, 0);   // whole waves
+    const uint64_t per = (p.total + a.waves - 1) / a.waves;
+    const uint64_t T = (uint64_t)w * per;
+    // first chunk whose prefix end exceeds T
+    uint32_t c = 0;
+    uint64_t base = 0;
+    if (p.regs) {
+        // the chunk ends sit in lane c: a fixed-length search so that every
+        // lane takes part in each cross-lane read
+        uint32_t n = a.nchunks;
+        for (int it = 0; it < 7; ++it) {
+            const uint32_t half = n / 2u;
+            const uint32_t mid = c + half;
+            const uint64_t v = __shfl(p.inc, (int)min(mid, 63u));
+            if (n > 0u && v <= T) {
+                c = mid + 1u;
+                n -= half + 1u;
+            } else {
+                n = half;
+            }
+        }
+        base = __shfl(p.excl, (int)min(c, 63u));
+    } else {
+        uint32_t n = a.nchunks;
+        while (n > 0u) {
+            const uint32_t half = n / 2u;
+            if (a.chunk_end[2 * (c + half)] <= T) {
+                c += half + 1u;
+                n -= half + 1u;
+            } else {
+                n = half;
+            }
+        }
+        if (c < a.nchunks) base = a.chunk_end[2 * c] - a.chunk_total[2 * c];
+    }
+    if (w >= a.waves) return;
+    uint32_t r = a.count;
+    if (T < p.total) {
+        r = c * kChunk;
+        uint32_t n = min(a.count - r, kChunk);
+        while (n > 0u) {
+            const uint32_t half = n / 2u;
+            if (base + a.local_end[2 * (r + half)] <= T) {
+                r += half + 1u;
+                n -= half + 1u;
+            } else {
+                n = half;
+            }
+        }
+    }
+    a.wave_start[w] = r;
+}
+
 template <int KIND>
 __device__ __forceinline__ void run_kind(const BatchDesc &d, uint32_t u0, uint32_t span,
                                          uint32_t lane)
@@ -383,14 +446,16 @@ __global__ __launch_bounds__(WIDE ? kWideBlock : 1024) void batch_main_kernel(Ba
 {
     const uint32_t lane = threadIdx.x & 63u;
     const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    // the chunk prefix and this wave's first request (from the start
+    // table) in one round of loads
     const ChunkPrefix p = chunk_prefix(a, 0);
+    uint32_t r = wave < a.waves ? uniform(a.wave_start[wave]) : a.count;
     const uint64_t per = (p.total + a.waves - 1) / a.waves;
     uint64_t t = wave * per;
     const uint64_t t1 = min(t + per, p.total);
-    if (t >= t1) return;
-    uint32_t c = find_chunk(a, 0, p, t);
+    if (t >= t1 || r >= a.count) return;
+    uint32_t c = r / kChunk;
     uint64_t base = chunk_base(a, 0, p, c);
-    uint32_t r = find_in_chunk(a, 0, c, base, t);
     while (t < t1 && r < a.count) {
         if (r / kChunk != c) {
             c = r / kChunk;
@@ -506,9 +571,17 @@ hipError_t launch_batch_plan(const BatchArgs &a, hipStream_t s)
 {
     hipLaunchKernelGGL(batch_plan_kernel, dim3(a.nchunks), dim3(kChunk), 0, s, a);
     hipError_t err = hipGetLastError();
-    if (err != hipSuccess || a.nchunks <= kWaveChunks) return err;
-    hipLaunchKernelGGL(batch_scan_kernel, dim3(1), dim3(kChunk), 0, s, a);
-    return hipGetLastError();
+    if (err != hipSuccess) return err;
+    if (a.nchunks > kWaveChunks) {
+        hipLaunchKernelGGL(batch_scan_kernel, dim3(1), dim3(kChunk), 0, s, a);
+        err = hipGetLastError();
+        if (err != hipSuccess) return err;
+    }
+    if (a.philox) {
+        hipLaunchKernelGGL(batch_start_kernel, dim3((a.waves + 255u) / 256u), dim3(256), 0, s, a);
+        err = hipGetLastError();
+    }
+    return err;
 }
 
 hipError_t launch_batch_generate(const BatchArgs &a, hipStream_t s)

@@ -224,6 +224,7 @@ struct BatchArgs {
     uint64_t *chunk_end;    // [2 nchunks] inclusive prefixes over chunks
     uint64_t *total;        // [2] Philox tiles, MRG chunks of the batch
     uint32_t waves;         // waves of the Philox generation grid
+    uint32_t *wave_start;   // [waves] first request of each Philox wave
     uint32_t mgroups;       // workgroups of the MRG generation grid
     int32_t *status;        // per request
     int32_t nt;             // streaming stores
