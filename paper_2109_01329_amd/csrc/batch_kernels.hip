@@ -117,8 +117,10 @@ __device__ void plan_one(const mirng_request &q, BatchDesc &d, int32_t &st, int 
         r.full_lo = (uint32_t)lo;
         r.full_count = (uint32_t)(hi > lo ? hi - lo : 0);
         r.out_base = (char *)q.out - (addr & 15u);
+        // slot 0's place in its 1 KiB block: the tiles follow that grid
+        d.slot0 = (uint32_t)(((uint64_t)(uintptr_t)r.out_base >> 4) & 63u);
     }
-    tiles = ((uint64_t)d.nunits + 63) / 64;
+    tiles = ((uint64_t)d.slot0 + d.nunits + 63) / 64;
 }
 
 // Inclusive scan over a workgroup of kChunk threads (16 waves).
@@ -389,15 +391,16 @@ __global__ __launch_bounds__(256) void batch_start_kernel(BatchArgs a)
     a.wave_start[w] = r;
 }
 
+// Slots [lo, hi) of request d in steps of 64 from s0 (see walk_slots_from).
 template <int KIND>
-__device__ __forceinline__ void run_kind(const BatchDesc &d, uint32_t u0, uint32_t span,
-                                         uint32_t lane)
+__device__ __forceinline__ void run_kind(const BatchDesc &d, uint32_t s0, uint32_t lo,
+                                         uint32_t hi, uint32_t lane)
 {
     switch (d.phase) {
-    case 0: walk_slots<KIND, 0>(d.run, u0, span, lane); break;
-    case 1: walk_slots<KIND, 1>(d.run, u0, span, lane); break;
-    case 2: walk_slots<KIND, 2>(d.run, u0, span, lane); break;
-    default: walk_slots<KIND, 3>(d.run, u0, span, lane); break;
+    case 0: walk_slots_from<KIND, 0>(d.run, s0, lo, hi, lane); break;
+    case 1: walk_slots_from<KIND, 1>(d.run, s0, lo, hi, lane); break;
+    case 2: walk_slots_from<KIND, 2>(d.run, s0, lo, hi, lane); break;
+    default: walk_slots_from<KIND, 3>(d.run, s0, lo, hi, lane); break;
     }
 }
 
@@ -405,20 +408,21 @@ __device__ __forceinline__ void run_kind(const BatchDesc &d, uint32_t u0, uint32
 // requests.  Their transforms need many more registers, so batches without
 // them run a kernel that does not contain them (and keeps its occupancy).
 template <bool WIDE>
-__device__ void run_segment(const BatchDesc &d, uint32_t u0, uint32_t span, uint32_t lane)
+__device__ void run_segment(const BatchDesc &d, uint32_t s0, uint32_t lo, uint32_t hi,
+                            uint32_t lane)
 {
     switch (d.kind) {
-    case kBits: run_kind<kBits>(d, u0, span, lane); break;
-    case kU32F: run_kind<kU32F>(d, u0, span, lane); break;
-    case kU64F: run_kind<kU64F>(d, u0, span, lane); break;
-    case kGauss: run_kind<kGauss>(d, u0, span, lane); break;
-    case kI32: run_kind<kI32>(d, u0, span, lane); break;
+    case kBits: run_kind<kBits>(d, s0, lo, hi, lane); break;
+    case kU32F: run_kind<kU32F>(d, s0, lo, hi, lane); break;
+    case kU64F: run_kind<kU64F>(d, s0, lo, hi, lane); break;
+    case kGauss: run_kind<kGauss>(d, s0, lo, hi, lane); break;
+    case kI32: run_kind<kI32>(d, s0, lo, hi, lane); break;
     default:
         if constexpr (WIDE) {
             switch (d.kind) {
-            case kGauss64: run_kind<kGauss64>(d, u0, span, lane); break;
-            case kIcdf: run_kind<kIcdf>(d, u0, span, lane); break;
-            default: run_kind<kIcdf64>(d, u0, span, lane); break;
+            case kGauss64: run_kind<kGauss64>(d, s0, lo, hi, lane); break;
+            case kIcdf: run_kind<kIcdf>(d, s0, lo, hi, lane); break;
+            default: run_kind<kIcdf64>(d, s0, lo, hi, lane); break;
             }
         }
         break;
@@ -464,12 +468,16 @@ __global__ __launch_bounds__(WIDE ? kWideBlock : 1024) void batch_main_kernel(Ba
         // the descriptor and the prefix end in one round of loads
         const BatchDesc d = load_desc(&a.desc[r]);
         const uint64_t end = base + uniform64(a.local_end[2 * r]);
-        const uint64_t start = end - ((uint64_t)d.nunits + 63) / 64;
+        const uint64_t start = end - ((uint64_t)d.slot0 + d.nunits + 63) / 64;
         if (end > t) {
+            // tiles are 64 slots of a grid shifted by slot0, so that a step's
+            // 1 KiB of stores falls on one 1 KiB block of memory
             const uint64_t seg = min(t1, end);
-            const uint32_t u0 = (uint32_t)((t - start) * 64);
-            const uint32_t u1 = (uint32_t)min((seg - start) * 64, (uint64_t)d.nunits);
-            run_segment<WIDE>(d, u0, u1 - u0, lane);
+            const uint32_t v0 = (uint32_t)((t - start) * 64);
+            const uint32_t v1 = (uint32_t)((seg - start) * 64);
+            const uint32_t lo = v0 > d.slot0 ? v0 - d.slot0 : 0u;
+            const uint32_t hi = min(v1 - d.slot0, d.nunits);
+            run_segment<WIDE>(d, v0 - d.slot0, lo, hi, lane);
             t = seg;
         }
         ++r;

@@ -204,7 +204,7 @@ struct BatchDesc {
     uint32_t engine;        // mirng_engine_type
     uint32_t mst[6];        // MRG: state after `offset` steps from the seed state
     uint32_t mchunks;       // MRG: chunks (0 for Philox)
-    uint32_t pad;
+    uint32_t slot0;         // Philox: slot 0's place in its 1 KiB block (tile grid offset)
 };
 
 // Steps per MRG thread in a batch chunk: two passes of L (L = 32 outputs,

@@ -207,11 +207,11 @@ __device__ __forceinline__ void emit_slot(const SlotRun &r, uint32_t slot, u32x4
               r.full_lo, r.full_count, e0, r.n, r.ep.nt);
 }
 
-// Whether the blocks base + j, j <= s0 + jmax, stay clear of a carry out of
-// the counter's low word (wave-uniform).
-__device__ __forceinline__ bool no_carry(const SlotRun &r, uint32_t s0, uint64_t jmax)
+// Whether the blocks base + j, j <= last, stay clear of a carry out of the
+// counter's low word (wave-uniform).
+__device__ __forceinline__ bool no_carry(const SlotRun &r, uint64_t last)
 {
-    return (uint64_t)r.base[0] + s0 + jmax < (1ull << 32);
+    return (uint64_t)r.base[0] + last < (1ull << 32);
 }
 
 // One wave writes slots [s0, s0 + span) of a run, 64 consecutive slots per
@@ -219,15 +219,20 @@ __device__ __forceinline__ bool no_carry(const SlotRun &r, uint32_t s0, uint64_t
 // tail of block base + s and the head of block base + s + 1: lane L takes
 // those words from lane L + 1 and lane 63 from lane 0 of the next step,
 // which is evaluated one step ahead.  Must be called by whole waves.
+// Slots s0 + 64 i + L for lane L, i < iters, storing those in [lo, hi).
+// s0 may lie below lo (modulo 2^32, even "negative"): the lanes before lo
+// evaluate blocks that nobody stores, which lets a caller align the steps
+// to a memory grid.
 template <int KIND, int PHASE, int RANGED, bool NC>
-__device__ __forceinline__ void walk_slots_body(const SlotRun &r, uint32_t s0, uint32_t span,
-                                                uint32_t lane, uint32_t iters)
+__device__ __forceinline__ void walk_slots_body(const SlotRun &r, uint32_t s0, uint32_t lo,
+                                                uint32_t hi, uint32_t lane, uint32_t iters)
 {
+    const uint32_t width = hi - lo;
     if constexpr (PHASE == 0) {
         for (uint32_t it = 0; it < iters; ++it) {
             const uint32_t slot = s0 + (it << 6) + lane;
             const u32x4 w = block_at<NC>(r.base, r.k0, r.k1, slot);
-            if (slot - s0 < span) emit_slot<KIND, RANGED>(r, slot, w);
+            if (slot - lo < width) emit_slot<KIND, RANGED>(r, slot, w);
         }
     } else {
         u32x4 cur = block_at<NC>(r.base, r.k0, r.k1, s0 + lane);
@@ -239,22 +244,34 @@ __device__ __forceinline__ void walk_slots_body(const SlotRun &r, uint32_t s0, u
             nb.x = from_next_lane(cur.x, lane0(nxt.x));
             if constexpr (PHASE >= 2) nb.y = from_next_lane(cur.y, lane0(nxt.y));
             if constexpr (PHASE >= 3) nb.z = from_next_lane(cur.z, lane0(nxt.z));
-            if (slot - s0 < span) emit_slot<KIND, RANGED>(r, slot, funnel<PHASE>(cur, nb));
+            if (slot - lo < width) emit_slot<KIND, RANGED>(r, slot, funnel<PHASE>(cur, nb));
             cur = nxt;
         }
     }
 }
 
+// Slots [lo, hi) of a run in steps of 64 starting at s0 (s0 <= lo, modulo
+// 2^32; lo - s0 < 64).  Must be called by whole waves.
+template <int KIND, int PHASE, int RANGED = 2>
+__device__ __forceinline__ void walk_slots_from(const SlotRun &r, uint32_t s0, uint32_t lo,
+                                                uint32_t hi, uint32_t lane)
+{
+    const uint32_t iters = (hi - s0 + 63u) >> 6;
+    // the last block evaluated is the look-ahead of the last step; lo is
+    // the first block anything stores
+    const uint64_t last = (uint64_t)lo + (uint32_t)(s0 + (iters << 6) + 63u - lo);
+    if (no_carry(r, last))
+        walk_slots_body<KIND, PHASE, RANGED, true>(r, s0, lo, hi, lane, iters);
+    else
+        walk_slots_body<KIND, PHASE, RANGED, false>(r, s0, lo, hi, lane, iters);
+}
+
+// Slots [s0, s0 + span) of a run, 64 consecutive slots per step.
 template <int KIND, int PHASE, int RANGED = 2>
 __device__ __forceinline__ void walk_slots(const SlotRun &r, uint32_t s0, uint32_t span,
                                            uint32_t lane)
 {
-    const uint32_t iters = (span + 63u) >> 6;
-    // the last block evaluated is the look-ahead of the last step
-    if (no_carry(r, s0, ((uint64_t)iters << 6) + 63u))
-        walk_slots_body<KIND, PHASE, RANGED, true>(r, s0, span, lane, iters);
-    else
-        walk_slots_body<KIND, PHASE, RANGED, false>(r, s0, span, lane, iters);
+    walk_slots_from<KIND, PHASE, RANGED>(r, s0, s0, s0 + span, lane);
 }
 
 // Chunked walk: a wave writes ITERS consecutive chunks of S slots, S = 64
@@ -296,7 +313,7 @@ __device__ __forceinline__ void walk_chunks(const SlotRun &r, uint32_t s0, uint3
                                             uint32_t lane)
 {
     constexpr uint32_t S = PHASE ? 63u : 64u;
-    if (no_carry(r, s0, (ITERS - 1) * S + 63u))
+    if (no_carry(r, (uint64_t)s0 + (ITERS - 1) * S + 63u))
         walk_chunks_body<KIND, PHASE, ITERS, RANGED, true>(r, s0, span, lane);
     else
         walk_chunks_body<KIND, PHASE, ITERS, RANGED, false>(r, s0, span, lane);
