@@ -33,6 +33,7 @@ struct Slot {
     bool pending = false;              // `done` recorded and maybe not reached
     hipEvent_t done = nullptr;
     hipEvent_t planned = nullptr;      // upload, planning and status copy done
+    hipEvent_t forked = nullptr;       // the caller's stream up to this batch's generation
     hipEvent_t mrg_done = nullptr;     // MRG generation done (its own stream)
     mirng_request *d_reqs = nullptr;
     mirng::BatchDesc *d_desc = nullptr;
@@ -68,6 +69,7 @@ void release(Slot &s)
     if (s.done) (void)hipEventDestroy(s.done);
     if (s.planned) (void)hipEventDestroy(s.planned);
     if (s.mrg_done) (void)hipEventDestroy(s.mrg_done);
+    if (s.forked) (void)hipEventDestroy(s.forked);
     s = Slot{};
 }
 
@@ -111,6 +113,7 @@ hipError_t prepare(Slot &s, size_t count, int dev)
     chk(hipEventCreateWithFlags(&s.done, hipEventDisableTiming));
     chk(hipEventCreateWithFlags(&s.planned, hipEventDisableTiming));
     chk(hipEventCreateWithFlags(&s.mrg_done, hipEventDisableTiming));
+    chk(hipEventCreateWithFlags(&s.forked, hipEventDisableTiming));
     if (err != hipSuccess) {
         release(s);
         return err;
@@ -366,12 +369,14 @@ mirng_status mirng_generate_batch(mirng_batcher b, const mirng_request *reqs, si
     if (err == hipSuccess) err = hipStreamWaitEvent(s, sl.planned, 0);
     if (a.philox && a.mrg) {
         // both engines: the MRG kernel (VALU-bound) runs on the side stream
-        // beside the Philox kernel (bound by HBM writes), and the caller's
-        // stream joins it before the batch counts as done
+        // beside the Philox kernel (bound by HBM writes), after everything
+        // enqueued on the caller's stream before this batch, and the
+        // caller's stream joins it before the batch counts as done
         BatchArgs ph = a, mg = a;
         ph.mrg = 0;
         mg.philox = 0;
-        if (err == hipSuccess) err = hipStreamWaitEvent(b->side, sl.planned, 0);
+        if (err == hipSuccess) err = hipEventRecord(sl.forked, s);
+        if (err == hipSuccess) err = hipStreamWaitEvent(b->side, sl.forked, 0);
         if (err == hipSuccess) err = launch_batch_generate(mg, b->side);
         if (err == hipSuccess) err = hipEventRecord(sl.mrg_done, b->side);
         if (err == hipSuccess) err = launch_batch_generate(ph, s);

@@ -121,6 +121,32 @@ def test_batch_counter_carries():
     _check_outputs(host, layout, st)
 
 
+def test_batch_follows_earlier_work_on_its_stream():
+    """A mixed batch (its MRG kernel runs beside the Philox kernel on an
+    internal stream) starts after the work enqueued before it on the
+    caller's stream: a long fill of the same buffers enqueued first never
+    overwrites the batch's outputs."""
+    import torch
+    stream = torch.cuda.Stream()
+    big = torch.empty(1 << 29, dtype=torch.float32, device="cuda")   # 2 GiB
+    n = 50000
+    reqs = mr.make_requests(2)
+    reqs[0] = (mr.PHILOX4X32_10, 0, mr.UNIFORM_F32, 0, 0.0, 1.0, 11, 0, n, 0)
+    reqs[1] = (mr.MRG32K3A, 0, mr.UNIFORM_F32, 0, 0.0, 1.0, 12, 0, n, 0)
+    reqs["out"] = [int(big.data_ptr()), int(big.data_ptr()) + 4 * n + 256]
+    b = mr.Batcher()
+    for _ in range(3):
+        with torch.cuda.stream(stream):
+            big.fill_(-1.0)
+        b.generate(reqs, stream=stream)
+        stream.synchronize()
+        host = big[: 2 * n + 64].cpu().numpy()
+        gh.assert_match(mr.UNIFORM_F32, host[:n], gh.oracle_request(mr.PHILOX4X32_10, 11, 0,
+                                                                      mr.UNIFORM_F32, n))
+        gh.assert_match(mr.UNIFORM_F32, host[n + 64: 2 * n + 64],
+                        gh.oracle_request(mr.MRG32K3A, 12, 0, mr.UNIFORM_F32, n))
+
+
 def test_batch_equals_plain_path_bytes():
     import torch
     rng = np.random.default_rng(72)
