@@ -40,6 +40,15 @@ def main():
     snap["mrg_seed42_state_after_2^76"] = [int(x) for x in j]
     z = oracle.philox_generate(42, 0, oracle.GAUSSIAN_F32, 8)
     snap["philox_seed42_gauss_fp64_first8"] = [float(x) for x in z]
+    i = oracle.philox_generate(42, 0, oracle.UNIFORM_I32, 4096, -1000.0, 1000.0)
+    snap["philox_seed42_i32_-1000_1000_first16"] = [int(x) for x in i[:16]]
+    snap["philox_seed42_i32_-1000_1000_n4096_sha256"] = digest(i)
+    for kind, name in ((oracle.GAUSSIAN_ICDF_F32, "icdf_f32"), (oracle.GAUSSIAN_ICDF_F64, "icdf_f64")):
+        zp = oracle.philox_generate(42, 0, kind, 4096)
+        zm, _ = oracle.mrg_generate(oracle.mrg_seed(42), kind, 4096)
+        snap[f"philox_seed42_{name}_first8"] = [float(x) for x in zp[:8]]
+        snap[f"philox_seed42_{name}_n4096_sha256"] = digest(zp)
+        snap[f"mrg_seed42_{name}_n4096_sha256"] = digest(zm)
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "oracle_snapshot.json")
     with open(path, "w") as f:
         json.dump(snap, f, indent=1)

@@ -28,3 +28,17 @@ def test_snapshot_unchanged(orc):
     assert [int(x) for x in orc.mrg_skip(st, 1 << 76)] == s["mrg_seed42_state_after_2^76"]
     z = orc.philox_generate(42, 0, orc.GAUSSIAN_F32, 8)
     assert np.array_equal(z, np.array(s["philox_seed42_gauss_fp64_first8"]))
+
+
+def test_snapshot_new_kinds_unchanged(orc):
+    """Uniform int32 and the inverse-CDF Gaussians (R23, R24)."""
+    s = _snap()
+    i = orc.philox_generate(42, 0, orc.UNIFORM_I32, 4096, -1000.0, 1000.0)
+    assert [int(x) for x in i[:16]] == s["philox_seed42_i32_-1000_1000_first16"]
+    assert hashlib.sha256(i.tobytes()).hexdigest() == s["philox_seed42_i32_-1000_1000_n4096_sha256"]
+    for kind, name in ((orc.GAUSSIAN_ICDF_F32, "icdf_f32"), (orc.GAUSSIAN_ICDF_F64, "icdf_f64")):
+        zp = orc.philox_generate(42, 0, kind, 4096)
+        zm, _ = orc.mrg_generate(orc.mrg_seed(42), kind, 4096)
+        assert [float(x) for x in zp[:8]] == s[f"philox_seed42_{name}_first8"]
+        assert hashlib.sha256(zp.tobytes()).hexdigest() == s[f"philox_seed42_{name}_n4096_sha256"]
+        assert hashlib.sha256(zm.tobytes()).hexdigest() == s[f"mrg_seed42_{name}_n4096_sha256"]
