@@ -241,17 +241,18 @@ __device__ __forceinline__ float icdf_f32(uint32_t w)
     return (float)normal_quantile_f32(u);
 }
 
-// Four inverse-CDF Gaussians, one quantile at a time (a rolled loop that
-// rotates the words through one lane of the vector), so that the registers
-// of one quantile suffice.
+// Four inverse-CDF Gaussians, two quantiles at a time (a rolled loop that
+// rotates the words through the vector), so that the registers of two
+// quantiles suffice while their two chains overlap.
 __device__ __forceinline__ f32x4 icdf4_f32(u32x4 w)
 {
     f32x4 f = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll 1
-    for (int j = 0; j < 4; ++j) {
-        const float z = icdf_f32(w.x);
-        w = u32x4{w.y, w.z, w.w, w.x};
-        f = f32x4{f.y, f.z, f.w, z};
+    for (int j = 0; j < 2; ++j) {
+        const float z0 = icdf_f32(w.x);
+        const float z1 = icdf_f32(w.y);
+        w = u32x4{w.z, w.w, w.x, w.y};
+        f = f32x4{f.z, f.w, z0, z1};
     }
     return f;
 }
