@@ -34,15 +34,22 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
-# HBM bytes per launch of the headline kernel (walk 0, 256-thread groups,
-# 1024 waves per CU, streaming stores) from rocprofv3 counters: WRITE_SIZE
-# 1048576 KiB x 1.0 + FETCH_SIZE 43.75 KiB (median of five launches) x 2.0,
-# each scaled by what the same counter reads for a plain 1 GiB device copy
-# (WRITE 1048576 KiB, FETCH 524300 KiB).  Reset to None whenever the kernel
-# changes.
-TRAFFIC_PER_LAUNCH = 1073741824 + 89600
-TRAFFIC_SHAPE = {"walk": 0, "block": 256, "waves_per_cu": 1024, "blocks_per_lane": 1,
-                 "nontemporal": 1, "reserved": 0}
+# HBM bytes per launch of the headline kernel, per launch shape the counters
+# were taken on (walk, block, waves per CU, blocks per lane, streaming
+# stores): WRITE_SIZE 1048576 KiB x 1.0 + FETCH_SIZE (median of five
+# launches: 43.75 KiB, 45.125 KiB) x 2.0, each scaled by what the same
+# counter reads for a plain 1 GiB device copy (WRITE 1048576 KiB, FETCH
+# 524300 KiB).  Other shapes report no traffic; reset whenever the kernel's
+# code changes.
+TRAFFIC_BY_SHAPE = {
+    (0, 256, 1024, 1, 1): 1073741824 + 89600,
+    (0, 1024, 256, 1, 1): 1073741824 + 92416,
+}
+
+
+def traffic_for(cfg: dict):
+    return TRAFFIC_BY_SHAPE.get((cfg["walk"], cfg["block"], cfg["waves_per_cu"],
+                                 cfg["blocks_per_lane"], cfg["nontemporal"]))
 
 
 def parse():
@@ -602,8 +609,7 @@ def main():
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": (TRAFFIC_PER_LAUNCH
-                            if mr.philox_config().as_dict() == TRAFFIC_SHAPE else None),
+                "traffic": traffic_for(mr.philox_config().as_dict()),
                 "kernel": "philox_fill_kernel<uniform_f32>",
                 "kernel_ms": {"avg": round(avg_ms, 4),
                               "bracketed_avg": round(b_avg, 4), "bracketed_median": round(b_med, 4),
