@@ -385,7 +385,14 @@ mirng_status mirng_generate_batch(mirng_batcher b, const mirng_request *reqs, si
         err = launch_batch_generate(a, s);
     }
     if (err == hipSuccess) err = hipEventRecord(sl.done, s);
-    if (err != hipSuccess) return MIRNG_E_LAUNCH;
+    if (err != hipSuccess) {
+        // part of the batch may be queued: let it drain before the slot's
+        // buffers can be reused
+        (void)hipStreamSynchronize(b->copy);
+        (void)hipStreamSynchronize(b->side);
+        (void)hipStreamSynchronize(s);
+        return MIRNG_E_LAUNCH;
+    }
     sl.pending = true;
     b->last = k;
     return MIRNG_OK;
