@@ -1,6 +1,7 @@
 // Host-only driver of the serving scheduler with a simulated executor: each
 // slot "runs" a batch for base_us + bytes * ns_per_byte and reports the
-// statuses the batched kernel would give (unknown kind -> UNSUPPORTED,
+// statuses the batched kernel would give (kinds 1-8 known; unknown kind ->
+// UNSUPPORTED,
 // n >= 2^32 -> CAPACITY).  Prints one JSON object for the Python tests.
 //
 // usage: sched_fake slots capacity max_batch ns_per_byte base_us count gap_us seed max_n
@@ -42,7 +43,7 @@ public:
         for (const mirng_request &r : reqs) {
             bytes += request_bytes(r);
             int32_t s = MIRNG_OK;
-            if (r.dist.kind < 1 || r.dist.kind > 4) s = MIRNG_E_UNSUPPORTED;
+            if (r.dist.kind < 1 || r.dist.kind > 8) s = MIRNG_E_UNSUPPORTED;
             else if (r.n >= (1ull << 32)) s = MIRNG_E_CAPACITY;
             st_[slot].push_back(s);
         }
@@ -96,7 +97,8 @@ int main(int argc, char **argv)
     std::uniform_real_distribution<double> U(0.0, 1.0);
     std::vector<int> ret(count);
     std::vector<uint64_t> ticket(count, ~0ull), bytes(count);
-    std::vector<int32_t> expect(count), got(count, -1);
+    std::vector<int32_t> expect(count), got(count, -1), kinds(count);
+    std::vector<uint64_t> ns(count);
     mirng_server_stats st{};
     std::vector<std::vector<uint64_t>> log;
     {
@@ -106,12 +108,14 @@ int main(int argc, char **argv)
             mirng_request r{};
             r.engine_type = (U(rng) < 0.5) ? 1 : 2;
             const double u = U(rng);
-            r.dist.kind = u < 0.05 ? 9 : 1 + (int)(U(rng) * 4) % 4;
+            r.dist.kind = u < 0.05 ? 9 : 1 + (int)(U(rng) * 8) % 8;
             r.dist.p1 = 1.0;
             r.n = (uint64_t)std::floor(std::pow(10.0, U(rng) * std::log10(max_n)));
             if (U(rng) < 0.02) r.n = 1ull << 32;
             bytes[i] = request_bytes(r);
-            expect[i] = (r.dist.kind < 1 || r.dist.kind > 4) ? MIRNG_E_UNSUPPORTED
+            kinds[i] = r.dist.kind;
+            ns[i] = r.n;
+            expect[i] = (r.dist.kind < 1 || r.dist.kind > 8) ? MIRNG_E_UNSUPPORTED
                         : (r.n >= (1ull << 32))              ? MIRNG_E_CAPACITY
                                                              : MIRNG_OK;
             if (gap_us > 0)
@@ -136,6 +140,10 @@ int main(int argc, char **argv)
     std::printf("], \"ticket\": [");
     for (int i = 0; i < count; ++i)
         std::printf("%s%lld", i ? "," : "", ret[i] ? -1LL : (long long)ticket[i]);
+    std::printf("], \"kind\": [");
+    for (int i = 0; i < count; ++i) std::printf("%s%d", i ? "," : "", kinds[i]);
+    std::printf("], \"n\": [");
+    for (int i = 0; i < count; ++i) std::printf("%s%llu", i ? "," : "", (unsigned long long)ns[i]);
     std::printf("], \"bytes\": [");
     for (int i = 0; i < count; ++i) std::printf("%s%llu", i ? "," : "", (unsigned long long)bytes[i]);
     std::printf("], \"expect\": [");

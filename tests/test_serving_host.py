@@ -31,9 +31,15 @@ def fake(tmp_path_factory):
     return run
 
 
+ELEM = {1: 4, 2: 4, 3: 8, 4: 4, 5: 8, 6: 4, 7: 4, 8: 8}
+
+
 def _common(d, slots, capacity, max_batch):
     ret = np.array(d["ret"])
     bytes_ = np.array(d["bytes"])
+    # admission counts n x element size, 0 for requests the kernel refuses
+    for k, n, b in zip(d["kind"], d["n"], d["bytes"]):
+        assert b == (n * ELEM[k] if k in ELEM and n < 2**32 else 0), (k, n, b)
     acc = np.nonzero(ret == 0)[0]
     # refused exactly when the request alone exceeds the capacity
     assert np.array_equal(ret != 0, bytes_ > capacity)
