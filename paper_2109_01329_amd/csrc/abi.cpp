@@ -34,7 +34,7 @@ bool philox_config_valid(const mirng_philox_config &c)
     const bool block_ok = c.block == 64 || c.block == 128 || c.block == 256 ||
                           c.block == 512 || c.block == 1024;
     const int wmax = 4096;
-    return (c.walk == 0 || c.walk == 1 || c.walk == 2) && block_ok && c.waves_per_cu >= 1 &&
+    return c.walk >= 0 && c.walk <= 3 && block_ok && c.waves_per_cu >= 1 &&
            c.waves_per_cu <= wmax &&
            (c.blocks_per_lane == 1 || c.blocks_per_lane == 2 || c.blocks_per_lane == 4) &&
            (c.nontemporal == 0 || c.nontemporal == 1) && c.reserved == 0;
@@ -175,7 +175,11 @@ hipError_t philox_plain(const uint32_t key[2], Pos130 p, const mirng_distributio
             r.n = chunk;
             const uint64_t nslots = (head + chunk + epv - 1) / epv;
             a.nslots = (uint32_t)nslots;
-            if (tu.walk == 2) {
+            if (tu.walk == 3) {
+                a.group_walk = 1;
+                a.iters = 0;
+                a.slots_per_wave = 64;
+            } else if (tu.walk == 2) {
                 a.iters = (uint32_t)tu.blocks_per_lane;
                 a.slots_per_wave = a.iters * (a.phase ? 63u : 64u);
             } else {

@@ -92,7 +92,7 @@ mirng_status mirng_autotune_philox(int32_t kind, uint64_t n, void *out, void *st
                                    int32_t prewarm_ms, int32_t rounds, int32_t reps,
                                    mirng_philox_config *best, float *best_ms)
 {
-    if (kind < kBits || kind > kGauss64) return MIRNG_E_UNSUPPORTED;
+    if (kind < kBits || kind > kIcdf64) return MIRNG_E_UNSUPPORTED;
     if (!out || n == 0 || !tune_args_ok(prewarm_ms, rounds, reps)) return MIRNG_E_INVALID_ARG;
     if ((uintptr_t)out % (uintptr_t)elem_bytes(kind)) return MIRNG_E_INVALID_ARG;
     if (ensure_device(nullptr) != hipSuccess) return MIRNG_E_DEVICE;
@@ -104,11 +104,14 @@ mirng_status mirng_autotune_philox(int32_t kind, uint64_t n, void *out, void *st
     for (int block : {256, 1024})
         for (int iters : {1, 2, 4})
             for (int nt : {0, 1}) cand.push_back({2, block, 1, iters, nt, 0});
+    for (int block : {256, 512, 1024})
+        for (int nt : {0, 1}) cand.push_back({3, block, 1, 1, nt, 0});
     const mirng_philox_config prev = philox_config();
     mirng_engine e = nullptr;
     if (mirng_engine_create(MIRNG_PHILOX4X32_10, 0x5EED5EEDull, 1, &e) != MIRNG_OK)
         return MIRNG_E_ALLOC;
-    const mirng_distribution d = {kind, 0, 0.0, 1.0};
+    // the unit range (or mean 0, sd 1); [0, 2^31) for uniform int32
+    const mirng_distribution d = {kind, 0, 0.0, kind == kI32 ? 2147483648.0 : 1.0};
     auto run = [&]() { return mirng_generate(e, &d, n, out, stream); };
     float ms = 0.0f;
     const int k = tune(cand.size(), [&](size_t i) { philox_config() = cand[i]; }, run,

@@ -106,6 +106,73 @@ __global__ __launch_bounds__(1024) void philox_chunk_kernel(PhiloxFill a)
         walk_chunks<KIND, PHASE, ITERS, 0>(a.run, s0, span, lane);
 }
 
+// ---------------------------------------------------------------- group walk
+
+// Each wave writes one aligned chunk of 64 slots (1 KiB of a 16-byte
+// aligned run), and a group of G waves covers 64 G consecutive slots, at
+// every phase.  At phases p != 0, slot s needs the tail of block s and the
+// head of block s + 1: lanes take it from lane + 1 (DPP), lane 63 from the
+// next wave's lane 0 through LDS, and the group's last wave evaluates the
+// one block past the group (so the group evaluates 64 G + 1 blocks).  Every
+// wave reaches the barrier, also past the end of the run, where it stores
+// nothing.
+template <int KIND, int PHASE, int RANGED, bool NC>
+__device__ __forceinline__ void group_chunk(const PhiloxFill &a, u32x4 *heads)
+{
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t w = threadIdx.x >> 6;
+    const uint32_t nw = blockDim.x >> 6;
+    const uint32_t s0 = (blockIdx.x * nw + w) * 64u;
+    const uint32_t slot = s0 + lane;
+    const SlotRun &r = a.run;
+    const u32x4 cur = block_at<NC>(r.base, r.k0, r.k1, slot);
+    if constexpr (PHASE == 0) {
+        if (slot < a.nslots) emit_slot<KIND, RANGED>(r, slot, cur);
+    } else {
+        if (lane == 0) heads[w] = cur;
+        const bool last = w + 1u == nw;
+        u32x4 head = {0u, 0u, 0u, 0u};
+        if (last) head = block_at<NC>(r.base, r.k0, r.k1, s0 + 64u);   // wave-uniform
+        __syncthreads();
+        if (!last) head = heads[w + 1u];
+        u32x4 nb;
+        nb.x = from_next_lane(cur.x, head.x);
+        if constexpr (PHASE >= 2) nb.y = from_next_lane(cur.y, head.y);
+        if constexpr (PHASE >= 3) nb.z = from_next_lane(cur.z, head.z);
+        if (slot < a.nslots) emit_slot<KIND, RANGED>(r, slot, funnel<PHASE>(cur, nb));
+    }
+}
+
+template <int KIND, int PHASE>
+__global__ __launch_bounds__(1024) void philox_group_kernel(PhiloxFill a)
+{
+    __shared__ u32x4 heads[16];
+    const uint32_t nw = blockDim.x >> 6;
+    // the group's blocks, the one past it included (group-uniform choice)
+    const uint64_t last = ((uint64_t)blockIdx.x + 1u) * nw * 64u;
+    const bool nc = no_carry(a.run, last);
+    const bool rg = has_range_step(KIND) && a.run.ep.ranged;
+    if (nc) {
+        if (rg) group_chunk<KIND, PHASE, 1, true>(a, heads);
+        else group_chunk<KIND, PHASE, 0, true>(a, heads);
+    } else {
+        if (rg) group_chunk<KIND, PHASE, 1, false>(a, heads);
+        else group_chunk<KIND, PHASE, 0, false>(a, heads);
+    }
+}
+
+template <int KIND>
+hipError_t launch_group_kind(const PhiloxFill &a, dim3 grid, dim3 block, hipStream_t s)
+{
+    switch (a.phase) {
+    case 0: hipLaunchKernelGGL((philox_group_kernel<KIND, 0>), grid, block, 0, s, a); break;
+    case 1: hipLaunchKernelGGL((philox_group_kernel<KIND, 1>), grid, block, 0, s, a); break;
+    case 2: hipLaunchKernelGGL((philox_group_kernel<KIND, 2>), grid, block, 0, s, a); break;
+    default: hipLaunchKernelGGL((philox_group_kernel<KIND, 3>), grid, block, 0, s, a); break;
+    }
+    return hipGetLastError();
+}
+
 template <int KIND, int PHASE>
 void launch_chunk_phase(const PhiloxFill &a, dim3 grid, dim3 block, hipStream_t s)
 {
@@ -174,6 +241,19 @@ hipError_t launch_philox_fill(const PhiloxFill &a, hipStream_t s)
     const uint64_t waves = ((uint64_t)a.nslots + a.slots_per_wave - 1) / a.slots_per_wave;
     const dim3 grid((uint32_t)((waves + waves_per_block - 1) / waves_per_block));
     const dim3 block(a.block);
+    if (a.group_walk) {
+        switch (a.kind) {
+        case kBits: return launch_group_kind<kBits>(a, grid, block, s);
+        case kU32F: return launch_group_kind<kU32F>(a, grid, block, s);
+        case kU64F: return launch_group_kind<kU64F>(a, grid, block, s);
+        case kGauss: return launch_group_kind<kGauss>(a, grid, block, s);
+        case kGauss64: return launch_group_kind<kGauss64>(a, grid, block, s);
+        case kI32: return launch_group_kind<kI32>(a, grid, block, s);
+        case kIcdf: return launch_group_kind<kIcdf>(a, grid, block, s);
+        case kIcdf64: return launch_group_kind<kIcdf64>(a, grid, block, s);
+        default: return hipErrorInvalidValue;
+        }
+    }
     if (a.iters) {
         switch (a.kind) {
         case kBits: return launch_chunk_kind<kBits>(a, grid, block, s);

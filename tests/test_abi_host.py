@@ -198,7 +198,8 @@ def test_philox_config_validation():
     c = mr.philox_config()
     assert c.block in (64, 128, 256, 512, 1024)
     for bad in (dict(block=100), dict(waves_per_cu=0), dict(walk=1, waves_per_cu=4097),
-                dict(walk=0, waves_per_cu=4097), dict(walk=3), dict(blocks_per_lane=3),
+                dict(walk=0, waves_per_cu=4097), dict(walk=4), dict(walk=-1),
+                dict(blocks_per_lane=3),
                 dict(nontemporal=2), dict(reserved=1)):
         with pytest.raises(mr.MirngError):
             mr.set_philox_config(**bad)

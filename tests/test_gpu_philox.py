@@ -159,6 +159,9 @@ CONFIGS = [
     dict(walk=2, block=256, waves_per_cu=1, blocks_per_lane=1, nontemporal=0),
     dict(walk=2, block=64, waves_per_cu=1, blocks_per_lane=2, nontemporal=1),
     dict(walk=2, block=1024, waves_per_cu=1, blocks_per_lane=4, nontemporal=0),
+    dict(walk=3, block=64, waves_per_cu=1, blocks_per_lane=1, nontemporal=0),
+    dict(walk=3, block=256, waves_per_cu=1, blocks_per_lane=1, nontemporal=1),
+    dict(walk=3, block=1024, waves_per_cu=1, blocks_per_lane=1, nontemporal=0),
 ]
 
 
@@ -200,7 +203,9 @@ AUTOTUNE_CANDIDATES = (
     + [dict(walk=1, block=256, waves_per_cu=8, blocks_per_lane=bpl, nontemporal=0)
        for bpl in (1, 2)]
     + [dict(walk=2, block=b, waves_per_cu=1, blocks_per_lane=i, nontemporal=nt)
-       for b in (256, 1024) for i in (1, 2, 4) for nt in (0, 1)])
+       for b in (256, 1024) for i in (1, 2, 4) for nt in (0, 1)]
+    + [dict(walk=3, block=b, waves_per_cu=1, blocks_per_lane=1, nontemporal=nt)
+       for b in (256, 512, 1024) for nt in (0, 1)])
 
 
 def test_outputs_invariant_under_every_autotuner_candidate():
