@@ -37,14 +37,19 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch of the headline kernel, per launch shape the counters
 # were taken on (walk, block, waves per CU, blocks per lane, streaming
 # stores): WRITE_SIZE 1048576 KiB x 1.0 + FETCH_SIZE (median of five
-# launches: 43.75 KiB, 45.125 KiB) x 2.0, each scaled by what the same
+# launches: 43.75 KiB, 45.125 KiB, 37.0 KiB) x 2.0, each scaled by what the same
 # counter reads for a plain 1 GiB device copy (WRITE 1048576 KiB, FETCH
 # 524300 KiB).  Other shapes report no traffic; reset whenever the kernel's
 # code changes.
 TRAFFIC_BY_SHAPE = {
     (0, 256, 1024, 1, 1): 1073741824 + 89600,
     (0, 1024, 256, 1, 1): 1073741824 + 92416,
+    (3, 256, 1, 1, 0): 1073741824 + 75776,
 }
+
+# the kernel each walk of the plain Philox path launches
+KERNEL_BY_WALK = {0: "philox_fill_kernel", 1: "philox_blocks_kernel", 2: "philox_chunk_kernel",
+                  3: "philox_group_kernel"}
 
 
 def traffic_for(cfg: dict):
@@ -618,7 +623,7 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic_for(mr.philox_config().as_dict()),
-                "kernel": "philox_fill_kernel<uniform_f32>",
+                "kernel": KERNEL_BY_WALK[mr.philox_config().walk] + "<uniform_f32>",
                 "kernel_ms": {"avg": round(avg_ms, 4),
                               "bracketed_avg": round(b_avg, 4), "bracketed_median": round(b_med, 4),
                               "bracketed_p90": round(b_p90, 4)},

@@ -144,11 +144,14 @@ mirng_status mirng_bench_store(void *out, uint64_t bytes, int32_t nontemporal, v
     const uint64_t nvec = bytes / 16;
     uint64_t groups;
     uint32_t vpw = 0;
-    if (tu.walk == 0 || tu.walk == 2) {
+    if (tu.walk == 0 || tu.walk == 2 || tu.walk == 3) {
+        // the store pattern of the installed walk: contiguous runs (0), or
+        // runs of 1, 2 or 4 chunks (2) or one chunk (3) of 64 vectors
         const uint64_t waves_target = (uint64_t)device_cu_count() * tu.waves_per_cu;
         const uint64_t iters = (nvec + 64 * waves_target - 1) / (64 * waves_target);
-        const uint64_t per_wave = tu.walk == 2 ? 64ull * tu.blocks_per_lane
-                                               : (iters ? iters : 1) * 64;
+        const uint64_t per_wave = tu.walk == 3   ? 64ull
+                                  : tu.walk == 2 ? 64ull * tu.blocks_per_lane
+                                                 : (iters ? iters : 1) * 64;
         if (per_wave >= (1ull << 32)) return MIRNG_E_INVALID_ARG;
         vpw = (uint32_t)per_wave;
         const uint64_t waves = (nvec + per_wave - 1) / per_wave;
@@ -172,7 +175,7 @@ mirng_status mirng_bench_philox_nostore(uint64_t nblocks, uint32_t k0, uint32_t 
     if (ensure_device(nullptr) != hipSuccess) return MIRNG_E_DEVICE;
     mirng_philox_config tu = philox_config();
     tu.blocks_per_lane = 1;
-    if (tu.waves_per_cu > 64) tu.waves_per_cu = 32;   // resident waves for the walk
+    tu.waves_per_cu = 32;   // a full complement of resident waves, whatever the walk
     hipLaunchKernelGGL(philox_nostore_kernel, dim3((uint32_t)grid_for(nblocks, tu)),
                        dim3(tu.block), 0, (hipStream_t)stream, nblocks, k0, k1, sink);
     return hipGetLastError() == hipSuccess ? MIRNG_OK : MIRNG_E_LAUNCH;
