@@ -289,19 +289,19 @@ mirng_status mirng_batcher_config_set(mirng_batcher b, const mirng_batch_config 
  *   16-byte outputs (63 when the position is not a multiple of 4 on the
  *   16-byte grid; the last lane then only supplies words to its neighbour);
  *   the grid size follows from n (any kind, any position).
- * walk 3: each wave writes one chunk of 64 16-byte outputs at any position;
- *   a workgroup's waves cover consecutive chunks, the last lane of a wave
- *   takes the words it lacks from the next wave through LDS and the
- *   group's last wave evaluates the one block past the group; the grid size
- *   follows from n (any kind, any position; waves_per_cu and
- *   blocks_per_lane unused).
+ * walk 3: each wave writes blocks_per_lane chunks of 64 16-byte outputs at
+ *   any position; a workgroup of G waves covers blocks_per_lane * G
+ *   consecutive chunks, wave w taking chunks w, G + w, ...; the last lane
+ *   of a chunk takes the words it lacks from the next chunk through LDS and
+ *   the group's last wave evaluates the one block past the group; the grid
+ *   size follows from n (any kind, any position; waves_per_cu unused).
  * Process-wide; set it while no generate call is being enqueued. */
 typedef struct {
     int32_t walk;             /* 0 contiguous runs, 1 grid-stride, 2 chunks, 3 group chunks */
     int32_t block;            /* threads per workgroup: 64, 128, 256, 512, 1024 */
     int32_t waves_per_cu;     /* 1..4096 (walk 1: waves in the grid; walks 2, 3: unused) */
-    int32_t blocks_per_lane;  /* walk 1: blocks per lane per step; walk 2: chunks
-                                 per wave; 1, 2 or 4 (ignored by walk 0)           */
+    int32_t blocks_per_lane;  /* walk 1: blocks per lane per step; walks 2, 3:
+                                 chunks per wave; 1, 2 or 4 (ignored by walk 0)    */
     int32_t nontemporal;      /* 0: plain stores, 1: streaming (nt) stores       */
     int32_t reserved;         /* must be 0 */
 } mirng_philox_config;

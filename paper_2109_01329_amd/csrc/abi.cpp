@@ -177,8 +177,8 @@ hipError_t philox_plain(const uint32_t key[2], Pos130 p, const mirng_distributio
             a.nslots = (uint32_t)nslots;
             if (tu.walk == 3) {
                 a.group_walk = 1;
-                a.iters = 0;
-                a.slots_per_wave = 64;
+                a.iters = (uint32_t)tu.blocks_per_lane;
+                a.slots_per_wave = 64u * a.iters;
             } else if (tu.walk == 2) {
                 a.iters = (uint32_t)tu.blocks_per_lane;
                 a.slots_per_wave = a.iters * (a.phase ? 63u : 64u);

@@ -104,8 +104,9 @@ mirng_status mirng_autotune_philox(int32_t kind, uint64_t n, void *out, void *st
     for (int block : {256, 1024})
         for (int iters : {1, 2, 4})
             for (int nt : {0, 1}) cand.push_back({2, block, 1, iters, nt, 0});
-    for (int block : {256, 512, 1024})
-        for (int nt : {0, 1}) cand.push_back({3, block, 1, 1, nt, 0});
+    for (int block : {128, 256, 512, 1024})
+        for (int chunks : {1, 2})
+            for (int nt : {0, 1}) cand.push_back({3, block, 1, chunks, nt, 0});
     const mirng_philox_config prev = philox_config();
     mirng_engine e = nullptr;
     if (mirng_engine_create(MIRNG_PHILOX4X32_10, 0x5EED5EEDull, 1, &e) != MIRNG_OK)

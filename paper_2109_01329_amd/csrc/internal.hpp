@@ -190,7 +190,7 @@ struct PhiloxFill {
     int32_t kind;
     uint32_t block;         // threads per workgroup
     uint32_t iters;         // 0: contiguous walk; 1, 2, 4: chunked walk, chunks per wave
-    uint32_t group_walk;    // 1: one aligned 64-slot chunk per wave, heads shared in LDS
+    uint32_t group_walk;    // 1: iters aligned 64-slot chunks per wave, heads shared in LDS
 };
 
 // One request of a batch, as planned on the device.  Philox requests are

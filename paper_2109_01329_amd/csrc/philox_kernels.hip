@@ -108,56 +108,82 @@ __global__ __launch_bounds__(1024) void philox_chunk_kernel(PhiloxFill a)
 
 // ---------------------------------------------------------------- group walk
 
-// Each wave writes one aligned chunk of 64 slots (1 KiB of a 16-byte
-// aligned run), and a group of G waves covers 64 G consecutive slots, at
-// every phase.  At phases p != 0, slot s needs the tail of block s and the
-// head of block s + 1: lanes take it from lane + 1 (DPP), lane 63 from the
-// next wave's lane 0 through LDS, and the group's last wave evaluates the
-// one block past the group (so the group evaluates 64 G + 1 blocks).  Every
-// wave reaches the barrier, also past the end of the run, where it stores
+// A group of G waves covers ITERS G consecutive chunks of 64 slots (1 KiB
+// each of a 16-byte aligned run), and wave w writes chunks w, G + w, ...,
+// so the waves in flight write one compact, moving window at every phase.
+// At phases p != 0, slot s needs the tail of block s and the head of block
+// s + 1: lanes take it from lane + 1 (DPP), lane 63 from lane 0 of the next
+// chunk through LDS, and the group's last wave evaluates the one block past
+// the group (so the group evaluates 64 ITERS G + 1 blocks).  Every wave
+// reaches the barrier, also past the end of the run, where it stores
 // nothing.
-template <int KIND, int PHASE, int RANGED, bool NC>
-__device__ __forceinline__ void group_chunk(const PhiloxFill &a, u32x4 *heads)
+template <int KIND, int PHASE, int ITERS, int RANGED, bool NC>
+__device__ __forceinline__ void group_chunks(const PhiloxFill &a, u32x4 *heads)
 {
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t w = threadIdx.x >> 6;
     const uint32_t nw = blockDim.x >> 6;
-    const uint32_t s0 = (blockIdx.x * nw + w) * 64u;
-    const uint32_t slot = s0 + lane;
+    const uint32_t g0 = blockIdx.x * nw * ITERS * 64u;   // the group's first slot
     const SlotRun &r = a.run;
-    const u32x4 cur = block_at<NC>(r.base, r.k0, r.k1, slot);
+    u32x4 cur[ITERS];
+#pragma unroll
+    for (int it = 0; it < ITERS; ++it)
+        cur[it] = block_at<NC>(r.base, r.k0, r.k1, g0 + (it * nw + w) * 64u + lane);
     if constexpr (PHASE == 0) {
-        if (slot < a.nslots) emit_slot<KIND, RANGED>(r, slot, cur);
+#pragma unroll
+        for (int it = 0; it < ITERS; ++it) {
+            const uint32_t slot = g0 + (it * nw + w) * 64u + lane;
+            if (slot < a.nslots) emit_slot<KIND, RANGED>(r, slot, cur[it]);
+        }
     } else {
-        if (lane == 0) heads[w] = cur;
+        if (lane == 0) {
+#pragma unroll
+            for (int it = 0; it < ITERS; ++it) heads[it * nw + w] = cur[it];
+        }
         const bool last = w + 1u == nw;
-        u32x4 head = {0u, 0u, 0u, 0u};
-        if (last) head = block_at<NC>(r.base, r.k0, r.k1, s0 + 64u);   // wave-uniform
+        u32x4 extra = {0u, 0u, 0u, 0u};
+        if (last) extra = block_at<NC>(r.base, r.k0, r.k1, g0 + ITERS * nw * 64u);   // uniform
         __syncthreads();
-        if (!last) head = heads[w + 1u];
-        u32x4 nb;
-        nb.x = from_next_lane(cur.x, head.x);
-        if constexpr (PHASE >= 2) nb.y = from_next_lane(cur.y, head.y);
-        if constexpr (PHASE >= 3) nb.z = from_next_lane(cur.z, head.z);
-        if (slot < a.nslots) emit_slot<KIND, RANGED>(r, slot, funnel<PHASE>(cur, nb));
+#pragma unroll
+        for (int it = 0; it < ITERS; ++it) {
+            const uint32_t c = it * nw + w;   // chunk within the group
+            u32x4 head = extra;
+            if (!last || it + 1 < ITERS) head = heads[c + 1u];
+            u32x4 nb;
+            nb.x = from_next_lane(cur[it].x, head.x);
+            if constexpr (PHASE >= 2) nb.y = from_next_lane(cur[it].y, head.y);
+            if constexpr (PHASE >= 3) nb.z = from_next_lane(cur[it].z, head.z);
+            const uint32_t slot = g0 + c * 64u + lane;
+            if (slot < a.nslots) emit_slot<KIND, RANGED>(r, slot, funnel<PHASE>(cur[it], nb));
+        }
+    }
+}
+
+template <int KIND, int PHASE, int ITERS>
+__global__ __launch_bounds__(1024) void philox_group_kernel(PhiloxFill a)
+{
+    __shared__ u32x4 heads[16 * ITERS + 1];
+    const uint32_t nw = blockDim.x >> 6;
+    // the group's blocks, the one past it included (group-uniform choice)
+    const uint64_t last = ((uint64_t)blockIdx.x + 1u) * nw * ITERS * 64u;
+    const bool nc = no_carry(a.run, last);
+    const bool rg = has_range_step(KIND) && a.run.ep.ranged;
+    if (nc) {
+        if (rg) group_chunks<KIND, PHASE, ITERS, 1, true>(a, heads);
+        else group_chunks<KIND, PHASE, ITERS, 0, true>(a, heads);
+    } else {
+        if (rg) group_chunks<KIND, PHASE, ITERS, 1, false>(a, heads);
+        else group_chunks<KIND, PHASE, ITERS, 0, false>(a, heads);
     }
 }
 
 template <int KIND, int PHASE>
-__global__ __launch_bounds__(1024) void philox_group_kernel(PhiloxFill a)
+void launch_group_phase(const PhiloxFill &a, dim3 grid, dim3 block, hipStream_t s)
 {
-    __shared__ u32x4 heads[16];
-    const uint32_t nw = blockDim.x >> 6;
-    // the group's blocks, the one past it included (group-uniform choice)
-    const uint64_t last = ((uint64_t)blockIdx.x + 1u) * nw * 64u;
-    const bool nc = no_carry(a.run, last);
-    const bool rg = has_range_step(KIND) && a.run.ep.ranged;
-    if (nc) {
-        if (rg) group_chunk<KIND, PHASE, 1, true>(a, heads);
-        else group_chunk<KIND, PHASE, 0, true>(a, heads);
-    } else {
-        if (rg) group_chunk<KIND, PHASE, 1, false>(a, heads);
-        else group_chunk<KIND, PHASE, 0, false>(a, heads);
+    switch (a.iters) {
+    case 1: hipLaunchKernelGGL((philox_group_kernel<KIND, PHASE, 1>), grid, block, 0, s, a); break;
+    case 2: hipLaunchKernelGGL((philox_group_kernel<KIND, PHASE, 2>), grid, block, 0, s, a); break;
+    default: hipLaunchKernelGGL((philox_group_kernel<KIND, PHASE, 4>), grid, block, 0, s, a); break;
     }
 }
 
@@ -165,10 +191,10 @@ template <int KIND>
 hipError_t launch_group_kind(const PhiloxFill &a, dim3 grid, dim3 block, hipStream_t s)
 {
     switch (a.phase) {
-    case 0: hipLaunchKernelGGL((philox_group_kernel<KIND, 0>), grid, block, 0, s, a); break;
-    case 1: hipLaunchKernelGGL((philox_group_kernel<KIND, 1>), grid, block, 0, s, a); break;
-    case 2: hipLaunchKernelGGL((philox_group_kernel<KIND, 2>), grid, block, 0, s, a); break;
-    default: hipLaunchKernelGGL((philox_group_kernel<KIND, 3>), grid, block, 0, s, a); break;
+    case 0: launch_group_phase<KIND, 0>(a, grid, block, s); break;
+    case 1: launch_group_phase<KIND, 1>(a, grid, block, s); break;
+    case 2: launch_group_phase<KIND, 2>(a, grid, block, s); break;
+    default: launch_group_phase<KIND, 3>(a, grid, block, s); break;
     }
     return hipGetLastError();
 }

@@ -162,6 +162,10 @@ CONFIGS = [
     dict(walk=3, block=64, waves_per_cu=1, blocks_per_lane=1, nontemporal=0),
     dict(walk=3, block=256, waves_per_cu=1, blocks_per_lane=1, nontemporal=1),
     dict(walk=3, block=1024, waves_per_cu=1, blocks_per_lane=1, nontemporal=0),
+    dict(walk=3, block=64, waves_per_cu=1, blocks_per_lane=2, nontemporal=0),
+    dict(walk=3, block=256, waves_per_cu=1, blocks_per_lane=2, nontemporal=1),
+    dict(walk=3, block=1024, waves_per_cu=1, blocks_per_lane=4, nontemporal=0),
+    dict(walk=3, block=512, waves_per_cu=1, blocks_per_lane=4, nontemporal=1),
 ]
 
 
@@ -204,8 +208,8 @@ AUTOTUNE_CANDIDATES = (
        for bpl in (1, 2)]
     + [dict(walk=2, block=b, waves_per_cu=1, blocks_per_lane=i, nontemporal=nt)
        for b in (256, 1024) for i in (1, 2, 4) for nt in (0, 1)]
-    + [dict(walk=3, block=b, waves_per_cu=1, blocks_per_lane=1, nontemporal=nt)
-       for b in (256, 512, 1024) for nt in (0, 1)])
+    + [dict(walk=3, block=b, waves_per_cu=1, blocks_per_lane=c, nontemporal=nt)
+       for b in (128, 256, 512, 1024) for c in (1, 2) for nt in (0, 1)])
 
 
 def test_outputs_invariant_under_every_autotuner_candidate():
