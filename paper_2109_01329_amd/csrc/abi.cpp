@@ -23,9 +23,9 @@ namespace mirng {
 mirng_philox_config &philox_config()
 {
     // measured on MI355X at n = 2^28 (launch-shape sweeps in the design
-    // notes): contiguous runs, 1024-thread groups, 256 waves of work per CU,
-    // streaming stores
-    static mirng_philox_config c = {0, 1024, 256, 1, 1, 0};
+    // notes): group chunks, 256-thread groups, two aligned 1 KiB chunks per
+    // wave, ordinary stores; ahead of the contiguous walk at every phase
+    static mirng_philox_config c = {3, 256, 1, 2, 0, 0};
     return c;
 }
 

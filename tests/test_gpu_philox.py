@@ -201,6 +201,27 @@ def test_outputs_invariant_under_launch_shape(cfg):
         mr.set_philox_config(prev)
 
 
+@pytest.mark.parametrize("cfg", [dict(walk=3, block=b, waves_per_cu=1, blocks_per_lane=c,
+                                      nontemporal=0) for b, c in ((64, 1), (256, 2), (1024, 4))])
+def test_group_walk_short_runs(cfg):
+    """Runs shorter than one group's tile (up to 64 x 1024 / 64 x 4 slots):
+    most waves store nothing but still take part in the head exchange and
+    reach the barrier; every phase, a carry, both alignments."""
+    prev = mr.set_philox_config(**cfg)
+    try:
+        for kind in KINDS:
+            for pos in (0, 1, 2, 3, CARRY_POSITIONS[0]):
+                for n in (1, 5, 63, 65, 257, 4097):
+                    for off in (0, 4 if mr.ELEM_BYTES[kind] == 4 else 8):
+                        e = mr.Engine(mr.PHILOX4X32_10, 31, 0)
+                        e.skip_ahead(pos)
+                        got, buf = gh.generate(e, kind, n, off)
+                        gh.assert_match(kind, got, gh.oracle_philox(31, pos, kind, n))
+                        assert gh.guards_intact(buf, off, n * mr.ELEM_BYTES[kind])
+    finally:
+        mr.set_philox_config(prev)
+
+
 AUTOTUNE_CANDIDATES = (
     [dict(walk=0, block=b, waves_per_cu=w, blocks_per_lane=1, nontemporal=nt)
      for b in (256, 512, 1024) for w in (64, 128, 256, 512, 1024) for nt in (0, 1)]
