@@ -392,16 +392,28 @@ __global__ __launch_bounds__(256) void batch_start_kernel(BatchArgs a)
 }
 
 // Slots [lo, hi) of request d in steps of 64 from s0 (see walk_slots_from).
+// The range (or mean / sd) step is chosen per segment, which is uniform
+// per request, so the loop holds no per-sample select.
+template <int KIND, int RANGED>
+__device__ __forceinline__ void run_phase(const BatchDesc &d, uint32_t s0, uint32_t lo,
+                                          uint32_t hi, uint32_t lane)
+{
+    switch (d.phase) {
+    case 0: walk_slots_from<KIND, 0, RANGED>(d.run, s0, lo, hi, lane); break;
+    case 1: walk_slots_from<KIND, 1, RANGED>(d.run, s0, lo, hi, lane); break;
+    case 2: walk_slots_from<KIND, 2, RANGED>(d.run, s0, lo, hi, lane); break;
+    default: walk_slots_from<KIND, 3, RANGED>(d.run, s0, lo, hi, lane); break;
+    }
+}
+
 template <int KIND>
 __device__ __forceinline__ void run_kind(const BatchDesc &d, uint32_t s0, uint32_t lo,
                                          uint32_t hi, uint32_t lane)
 {
-    switch (d.phase) {
-    case 0: walk_slots_from<KIND, 0>(d.run, s0, lo, hi, lane); break;
-    case 1: walk_slots_from<KIND, 1>(d.run, s0, lo, hi, lane); break;
-    case 2: walk_slots_from<KIND, 2>(d.run, s0, lo, hi, lane); break;
-    default: walk_slots_from<KIND, 3>(d.run, s0, lo, hi, lane); break;
-    }
+    if (has_range_step(KIND) && d.run.ep.ranged)
+        run_phase<KIND, 1>(d, s0, lo, hi, lane);
+    else
+        run_phase<KIND, 0>(d, s0, lo, hi, lane);
 }
 
 // WIDE: the batch holds Philox Gaussian FP64 or inverse-CDF Gaussian

@@ -202,9 +202,9 @@ template <int ESZ>
 __device__ __forceinline__ void put_elem(char *out, uint64_t e, const char *src)
 {
     if constexpr (ESZ == 4)
-        *(uint32_t *)(out + e * 4) = *(const uint32_t *)src;
+        *(g_u32 *)(out + e * 4) = *(const uint32_t *)src;
     else
-        *(uint64_t *)(out + e * 8) = *(const uint64_t *)src;
+        *(g_u64 *)(out + e * 8) = *(const uint64_t *)src;
 }
 
 // Writes one pass back to memory.  Row t of `lds` holds the L outputs of
@@ -245,9 +245,9 @@ __device__ void mrg_store_pass(const char *lds, uint64_t e0, uint64_t stride, ui
                 val = u32x4{x.x, x.y, y.x, y.y};
             }
             if (nt)
-                __builtin_nontemporal_store(val, (u32x4 *)dst);
+                __builtin_nontemporal_store(val, (g_u32x4 *)dst);
             else
-                *(u32x4 *)dst = val;
+                *(g_u32x4 *)dst = val;
         } else {
 #pragma unroll
             for (int k = 0; k < EPV; ++k) {

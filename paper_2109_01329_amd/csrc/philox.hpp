@@ -60,6 +60,7 @@ __device__ __forceinline__ u32x4 block_at(const uint32_t base[4], uint32_t k0, u
 
 // 16 bytes at a 4-byte-aligned address (one global_store_dwordx4 on gfx950).
 typedef uint32_t u32x4_a4 __attribute__((ext_vector_type(4), aligned(4)));
+typedef __attribute__((address_space(1))) u32x4_a4 g_u32x4_a4;
 
 // Whether the range (or mean / sd) step applies: RANGED 0 never, 1 always,
 // 2 as the epilogue says.  Kernels that know it per launch pass 0 or 1, so
@@ -152,8 +153,8 @@ __device__ __forceinline__ void put(char *p, u32x4 v, uint32_t u, uint32_t full_
     constexpr int EPV = 16 / elem_bytes(KIND);
     constexpr int ESZ = elem_bytes(KIND);
     if (u - full_lo < full_count) {
-        if (nt) __builtin_nontemporal_store(v, (u32x4_a4 *)p);
-        else *(u32x4_a4 *)p = v;
+        if (nt) __builtin_nontemporal_store(v, (g_u32x4_a4 *)p);
+        else *(g_u32x4_a4 *)p = v;
         return;
     }
 #pragma unroll
@@ -161,9 +162,9 @@ __device__ __forceinline__ void put(char *p, u32x4 v, uint32_t u, uint32_t full_
         const int64_t e = e0 + j;
         if (e >= 0 && e < (int64_t)n) {
             if constexpr (ESZ == 4) {
-                ((uint32_t *)p)[j] = v[j];
+                ((g_u32 *)p)[j] = v[j];
             } else {
-                ((uint64_t *)p)[j] = ((uint64_t)v[2 * j + 1] << 32) | v[2 * j];
+                ((g_u64 *)p)[j] = ((uint64_t)v[2 * j + 1] << 32) | v[2 * j];
             }
         }
     }

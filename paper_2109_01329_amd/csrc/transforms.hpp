@@ -16,6 +16,16 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 
+// Output stores go through global (address space 1) pointers.  Where an
+// output pointer reaches a kernel through a descriptor in memory, the
+// compiler cannot tell its address space and emits flat stores, which also
+// count against the scalar-load counter (so each descriptor load waits for
+// the stores in flight).  Every output is device-visible global memory
+// (device, pinned host or managed), never LDS or scratch.
+typedef __attribute__((address_space(1))) uint32_t g_u32;
+typedef __attribute__((address_space(1))) uint64_t g_u64;
+typedef __attribute__((address_space(1))) u32x4 g_u32x4;
+
 // (w >> 8) * 2^-24, exact.
 __device__ __forceinline__ float u01f(uint32_t w)
 {
