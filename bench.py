@@ -532,7 +532,8 @@ def main():
         order.append("valu probe fma_f32: 1048576 lanes x 256 iterations x 8 FMAs")
         stream.synchronize()
         print(json.dumps({"profile": "cells, two launches each (warm-up, measured)",
-                          "order": order, "config": mr.philox_config().as_dict()}), flush=True)
+                          "order": order,
+                          "config": mr.philox_config(mr.UNIFORM_F32).as_dict()}), flush=True)
         return
 
     if args.profile_batch:
@@ -572,7 +573,7 @@ def main():
                 out.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"profile": "philox uniform_f32 n=2^28 x5, then 1 GiB copy x3",
-                          "config": mr.philox_config().as_dict()}), flush=True)
+                          "config": mr.philox_config(mr.UNIFORM_F32).as_dict()}), flush=True)
         return
 
     # launch shape: the library's autotuner on this workload (outside the
@@ -622,8 +623,8 @@ def main():
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic_for(mr.philox_config().as_dict()),
-                "kernel": KERNEL_BY_WALK[mr.philox_config().walk] + "<uniform_f32>",
+                "traffic": traffic_for(mr.philox_config(mr.UNIFORM_F32).as_dict()),
+                "kernel": KERNEL_BY_WALK[mr.philox_config(mr.UNIFORM_F32).walk] + "<uniform_f32>",
                 "kernel_ms": {"avg": round(avg_ms, 4),
                               "bracketed_avg": round(b_avg, 4), "bracketed_median": round(b_med, 4),
                               "bracketed_p90": round(b_p90, 4)},
@@ -665,6 +666,11 @@ def main():
         big = torch.empty(n * 2, dtype=torch.float32, device=dev)   # 2 GiB
         for engine, kind, s, o in cells + synth.extra_draws():
             name = f"{synth.ENGINE_NAME[engine]}/{synth.KIND_NAME[kind]}"
+            if engine == mr.PHILOX4X32_10 and kind != mr.UNIFORM_F32:
+                # each Philox kind at its own tuned launch shape (uniform
+                # FP32 was tuned on the headline workload above)
+                mr.autotune_philox(kind, n, big, stream=stream, prewarm_ms=100, rounds=3,
+                                   reps=5)
 
             def gen(engine=engine, kind=kind, s=s, o=o):
                 mr.Engine(engine, s, o).generate(kind, n, big, stream=stream)
@@ -675,6 +681,8 @@ def main():
             res[name] = {"ms": round(ms, 4), "Gsamples_s": round(n / (ms * 1e-3) / 1e9, 1),
                          "GBs": round(nbytes / (ms * 1e-3) / 1e9, 1),
                          "hbm_frac": round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+            if engine == mr.PHILOX4X32_10:
+                res[name]["config"] = mr.philox_config(kind).as_dict()
         cfg = synth.SUBSTREAMS
         e = mr.Engine(mr.MRG32K3A, synth.substream_seed(), 0)
 
@@ -716,7 +724,7 @@ def main():
         "hbm_write_frac": round(n * 4 / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "roofline": roofline,
         "prewarm": prewarm,
-        "philox_config": mr.philox_config().as_dict(),
+        "philox_config": mr.philox_config(mr.UNIFORM_F32).as_dict(),
         "autotune": tuned,
     }
     line.update(extra)

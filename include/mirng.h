@@ -306,12 +306,25 @@ typedef struct {
     int32_t reserved;         /* must be 0 */
 } mirng_philox_config;
 
-/* Copy the current shape out.  c == NULL -> INVALID_ARG. */
+/* Copy the process-wide shape out.  c == NULL -> INVALID_ARG. */
 mirng_status mirng_philox_config_get(mirng_philox_config *c);
 
-/* Install a shape.  c == NULL or any field out of range -> INVALID_ARG and
- * the current shape is kept.  Host-only. */
+/* Install the process-wide shape and drop every kind's own shape (so every
+ * kind then uses this one).  c == NULL or any field out of range ->
+ * INVALID_ARG and nothing changes.  Host-only. */
 mirng_status mirng_philox_config_set(const mirng_philox_config *c);
+
+/* The shape that Philox generate calls of distribution `kind` use: the
+ * kind's own (installed by mirng_philox_config_set_kind or by the
+ * autotuner), else the process-wide one.  c == NULL -> INVALID_ARG; kind
+ * not a MIRNG_* distribution -> UNSUPPORTED. */
+mirng_status mirng_philox_config_get_kind(int32_t kind, mirng_philox_config *c);
+
+/* Give distribution `kind` its own shape (c != NULL), or drop it (c ==
+ * NULL: the kind follows the process-wide shape again).  Bad kind ->
+ * UNSUPPORTED; a field out of range -> INVALID_ARG and nothing changes.
+ * Same threading rule as the process-wide shape.  Host-only. */
+mirng_status mirng_philox_config_set_kind(int32_t kind, const mirng_philox_config *c);
 
 /* ---------------------------------------------------------------- serving */
 
@@ -396,10 +409,12 @@ mirng_status mirng_server_stats_get(mirng_server s, mirng_server_stats *out);
  * score is its median round.  It synchronises the stream (host-blocking).
  * The paper notes that the block size chosen for a kernel matters (256 vs
  * 1024 threads, Sec. 6) and that per-architecture tuning is future work
- * (Sec. 7).  Results: the chosen shape (also installed) and its time per
- * launch in milliseconds; either pointer may be NULL.  Errors: bad
- * arguments -> INVALID_ARG; device or launch failures -> DEVICE / LAUNCH
- * (the previous shape is then kept). */
+ * (Sec. 7).  Results: the chosen shape and its time per launch in
+ * milliseconds; either pointer may be NULL.  mirng_autotune_philox installs
+ * the shape as the shape of `kind` only (other kinds keep theirs);
+ * mirng_autotune_batch installs it on the batcher.  Errors: bad arguments
+ * -> INVALID_ARG; device or launch failures -> DEVICE / LAUNCH (the
+ * previous shape is then kept). */
 mirng_status mirng_autotune_philox(int32_t kind, uint64_t n, void *out, void *stream,
                                    int32_t prewarm_ms, int32_t rounds, int32_t reps,
                                    mirng_philox_config *best, float *best_ms);

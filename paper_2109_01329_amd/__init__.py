@@ -136,6 +136,10 @@ def lib() -> ctypes.CDLL:
         "mirng_status_string": ([ctypes.c_int], ctypes.c_char_p),
         "mirng_philox_config_get": ([ctypes.POINTER(PhiloxConfig)], ctypes.c_int),
         "mirng_philox_config_set": ([ctypes.POINTER(PhiloxConfig)], ctypes.c_int),
+        "mirng_philox_config_get_kind": ([ctypes.c_int32, ctypes.POINTER(PhiloxConfig)],
+                                         ctypes.c_int),
+        "mirng_philox_config_set_kind": ([ctypes.c_int32, ctypes.POINTER(PhiloxConfig)],
+                                         ctypes.c_int),
         "mirng_abi_version": ([], ctypes.c_int32),
         "mirng_batcher_create": ([ctypes.POINTER(vp)], ctypes.c_int),
         "mirng_batcher_destroy": ([vp], ctypes.c_int),
@@ -297,21 +301,38 @@ class Engine:
                "generate_streams")
 
 
-def philox_config() -> PhiloxConfig:
+def philox_config(kind: int | None = None) -> PhiloxConfig:
+    """The process-wide launch shape, or (with `kind`) the shape Philox
+    generate calls of that distribution use."""
     c = PhiloxConfig()
-    _check(lib().mirng_philox_config_get(ctypes.byref(c)), "philox_config_get")
+    if kind is None:
+        _check(lib().mirng_philox_config_get(ctypes.byref(c)), "philox_config_get")
+    else:
+        _check(lib().mirng_philox_config_get_kind(kind, ctypes.byref(c)),
+               "philox_config_get_kind")
     return c
 
 
-def set_philox_config(c: PhiloxConfig | None = None, **fields) -> PhiloxConfig:
+def set_philox_config(c: PhiloxConfig | None = None, kind: int | None = None,
+                      **fields) -> PhiloxConfig:
     """Install a launch shape (fields not given keep their current value);
-    returns the previous shape."""
-    prev = philox_config()
+    returns the previous one.  Without `kind` it is the process-wide shape
+    and every kind's own shape is dropped; with `kind`, that kind's own."""
+    prev = philox_config(kind)
     new = PhiloxConfig.from_buffer_copy(c if c is not None else prev)
     for k, v in fields.items():
         setattr(new, k, int(v))
-    _check(lib().mirng_philox_config_set(ctypes.byref(new)), "philox_config_set")
+    if kind is None:
+        _check(lib().mirng_philox_config_set(ctypes.byref(new)), "philox_config_set")
+    else:
+        _check(lib().mirng_philox_config_set_kind(kind, ctypes.byref(new)),
+               "philox_config_set_kind")
     return prev
+
+
+def clear_philox_config(kind: int) -> None:
+    """Drop `kind`'s own launch shape: it follows the process-wide one."""
+    _check(lib().mirng_philox_config_set_kind(kind, None), "philox_config_set_kind")
 
 
 class TuningCache:
@@ -351,14 +372,15 @@ def size_class(n: int) -> int:
 def autotune_philox(kind: int, n: int, out, stream=None, prewarm_ms: int = 300,
                     rounds: int = 5, reps: int = 10, cache: TuningCache | None = None):
     """Time the candidate Philox launch shapes on `n` outputs of `kind` into
-    `out` (overwritten), install the fastest and return (shape, ms).  With a
-    cache, a shape stored for the same architecture, kind and size class is
-    installed without timing, and a newly timed one is stored."""
+    `out` (overwritten), install the fastest as `kind`'s own shape and
+    return (shape, ms).  With a cache, a shape stored for the same
+    architecture, kind and size class is installed without timing, and a
+    newly timed one is stored."""
     key = f"{_arch()}/philox4x32_10/{kind}/{size_class(n)}" if cache is not None else None
     if key is not None and cache.get(key) is not None:
         hit = cache.get(key)
-        set_philox_config(**hit["config"])
-        return philox_config(), float(hit["ms"])
+        set_philox_config(kind=kind, **hit["config"])
+        return philox_config(kind), float(hit["ms"])
     c = PhiloxConfig()
     ms = ctypes.c_float()
     _check(lib().mirng_autotune_philox(kind, n, _ptr(out), _stream(stream), prewarm_ms, rounds,

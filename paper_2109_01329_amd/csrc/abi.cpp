@@ -29,6 +29,36 @@ mirng_philox_config &philox_config()
     return c;
 }
 
+namespace {
+// A kind's own launch shape, if one was installed (per kind or by the
+// autotuner); otherwise the kind follows the process-wide shape.
+struct KindShape {
+    bool set = false;
+    mirng_philox_config c{};
+};
+KindShape g_kind_shape[kIcdf64 + 1];
+}  // namespace
+
+bool philox_kind_ok(int kind) { return kind >= kBits && kind <= kIcdf64; }
+
+mirng_philox_config philox_config_for(int kind)
+{
+    if (philox_kind_ok(kind) && g_kind_shape[kind].set) return g_kind_shape[kind].c;
+    return philox_config();
+}
+
+void philox_config_set_kind(int kind, const mirng_philox_config *c)
+{
+    g_kind_shape[kind].set = c != nullptr;
+    if (c) g_kind_shape[kind].c = *c;
+}
+
+bool philox_config_kind_set(int kind, mirng_philox_config *c)
+{
+    if (g_kind_shape[kind].set && c) *c = g_kind_shape[kind].c;
+    return g_kind_shape[kind].set;
+}
+
 bool philox_config_valid(const mirng_philox_config &c)
 {
     const bool block_ok = c.block == 64 || c.block == 128 || c.block == 256 ||
@@ -105,8 +135,8 @@ Epilogue make_epilogue(const mirng_distribution *d, int nt)
 hipError_t philox_plain(const uint32_t key[2], Pos130 p, const mirng_distribution *d,
                         uint64_t n, char *out, hipStream_t s)
 {
-    const mirng_philox_config tu = philox_config();
     const int kind = d->kind;
+    const mirng_philox_config tu = philox_config_for(kind);
     const size_t esz = elem_size(kind);
     const uint32_t wpe = (uint32_t)philox_words_per_elem(kind);
     const Epilogue ep = make_epilogue(d, tu.nontemporal);
@@ -251,6 +281,23 @@ mirng_status mirng_philox_config_set(const mirng_philox_config *c)
 {
     if (!c || !philox_config_valid(*c)) return MIRNG_E_INVALID_ARG;
     philox_config() = *c;
+    for (int k = kBits; k <= kIcdf64; ++k) philox_config_set_kind(k, nullptr);
+    return MIRNG_OK;
+}
+
+mirng_status mirng_philox_config_get_kind(int32_t kind, mirng_philox_config *c)
+{
+    if (!c) return MIRNG_E_INVALID_ARG;
+    if (!philox_kind_ok(kind)) return MIRNG_E_UNSUPPORTED;
+    *c = philox_config_for(kind);
+    return MIRNG_OK;
+}
+
+mirng_status mirng_philox_config_set_kind(int32_t kind, const mirng_philox_config *c)
+{
+    if (!philox_kind_ok(kind)) return MIRNG_E_UNSUPPORTED;
+    if (c && !philox_config_valid(*c)) return MIRNG_E_INVALID_ARG;
+    philox_config_set_kind(kind, c);
     return MIRNG_OK;
 }
 

@@ -107,7 +107,8 @@ mirng_status mirng_autotune_philox(int32_t kind, uint64_t n, void *out, void *st
     for (int block : {128, 256, 512, 1024})
         for (int chunks : {1, 2})
             for (int nt : {0, 1}) cand.push_back({3, block, 1, chunks, nt, 0});
-    const mirng_philox_config prev = philox_config();
+    mirng_philox_config prev{};
+    const bool had_own = philox_config_kind_set(kind, &prev);
     mirng_engine e = nullptr;
     if (mirng_engine_create(MIRNG_PHILOX4X32_10, 0x5EED5EEDull, 1, &e) != MIRNG_OK)
         return MIRNG_E_ALLOC;
@@ -115,14 +116,15 @@ mirng_status mirng_autotune_philox(int32_t kind, uint64_t n, void *out, void *st
     const mirng_distribution d = {kind, 0, 0.0, kind == kI32 ? 2147483648.0 : 1.0};
     auto run = [&]() { return mirng_generate(e, &d, n, out, stream); };
     float ms = 0.0f;
-    const int k = tune(cand.size(), [&](size_t i) { philox_config() = cand[i]; }, run,
-                       (hipStream_t)stream, prewarm_ms, rounds, reps, &ms);
+    const int k = tune(cand.size(), [&](size_t i) { philox_config_set_kind(kind, &cand[i]); },
+                       run, (hipStream_t)stream, prewarm_ms, rounds, reps, &ms);
     mirng_engine_destroy(e);
     if (k < 0) {
-        philox_config() = prev;
+        philox_config_set_kind(kind, had_own ? &prev : nullptr);
         return MIRNG_E_LAUNCH;
     }
-    philox_config() = cand[k];
+    // installed for this kind only; other kinds keep their shapes
+    philox_config_set_kind(kind, &cand[k]);
     if (best) *best = cand[k];
     if (best_ms) *best_ms = ms;
     return MIRNG_OK;

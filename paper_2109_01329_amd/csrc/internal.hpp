@@ -261,8 +261,15 @@ hipError_t launch_philox_fill(const PhiloxFill &a, hipStream_t s);
 
 // Launch shape of the Philox fill kernel (process-wide, set through the
 // ABI or by the autotuner).
-mirng_philox_config &philox_config();
+mirng_philox_config &philox_config();   // the process-wide shape
 bool philox_config_valid(const mirng_philox_config &c);
+bool philox_kind_ok(int kind);
+// The shape generate calls of `kind` use: its own, else the process-wide one.
+mirng_philox_config philox_config_for(int kind);
+// Install (c != nullptr) or drop (c == nullptr) a kind's own shape; kind valid.
+void philox_config_set_kind(int kind, const mirng_philox_config *c);
+// Whether `kind` has its own shape (copied to *c if so and c != nullptr).
+bool philox_config_kind_set(int kind, mirng_philox_config *c);
 
 int device_cu_count();
 hipError_t ensure_device(int *dev);

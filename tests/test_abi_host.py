@@ -210,6 +210,36 @@ def test_philox_config_validation():
     assert mr.philox_config().as_dict() == c.as_dict()
 
 
+def test_per_kind_philox_config_validation():
+    """Per-kind shapes: unknown kinds are UNSUPPORTED, bad shapes INVALID_ARG
+    (nothing changes), NULL drops the kind's own shape, and the process-wide
+    set drops them all (no device needed)."""
+    import ctypes
+    L = mr.lib()
+    c = mr.philox_config()
+    out = mr.PhiloxConfig()
+    assert L.mirng_philox_config_get_kind(0, ctypes.byref(out)) == 2      # UNSUPPORTED
+    assert L.mirng_philox_config_get_kind(9, ctypes.byref(out)) == 2
+    assert L.mirng_philox_config_get_kind(mr.UNIFORM_F32, None) == 1      # INVALID_ARG
+    assert L.mirng_philox_config_set_kind(9, None) == 2
+    bad = mr.PhiloxConfig.from_buffer_copy(c)
+    bad.block = 100
+    assert L.mirng_philox_config_set_kind(mr.UNIFORM_F32, ctypes.byref(bad)) == 1
+    assert mr.philox_config(mr.UNIFORM_F32).as_dict() == c.as_dict()
+    try:
+        mr.set_philox_config(kind=mr.GAUSSIAN_F32, walk=0, block=512, waves_per_cu=64)
+        assert mr.philox_config(mr.GAUSSIAN_F32).block == 512
+        assert mr.philox_config().as_dict() == c.as_dict()
+        assert mr.philox_config(mr.UNIFORM_F32).as_dict() == c.as_dict()
+        mr.clear_philox_config(mr.GAUSSIAN_F32)
+        assert mr.philox_config(mr.GAUSSIAN_F32).as_dict() == c.as_dict()
+        mr.set_philox_config(kind=mr.BITS_U32, walk=2, waves_per_cu=1)
+        mr.set_philox_config(c)
+        assert mr.philox_config(mr.BITS_U32).as_dict() == c.as_dict()
+    finally:
+        mr.set_philox_config(c)
+
+
 def test_request_record_layout():
     import ctypes as ct
     dt = mr.request_dtype()

@@ -20,7 +20,10 @@ def test_autotune_philox_installs_a_valid_shape():
         cfg, ms = mr.autotune_philox(mr.UNIFORM_F32, n, buf, prewarm_ms=50, rounds=2, reps=3)
         torch.cuda.synchronize()
         assert ms > 0.0
-        assert mr.philox_config().as_dict() == cfg.as_dict()
+        # installed for the tuned kind only
+        assert mr.philox_config(mr.UNIFORM_F32).as_dict() == cfg.as_dict()
+        assert mr.philox_config().as_dict() == prev.as_dict()
+        assert mr.philox_config(mr.BITS_U32).as_dict() == prev.as_dict()
         e = mr.Engine(mr.PHILOX4X32_10, 0xFEEDFACE12345678, 12345)
         got, out = gh.generate(e, mr.UNIFORM_F32, n, 4)
         assert gh.guards_intact(out, 4, n * 4)
@@ -62,7 +65,34 @@ def test_autotune_cache_hit_installs_stored_shape(tmp_path):
         t0 = time.perf_counter()
         cfg2, ms2 = mr.autotune_philox(mr.UNIFORM_F32, n, buf, cache=mr.TuningCache(cache.path))
         assert time.perf_counter() - t0 < 0.2          # no timing loop ran
-        assert cfg2.as_dict() == cfg.as_dict() == mr.philox_config().as_dict()
+        assert cfg2.as_dict() == cfg.as_dict() == mr.philox_config(mr.UNIFORM_F32).as_dict()
         assert ms2 == ms
+    finally:
+        mr.set_philox_config(prev)
+
+
+def test_per_kind_shapes_apply_to_their_kind_only():
+    """A kind's own shape serves that kind; the others follow the
+    process-wide shape; both give the oracle's values; the process-wide set
+    drops every kind's own shape."""
+    prev = mr.philox_config()
+    try:
+        mr.set_philox_config(walk=3, block=256, waves_per_cu=1, blocks_per_lane=2, nontemporal=0)
+        mr.set_philox_config(kind=mr.UNIFORM_F32, walk=0, block=1024, waves_per_cu=256,
+                             blocks_per_lane=1, nontemporal=1)
+        assert mr.philox_config(mr.UNIFORM_F32).walk == 0
+        assert mr.philox_config(mr.GAUSSIAN_F32).walk == 3
+        n = 300007
+        for kind in (mr.UNIFORM_F32, mr.GAUSSIAN_F32, mr.UNIFORM_I32):
+            e = mr.Engine(mr.PHILOX4X32_10, 12, 0)
+            e.skip_ahead(2**40 + 1)
+            got, buf = gh.generate(e, kind, n, 4)
+            gh.assert_match(kind, got, gh.oracle_philox(12, 2**40 + 1, kind, n))
+            assert gh.guards_intact(buf, 4, n * 4)
+        mr.clear_philox_config(mr.UNIFORM_F32)
+        assert mr.philox_config(mr.UNIFORM_F32).walk == 3
+        mr.set_philox_config(kind=mr.BITS_U32, walk=2)
+        mr.set_philox_config(walk=3)
+        assert mr.philox_config(mr.BITS_U32).walk == 3
     finally:
         mr.set_philox_config(prev)
