@@ -1,6 +1,6 @@
 /*
  * mirng measurement kernels: the denominators against which the generation
- * kernels are judged on one MI355X.  Same conventions as mirng.h (device
+ * kernels are measured on one MI355X.  Same conventions as mirng.h (device
  * pointers, `void *` hipStream_t, status codes, asynchronous on the stream).
  *
  * The paper profiles per-kernel durations of its seeding, generation and
