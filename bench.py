@@ -45,6 +45,7 @@ TRAFFIC_BY_SHAPE = {
     (0, 256, 1024, 1, 1): 1073741824 + 89600,
     (0, 1024, 256, 1, 1): 1073741824 + 92416,
     (3, 256, 1, 2, 0): 1073741824 + 69632,
+    (3, 256, 1, 2, 1): 1073741824 + 69632,
 }
 
 # the kernel each walk of the plain Philox path launches
