@@ -5,7 +5,7 @@
 // uniform FP32 output (arXiv:2109.01329, Sec. 6).  Its separate range-
 // transform kernel (Sec. 4.3) is fused here into the store epilogue.
 //
-// Contiguous walk (philox_fill_kernel, the default).  The output is cut
+// Contiguous walk (philox_fill_kernel).  The output is cut
 // into 16-byte slots; each wave owns a contiguous run of slots and lane L
 // evaluates the Philox block of slot s0 + 64 i + L, so a wave writes 1 KiB
 // contiguously per step.  When the engine position is not a multiple of 4
@@ -19,6 +19,11 @@
 // wave writes only 1, 2 or 4 chunks of 64 slots (63 at odd phases, where
 // lane 63 just supplies its block's head to lane 62), evaluated together.
 // Many waves of 1-4 KiB keep the in-flight stores on one compact window.
+//
+// Group walk (philox_group_kernel, the default).  Aligned 64-slot chunks at
+// every phase: a workgroup's waves cover consecutive chunks, lane 63 of a
+// chunk takes the next chunk's head from LDS, and the group's last wave
+// evaluates the one block past the group (see group_chunks below).
 //
 // Grid-stride walk (philox_blocks_kernel, selectable).  Whenever outputs do
 // not straddle Philox blocks (bits and uniform FP32 at any position; FP64
