@@ -37,15 +37,19 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch of the headline kernel, per launch shape the counters
 # were taken on (walk, block, waves per CU, blocks per lane, streaming
 # stores): WRITE_SIZE 1048576 KiB x 1.0 + FETCH_SIZE (median of five
-# launches: 43.75 KiB, 45.125 KiB, 34.0 KiB) x 2.0, each scaled by what the same
+# launches: 43.75, 45.125, 37.5 or 34.0 KiB) x 2.0, each scaled by what the same
 # counter reads for a plain 1 GiB device copy (WRITE 1048576 KiB, FETCH
 # 524300 KiB).  Other shapes report no traffic; reset whenever the kernel's
 # code changes.
 TRAFFIC_BY_SHAPE = {
     (0, 256, 1024, 1, 1): 1073741824 + 89600,
     (0, 1024, 256, 1, 1): 1073741824 + 92416,
+    (3, 256, 1, 1, 0): 1073741824 + 76800,
+    (3, 256, 1, 1, 1): 1073741824 + 76800,
+    (3, 128, 1, 2, 0): 1073741824 + 69632,
     (3, 256, 1, 2, 0): 1073741824 + 69632,
     (3, 256, 1, 2, 1): 1073741824 + 69632,
+    (3, 512, 1, 2, 0): 1073741824 + 69632,
 }
 
 # the kernel each walk of the plain Philox path launches
