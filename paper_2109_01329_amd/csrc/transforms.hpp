@@ -38,27 +38,28 @@ __device__ __forceinline__ double u01d(uint32_t lo, uint32_t hi)
     return __builtin_fma((double)hi, 0x1p-32, (double)(lo >> 11) * 0x1p-53);
 }
 
-// 1/d for positive normal d: the hardware estimate refined by two Newton
-// steps (each squares the relative error; the result is within a few ulp).
+// 1/d for positive normal d: the hardware estimate refined by one Newton
+// step, which squares its relative error.  The gfx950 estimate (v_rcp_f64)
+// measured within 4.6e-8 (2^-24.4) relative over 2^22 arguments spanning
+// 2^-40 .. 2^40, and within 2.2e-15 (2^-48.7) after the step.
 __device__ __forceinline__ double recip_fast(double d)
 {
-    double r = __builtin_amdgcn_rcp(d);
-    double e = __builtin_fma(-d, r, 1.0);
-    r = __builtin_fma(r, e, r);
-    e = __builtin_fma(-d, r, 1.0);
+    const double r = __builtin_amdgcn_rcp(d);
+    const double e = __builtin_fma(-d, r, 1.0);
     return __builtin_fma(r, e, r);
 }
 
-// sqrt(x) for x in [0, 34] as x * (1 / sqrt(x)): the hardware reciprocal square
-// root of max(x, 2^-100) refined by two Newton steps, so x = 0 gives 0.
+// sqrt(x) for x in [0, 34] as x * (1 / sqrt(x)): the hardware reciprocal
+// square root of max(x, 2^-100) refined by one Newton step, so x = 0 gives
+// 0.  The gfx950 estimate (v_rsq_f64) measured within 5.2e-8 (2^-24.2)
+// relative over the same arguments, and within 4.1e-15 (2^-47.8) after the
+// step.
 __device__ __forceinline__ double sqrt_fast(double x)
 {
     const double xs = __builtin_fmax(x, 0x1p-100);
     const double h = 0.5 * xs;
     double y = __builtin_amdgcn_rsq(xs);
-    double e = __builtin_fma(-h * y, y, 0.5);
-    y = __builtin_fma(y, e, y);
-    e = __builtin_fma(-h * y, y, 0.5);
+    const double e = __builtin_fma(-h * y, y, 0.5);
     y = __builtin_fma(y, e, y);
     return x * y;
 }
