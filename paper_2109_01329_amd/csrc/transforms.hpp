@@ -64,9 +64,11 @@ __device__ __forceinline__ double sqrt_fast(double x)
     return x * y;
 }
 
-// ln x for positive normal x, to about 2^-34 relative error: x = 2^e m with
-// m in [sqrt(1/2), sqrt(2)), ln m = 2 atanh(s), s = (m - 1)/(m + 1),
-// |s| <= 0.1716, series to s^11, plus e ln 2.
+// ln x for positive normal x in (0, 1], to about 2^-29 relative error (the
+// budget of FP32 outputs): x = 2^e m with m in [sqrt(1/2), sqrt(2)),
+// ln m = 2 atanh(s), s = (m - 1)/(m + 1), |s| <= 0.1716, series to s^9
+// (the omitted terms stay below s^10 / 11 * 1.03 <= 2.1e-9 relative), plus
+// e ln 2 (for e != 0, |ln x| >= ln 2 - |ln m|, so nothing cancels).
 __device__ __forceinline__ double ln_fast(double x)
 {
     int e;
@@ -77,8 +79,7 @@ __device__ __forceinline__ double ln_fast(double x)
     const double f = m - 1.0;
     const double s = f * recip_fast(m + 1.0);
     const double s2 = s * s;
-    double q = 0x1.745d1745d1746p-4;               // 1/11
-    q = __builtin_fma(q, s2, 0x1.c71c71c71c71cp-4); // 1/9
+    double q = 0x1.c71c71c71c71cp-4;               // 1/9
     q = __builtin_fma(q, s2, 0x1.2492492492492p-3); // 1/7
     q = __builtin_fma(q, s2, 0x1.999999999999ap-3); // 1/5
     q = __builtin_fma(q, s2, 0x1.5555555555555p-2); // 1/3
@@ -88,8 +89,8 @@ __device__ __forceinline__ double ln_fast(double x)
 }
 
 // Box-Muller on one word pair.  The radius and the rotation are evaluated
-// in FP64 to about 2^-34 relative error and rounded once to FP32, so each
-// output is within 0.51 ulp of the exact transform of the same two inputs.
+// in FP64 to about 2^-28 relative error and rounded once to FP32, so each
+// output is within 0.56 ulp of the exact transform of the same two inputs.
 // The one division and the square root use refined hardware estimates
 // (recip_fast, sqrt_fast) instead of the IEEE sequences, whose exactness
 // this accuracy does not need.
@@ -97,7 +98,9 @@ __device__ __forceinline__ double ln_fast(double x)
 //          s = (m - 1)/(m + 1), |s| <= 0.1716, series to s^11.
 //   sin/cos(2 pi u2): 2 u2 = k 2^-23; j = nearest quarter turn; the exact
 //          remainder t = (k - j 2^22) 2^-23 in [-1/4, 1/4]; Taylor series of
-//          sin(pi t) to t^13 and cos(pi t) to t^14; rotate by j quarters.
+//          sin(pi t) through t^9 (the rest below (pi/4)^10 / 11! = 2.2e-9
+//          relative) and cos(pi t) through t^10 (below 1.6e-10); rotate by
+//          j quarters.
 __device__ __forceinline__ f32x2 box_muller(uint32_t wa, uint32_t wb)
 {
     const double u1 = (double)((wa >> 8) + 1u) * 0x1p-24;
@@ -108,15 +111,13 @@ __device__ __forceinline__ f32x2 box_muller(uint32_t wa, uint32_t wb)
     const int32_t ti = (int32_t)k - (int32_t)(j << 22);
     const double t = (double)ti * 0x1p-23;
     const double t2 = t * t;
-    double sp = -0x1.e3074fde8871fp-8;
-    sp = __builtin_fma(sp, t2, 0x1.50783487ee782p-4);
+    double sp = 0x1.50783487ee782p-4;
     sp = __builtin_fma(sp, t2, -0x1.32d2cce62bd86p-1);
     sp = __builtin_fma(sp, t2, 0x1.466bc6775aae2p+1);
     sp = __builtin_fma(sp, t2, -0x1.4abbce625be53p+2);
     sp = __builtin_fma(sp, t2, 0x1.921fb54442d18p+1);
     sp = sp * t;                                   // sin(pi t)
-    double cp = 0x1.f9d38a3763cc3p-10;
-    cp = __builtin_fma(cp, t2, -0x1.a6d1f2a204a8cp-6);
+    double cp = -0x1.a6d1f2a204a8cp-6;
     cp = __builtin_fma(cp, t2, 0x1.e1f506891babbp-3);
     cp = __builtin_fma(cp, t2, -0x1.55d3c7e3cbffap+0);
     cp = __builtin_fma(cp, t2, 0x1.03c1f081b5ac4p+2);
@@ -195,7 +196,8 @@ __device__ __forceinline__ double ppnd16_poly(int j, double x)
 // Phi^-1(u) by AS 241 (as normal_quantile below) for FP32 outputs: the
 // tail's logarithm, square root and both divisions use the refined
 // estimates above (ln_fast, sqrt_fast for -ln t <= 34, recip_fast), so z
-// carries about 1e-10 relative error before its one rounding to FP32.
+// carries about 2e-9 relative error (from the logarithm) before its one
+// rounding to FP32.
 __device__ __forceinline__ double normal_quantile_f32(double u)
 {
     const double q = u - 0.5;

@@ -144,7 +144,9 @@ def test_gaussian_error_distribution():
     got, _ = gh.generate(e, mr.GAUSSIAN_F32, n)
     want = gh.oracle_philox(2024, 0, mr.GAUSSIAN_F32, n)
     worst = gh.assert_match(mr.GAUSSIAN_F32, got, want)
-    # in tolerance units (2 ulp): the kernel rounds an FP64 value once
+    print(f"worst FP32 Gaussian error: {2.0 * worst:.4f} ulp")
+    # in tolerance units (2 ulp): the kernel rounds once an FP64 value within
+    # about 2^-28 relative of the transform (at most 0.56 ulp)
     assert worst <= 0.5 * 1.02
 
 
