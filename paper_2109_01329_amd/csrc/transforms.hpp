@@ -26,6 +26,11 @@ typedef __attribute__((address_space(1))) uint32_t g_u32;
 typedef __attribute__((address_space(1))) uint64_t g_u64;
 typedef __attribute__((address_space(1))) u32x4 g_u32x4;
 
+// Adding 1.5 * 2^52 to a double of magnitude below 2^51 rounds it to an
+// integer (to nearest, ties to even); subtracting it again gives that
+// integer, with two full-rate adds instead of a rounding instruction.
+constexpr double kRound2 = 0x1.8p52;
+
 // (w >> 8) * 2^-24, exact.
 __device__ __forceinline__ float u01f(uint32_t w)
 {
@@ -135,18 +140,94 @@ __device__ __forceinline__ f32x2 box_muller(uint32_t wa, uint32_t wb)
     return z;
 }
 
+// ln x for x in (0, 1] in FP64, to a few ulp: x = 2^e m with m in
+// [sqrt(1/2), sqrt(2)), f = m - 1 (exact), s = f / (m + 1) from the refined
+// reciprocal and one Newton step on the quotient, ln m = 2 atanh(s) =
+// 2 s + s^3 (2/3 + 2/5 s^2 + ... + 2/21 s^18) (|s| <= 0.1716: the omitted
+// terms stay below 2.4e-17 relative), plus e ln 2 with ln 2 split so that
+// e ln2_hi is exact (ln2_hi has 42 significant bits, |e| < 2^11).
+__device__ __forceinline__ double ln_f64(double x)
+{
+    int e;
+    double m = __builtin_frexp(x, &e);             // [0.5, 1)
+    const bool low = m < 0x1.6a09e667f3bcdp-1;     // sqrt(1/2)
+    m = low ? m * 2.0 : m;
+    e = low ? e - 1 : e;
+    const double f = m - 1.0;
+    const double d = m + 1.0;
+    const double r = recip_fast(d);
+    double s = f * r;
+    s = __builtin_fma(r, __builtin_fma(-s, d, f), s);
+    const double s2 = s * s;
+    double q = 0x1.8618618618618p-4;                 // 2/21
+    q = __builtin_fma(q, s2, 0x1.af286bca1af28p-4);  // 2/19
+    q = __builtin_fma(q, s2, 0x1.e1e1e1e1e1e1ep-4);  // 2/17
+    q = __builtin_fma(q, s2, 0x1.1111111111111p-3);  // 2/15
+    q = __builtin_fma(q, s2, 0x1.3b13b13b13b14p-3);  // 2/13
+    q = __builtin_fma(q, s2, 0x1.745d1745d1746p-3);  // 2/11
+    q = __builtin_fma(q, s2, 0x1.c71c71c71c71cp-3);  // 2/9
+    q = __builtin_fma(q, s2, 0x1.2492492492492p-2);  // 2/7
+    q = __builtin_fma(q, s2, 0x1.999999999999ap-2);  // 2/5
+    q = __builtin_fma(q, s2, 0x1.5555555555555p-1);  // 2/3
+    const double ln_m = __builtin_fma(s * s2, q, 2.0 * s);
+    const double de = (double)e;
+    return __builtin_fma(de, 0x1.62e42fefa3800p-1,
+                         __builtin_fma(de, 0x1.ef35793c76730p-45, ln_m));
+}
+
+// sqrt(x) for x in [0, 80] in FP64, to about one ulp: the refined
+// reciprocal square root y of max(x, 2^-200), then r = x y corrected once,
+// r + (y / 2)(x - r^2); x = 0 gives 0.
+__device__ __forceinline__ double sqrt_f64(double x)
+{
+    const double xs = __builtin_fmax(x, 0x1p-200);
+    const double h = 0.5 * xs;
+    double y = __builtin_amdgcn_rsq(xs);
+    y = __builtin_fma(y, __builtin_fma(-h * y, y, 0.5), y);
+    const double r = x * y;
+    return __builtin_fma(0.5 * y, __builtin_fma(-r, r, x), r);
+}
+
 // Box-Muller in FP64 on a pair of FP64 uniforms u1 in (0, 1], u2 in [0, 1):
-// r = sqrt(-2 ln u1), (z0, z1) = r (cos 2 pi u2, sin 2 pi u2), with the
-// device library's log, IEEE sqrt and sincospi (whose argument reduction is
-// exact, as 2 u2 is).  u1 = 1 gives +-0.
+// r = sqrt(-2 ln u1), (z0, z1) = r (cos 2 pi u2, sin 2 pi u2), each within a
+// few ulp.  The angle 2 pi u2 = pi x, x = 2 u2 in [0, 2], is reduced
+// exactly: j = nearest quarter turn (x rounded to a multiple of 1/2) and
+// t = x - j/2 in [-1/4, 1/4] (exact, by Sterbenz's lemma); sin(pi t) by
+// its Taylor series through t^15 (the rest below 5.9e-17 relative) and
+// cos(pi t) through t^16 (below 2.1e-18); then a rotation by j quarter
+// turns.  u1 = 1 gives +-0.
 __device__ __forceinline__ f64x2 box_muller64(double u1, double u2)
 {
-    const double r = __builtin_sqrt(-2.0 * log(u1));
-    double s, c;
-    sincospi(2.0 * u2, &s, &c);
+    const double r = sqrt_f64(-2.0 * ln_f64(u1));
+    const double x = 2.0 * u2;
+    const double jd = __builtin_fma(x, 2.0, kRound2) - kRound2;   // 0..4
+    const double t = __builtin_fma(jd, -0.5, x);
+    const double t2 = t * t;
+    double sp = -0x1.6fadb9f155744p-16;
+    sp = __builtin_fma(sp, t2, 0x1.e8f434d018d63p-12);
+    sp = __builtin_fma(sp, t2, -0x1.e3074fde8871fp-8);
+    sp = __builtin_fma(sp, t2, 0x1.50783487ee782p-4);
+    sp = __builtin_fma(sp, t2, -0x1.32d2cce62bd86p-1);
+    sp = __builtin_fma(sp, t2, 0x1.466bc6775aae2p+1);
+    sp = __builtin_fma(sp, t2, -0x1.4abbce625be53p+2);
+    sp = __builtin_fma(sp, t2, 0x1.921fb54442d18p+1);
+    sp = sp * t;                                   // sin(pi t)
+    double cp = 0x1.20c62c2f2d7f5p-18;
+    cp = __builtin_fma(cp, t2, -0x1.b6e24f44b128fp-14);
+    cp = __builtin_fma(cp, t2, 0x1.f9d38a3763cc3p-10);
+    cp = __builtin_fma(cp, t2, -0x1.a6d1f2a204a8cp-6);
+    cp = __builtin_fma(cp, t2, 0x1.e1f506891babbp-3);
+    cp = __builtin_fma(cp, t2, -0x1.55d3c7e3cbffap+0);
+    cp = __builtin_fma(cp, t2, 0x1.03c1f081b5ac4p+2);
+    cp = __builtin_fma(cp, t2, -0x1.3bd3cc9be45dep+2);
+    cp = __builtin_fma(cp, t2, 1.0);               // cos(pi t)
+    const uint32_t quad = (uint32_t)jd & 3u;
+    // quad 0: (cos, sin) = ( C,  S); 1: (-S,  C); 2: (-C, -S); 3: ( S, -C)
+    const double c_abs = (quad & 1u) ? sp : cp;
+    const double s_abs = (quad & 1u) ? cp : sp;
     f64x2 z;
-    z.x = r * c;
-    z.y = r * s;
+    z.x = r * ((quad == 1u || quad == 2u) ? -c_abs : c_abs);
+    z.y = r * ((quad >= 2u) ? -s_abs : s_abs);
     return z;
 }
 
