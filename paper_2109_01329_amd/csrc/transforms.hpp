@@ -175,6 +175,15 @@ __device__ __forceinline__ double ln_f64(double x)
                          __builtin_fma(de, 0x1.ef35793c76730p-45, ln_m));
 }
 
+// a / b in FP64 for positive normal b, to about one ulp: the refined
+// reciprocal, then one Newton step on the quotient.
+__device__ __forceinline__ double div_f64(double a, double b)
+{
+    const double r = recip_fast(b);
+    const double q = a * r;
+    return __builtin_fma(r, __builtin_fma(-q, b, a), q);
+}
+
 // sqrt(x) for x in [0, 80] in FP64, to about one ulp: the refined
 // reciprocal square root y of max(x, 2^-200), then r = x y corrected once,
 // r + (y / 2)(x - r^2); x = 0 gives 0.
@@ -305,23 +314,25 @@ __device__ __forceinline__ double normal_quantile_f32(double u)
 // r = 0.180625 - q^2.  Tails: r = sqrt(-ln min(u, 1 - u)), then
 // C(r - 1.6) / D(r - 1.6) for r <= 5 and E(r - 5) / F(r - 5) beyond, with
 // the sign of q.  (The device library's quantile is several times larger
-// and spills registers when inlined into the generation loops.)
+// and spills registers when inlined into the generation loops.)  The
+// logarithm, square root and divisions are the FP64 routines above (each
+// within about an ulp), so z is within a few ulp.
 __device__ __forceinline__ double normal_quantile(double u)
 {
     const double q = u - 0.5;
     if (__builtin_fabs(q) <= 0.425) {
         const double r = __builtin_fma(-q, q, 0.180625);
-        return q * ppnd16_poly(0, r) / ppnd16_poly(1, r);
+        return q * div_f64(ppnd16_poly(0, r), ppnd16_poly(1, r));
     }
-    const double t = q < 0.0 ? u : 1.0 - u;
-    double r = __builtin_sqrt(-log(t));
+    const double t = q < 0.0 ? u : 1.0 - u;   // exact; t <= 0.075
+    double r = sqrt_f64(-ln_f64(t));
     double z;
     if (r <= 5.0) {
         r -= 1.6;
-        z = ppnd16_poly(2, r) / ppnd16_poly(3, r);
+        z = div_f64(ppnd16_poly(2, r), ppnd16_poly(3, r));
     } else {
         r -= 5.0;
-        z = ppnd16_poly(4, r) / ppnd16_poly(5, r);
+        z = div_f64(ppnd16_poly(4, r), ppnd16_poly(5, r));
     }
     return q < 0.0 ? -z : z;
 }
