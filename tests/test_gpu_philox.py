@@ -137,6 +137,18 @@ def test_many_seeds_bits():
         gh.assert_match(mr.BITS_U32, got, gh.oracle_philox(seed, pos, mr.BITS_U32, n))
 
 
+@pytest.mark.parametrize("kind", [mr.GAUSSIAN_ICDF_F32, mr.GAUSSIAN_ICDF_F64])
+def test_icdf_error_distribution(kind):
+    """Worst error of 2^18 inverse-CDF Gaussians against the oracle's
+    quantile, in units of the tolerance (FP32: 2 ulp of the FP64 quantile;
+    FP64: 8 ulp64)."""
+    n = 1 << 18
+    e = mr.Engine(mr.PHILOX4X32_10, 2026, 0)
+    got, _ = gh.generate(e, kind, n)
+    worst = gh.assert_match(kind, got, gh.oracle_philox(2026, 0, kind, n))
+    print(f"worst inverse-CDF error (kind {kind}): {worst:.3f} of the tolerance")
+
+
 def test_gaussian_error_distribution():
     """Worst error of 2^22 Gaussians in ulp of the FP64 transform."""
     n = 1 << 22
