@@ -86,13 +86,18 @@ def parse():
                         "warm-up and one measured launch each, then the VALU-rate probe "
                         "(known instruction count) for calibration")
     p.add_argument("--profile-batch", action="store_true",
-                   help="for rocprofv3: the calorimeter batch (default launch shape), 25 "
-                        "batches in a row")
+                   help="for rocprofv3: the calorimeter batch, 25 batches in a row")
     p.add_argument("--profile-scenario", default=None,
                    choices=("single_electron", "ttbar", "single_electron_min200k",
                             "single_electron_soa"),
-                   help="for rocprofv3: one FastCaloSim-shaped scenario (default launch "
-                        "shape), 25 batches in a row, then 5 plain launches of the same total")
+                   help="for rocprofv3: one FastCaloSim-shaped scenario, 25 batches in a "
+                        "row, then 5 plain launches of the same total")
+    p.add_argument("--batch-shape", default=None,
+                   help="block,waves_per_cu,nontemporal: the batch launch shape of "
+                        "--profile-batch / --profile-scenario (default: the library's)")
+    p.add_argument("--profile-shapes", action="store_true",
+                   help="for rocprofv3 counters: the headline workload at every launch shape "
+                        "the autotuner can install, two launches each (warm-up, measured)")
     return p.parse_args()
 
 
@@ -322,12 +327,15 @@ def scenario_leg(mr, synth, torch, stream, dev):
     return res
 
 
-def serve_leg(mr, synth, torch, dev, cells=None, counts=(10000, 20000, 20000), streams=4,
-              capacity=32 * 10**9, ring_gib=64):
+def serve_leg(mr, synth, torch, dev, cells=None, counts=(10500, 20000, 20000), streams=4,
+              capacity=32 * 10**9, ring_gib=64, engines_per_type=512):
     """Serving loop under open-loop Poisson arrivals at 1e3, 1e4 and 1e5
-    requests/s (`counts` requests each): sizes floor(10^U(3, 8)), engine and
-    distribution uniform over the 2 x 4 mix, seeds uint64, offsets in
-    [0, 2^40).  Latency runs from each request's scheduled arrival to its
+    requests/s (`counts` requests each, at least 10 s of arrivals at 1e3/s):
+    sizes floor(10^U(3, 8)), engine type and distribution uniform over the
+    2 x 4 mix.  Engine states are resident on the device: each server holds
+    `engines_per_type` engines of each type (seeds uint64, offsets in
+    [0, 2^40)), and every request continues an engine of its type drawn
+    uniformly.  Latency runs from each request's scheduled arrival to its
     completion.  Outputs go to a ring of `ring_gib` GiB of device memory
     (placed in arrival order, 256-byte aligned).  Reports completed
     throughput (samples / span), p50/p99 latency overall and by size decade
@@ -361,8 +369,19 @@ def serve_leg(mr, synth, torch, dev, cells=None, counts=(10000, 20000, 20000), s
 
     def run(rate, count, k):
         tr, reqs = requests(rate, count, k)
-        srv = mr.Server(streams=streams, capacity_bytes=capacity, max_batch=65536)
-        tickets, sub = srv.replay(reqs, tr.arrival_s)
+        srv = mr.Server(streams=streams, capacity_bytes=capacity, max_batch=65536,
+                        max_engines=2 * engines_per_type)
+        g = np.random.default_rng(1329 + 500 + k)
+        pool = {}
+        for et in (mr.PHILOX4X32_10, mr.MRG32K3A):
+            seeds = g.integers(0, 2**64, engines_per_type, dtype=np.uint64)
+            offs = g.integers(0, 2**40, engines_per_type, dtype=np.uint64)
+            pool[et] = np.array([srv.engine_create(et, int(a), int(b))
+                                 for a, b in zip(seeds, offs)], dtype=np.uint32)
+        pick = g.integers(0, engines_per_type, count)
+        eng = np.where(tr.engine == mr.PHILOX4X32_10, pool[mr.PHILOX4X32_10][pick],
+                       pool[mr.MRG32K3A][pick]).astype(np.uint32)
+        tickets, sub = srv.replay(reqs, tr.arrival_s, engines=eng)
         srv.drain()
         lat = np.array([srv.wait(int(x))[1] for x in tickets])
         st = srv.stats()
@@ -403,7 +422,8 @@ def serve_leg(mr, synth, torch, dev, cells=None, counts=(10000, 20000, 20000), s
             row["served_over_plain"] = round(row["served_Gsamples_s"] / plain, 3)
         res[f"{int(rate)}_per_s"] = row
     del ring
-    return {"streams": streams, "capacity_GB": capacity / 1e9, "rates": res}
+    return {"streams": streams, "capacity_GB": capacity / 1e9,
+            "resident_engines": 2 * engines_per_type, "rates": res}
 
 
 def tts_leg(mr, torch, iters=100, decades=range(0, 9)):
@@ -461,7 +481,7 @@ def tts_leg(mr, torch, iters=100, decades=range(0, 9)):
     def tts(flow, n):
         flow(n)
         ts = []
-        for _ in range(iters if n < 10**7 else max(10, iters // 10)):
+        for _ in range(iters):
             t0 = time.perf_counter()
             flow(n)
             ts.append((time.perf_counter() - t0) * 1e3)
@@ -475,6 +495,7 @@ def tts_leg(mr, torch, iters=100, decades=range(0, 9)):
         return time_kernel_calls(lambda: e.generate(mr.UNIFORM_F32, n, buf, stream=s), 20, s)[1]
 
     rows = {}
+    eff = []
     for dcd in decades:
         n = 10 ** dcd
         ours, k = tts(flow_mirng, n)
@@ -484,8 +505,15 @@ def tts_leg(mr, torch, iters=100, decades=range(0, 9)):
             theirs, _ = tts(flow_vendor, n)
             row["tts_ms_rocrand"] = round(theirs, 4)
             row["rocrand_over_mirng"] = round(theirs / ours, 3)
+            eff.append(theirs / ours)
         rows[f"1e{dcd}"] = row
-    return rows
+    res = {"by_size": rows}
+    if eff:
+        # one efficiency for this platform: the harmonic mean over the sizes
+        # of e(n) = TTS_native / TTS_portable (above 1: this library faster),
+        # the form of the paper's performance-portability mean (eq. 1)
+        res["efficiency_harmonic_mean"] = round(len(eff) / sum(1.0 / e for e in eff), 3)
+    return res
 
 
 def main():
@@ -508,6 +536,7 @@ def main():
     head = [c for c in cells if c[0] == mr.PHILOX4X32_10 and c[1] == mr.UNIFORM_F32][0]
     _, _, seed, offset = head
     out = torch.empty(n, dtype=torch.float32, device=dev)
+    phase = mr.philox_phase(mr.UNIFORM_F32, offset, out)
 
     def step():
         e = mr.Engine(mr.PHILOX4X32_10, seed, offset)
@@ -538,12 +567,33 @@ def main():
         stream.synchronize()
         print(json.dumps({"profile": "cells, two launches each (warm-up, measured)",
                           "order": order,
-                          "config": mr.philox_config(mr.UNIFORM_F32).as_dict()}), flush=True)
+                          "config": mr.philox_config(mr.UNIFORM_F32, phase).as_dict()}),
+              flush=True)
+        return
+
+    def batcher():
+        b = mr.Batcher()
+        if args.batch_shape:
+            blk, wpc, nt = (int(x) for x in args.batch_shape.split(","))
+            b.set_config(block=blk, waves_per_cu=wpc, nontemporal=nt)
+        return b
+
+    if args.profile_shapes:
+        order = []
+        for c in mr.philox_candidates():
+            mr.set_philox_config(kind=mr.UNIFORM_F32, phase=phase, **c.as_dict())
+            for _ in range(2):
+                step()
+            order.append(c.as_dict())
+        stream.synchronize()
+        print(json.dumps({"profile": "headline workload at every autotuner shape, two launches "
+                                     "each (warm-up, measured)", "phase": phase,
+                          "order": order}), flush=True)
         return
 
     if args.profile_batch:
         _, reqs, _, total = calo_requests(mr, synth, torch, dev)
-        b = mr.Batcher()
+        b = batcher()
         for _ in range(25):
             b.generate(reqs, stream=stream)
         stream.synchronize()
@@ -555,7 +605,7 @@ def main():
         import numpy as np
         sc = synth.calo_scenario(args.profile_scenario)
         reqs, out, total = scenario_requests(mr, sc, torch, dev)
-        b = mr.Batcher()
+        b = batcher()
         for _ in range(25):
             b.generate(reqs, stream=stream)
         e = mr.Engine(mr.PHILOX4X32_10, 42, 0)
@@ -578,7 +628,9 @@ def main():
                 out.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"profile": "philox uniform_f32 n=2^28 x5, then 1 GiB copy x3",
-                          "config": mr.philox_config(mr.UNIFORM_F32).as_dict()}), flush=True)
+                          "phase": phase,
+                          "config": mr.philox_config(mr.UNIFORM_F32, phase).as_dict()}),
+              flush=True)
         return
 
     # launch shape: the library's autotuner on this workload (outside the
@@ -587,7 +639,7 @@ def main():
     if not args.shape and not args.no_tune:
         t_tune = time.perf_counter()
         cfg, tms = mr.autotune_philox(mr.UNIFORM_F32, n, out, stream=stream, prewarm_ms=300,
-                                      rounds=3, reps=30)
+                                      rounds=3, reps=30, offset=offset)
         tuned = {"config": cfg.as_dict(), "ms": round(tms, 4),
                  "tuning_s": round(time.perf_counter() - t_tune, 3)}
 
@@ -628,8 +680,9 @@ def main():
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic_for(mr.philox_config(mr.UNIFORM_F32).as_dict()),
-                "kernel": KERNEL_BY_WALK[mr.philox_config(mr.UNIFORM_F32).walk] + "<uniform_f32>",
+                "traffic": traffic_for(mr.philox_config(mr.UNIFORM_F32, phase).as_dict()),
+                "kernel": (KERNEL_BY_WALK[mr.philox_config(mr.UNIFORM_F32, phase).walk]
+                           + "<uniform_f32>"),
                 "kernel_ms": {"avg": round(avg_ms, 4),
                               "bracketed_avg": round(b_avg, 4), "bracketed_median": round(b_med, 4),
                               "bracketed_p90": round(b_p90, 4)},
@@ -675,7 +728,7 @@ def main():
                 # each Philox kind at its own tuned launch shape (uniform
                 # FP32 was tuned on the headline workload above)
                 mr.autotune_philox(kind, n, big, stream=stream, prewarm_ms=100, rounds=3,
-                                   reps=5)
+                                   reps=5, offset=o)
 
             def gen(engine=engine, kind=kind, s=s, o=o):
                 mr.Engine(engine, s, o).generate(kind, n, big, stream=stream)
@@ -687,7 +740,9 @@ def main():
                          "GBs": round(nbytes / (ms * 1e-3) / 1e9, 1),
                          "hbm_frac": round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
             if engine == mr.PHILOX4X32_10:
-                res[name]["config"] = mr.philox_config(kind).as_dict()
+                ph = mr.philox_phase(kind, o, big)
+                res[name]["phase"] = ph
+                res[name]["config"] = mr.philox_config(kind, ph).as_dict()
         cfg = synth.SUBSTREAMS
         e = mr.Engine(mr.MRG32K3A, synth.substream_seed(), 0)
 
@@ -724,12 +779,13 @@ def main():
         "data": "synthetic",
         "config": {"workload": "philox4x32_10 uniform_f32 n=2^28, seed/offset from the bulk "
                                "draw (offset uniform in [0, 2^40))",
-                   "n": n, "seed": seed, "offset": offset, "parallelism": "single GPU"},
+                   "n": n, "seed": seed, "offset": offset, "phase": phase,
+                   "parallelism": "single GPU"},
         "write_GBs": round(n * 4 / (ms_per_step * 1e-3) / 1e9, 1),
         "hbm_write_frac": round(n * 4 / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "roofline": roofline,
         "prewarm": prewarm,
-        "philox_config": mr.philox_config(mr.UNIFORM_F32).as_dict(),
+        "philox_config": mr.philox_config(mr.UNIFORM_F32, phase).as_dict(),
         "autotune": tuned,
     }
     line.update(extra)

@@ -68,7 +68,7 @@
 extern "C" {
 #endif
 
-#define MIRNG_ABI_VERSION 1
+#define MIRNG_ABI_VERSION 2
 
 typedef struct mirng_engine_s *mirng_engine;
 
@@ -136,6 +136,18 @@ typedef struct {
     void *out;         /* device pointer, aligned to the output element */
 } mirng_request;
 
+/* ------------------------------------------------------------ device set-up */
+
+/* Set up the current device for the library: check that it is a gfx950 GPU
+ * and copy the library's resident MRG32k3a jump tables (about 310 KB, a
+ * file-scope device array) to it with a host-synchronous copy.  Optional:
+ * the first call of any entry point that uses a device does the same, once
+ * per device; calling this first keeps that one-time copy out of later
+ * calls, which then never synchronise the host or allocate device memory
+ * for the tables.  Not a gfx950 device -> DEVICE; copy failure -> DEVICE
+ * (retried on the next call). */
+mirng_status mirng_device_init(void);
+
 /* ---------------------------------------------------------------- engines */
 
 /* Create an engine of `type` at position `offset` (engine words for Philox,
@@ -185,7 +197,10 @@ mirng_status mirng_engine_set_state(mirng_engine e, const mirng_state *s);
  * Gaussian stddev <= 0 or non-finite; reserved != 0) -> INVALID_ARG;
  * unknown kind -> UNSUPPORTED; no usable device -> DEVICE.
  * A failed kernel launch returns LAUNCH; the engine has then already been
- * advanced, as the work was accepted for enqueue. */
+ * advanced, as the work was accepted for enqueue.  The first call on a
+ * device that has not been set up does the one-time set-up of
+ * mirng_device_init (a host-synchronous copy); no other host
+ * synchronisation or allocation happens here. */
 mirng_status mirng_generate(mirng_engine e, const mirng_distribution *d,
                             uint64_t n, void *out, void *stream);
 
@@ -314,17 +329,31 @@ mirng_status mirng_philox_config_get(mirng_philox_config *c);
  * INVALID_ARG and nothing changes.  Host-only. */
 mirng_status mirng_philox_config_set(const mirng_philox_config *c);
 
-/* The shape that Philox generate calls of distribution `kind` use: the
- * kind's own (installed by mirng_philox_config_set_kind or by the
- * autotuner), else the process-wide one.  c == NULL -> INVALID_ARG; kind
- * not a MIRNG_* distribution -> UNSUPPORTED. */
-mirng_status mirng_philox_config_get_kind(int32_t kind, mirng_philox_config *c);
+/* Phase of a Philox launch: the engine word position of the launch's first
+ * 16-byte output slot, modulo 4.  It follows from the position and the
+ * output address: (position - head * words per element) mod 4, where head
+ * is the number of elements between the previous 16-byte boundary and
+ * `out` (0 for two-element Gaussian pairs that would straddle that grid).
+ * Phase 0 needs no exchange of words between lanes; the other phases do, so
+ * the fastest launch shape can differ between them.  Returns the phase of
+ * a launch of `kind` at word position `position` (only its value mod 4
+ * matters) into `out`; 0 for an unknown kind.  Host-only. */
+uint32_t mirng_philox_phase(int32_t kind, uint64_t position, const void *out);
 
-/* Give distribution `kind` its own shape (c != NULL), or drop it (c ==
- * NULL: the kind follows the process-wide shape again).  Bad kind ->
- * UNSUPPORTED; a field out of range -> INVALID_ARG and nothing changes.
- * Same threading rule as the process-wide shape.  Host-only. */
-mirng_status mirng_philox_config_set_kind(int32_t kind, const mirng_philox_config *c);
+/* The shape that Philox generate calls of distribution `kind` use at phase
+ * `phase` (0..3): the kind's own shape at that phase (installed by
+ * mirng_philox_config_set_kind or by the autotuner), else the process-wide
+ * one.  c == NULL or phase out of range -> INVALID_ARG; kind not a MIRNG_*
+ * distribution -> UNSUPPORTED. */
+mirng_status mirng_philox_config_get_kind(int32_t kind, int32_t phase, mirng_philox_config *c);
+
+/* Give distribution `kind` its own shape at phase `phase` (0..3), or at all
+ * four phases (phase = -1); c == NULL drops it (the kind then follows the
+ * process-wide shape there).  Bad kind -> UNSUPPORTED; phase out of range
+ * or a field out of range -> INVALID_ARG and nothing changes.  Same
+ * threading rule as the process-wide shape.  Host-only. */
+mirng_status mirng_philox_config_set_kind(int32_t kind, int32_t phase,
+                                          const mirng_philox_config *c);
 
 /* ---------------------------------------------------------------- serving */
 
@@ -344,13 +373,31 @@ mirng_status mirng_philox_config_set_kind(int32_t kind, const mirng_philox_confi
  * output memory and must keep it valid until the request completes.
  * Tickets (about 64 bytes of host memory each) are kept for the server's
  * lifetime, so that any ticket can be polled and the statistics cover
- * every request. */
+ * every request.  Each stream's batch completes (and frees its stream and
+ * its admitted bytes) as soon as it is done, independently of the others.
+ *
+ * Resident engines: a server holds a table of engine states in device
+ * memory (max_engines entries, 56 bytes each), following the paper's
+ * native flow "create a generator -> set seed and offset -> generate"
+ * (Sec. 4.2) with the generator kept on the device.  A request submitted
+ * with mirng_server_submit_engine continues its engine where the requests
+ * admitted before it on that engine stopped: its start position is fixed
+ * at admission, in arrival order (any 192-bit count of words or steps past
+ * the table entry), and the planning kernel derives its start state on the
+ * device from the resident entry.  So a sequence of requests served on one
+ * engine gives the same values as the same sequence of mirng_generate
+ * calls on one engine, whatever the batching, and positions are not
+ * limited to 64-bit offsets (MRG32k3a substreams and streams, Philox
+ * positions up to 2^130).  Requests on resident engines are validated at
+ * submission, so their consumption is final when they are accepted (a
+ * request whose batch then fails to launch has still consumed its words,
+ * as with mirng_generate).  Engines live as long as the server. */
 
 typedef struct mirng_server_s *mirng_server;
 
 typedef struct {
     int32_t streams;            /* S: batches in flight at once, 1..8 */
-    int32_t reserved;           /* must be 0 */
+    int32_t max_engines;        /* resident engine table entries, 0 .. 2^24; 0 selects 65536 */
     uint64_t capacity_bytes;    /* in-flight output bytes, >= 1 */
     uint64_t max_batch;         /* requests per batch, 1 .. 2^24 */
 } mirng_server_config;
@@ -383,6 +430,52 @@ mirng_status mirng_server_destroy(mirng_server s);
  * ticket); NULL arguments -> INVALID_ARG. */
 mirng_status mirng_server_submit(mirng_server s, const mirng_request *req, uint64_t *ticket);
 
+/* Create a resident engine of `type` at position `offset` from the seed
+ * state of `seed` (as mirng_engine_create) in the next free entry of the
+ * server's device table; *engine names it.  The entry is written with a
+ * host-synchronous copy before the call returns.  Table full -> CAPACITY;
+ * unknown type -> UNSUPPORTED; NULL arguments -> INVALID_ARG; copy failure
+ * -> DEVICE. */
+mirng_status mirng_server_engine_create(mirng_server s, int32_t type, uint64_t seed,
+                                        uint64_t offset, uint32_t *engine);
+
+/* Queue n outputs of distribution d into `out` (device memory, element
+ * aligned, kept valid until the request completes) on resident engine
+ * `engine`, continuing it: the request starts where the requests admitted
+ * on this engine before it (and its skips) end, and the engine advances by
+ * the words (Philox) or steps (MRG32k3a) the request consumes, as
+ * mirng_generate on an engine does.  Validation at submission, engine
+ * unchanged on error: unknown engine, NULL d or ticket, bad parameters,
+ * NULL or misaligned out with n > 0 -> INVALID_ARG; unknown kind ->
+ * UNSUPPORTED; n >= 2^32, or the output alone larger than the capacity ->
+ * CAPACITY. */
+mirng_status mirng_server_submit_engine(mirng_server s, uint32_t engine,
+                                        const mirng_distribution *d, uint64_t n, void *out,
+                                        uint64_t *ticket);
+
+/* Advance resident engine `engine` by n = sum limbs[i] 2^(64 i) words or
+ * steps (nlimbs <= 3), in arrival order with its requests: requests
+ * submitted after this call start past the skip.  The count is kept modulo
+ * 2^192 (Philox positions modulo 2^130).  Unknown engine, nlimbs > 3 or
+ * limbs NULL with nlimbs > 0 -> INVALID_ARG. */
+mirng_status mirng_server_engine_skip_ahead(mirng_server s, uint32_t engine,
+                                            const uint64_t *limbs, size_t nlimbs);
+
+/* The state of resident engine `engine` after every request and skip
+ * submitted on it so far (in the mirng_state layout; for MRG32k3a, pos
+ * counts steps since the seed state).  Host-only: the table entry plus the
+ * admitted consumption.  Unknown engine or NULL out -> INVALID_ARG. */
+mirng_status mirng_server_engine_get_state(mirng_server s, uint32_t engine, mirng_state *out);
+
+/* Replace resident engine `engine`'s state (checkpoint / resume): waits
+ * until every accepted request has completed, then rewrites the table
+ * entry (host-synchronous) and restarts the engine's count there.  No
+ * request may be submitted on this engine while the call runs.  The
+ * state's type must equal the engine's and be valid as for
+ * mirng_engine_set_state, else INVALID_ARG and nothing changes. */
+mirng_status mirng_server_engine_set_state(mirng_server s, uint32_t engine,
+                                           const mirng_state *st);
+
 /* Non-blocking: *done = 1 and *status = the request's status once it has
  * completed, else *done = 0.  Unknown ticket -> INVALID_ARG. */
 mirng_status mirng_server_poll(mirng_server s, uint64_t ticket, int32_t *done, int32_t *status);
@@ -410,14 +503,22 @@ mirng_status mirng_server_stats_get(mirng_server s, mirng_server_stats *out);
  * The paper notes that the block size chosen for a kernel matters (256 vs
  * 1024 threads, Sec. 6) and that per-architecture tuning is future work
  * (Sec. 7).  Results: the chosen shape and its time per launch in
- * milliseconds; either pointer may be NULL.  mirng_autotune_philox installs
- * the shape as the shape of `kind` only (other kinds keep theirs);
+ * milliseconds; either pointer may be NULL.  mirng_autotune_philox times
+ * n outputs of `kind` into `out` from an engine at word position `offset`
+ * (every launch restarts there) and installs the shape as the shape of
+ * `kind` at the phase that position and `out` give (mirng_philox_phase;
+ * other kinds and phases keep theirs);
  * mirng_autotune_batch installs it on the batcher.  Errors: bad arguments
  * -> INVALID_ARG; device or launch failures -> DEVICE / LAUNCH (the
  * previous shape is then kept). */
-mirng_status mirng_autotune_philox(int32_t kind, uint64_t n, void *out, void *stream,
-                                   int32_t prewarm_ms, int32_t rounds, int32_t reps,
-                                   mirng_philox_config *best, float *best_ms);
+mirng_status mirng_autotune_philox(int32_t kind, uint64_t offset, uint64_t n, void *out,
+                                   void *stream, int32_t prewarm_ms, int32_t rounds,
+                                   int32_t reps, mirng_philox_config *best, float *best_ms);
+
+/* The Philox launch shapes mirng_autotune_philox times, in its order: the
+ * first min(max, total) are copied to out (out may be NULL); returns the
+ * total.  Host-only. */
+int32_t mirng_philox_candidates(mirng_philox_config *out, int32_t max);
 
 mirng_status mirng_autotune_batch(mirng_batcher b, const mirng_request *reqs, size_t count,
                                   void *stream, int32_t prewarm_ms, int32_t rounds,

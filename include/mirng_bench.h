@@ -49,15 +49,19 @@ mirng_status mirng_bench_valu(int32_t op, uint32_t threads, uint32_t iters,
 /* Open-loop load generator for the serving loop: submits reqs[i] to `s` at
  * arrival_s[i] seconds after the call starts (non-decreasing times; the
  * caller's thread sleeps until each one, spinning for the last 50 us),
- * storing each submission's status and ticket.  Latencies of these
+ * storing each submission's status and ticket.  With `engines` not NULL,
+ * request i goes to resident engine engines[i] (mirng_server_submit_engine
+ * with reqs[i]'s distribution, n and out; its engine type, seed and offset
+ * are ignored); otherwise it is submitted as it is.  Latencies of these
  * requests count from their scheduled arrival, not from the (possibly
  * later) submission, so a generator that falls behind does not hide
  * queueing delay.  Returns once the last request has been submitted;
  * completion is left to mirng_server_wait / mirng_server_drain.  NULL
  * arguments -> INVALID_ARG. */
 mirng_status mirng_bench_server_replay(mirng_server s, const mirng_request *reqs,
-                                       const double *arrival_s, size_t count,
-                                       uint64_t *tickets, int32_t *submit_status);
+                                       const uint32_t *engines, const double *arrival_s,
+                                       size_t count, uint64_t *tickets,
+                                       int32_t *submit_status);
 
 #ifdef __cplusplus
 }

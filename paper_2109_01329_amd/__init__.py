@@ -69,7 +69,7 @@ class BatchConfig(ctypes.Structure):
 
 
 class ServerConfig(ctypes.Structure):
-    _fields_ = [("streams", ctypes.c_int32), ("reserved", ctypes.c_int32),
+    _fields_ = [("streams", ctypes.c_int32), ("max_engines", ctypes.c_int32),
                 ("capacity_bytes", ctypes.c_uint64), ("max_batch", ctypes.c_uint64)]
 
 
@@ -136,11 +136,15 @@ def lib() -> ctypes.CDLL:
         "mirng_status_string": ([ctypes.c_int], ctypes.c_char_p),
         "mirng_philox_config_get": ([ctypes.POINTER(PhiloxConfig)], ctypes.c_int),
         "mirng_philox_config_set": ([ctypes.POINTER(PhiloxConfig)], ctypes.c_int),
-        "mirng_philox_config_get_kind": ([ctypes.c_int32, ctypes.POINTER(PhiloxConfig)],
-                                         ctypes.c_int),
-        "mirng_philox_config_set_kind": ([ctypes.c_int32, ctypes.POINTER(PhiloxConfig)],
-                                         ctypes.c_int),
+        "mirng_philox_config_get_kind": ([ctypes.c_int32, ctypes.c_int32,
+                                          ctypes.POINTER(PhiloxConfig)], ctypes.c_int),
+        "mirng_philox_config_set_kind": ([ctypes.c_int32, ctypes.c_int32,
+                                          ctypes.POINTER(PhiloxConfig)], ctypes.c_int),
+        "mirng_philox_phase": ([ctypes.c_int32, u64, vp], ctypes.c_uint32),
+        "mirng_philox_candidates": ([ctypes.POINTER(PhiloxConfig), ctypes.c_int32],
+                                    ctypes.c_int32),
         "mirng_abi_version": ([], ctypes.c_int32),
+        "mirng_device_init": ([], ctypes.c_int),
         "mirng_batcher_create": ([ctypes.POINTER(vp)], ctypes.c_int),
         "mirng_batcher_destroy": ([vp], ctypes.c_int),
         "mirng_batcher_stage": ([vp, ctypes.c_size_t, ctypes.POINTER(vp)], ctypes.c_int),
@@ -158,9 +162,19 @@ def lib() -> ctypes.CDLL:
                                ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
         "mirng_server_drain": ([vp], ctypes.c_int),
         "mirng_server_stats_get": ([vp, ctypes.POINTER(ServerStats)], ctypes.c_int),
-        "mirng_bench_server_replay": ([vp, vp, vp, ctypes.c_size_t, vp, vp], ctypes.c_int),
-        "mirng_autotune_philox": ([ctypes.c_int32, u64, vp, vp, ctypes.c_int32, ctypes.c_int32,
-                                   ctypes.c_int32, ctypes.POINTER(PhiloxConfig),
+        "mirng_bench_server_replay": ([vp, vp, vp, vp, ctypes.c_size_t, vp, vp], ctypes.c_int),
+        "mirng_server_engine_create": ([vp, ctypes.c_int32, u64, u64,
+                                        ctypes.POINTER(ctypes.c_uint32)], ctypes.c_int),
+        "mirng_server_submit_engine": ([vp, ctypes.c_uint32, ctypes.POINTER(Distribution), u64,
+                                        vp, ctypes.POINTER(u64)], ctypes.c_int),
+        "mirng_server_engine_skip_ahead": ([vp, ctypes.c_uint32, ctypes.POINTER(u64),
+                                            ctypes.c_size_t], ctypes.c_int),
+        "mirng_server_engine_get_state": ([vp, ctypes.c_uint32, ctypes.POINTER(State)],
+                                          ctypes.c_int),
+        "mirng_server_engine_set_state": ([vp, ctypes.c_uint32, ctypes.POINTER(State)],
+                                          ctypes.c_int),
+        "mirng_autotune_philox": ([ctypes.c_int32, u64, u64, vp, vp, ctypes.c_int32,
+                                   ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(PhiloxConfig),
                                    ctypes.POINTER(ctypes.c_float)], ctypes.c_int),
         "mirng_autotune_batch": ([vp, vp, ctypes.c_size_t, vp, ctypes.c_int32, ctypes.c_int32,
                                   ctypes.c_int32, ctypes.POINTER(BatchConfig),
@@ -207,6 +221,11 @@ def _stream(stream) -> int:
     if stream is None:
         stream = torch.cuda.current_stream()
     return int(stream.cuda_stream)
+
+
+def device_init() -> None:
+    """Set up the current device (resident tables) ahead of the first call."""
+    _check(lib().mirng_device_init(), "device_init")
 
 
 def words_consumed(engine_type: int, kind: int, n: int) -> int:
@@ -301,38 +320,54 @@ class Engine:
                "generate_streams")
 
 
-def philox_config(kind: int | None = None) -> PhiloxConfig:
+def philox_phase(kind: int, position: int, out) -> int:
+    """Phase (0..3) of a Philox launch of `kind` at word `position` into
+    `out`: the position of its first 16-byte slot modulo 4."""
+    return int(lib().mirng_philox_phase(kind, position % 2**64, _ptr(out)))
+
+
+def philox_config(kind: int | None = None, phase: int = 1) -> PhiloxConfig:
     """The process-wide launch shape, or (with `kind`) the shape Philox
-    generate calls of that distribution use."""
+    generate calls of that distribution use at `phase`."""
     c = PhiloxConfig()
     if kind is None:
         _check(lib().mirng_philox_config_get(ctypes.byref(c)), "philox_config_get")
     else:
-        _check(lib().mirng_philox_config_get_kind(kind, ctypes.byref(c)),
+        _check(lib().mirng_philox_config_get_kind(kind, phase, ctypes.byref(c)),
                "philox_config_get_kind")
     return c
 
 
 def set_philox_config(c: PhiloxConfig | None = None, kind: int | None = None,
-                      **fields) -> PhiloxConfig:
+                      phase: int = -1, **fields) -> PhiloxConfig:
     """Install a launch shape (fields not given keep their current value);
     returns the previous one.  Without `kind` it is the process-wide shape
-    and every kind's own shape is dropped; with `kind`, that kind's own."""
-    prev = philox_config(kind)
+    and every kind's own shape is dropped; with `kind`, that kind's own at
+    `phase` (0..3) or at every phase (-1)."""
+    prev = philox_config(kind, phase if phase >= 0 else 1)
     new = PhiloxConfig.from_buffer_copy(c if c is not None else prev)
     for k, v in fields.items():
         setattr(new, k, int(v))
     if kind is None:
         _check(lib().mirng_philox_config_set(ctypes.byref(new)), "philox_config_set")
     else:
-        _check(lib().mirng_philox_config_set_kind(kind, ctypes.byref(new)),
+        _check(lib().mirng_philox_config_set_kind(kind, phase, ctypes.byref(new)),
                "philox_config_set_kind")
     return prev
 
 
-def clear_philox_config(kind: int) -> None:
-    """Drop `kind`'s own launch shape: it follows the process-wide one."""
-    _check(lib().mirng_philox_config_set_kind(kind, None), "philox_config_set_kind")
+def philox_candidates() -> list:
+    """The launch shapes the Philox autotuner times, in its order."""
+    total = int(lib().mirng_philox_candidates(None, 0))
+    arr = (PhiloxConfig * total)()
+    lib().mirng_philox_candidates(arr, total)
+    return [PhiloxConfig.from_buffer_copy(c) for c in arr]
+
+
+def clear_philox_config(kind: int, phase: int = -1) -> None:
+    """Drop `kind`'s own launch shape at `phase` (every phase for -1): it
+    follows the process-wide one there."""
+    _check(lib().mirng_philox_config_set_kind(kind, phase, None), "philox_config_set_kind")
 
 
 class TuningCache:
@@ -370,22 +405,26 @@ def size_class(n: int) -> int:
 
 
 def autotune_philox(kind: int, n: int, out, stream=None, prewarm_ms: int = 300,
-                    rounds: int = 5, reps: int = 10, cache: TuningCache | None = None):
+                    rounds: int = 5, reps: int = 10, cache: TuningCache | None = None,
+                    offset: int = 1):
     """Time the candidate Philox launch shapes on `n` outputs of `kind` into
-    `out` (overwritten), install the fastest as `kind`'s own shape and
-    return (shape, ms).  With a cache, a shape stored for the same
-    architecture, kind and size class is installed without timing, and a
-    newly timed one is stored."""
-    key = f"{_arch()}/philox4x32_10/{kind}/{size_class(n)}" if cache is not None else None
+    `out` (overwritten) from engine word position `offset`, install the
+    fastest as `kind`'s own shape at the phase of that position and output
+    (philox_phase) and return (shape, ms).  With a cache, a shape stored for
+    the same architecture, kind, phase and size class is installed without
+    timing, and a newly timed one is stored."""
+    phase = philox_phase(kind, offset, out)
+    key = (f"{_arch()}/philox4x32_10/{kind}/phase{phase}/{size_class(n)}"
+           if cache is not None else None)
     if key is not None and cache.get(key) is not None:
         hit = cache.get(key)
-        set_philox_config(kind=kind, **hit["config"])
-        return philox_config(kind), float(hit["ms"])
+        set_philox_config(kind=kind, phase=phase, **hit["config"])
+        return philox_config(kind, phase), float(hit["ms"])
     c = PhiloxConfig()
     ms = ctypes.c_float()
-    _check(lib().mirng_autotune_philox(kind, n, _ptr(out), _stream(stream), prewarm_ms, rounds,
-                                       reps, ctypes.byref(c), ctypes.byref(ms)),
-           "autotune_philox")
+    _check(lib().mirng_autotune_philox(kind, offset % 2**64, n, _ptr(out), _stream(stream),
+                                       prewarm_ms, rounds, reps, ctypes.byref(c),
+                                       ctypes.byref(ms)), "autotune_philox")
     if key is not None:
         cache.put(key, {"config": c.as_dict(), "ms": float(ms.value)})
     return c, float(ms.value)
@@ -482,8 +521,8 @@ class Server:
     at most `capacity_bytes` of admitted, unfinished output."""
 
     def __init__(self, streams: int = 2, capacity_bytes: int = 32 * 10**9,
-                 max_batch: int = 65536):
-        cfg = ServerConfig(streams, 0, capacity_bytes, max_batch)
+                 max_batch: int = 65536, max_engines: int = 0):
+        cfg = ServerConfig(streams, max_engines, capacity_bytes, max_batch)
         h = ctypes.c_void_p()
         _check(lib().mirng_server_create(ctypes.byref(cfg), ctypes.byref(h)), "server_create")
         self._h = h
@@ -507,6 +546,37 @@ class Server:
         _check(lib().mirng_server_submit(self._h, r.ctypes.data, ctypes.byref(t)), "server_submit")
         return int(t.value)
 
+    def engine_create(self, engine_type: int, seed: int, offset: int = 0) -> int:
+        """A resident engine in the server's device table; returns its index."""
+        e = ctypes.c_uint32()
+        _check(lib().mirng_server_engine_create(self._h, engine_type, seed & (2**64 - 1), offset,
+                                                ctypes.byref(e)), "server_engine_create")
+        return int(e.value)
+
+    def submit_engine(self, engine: int, kind: int, n: int, out, p0: float | None = None,
+                      p1: float | None = None) -> int:
+        """Queue n outputs of `kind` on resident engine `engine`, continuing
+        it; returns the ticket."""
+        d = distribution(kind, p0, p1)
+        t = ctypes.c_uint64()
+        _check(lib().mirng_server_submit_engine(self._h, engine, ctypes.byref(d), n, _ptr(out),
+                                                ctypes.byref(t)), "server_submit_engine")
+        return int(t.value)
+
+    def engine_skip_ahead(self, engine: int, n: int) -> None:
+        _check(lib().mirng_server_engine_skip_ahead(self._h, engine, _limbs(n), 3),
+               "server_engine_skip_ahead")
+
+    def engine_state(self, engine: int) -> State:
+        st = State()
+        _check(lib().mirng_server_engine_get_state(self._h, engine, ctypes.byref(st)),
+               "server_engine_get_state")
+        return st
+
+    def engine_set_state(self, engine: int, st: State) -> None:
+        _check(lib().mirng_server_engine_set_state(self._h, engine, ctypes.byref(st)),
+               "server_engine_set_state")
+
     def poll(self, ticket: int):
         """(done, status) of a ticket, without blocking."""
         d, s = ctypes.c_int32(), ctypes.c_int32()
@@ -529,18 +599,24 @@ class Server:
         _check(lib().mirng_server_stats_get(self._h, ctypes.byref(st)), "server_stats")
         return st.as_dict()
 
-    def replay(self, reqs, arrival_s):
+    def replay(self, reqs, arrival_s, engines=None):
         """Submit reqs[i] at arrival_s[i] seconds from now (native open-loop
-        load generator); returns (tickets, submission statuses)."""
+        load generator), on resident engine engines[i] when `engines` is
+        given; returns (tickets, submission statuses)."""
         import numpy as np
         reqs = np.ascontiguousarray(reqs, dtype=request_dtype())
         arr = np.ascontiguousarray(arrival_s, dtype=np.float64)
         assert len(arr) == len(reqs)
+        eng = None
+        if engines is not None:
+            eng = np.ascontiguousarray(engines, dtype=np.uint32)
+            assert len(eng) == len(reqs)
         tickets = np.zeros(len(reqs), dtype=np.uint64)
         st = np.zeros(len(reqs), dtype=np.int32)
-        _check(lib().mirng_bench_server_replay(self._h, reqs.ctypes.data, arr.ctypes.data,
-                                               len(reqs), tickets.ctypes.data, st.ctypes.data),
-               "server_replay")
+        _check(lib().mirng_bench_server_replay(self._h, reqs.ctypes.data,
+                                               None if eng is None else eng.ctypes.data,
+                                               arr.ctypes.data, len(reqs), tickets.ctypes.data,
+                                               st.ctypes.data), "server_replay")
         return tickets, st
 
 

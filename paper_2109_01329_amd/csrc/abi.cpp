@@ -30,33 +30,49 @@ mirng_philox_config &philox_config()
 }
 
 namespace {
-// A kind's own launch shape, if one was installed (per kind or by the
-// autotuner); otherwise the kind follows the process-wide shape.
+// A kind's own launch shape at a phase, if one was installed (per kind or by
+// the autotuner); otherwise the kind follows the process-wide shape.  The
+// phase is the word position of a launch's first 16-byte slot modulo 4:
+// the walks differ there (phase 0 needs no word exchange between lanes),
+// and so does the fastest shape.
 struct KindShape {
     bool set = false;
     mirng_philox_config c{};
 };
-KindShape g_kind_shape[kIcdf64 + 1];
+KindShape g_kind_shape[kIcdf64 + 1][4];
 }  // namespace
 
 bool philox_kind_ok(int kind) { return kind >= kBits && kind <= kIcdf64; }
 
-mirng_philox_config philox_config_for(int kind)
+uint32_t philox_phase(int kind, uint64_t pos_lo, uintptr_t out)
 {
-    if (philox_kind_ok(kind) && g_kind_shape[kind].set) return g_kind_shape[kind].c;
+    const uintptr_t esz = (uintptr_t)elem_bytes(kind);
+    const bool at_out = paired(kind) && (((out & 15u) / esz) & 1u);
+    const uint64_t head = at_out ? 0u : (uint64_t)((out & 15u) / esz);
+    return (uint32_t)((pos_lo - head * (uint64_t)philox_words_per_elem(kind)) & 3u);
+}
+
+mirng_philox_config philox_config_for(int kind, uint32_t phase)
+{
+    if (philox_kind_ok(kind) && g_kind_shape[kind][phase & 3u].set)
+        return g_kind_shape[kind][phase & 3u].c;
     return philox_config();
 }
 
-void philox_config_set_kind(int kind, const mirng_philox_config *c)
+void philox_config_set_kind(int kind, int phase, const mirng_philox_config *c)
 {
-    g_kind_shape[kind].set = c != nullptr;
-    if (c) g_kind_shape[kind].c = *c;
+    for (int ph = 0; ph < 4; ++ph) {
+        if (phase >= 0 && ph != phase) continue;
+        g_kind_shape[kind][ph].set = c != nullptr;
+        if (c) g_kind_shape[kind][ph].c = *c;
+    }
 }
 
-bool philox_config_kind_set(int kind, mirng_philox_config *c)
+bool philox_config_kind_set(int kind, int phase, mirng_philox_config *c)
 {
-    if (g_kind_shape[kind].set && c) *c = g_kind_shape[kind].c;
-    return g_kind_shape[kind].set;
+    const KindShape &k = g_kind_shape[kind][phase & 3];
+    if (k.set && c) *c = k.c;
+    return k.set;
 }
 
 bool philox_config_valid(const mirng_philox_config &c)
@@ -73,8 +89,8 @@ bool philox_config_valid(const mirng_philox_config &c)
 namespace {
 
 std::mutex g_dev_mu;
-int g_dev_checked[64];   // 0 unknown, 1 ok, -1 unusable
-int g_dev_cus[64];
+int g_dev_checked[kMaxDevices];   // 0 unknown, 1 ok (set up), -1 unusable
+int g_dev_cus[kMaxDevices];
 
 }  // namespace
 
@@ -83,14 +99,20 @@ hipError_t ensure_device(int *dev_out)
     int dev = 0;
     hipError_t err = hipGetDevice(&dev);
     if (err != hipSuccess) return err;
-    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
     std::lock_guard<std::mutex> lk(g_dev_mu);
     if (g_dev_checked[dev] == 0) {
         hipDeviceProp_t prop;
         err = hipGetDeviceProperties(&prop, dev);
         if (err != hipSuccess) return err;
-        const bool ok = std::strncmp(prop.gcnArchName, "gfx950", 6) == 0;
-        g_dev_checked[dev] = ok ? 1 : -1;
+        if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+            g_dev_checked[dev] = -1;
+        } else {
+            // one-time set-up of this device (host-synchronous copies)
+            err = mrg_tables_init(dev);
+            if (err != hipSuccess) return err;   // retried on the next call
+            g_dev_checked[dev] = 1;
+        }
         g_dev_cus[dev] = prop.multiProcessorCount;
     }
     if (g_dev_checked[dev] < 0) return hipErrorInvalidDeviceFunction;
@@ -101,7 +123,7 @@ hipError_t ensure_device(int *dev_out)
 int device_cu_count()
 {
     int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return 256;
     std::lock_guard<std::mutex> lk(g_dev_mu);
     return g_dev_cus[dev] > 0 ? g_dev_cus[dev] : 256;
 }
@@ -136,12 +158,13 @@ hipError_t philox_plain(const uint32_t key[2], Pos130 p, const mirng_distributio
                         uint64_t n, char *out, hipStream_t s)
 {
     const int kind = d->kind;
-    const mirng_philox_config tu = philox_config_for(kind);
     const size_t esz = elem_size(kind);
     const uint32_t wpe = (uint32_t)philox_words_per_elem(kind);
-    const Epilogue ep = make_epilogue(d, tu.nontemporal);
     const uint64_t cus = (uint64_t)device_cu_count();
     while (n > 0) {
+        const mirng_philox_config tu = philox_config_for(kind, philox_phase(kind, p.l[0],
+                                                                            (uintptr_t)out));
+        const Epilogue ep = make_epilogue(d, tu.nontemporal);
         const uint64_t chunk = n < kMaxPerLaunch ? n : kMaxPerLaunch;
         const uint64_t b_lo = (p.l[0] >> 2) | (p.l[1] << 62);   // floor(p / 4), 128 bits
         const uint64_t b_hi = (p.l[1] >> 2) | (p.l[2] << 62);
@@ -270,6 +293,11 @@ extern "C" {
 
 int32_t mirng_abi_version(void) { return MIRNG_ABI_VERSION; }
 
+mirng_status mirng_device_init(void)
+{
+    return ensure_device(nullptr) == hipSuccess ? MIRNG_OK : MIRNG_E_DEVICE;
+}
+
 mirng_status mirng_philox_config_get(mirng_philox_config *c)
 {
     if (!c) return MIRNG_E_INVALID_ARG;
@@ -281,24 +309,30 @@ mirng_status mirng_philox_config_set(const mirng_philox_config *c)
 {
     if (!c || !philox_config_valid(*c)) return MIRNG_E_INVALID_ARG;
     philox_config() = *c;
-    for (int k = kBits; k <= kIcdf64; ++k) philox_config_set_kind(k, nullptr);
+    for (int k = kBits; k <= kIcdf64; ++k) philox_config_set_kind(k, -1, nullptr);
     return MIRNG_OK;
 }
 
-mirng_status mirng_philox_config_get_kind(int32_t kind, mirng_philox_config *c)
+mirng_status mirng_philox_config_get_kind(int32_t kind, int32_t phase, mirng_philox_config *c)
 {
-    if (!c) return MIRNG_E_INVALID_ARG;
+    if (!c || phase < 0 || phase > 3) return MIRNG_E_INVALID_ARG;
     if (!philox_kind_ok(kind)) return MIRNG_E_UNSUPPORTED;
-    *c = philox_config_for(kind);
+    *c = philox_config_for(kind, (uint32_t)phase);
     return MIRNG_OK;
 }
 
-mirng_status mirng_philox_config_set_kind(int32_t kind, const mirng_philox_config *c)
+mirng_status mirng_philox_config_set_kind(int32_t kind, int32_t phase,
+                                          const mirng_philox_config *c)
 {
     if (!philox_kind_ok(kind)) return MIRNG_E_UNSUPPORTED;
-    if (c && !philox_config_valid(*c)) return MIRNG_E_INVALID_ARG;
-    philox_config_set_kind(kind, c);
+    if (phase < -1 || phase > 3 || (c && !philox_config_valid(*c))) return MIRNG_E_INVALID_ARG;
+    philox_config_set_kind(kind, phase, c);
     return MIRNG_OK;
+}
+
+uint32_t mirng_philox_phase(int32_t kind, uint64_t position, const void *out)
+{
+    return philox_kind_ok(kind) ? philox_phase(kind, position, (uintptr_t)out) : 0u;
 }
 
 const char *mirng_status_string(mirng_status s)

@@ -76,6 +76,23 @@ int tune(size_t count, const std::function<void(size_t)> &apply,
     return best;
 }
 
+// The Philox launch shapes the autotuner times, in timing order.
+std::vector<mirng_philox_config> philox_candidates()
+{
+    std::vector<mirng_philox_config> cand;
+    for (int block : {256, 512, 1024})
+        for (int wpc : {64, 128, 256, 512, 1024})
+            for (int nt : {0, 1}) cand.push_back({0, block, wpc, 1, nt, 0});
+    for (int bpl : {1, 2}) cand.push_back({1, 256, 8, bpl, 0, 0});
+    for (int block : {256, 1024})
+        for (int iters : {1, 2, 4})
+            for (int nt : {0, 1}) cand.push_back({2, block, 1, iters, nt, 0});
+    for (int block : {128, 256, 512, 1024})
+        for (int chunks : {1, 2})
+            for (int nt : {0, 1}) cand.push_back({3, block, 1, chunks, nt, 0});
+    return cand;
+}
+
 bool tune_args_ok(int32_t prewarm_ms, int32_t rounds, int32_t reps)
 {
     return prewarm_ms >= 0 && prewarm_ms <= 60000 && rounds >= 1 && rounds <= 64 && reps >= 1 &&
@@ -88,46 +105,53 @@ using namespace mirng;
 
 extern "C" {
 
-mirng_status mirng_autotune_philox(int32_t kind, uint64_t n, void *out, void *stream,
-                                   int32_t prewarm_ms, int32_t rounds, int32_t reps,
-                                   mirng_philox_config *best, float *best_ms)
+mirng_status mirng_autotune_philox(int32_t kind, uint64_t offset, uint64_t n, void *out,
+                                   void *stream, int32_t prewarm_ms, int32_t rounds,
+                                   int32_t reps, mirng_philox_config *best, float *best_ms)
 {
     if (kind < kBits || kind > kIcdf64) return MIRNG_E_UNSUPPORTED;
     if (!out || n == 0 || !tune_args_ok(prewarm_ms, rounds, reps)) return MIRNG_E_INVALID_ARG;
     if ((uintptr_t)out % (uintptr_t)elem_bytes(kind)) return MIRNG_E_INVALID_ARG;
     if (ensure_device(nullptr) != hipSuccess) return MIRNG_E_DEVICE;
-    std::vector<mirng_philox_config> cand;
-    for (int block : {256, 512, 1024})
-        for (int wpc : {64, 128, 256, 512, 1024})
-            for (int nt : {0, 1}) cand.push_back({0, block, wpc, 1, nt, 0});
-    for (int bpl : {1, 2}) cand.push_back({1, 256, 8, bpl, 0, 0});
-    for (int block : {256, 1024})
-        for (int iters : {1, 2, 4})
-            for (int nt : {0, 1}) cand.push_back({2, block, 1, iters, nt, 0});
-    for (int block : {128, 256, 512, 1024})
-        for (int chunks : {1, 2})
-            for (int nt : {0, 1}) cand.push_back({3, block, 1, chunks, nt, 0});
+    const std::vector<mirng_philox_config> cand = philox_candidates();
+    // every launch runs at the caller's position, so at its phase; the
+    // result is installed for this kind at this phase only
+    const int phase = (int)philox_phase(kind, offset, (uintptr_t)out);
     mirng_philox_config prev{};
-    const bool had_own = philox_config_kind_set(kind, &prev);
+    const bool had_own = philox_config_kind_set(kind, phase, &prev);
     mirng_engine e = nullptr;
-    if (mirng_engine_create(MIRNG_PHILOX4X32_10, 0x5EED5EEDull, 1, &e) != MIRNG_OK)
+    if (mirng_engine_create(MIRNG_PHILOX4X32_10, 0x5EED5EEDull, offset, &e) != MIRNG_OK)
         return MIRNG_E_ALLOC;
+    mirng_state start;
+    (void)mirng_engine_get_state(e, &start);
     // the unit range (or mean 0, sd 1); [0, 2^31) for uniform int32
     const mirng_distribution d = {kind, 0, 0.0, kind == kI32 ? 2147483648.0 : 1.0};
-    auto run = [&]() { return mirng_generate(e, &d, n, out, stream); };
+    auto run = [&]() {
+        (void)mirng_engine_set_state(e, &start);
+        return mirng_generate(e, &d, n, out, stream);
+    };
     float ms = 0.0f;
-    const int k = tune(cand.size(), [&](size_t i) { philox_config_set_kind(kind, &cand[i]); },
-                       run, (hipStream_t)stream, prewarm_ms, rounds, reps, &ms);
+    const int k = tune(cand.size(),
+                       [&](size_t i) { philox_config_set_kind(kind, phase, &cand[i]); }, run,
+                       (hipStream_t)stream, prewarm_ms, rounds, reps, &ms);
     mirng_engine_destroy(e);
     if (k < 0) {
-        philox_config_set_kind(kind, had_own ? &prev : nullptr);
+        philox_config_set_kind(kind, phase, had_own ? &prev : nullptr);
         return MIRNG_E_LAUNCH;
     }
-    // installed for this kind only; other kinds keep their shapes
-    philox_config_set_kind(kind, &cand[k]);
+    // installed for this kind and phase only; other kinds and phases keep
+    // their shapes
+    philox_config_set_kind(kind, phase, &cand[k]);
     if (best) *best = cand[k];
     if (best_ms) *best_ms = ms;
     return MIRNG_OK;
+}
+
+int32_t mirng_philox_candidates(mirng_philox_config *out, int32_t max)
+{
+    const std::vector<mirng_philox_config> cand = philox_candidates();
+    for (int32_t i = 0; out && i < max && i < (int32_t)cand.size(); ++i) out[i] = cand[(size_t)i];
+    return (int32_t)cand.size();
 }
 
 mirng_status mirng_autotune_batch(mirng_batcher b, const mirng_request *reqs, size_t count,

@@ -26,6 +26,7 @@ constexpr uint64_t kMaxMrgGroups = 1u << 24;
 
 struct Slot {
     mirng_request *h_reqs = nullptr;   // pinned
+    mirng::EngineRef *h_refs = nullptr;  // pinned (engine references of server batches)
     int32_t *h_status = nullptr;       // pinned
     size_t cap = 0;
     size_t count = 0;
@@ -36,6 +37,7 @@ struct Slot {
     hipEvent_t forked = nullptr;       // the caller's stream up to this batch's generation
     hipEvent_t mrg_done = nullptr;     // MRG generation done (its own stream)
     mirng_request *d_reqs = nullptr;
+    mirng::EngineRef *d_refs = nullptr;
     mirng::BatchDesc *d_desc = nullptr;
     uint64_t *d_local_end = nullptr;
     uint64_t *d_chunk_total = nullptr;
@@ -57,8 +59,10 @@ void release(Slot &s)
 {
     if (s.done && s.pending) (void)hipEventSynchronize(s.done);
     if (s.h_reqs) (void)hipHostFree(s.h_reqs);
+    if (s.h_refs) (void)hipHostFree(s.h_refs);
     if (s.h_status) (void)hipHostFree(s.h_status);
     if (s.d_reqs) (void)hipFree(s.d_reqs);
+    if (s.d_refs) (void)hipFree(s.d_refs);
     if (s.d_desc) (void)hipFree(s.d_desc);
     if (s.d_local_end) (void)hipFree(s.d_local_end);
     if (s.d_chunk_total) (void)hipFree(s.d_chunk_total);
@@ -102,8 +106,10 @@ hipError_t prepare(Slot &s, size_t count, int dev)
     hipError_t err = hipSuccess;
     auto chk = [&](hipError_t e) { if (err == hipSuccess) err = e; };
     chk(hipHostMalloc((void **)&s.h_reqs, cap * sizeof(mirng_request), hipHostMallocDefault));
+    chk(hipHostMalloc((void **)&s.h_refs, cap * sizeof(mirng::EngineRef), hipHostMallocDefault));
     chk(hipHostMalloc((void **)&s.h_status, cap * sizeof(int32_t), hipHostMallocDefault));
     chk(hipMalloc((void **)&s.d_reqs, cap * sizeof(mirng_request)));
+    chk(hipMalloc((void **)&s.d_refs, cap * sizeof(mirng::EngineRef)));
     chk(hipMalloc((void **)&s.d_desc, cap * sizeof(mirng::BatchDesc)));
     chk(hipMalloc((void **)&s.d_local_end, 2 * cap * sizeof(uint64_t)));
     chk(hipMalloc((void **)&s.d_chunk_total, 2 * nchunks * sizeof(uint64_t)));
@@ -188,17 +194,53 @@ struct mirng_batcher_s {
     int next = 0;
     int last = -1;     // slot of the most recent batch
     int staged = -1;   // slot handed out by mirng_batcher_stage
-    mirng_batch_config cfg = {1024, 256, 1, 0};
+    mirng_batch_config cfg = mirng::batch_default_config();
 };
 
 namespace mirng {
 
-// Waves of the Philox generation grid for launch shape c (whole groups).
+mirng_batch_config batch_default_config()
+{
+    // the shape the autotuner picked for the calorimeter batch on MI355X
+    // (512-thread groups, 128 waves of work per CU, ordinary stores)
+    return mirng_batch_config{512, 128, 0, 0};
+}
+
 size_t grid_waves(const mirng_batch_config &c)
 {
     const size_t wpb = (size_t)c.block / 64;
     const size_t w = (size_t)device_cu_count() * (size_t)c.waves_per_cu;
     return (w + wpb - 1) / wpb * wpb;
+}
+
+void batch_grids(const mirng_batch_config &cfg, const mirng_request *reqs, size_t count,
+                 uint64_t max_waves, BatchArgs &a)
+{
+    const uint64_t wpb = (uint64_t)cfg.block / 64;
+    uint64_t waves = grid_waves(cfg);
+    const Work w = scan_requests(reqs, count);
+    // Philox: no more waves than about two tiles of work each
+    const uint64_t want = ((w.tiles + 1) / 2 + wpb - 1) / wpb * wpb;
+    waves = std::max<uint64_t>(wpb, std::min(waves, want));
+    if (max_waves) waves = std::min(waves, max_waves / wpb * wpb);
+    // MRG: a chunk per group while that fills the resident groups, then
+    // kMrgChunksPerGroup per group.  Chunks of different kinds cost
+    // different times; many short groups let the hardware dispatcher
+    // balance them where a few long ones would wait on the slowest.
+    const uint64_t resident = mrg_groups();
+    const uint64_t mgroups = std::min<uint64_t>(
+        kMaxMrgGroups,
+        std::max<uint64_t>(1, std::max(std::min(w.chunks, resident),
+                                       (w.chunks + kMrgChunksPerGroup - 1) / kMrgChunksPerGroup)));
+    a.waves = (uint32_t)waves;
+    a.mgroups = (uint32_t)mgroups;
+    a.nt = cfg.nontemporal;
+    a.wide = w.wide;
+    a.philox = w.philox;
+    a.mrg = w.mrg;
+    a.mrg_wide = w.mrg_wide;
+    a.block = (uint32_t)cfg.block;
+    a.groups = (uint32_t)(waves / wpb);
 }
 
 hipError_t batcher_reserve(mirng_batcher b, size_t count)
@@ -281,12 +323,21 @@ mirng_status mirng_batcher_stage(mirng_batcher b, size_t count, mirng_request **
 mirng_status mirng_generate_batch(mirng_batcher b, const mirng_request *reqs, size_t count,
                                   void *stream)
 {
+    return generate_batch_refs(b, reqs, nullptr, count, nullptr, (hipStream_t)stream);
+}
+
+}  // extern "C"
+
+mirng_status mirng::generate_batch_refs(mirng_batcher b, const mirng_request *reqs,
+                                        const EngineRef *refs, size_t count,
+                                        const mirng_state *engines, hipStream_t stream)
+{
     if (!b || !reqs) return MIRNG_E_INVALID_ARG;
     if (count >= (1ull << 31)) return MIRNG_E_INVALID_ARG;
     if (count == 0) return MIRNG_OK;
     int dev = 0;
     if (ensure_device(&dev) != hipSuccess) return MIRNG_E_DEVICE;
-    hipStream_t s = (hipStream_t)stream;
+    hipStream_t s = stream;
     std::lock_guard<std::mutex> lk(b->mu);
     if (b->copy_dev != dev) {
         if (b->copy) (void)hipStreamDestroy(b->copy);
@@ -300,22 +351,9 @@ mirng_status mirng_generate_batch(mirng_batcher b, const mirng_request *reqs, si
         b->copy_dev = dev;
     }
     MrgBatchTables tabs;
-    if (mrg_batch_tables(dev, tabs) != hipSuccess) return MIRNG_E_ALLOC;
-    const uint64_t wpb = (uint64_t)b->cfg.block / 64;
-    uint64_t waves = grid_waves(b->cfg);
-    const Work w = scan_requests(reqs, count);
-    // Philox: no more waves than about two tiles of work each
-    const uint64_t want = ((w.tiles + 1) / 2 + wpb - 1) / wpb * wpb;
-    waves = std::max<uint64_t>(wpb, std::min(waves, want));
-    // MRG: a chunk per group while that fills the resident groups, then
-    // kMrgChunksPerGroup per group.  Chunks of different kinds cost
-    // different times; many short groups let the hardware dispatcher
-    // balance them where a few long ones would wait on the slowest.
-    const uint64_t resident = mrg_groups();
-    const uint64_t mgroups = std::min<uint64_t>(
-        kMaxMrgGroups,
-        std::max<uint64_t>(1, std::max(std::min(w.chunks, resident),
-                                       (w.chunks + kMrgChunksPerGroup - 1) / kMrgChunksPerGroup)));
+    if (mrg_batch_tables(dev, tabs) != hipSuccess) return MIRNG_E_DEVICE;
+    BatchArgs a{};
+    batch_grids(b->cfg, reqs, count, 0, a);
     int k;
     if (b->staged >= 0 && reqs == b->slots[b->staged].h_reqs &&
         count <= b->slots[b->staged].cap && b->slots[b->staged].dev == dev) {
@@ -329,10 +367,12 @@ mirng_status mirng_generate_batch(mirng_batcher b, const mirng_request *reqs, si
     }
     b->staged = -1;
     Slot &sl = b->slots[k];
+    if (refs) std::memcpy(sl.h_refs, refs, count * sizeof(EngineRef));
     sl.count = count;
-    if (ensure_waves(sl, waves) != hipSuccess) return MIRNG_E_ALLOC;
-    BatchArgs a{};
+    if (ensure_waves(sl, a.waves) != hipSuccess) return MIRNG_E_ALLOC;
     a.reqs = sl.d_reqs;
+    a.refs = refs ? sl.d_refs : nullptr;
+    a.engines = refs ? engines : nullptr;
     a.count = (uint32_t)count;
     a.nchunks = (uint32_t)((count + kChunk - 1) / kChunk);
     a.desc = sl.d_desc;
@@ -340,27 +380,21 @@ mirng_status mirng_generate_batch(mirng_batcher b, const mirng_request *reqs, si
     a.chunk_total = sl.d_chunk_total;
     a.chunk_end = sl.d_chunk_end;
     a.total = sl.d_total;
-    a.waves = (uint32_t)waves;
     a.wave_start = sl.d_wave_start;
-    a.mgroups = (uint32_t)mgroups;
     a.pow2 = tabs.pow2;
     a.c_tab4 = tabs.c_tab4;
     a.u_tab4 = tabs.u_tab4;
     a.c_tab8 = tabs.c_tab8;
     a.u_tab8 = tabs.u_tab8;
     a.status = sl.d_status;
-    a.nt = b->cfg.nontemporal;
-    a.wide = w.wide;
-    a.philox = w.philox;
-    a.mrg = w.mrg;
-    a.mrg_wide = w.mrg_wide;
-    a.block = (uint32_t)b->cfg.block;
-    a.groups = (uint32_t)(waves / wpb);
     // upload, planning and the status copy run on the batcher's own stream,
     // where they overlap the generation of the batches before this one; the
     // caller's stream waits for them, then generates
     hipError_t err = hipMemcpyAsync(sl.d_reqs, sl.h_reqs, count * sizeof(mirng_request),
                                     hipMemcpyHostToDevice, b->copy);
+    if (err == hipSuccess && refs)
+        err = hipMemcpyAsync(sl.d_refs, sl.h_refs, count * sizeof(EngineRef),
+                             hipMemcpyHostToDevice, b->copy);
     if (err == hipSuccess) err = launch_batch_plan(a, b->copy);
     if (err == hipSuccess)
         err = hipMemcpyAsync(sl.h_status, sl.d_status, count * sizeof(int32_t),
@@ -397,6 +431,8 @@ mirng_status mirng_generate_batch(mirng_batcher b, const mirng_request *reqs, si
     b->last = k;
     return MIRNG_OK;
 }
+
+extern "C" {
 
 mirng_status mirng_batcher_statuses(mirng_batcher b, int32_t *statuses, size_t count)
 {

@@ -33,8 +33,37 @@ namespace {
 
 constexpr uint32_t kChunk = 1024;
 
+// p <- (p + n) mod 2^130 over little-endian 64-bit limbs.
+__device__ __forceinline__ void add130(uint64_t p[3], const uint64_t n[3])
+{
+    uint64_t carry = 0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const uint64_t s1 = p[i] + n[i];
+        const uint64_t c1 = s1 < n[i] ? 1u : 0u;
+        const uint64_t s2 = s1 + carry;
+        carry = c1 | (s2 < carry ? 1u : 0u);
+        p[i] = s2;
+    }
+    p[2] &= 3u;
+}
+
+// MRG32k3a state v <- A^n v for an n of `limbs` 64-bit limbs, through the
+// resident A^(2^k) table.
+__device__ __forceinline__ void mrg_jump_limbs(uint32_t v[6], const uint64_t *n, int limbs,
+                                               const uint32_t *pow2)
+{
+    for (int l = 0; l < limbs; ++l)
+        for (int k = 0; k < 64; ++k)
+            if ((n[l] >> k) & 1u) apply_mat(pow2 + (64 * l + k) * kMatWords, v);
+}
+
 // Validation and planning of one request: its Philox tiles or MRG chunks.
-__device__ void plan_one(const mirng_request &q, BatchDesc &d, int32_t &st, int nt,
+// The start is (seed, offset) of the request, or, when `ref` names a
+// resident engine, entry ref.slot of the device engine table advanced by
+// ref.skip words (Philox, modulo 2^130) or steps (MRG, a 192-bit jump).
+__device__ void plan_one(const mirng_request &q, const EngineRef &ref,
+                         const mirng_state *engines, BatchDesc &d, int32_t &st, int nt,
                          const uint32_t *pow2, uint64_t &tiles, uint64_t &mchunks)
 {
     st = MIRNG_OK;
@@ -56,6 +85,12 @@ __device__ void plan_one(const mirng_request &q, BatchDesc &d, int32_t &st, int 
     const uint64_t addr = (uint64_t)(uintptr_t)q.out;
     if (addr == 0 || addr % esz) { st = MIRNG_E_INVALID_ARG; return; }
     if (q.n >= (1ull << 32)) { st = MIRNG_E_CAPACITY; return; }
+    const bool resident = (ref.flags & kRefEngine) != 0;
+    mirng_state e{};
+    if (resident) {
+        e = engines[ref.slot];
+        if (e.engine_type != q.engine_type) { st = MIRNG_E_INVALID_ARG; return; }
+    }
 
     const Epilogue ep = epilogue_of(kind, p0, p1, nt);
     SlotRun &r = d.run;
@@ -63,13 +98,22 @@ __device__ void plan_one(const mirng_request &q, BatchDesc &d, int32_t &st, int 
     r.ep = ep;
     r.pad = 0;
     d.kind = (uint32_t)kind;
-    const uint64_t p = q.offset;   // engine words (Philox) or steps (MRG) from the seed state
 
     if (q.engine_type == MIRNG_MRG32K3A) {
-        uint32_t v[6] = {(uint32_t)((q.seed & 0xFFFFFFFFull) % kM1), 1u, 1u,
-                         (uint32_t)((q.seed >> 32) % kM2), 1u, 1u};
-        for (int k = 0; k < 64; ++k)
-            if ((p >> k) & 1u) apply_mat(pow2 + k * kMatWords, v);
+        uint32_t v[6];
+        if (resident) {
+#pragma unroll
+            for (int i = 0; i < 6; ++i) v[i] = e.words[i];
+            mrg_jump_limbs(v, ref.skip, 3, pow2);
+        } else {
+            v[0] = (uint32_t)((q.seed & 0xFFFFFFFFull) % kM1);
+            v[1] = 1u;
+            v[2] = 1u;
+            v[3] = (uint32_t)((q.seed >> 32) % kM2);
+            v[4] = 1u;
+            v[5] = 1u;
+            mrg_jump_limbs(v, &q.offset, 1, pow2);   // steps from the seed state
+        }
 #pragma unroll
         for (int i = 0; i < 6; ++i) d.mst[i] = v[i];
         const uint64_t per = (uint64_t)kMrgThreads * kBatchMrgPasses * (esz == 8 ? 16 : 32);
@@ -79,19 +123,28 @@ __device__ void plan_one(const mirng_request &q, BatchDesc &d, int32_t &st, int 
         return;
     }
 
-    r.k0 = (uint32_t)q.seed;
-    r.k1 = (uint32_t)(q.seed >> 32);
+    // Philox: key and 130-bit word position of output 0
+    uint64_t p[3] = {q.offset, 0, 0};
+    if (resident) {
+        r.k0 = e.words[0];
+        r.k1 = e.words[1];
+        p[0] = e.pos[0];
+        p[1] = e.pos[1];
+        p[2] = e.pos[2] & 3u;
+        add130(p, ref.skip);
+    } else {
+        r.k0 = (uint32_t)q.seed;
+        r.k1 = (uint32_t)(q.seed >> 32);
+    }
     const uint32_t head = (uint32_t)((addr & 15u) / esz);
     const uint32_t wpe = (uint32_t)philox_words_per_elem(kind);
     const uint32_t epv = (uint32_t)(16 / esz);
+    // position of slot 0: p, or p - head * wpe (mod 2^130) when slot 0 starts
+    // on the 16-byte grid before the output
+    uint64_t g[3] = {p[0], p[1], p[2]};
     if (paired(kind) && (head & 1u)) {
         // pairs would straddle the 16-byte grid: slots (two FP32 pairs or
         // one FP64 pair) start at the output itself
-        r.base[0] = (uint32_t)(p >> 2);
-        r.base[1] = (uint32_t)(p >> 34);
-        r.base[2] = 0;
-        r.base[3] = 0;
-        d.phase = (uint32_t)(p & 3u);
         r.head = 0;
         d.nunits = (uint32_t)((q.n + epv - 1) / epv);
         r.full_lo = 0;
@@ -99,17 +152,11 @@ __device__ void plan_one(const mirng_request &q, BatchDesc &d, int32_t &st, int 
         r.out_base = (char *)q.out;
     } else {
         const uint64_t dq = (uint64_t)head * wpe;
-        // q = p - dq modulo 2^130
-        const uint64_t q_lo = p - dq;
-        const uint64_t q_mid = p >= dq ? 0ull : ~0ull;
-        const uint64_t q_top = p >= dq ? 0ull : 3ull;
-        const uint64_t b_lo = (q_lo >> 2) | (q_mid << 62);
-        const uint64_t b_hi = (q_mid >> 2) | (q_top << 62);
-        r.base[0] = (uint32_t)b_lo;
-        r.base[1] = (uint32_t)(b_lo >> 32);
-        r.base[2] = (uint32_t)b_hi;
-        r.base[3] = (uint32_t)(b_hi >> 32);
-        d.phase = (uint32_t)(q_lo & 3u);
+        const uint64_t b0 = p[0] < dq ? 1u : 0u;
+        g[0] = p[0] - dq;
+        const uint64_t b1 = p[1] < b0 ? 1u : 0u;
+        g[1] = p[1] - b0;
+        g[2] = (p[2] - b1) & 3u;
         r.head = head;
         d.nunits = (uint32_t)((head + q.n + epv - 1) / epv);
         const uint64_t lo = head ? 1 : 0;
@@ -120,6 +167,14 @@ __device__ void plan_one(const mirng_request &q, BatchDesc &d, int32_t &st, int 
         // slot 0's place in its 1 KiB block: the tiles follow that grid
         d.slot0 = (uint32_t)(((uint64_t)(uintptr_t)r.out_base >> 4) & 63u);
     }
+    // block index floor(g / 4) (128 bits) and phase g mod 4
+    const uint64_t b_lo = (g[0] >> 2) | (g[1] << 62);
+    const uint64_t b_hi = (g[1] >> 2) | (g[2] << 62);
+    r.base[0] = (uint32_t)b_lo;
+    r.base[1] = (uint32_t)(b_lo >> 32);
+    r.base[2] = (uint32_t)b_hi;
+    r.base[3] = (uint32_t)(b_hi >> 32);
+    d.phase = (uint32_t)(g[0] & 3u);
     tiles = ((uint64_t)d.slot0 + d.nunits + 63) / 64;
 }
 
@@ -176,7 +231,9 @@ __global__ __launch_bounds__(kChunk) void batch_plan_kernel(BatchArgs a)
         int32_t st;
         BatchDesc d;
         const mirng_request q = load_request(&a.reqs[r]);
-        plan_one(q, d, st, a.nt, a.pow2, tiles, mchunks);
+        EngineRef ref{};
+        if (a.refs) ref = a.refs[r];
+        plan_one(q, ref, a.engines, d, st, a.nt, a.pow2, tiles, mchunks);
         a.status[r] = st;
         if (st != MIRNG_OK) {
             d.nunits = 0;

@@ -7,6 +7,7 @@
 #include <cstddef>
 #include <cstdint>
 
+#include "jobs.hpp"
 #include "mirng.h"
 
 namespace mirng {
@@ -25,6 +26,9 @@ constexpr uint64_t kA12 = 1403580ull;     // x1[n] uses  a12 x1[n-2]
 constexpr uint64_t kA13 = 810728ull;      //           - a13 x1[n-3]
 constexpr uint64_t kA21 = 527612ull;      // x2[n] uses  a21 x2[n-1]
 constexpr uint64_t kA23 = 1370589ull;     //           - a23 x2[n-3]
+
+// Devices the library keeps per-device state for (device ordinals below it).
+constexpr int kMaxDevices = 64;
 
 // ------------------------------------------------------------ host math
 // 130-bit Philox word position, little-endian 64-bit limbs, l[2] < 4.
@@ -217,6 +221,8 @@ constexpr uint32_t kBatchMrgPasses = 2;
 // per chunk of 1024 requests plus a prefix over chunks.
 struct BatchArgs {
     const mirng_request *reqs;
+    const EngineRef *refs;          // per request, or nullptr: every request has (seed, offset)
+    const mirng_state *engines;     // device engine table the references name
     uint32_t count;
     uint32_t nchunks;
     BatchDesc *desc;
@@ -240,12 +246,30 @@ struct BatchArgs {
     const uint32_t *c_tab8, *u_tab8;   // MRG chunk / thread jumps, FP64
 };
 
+// Entries A^(2^k), k < kPow2Entries, of the resident MRG jump tables
+// (enough for any 192-bit step count).
+constexpr int kPow2Entries = 192;
+
 // Resident MRG jump tables for batches on device `dev`.
 struct MrgBatchTables {
-    const uint32_t *pow2;
+    const uint32_t *pow2;   // A^(2^k), k < kPow2Entries: [k][comp][9]
     const uint32_t *c_tab4, *u_tab4, *c_tab8, *u_tab8;
 };
 hipError_t mrg_batch_tables(int dev, MrgBatchTables &t);
+
+// Per-device set-up, once per device with that device current (called by
+// ensure_device): the resident MRG jump tables.
+hipError_t mrg_tables_init(int dev);
+
+// Launch shape and grids of a batch from one pass over its requests (host):
+// fills a.waves, a.mgroups, a.block, a.groups, a.nt and the flags of which
+// generation kernels have work.  max_waves caps the Philox grid (0: none).
+void batch_grids(const mirng_batch_config &cfg, const mirng_request *reqs, size_t count,
+                 uint64_t max_waves, BatchArgs &a);
+// Waves of the Philox generation grid for launch shape c (whole groups).
+size_t grid_waves(const mirng_batch_config &c);
+// The batched launch shape a new batcher starts with.
+mirng_batch_config batch_default_config();
 
 // Planning (validation, per-request plans, prefix sums) of a batch, then its
 // generation kernels; the second may run on another stream once the first
@@ -255,6 +279,12 @@ hipError_t launch_batch_generate(const BatchArgs &a, hipStream_t s);
 // Allocates every staging slot of `b` for `count` requests on the current
 // device (so that later batches of up to `count` requests allocate nothing).
 hipError_t batcher_reserve(mirng_batcher b, size_t count);
+// mirng_generate_batch with per-request engine references (refs may be
+// nullptr): a request whose reference names a resident engine starts from
+// entry engines[ref.slot] of a device engine table advanced by ref.skip.
+mirng_status generate_batch_refs(mirng_batcher b, const mirng_request *reqs,
+                                 const EngineRef *refs, size_t count,
+                                 const mirng_state *engines, hipStream_t s);
 
 hipError_t launch_philox_blocks(const PhiloxBlocks &a, hipStream_t s);
 hipError_t launch_philox_fill(const PhiloxFill &a, hipStream_t s);
@@ -264,12 +294,18 @@ hipError_t launch_philox_fill(const PhiloxFill &a, hipStream_t s);
 mirng_philox_config &philox_config();   // the process-wide shape
 bool philox_config_valid(const mirng_philox_config &c);
 bool philox_kind_ok(int kind);
-// The shape generate calls of `kind` use: its own, else the process-wide one.
-mirng_philox_config philox_config_for(int kind);
-// Install (c != nullptr) or drop (c == nullptr) a kind's own shape; kind valid.
-void philox_config_set_kind(int kind, const mirng_philox_config *c);
-// Whether `kind` has its own shape (copied to *c if so and c != nullptr).
-bool philox_config_kind_set(int kind, mirng_philox_config *c);
+// The phase of a Philox launch of `kind` at word position pos (low limb)
+// into out: the position of its first 16-byte slot modulo 4.
+uint32_t philox_phase(int kind, uint64_t pos_lo, uintptr_t out);
+// The shape generate calls of `kind` at `phase` use: its own, else the
+// process-wide one.
+mirng_philox_config philox_config_for(int kind, uint32_t phase);
+// Install (c != nullptr) or drop (c == nullptr) a kind's own shape at one
+// phase (0..3) or at all four (-1); kind valid.
+void philox_config_set_kind(int kind, int phase, const mirng_philox_config *c);
+// Whether `kind` has its own shape at `phase` (copied to *c if so and c !=
+// nullptr).
+bool philox_config_kind_set(int kind, int phase, mirng_philox_config *c);
 
 int device_cu_count();
 hipError_t ensure_device(int *dev);

@@ -9,9 +9,6 @@
 // base-64 digit powers (at most 4 + 5 matrix-vector products, done by one
 // wave); thread t then applies A^(t q) from a resident table and runs q
 // sequential steps, L at a time through LDS (the shared pass code).
-#include <map>
-#include <mutex>
-#include <utility>
 #include <vector>
 
 #include "internal.hpp"
@@ -96,6 +93,32 @@ __global__ __launch_bounds__(kThreads) void mrg_kernel(MrgLaunch a)
 
 // ---------------------------------------------------------------- tables
 
+// Every jump table the MRG32k3a kernels read, in one resident array per
+// GPU (a file-scope device array, so that no generate call allocates):
+//   per steps-per-thread value q = 16 << i, i < kNumQ: A^(t q) for t < 256
+//     (the thread table), then A^(k 64^d 256 q) for d < 4, k < 64 (chunk
+//     digits);
+//   A^(k 64^d 2^76) and A^(k 64^d 2^127), d < 5, k < 64 (substream and
+//     stream digits);
+//   A^(2^k), k < 192 (jumps by any 192-bit count).
+// Each entry is one matrix per component (18 words).  The host builds the
+// array once per process; the library's per-device set-up copies it to
+// each GPU (about 310 KB).  The jump tables stay in global memory rather
+// than LDS: a thread reads its own A^(t q) once per launch (18 words) and
+// the digit tables are read by one wave per group, so staging them in LDS
+// would copy far more than any group reads.
+constexpr int kNumQ = 7;                                       // q = 16 .. 1024
+constexpr size_t kUWords = (size_t)kThreads * kMatWords;       // thread table
+constexpr size_t kCWords = (size_t)kCDigits * 64 * kMatWords;  // chunk digits
+constexpr size_t kSWords = (size_t)kSDigits * 64 * kMatWords;  // spacing digits
+constexpr size_t kQWords = kUWords + kCWords;
+constexpr size_t kOffS76 = kNumQ * kQWords;
+constexpr size_t kOffS127 = kOffS76 + kSWords;
+constexpr size_t kOffPow2 = kOffS127 + kSWords;
+constexpr size_t kTabWords = kOffPow2 + (size_t)kPow2Entries * kMatWords;
+
+__device__ __align__(256) uint32_t g_mrg_tables[kTabWords];
+
 void put_mat(std::vector<uint32_t> &dst, size_t idx, const Mat3 &m1, const Mat3 &m2)
 {
     for (int i = 0; i < 9; ++i) {
@@ -104,97 +127,71 @@ void put_mat(std::vector<uint32_t> &dst, size_t idx, const Mat3 &m1, const Mat3 
     }
 }
 
-// Powers k * base for k < 64, written at [row][k].
-void digit_row(std::vector<uint32_t> &dst, size_t row, const Mat3 &b1, const Mat3 &b2)
+// Powers k * base for k < 64, written at [row][k] from entry `at`.
+void digit_row(std::vector<uint32_t> &dst, size_t at, size_t row, const Mat3 &b1,
+               const Mat3 &b2)
 {
     Mat3 p1 = mat_identity(), p2 = mat_identity();
     for (int k = 0; k < 64; ++k) {
-        put_mat(dst, row * 64 + k, p1, p2);
+        put_mat(dst, at + row * 64 + k, p1, p2);
         p1 = mat_mul(p1, b1, kM1);
         p2 = mat_mul(p2, b2, kM2);
     }
 }
 
-// A^n for n = 2^e * m with small m, through the power-of-two table.
-void pow_shifted(uint64_t mult, int shift, Mat3 &r1, Mat3 &r2)
+std::vector<uint32_t> build_tables()
 {
-    r1 = mat_identity();
-    r2 = mat_identity();
-    for (int b = 0; mult; ++b, mult >>= 1) {
-        if (mult & 1) {
-            r1 = mat_mul(r1, mrg_pow2(0, b + shift), kM1);
-            r2 = mat_mul(r2, mrg_pow2(1, b + shift), kM2);
+    std::vector<uint32_t> h(kTabWords);
+    for (int i = 0; i < kNumQ; ++i) {
+        const int lg = 4 + i;                   // q = 2^lg
+        const size_t at = (size_t)i * kQWords / kMatWords;
+        const Mat3 &aq1 = mrg_pow2(0, lg), &aq2 = mrg_pow2(1, lg);
+        Mat3 p1 = mat_identity(), p2 = mat_identity();
+        for (int t = 0; t < kThreads; ++t) {
+            put_mat(h, at + t, p1, p2);
+            p1 = mat_mul(p1, aq1, kM1);
+            p2 = mat_mul(p2, aq2, kM2);
+        }
+        // chunk digit d: base A^(64^d * 256 * q) = A^(2^(6d + 8 + lg))
+        for (int d = 0; d < kCDigits; ++d) {
+            const int e = 6 * d + 8 + lg;
+            digit_row(h, at + kThreads, d, mrg_pow2(0, e), mrg_pow2(1, e));
         }
     }
+    for (int d = 0; d < kSDigits; ++d) {
+        digit_row(h, kOffS76 / kMatWords, d, mrg_pow2(0, 76 + 6 * d), mrg_pow2(1, 76 + 6 * d));
+        digit_row(h, kOffS127 / kMatWords, d, mrg_pow2(0, 127 + 6 * d),
+                  mrg_pow2(1, 127 + 6 * d));
+    }
+    for (int k = 0; k < kPow2Entries; ++k)
+        put_mat(h, kOffPow2 / kMatWords + k, mrg_pow2(0, k), mrg_pow2(1, k));
+    return h;
 }
 
-struct DeviceTables {
-    uint32_t *u = nullptr;   // per q
-    uint32_t *c = nullptr;   // per q
-};
-
-std::mutex g_tab_mu;
-std::map<std::pair<int, uint32_t>, DeviceTables> g_q_tables;
-std::map<std::pair<int, int>, uint32_t *> g_sub_tables;   // (device, log2 spacing)
-
-hipError_t upload(const std::vector<uint32_t> &h, uint32_t **d)
+const std::vector<uint32_t> &host_tables()
 {
-    hipError_t err = hipMalloc((void **)d, h.size() * sizeof(uint32_t));
-    if (err != hipSuccess) return err;
-    return hipMemcpy(*d, h.data(), h.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
+    static const std::vector<uint32_t> h = build_tables();
+    return h;
 }
 
-hipError_t tables_for(int dev, uint32_t q, DeviceTables &out)
+const uint32_t *g_tab_dev[kMaxDevices];   // device address of g_mrg_tables, per GPU
+
+// Device address of the tables on `dev` (set up by mrg_tables_init).
+const uint32_t *tables_of(int dev)
 {
-    std::lock_guard<std::mutex> lk(g_tab_mu);
-    auto it = g_q_tables.find({dev, q});
-    if (it != g_q_tables.end()) {
-        out = it->second;
-        return hipSuccess;
-    }
-    // q is a power of two: A^q from the 2^k table
-    int lg = 0;
-    while ((1u << lg) < q) ++lg;
-    const Mat3 &aq1 = mrg_pow2(0, lg), &aq2 = mrg_pow2(1, lg);
-    std::vector<uint32_t> u((size_t)kThreads * kMatWords);
-    Mat3 p1 = mat_identity(), p2 = mat_identity();
-    for (int t = 0; t < kThreads; ++t) {
-        put_mat(u, t, p1, p2);
-        p1 = mat_mul(p1, aq1, kM1);
-        p2 = mat_mul(p2, aq2, kM2);
-    }
-    std::vector<uint32_t> c((size_t)kCDigits * 64 * kMatWords);
-    for (int d = 0; d < kCDigits; ++d) {
-        // base = A^(64^d * 256 * q) = A^(2^(6d + 8 + lg))
-        const int e = 6 * d + 8 + lg;
-        digit_row(c, d, mrg_pow2(0, e), mrg_pow2(1, e));
-    }
-    DeviceTables t;
-    hipError_t err = upload(u, &t.u);
-    if (err == hipSuccess) err = upload(c, &t.c);
-    if (err != hipSuccess) return err;
-    g_q_tables[{dev, q}] = t;
-    out = t;
-    return hipSuccess;
+    return (dev >= 0 && dev < kMaxDevices) ? g_tab_dev[dev] : nullptr;
 }
 
-// Digit tables A^(k 64^d 2^e), d < 5, for substreams (e = 76) or streams
-// (e = 127) spaced 2^e steps apart.
-hipError_t spacing_table(int dev, int e, uint32_t **out)
+// The thread and chunk tables of steps-per-thread q (a power of two in
+// [16, 1024]) on `dev`.
+hipError_t tables_for(int dev, uint32_t q, const uint32_t *&u, const uint32_t *&c)
 {
-    std::lock_guard<std::mutex> lk(g_tab_mu);
-    auto it = g_sub_tables.find({dev, e});
-    if (it != g_sub_tables.end()) {
-        *out = it->second;
-        return hipSuccess;
-    }
-    std::vector<uint32_t> s((size_t)kSDigits * 64 * kMatWords);
-    for (int d = 0; d < kSDigits; ++d) digit_row(s, d, mrg_pow2(0, e + 6 * d), mrg_pow2(1, e + 6 * d));
-    uint32_t *ptr = nullptr;
-    hipError_t err = upload(s, &ptr);
-    if (err != hipSuccess) return err;
-    g_sub_tables[{dev, e}] = ptr;
-    *out = ptr;
+    const uint32_t *base = tables_of(dev);
+    int i = 0;
+    while (i < kNumQ && (16u << i) != q) ++i;
+    if (!base || i == kNumQ) return hipErrorInvalidValue;
+    u = base + (size_t)i * kQWords;
+    c = u + kUWords;
     return hipSuccess;
 }
 
@@ -239,15 +236,12 @@ hipError_t run(const uint32_t st[6], const mirng_distribution *d, uint64_t s_fir
     hipError_t err = hipGetDevice(&dev);
     if (err != hipSuccess) return err;
     const uint32_t q = pick_q(d->kind, n_each, nsub);
-    DeviceTables tb;
-    err = tables_for(dev, q, tb);
+    const uint32_t *utab = nullptr, *ctab = nullptr;
+    err = tables_for(dev, q, utab, ctab);
     if (err != hipSuccess) return err;
     const bool use_sub = spacing_log2 > 0;
-    uint32_t *stab = nullptr;
-    if (use_sub) {
-        err = spacing_table(dev, spacing_log2, &stab);
-        if (err != hipSuccess) return err;
-    }
+    const uint32_t *stab = nullptr;
+    if (use_sub) stab = tables_of(dev) + (spacing_log2 == 76 ? kOffS76 : kOffS127);
     MrgLaunch a{};
     for (int i = 0; i < 6; ++i) a.st[i] = st[i];
     a.q = q;
@@ -257,8 +251,8 @@ hipError_t run(const uint32_t st[6], const mirng_distribution *d, uint64_t s_fir
     a.use_sub = use_sub ? 1 : 0;
     a.n_each = n_each;
     a.s_first = s_first;
-    a.u_tab = tb.u;
-    a.c_tab = tb.c;
+    a.u_tab = utab;
+    a.c_tab = ctab;
     a.s_tab = stab;
     a.out = out;
     fill_params(a, d);
@@ -269,42 +263,29 @@ hipError_t run(const uint32_t st[6], const mirng_distribution *d, uint64_t s_fir
     return launch(a, d->kind, groups, s);
 }
 
-std::map<int, uint32_t *> g_pow2_tables;
+}  // namespace
 
-hipError_t pow2_table(int dev, uint32_t **out)
+hipError_t mrg_tables_init(int dev)
 {
-    std::lock_guard<std::mutex> lk(g_tab_mu);
-    auto it = g_pow2_tables.find(dev);
-    if (it != g_pow2_tables.end()) {
-        *out = it->second;
-        return hipSuccess;
-    }
-    std::vector<uint32_t> h((size_t)64 * kMatWords);
-    for (int k = 0; k < 64; ++k) put_mat(h, k, mrg_pow2(0, k), mrg_pow2(1, k));
-    uint32_t *ptr = nullptr;
-    hipError_t err = upload(h, &ptr);
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    const std::vector<uint32_t> &h = host_tables();
+    void *p = nullptr;
+    hipError_t err = hipGetSymbolAddress(&p, HIP_SYMBOL(g_mrg_tables));
     if (err != hipSuccess) return err;
-    g_pow2_tables[dev] = ptr;
-    *out = ptr;
+    err = hipMemcpy(p, h.data(), h.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
+    if (err != hipSuccess) return err;
+    g_tab_dev[dev] = (const uint32_t *)p;
     return hipSuccess;
 }
 
-}  // namespace
-
 hipError_t mrg_batch_tables(int dev, MrgBatchTables &t)
 {
-    uint32_t *p2 = nullptr;
-    DeviceTables t4, t8;
-    hipError_t err = pow2_table(dev, &p2);
-    if (err == hipSuccess) err = tables_for(dev, 32 * kBatchMrgPasses, t4);
-    if (err == hipSuccess) err = tables_for(dev, 16 * kBatchMrgPasses, t8);
-    if (err != hipSuccess) return err;
-    t.pow2 = p2;
-    t.c_tab4 = t4.c;
-    t.u_tab4 = t4.u;
-    t.c_tab8 = t8.c;
-    t.u_tab8 = t8.u;
-    return hipSuccess;
+    const uint32_t *base = tables_of(dev);
+    if (!base) return hipErrorNotInitialized;
+    t.pow2 = base + kOffPow2;
+    hipError_t err = tables_for(dev, 32 * kBatchMrgPasses, t.u_tab4, t.c_tab4);
+    if (err == hipSuccess) err = tables_for(dev, 16 * kBatchMrgPasses, t.u_tab8, t.c_tab8);
+    return err;
 }
 
 hipError_t mrg_plain(const uint32_t st[6], const mirng_distribution *d, uint64_t n,

@@ -1,6 +1,6 @@
 // Continuous-batching scheduler (host only, no HIP): admission by in-flight
-// output bytes, arrival-order batching onto free executor slots, completion
-// bookkeeping and latency statistics.
+// output bytes, arrival-order batching onto free executor slots, per-slot
+// completion, resident-engine positions, and latency statistics.
 #include "scheduler.hpp"
 
 #include <algorithm>
@@ -18,12 +18,32 @@ uint64_t request_bytes(const mirng_request &r)
     return r.n * (f64 ? 8u : 4u);
 }
 
-Scheduler::Scheduler(Executor &ex, uint64_t capacity_bytes, size_t max_batch)
+namespace {
+
+// a += b over 192-bit little-endian limbs (mod 2^192).
+void add192(uint64_t a[3], const uint64_t *b, size_t nb)
+{
+    uint64_t carry = 0;
+    for (size_t i = 0; i < 3; ++i) {
+        const uint64_t add = i < nb ? b[i] : 0;
+        const uint64_t s1 = a[i] + add;
+        const uint64_t c1 = s1 < add ? 1 : 0;
+        const uint64_t s2 = s1 + carry;
+        const uint64_t c2 = s2 < carry ? 1 : 0;
+        a[i] = s2;
+        carry = c1 | c2;
+    }
+}
+
+}  // namespace
+
+Scheduler::Scheduler(Executor &ex, uint64_t capacity_bytes, size_t max_batch, size_t max_engines)
     : ex_(ex), capacity_(capacity_bytes), max_batch_(max_batch),
-      slot_busy_((size_t)ex.slots(), false)
+      slot_busy_((size_t)ex.slots(), false), slot_ready_((size_t)ex.slots(), false),
+      slot_batch_((size_t)ex.slots()), engines_(max_engines)
 {
     dispatcher_ = std::thread([this] { dispatch_loop(); });
-    completer_ = std::thread([this] { complete_loop(); });
+    for (int k = 0; k < ex.slots(); ++k) completers_.emplace_back([this, k] { complete_loop(k); });
 }
 
 Scheduler::~Scheduler()
@@ -34,7 +54,27 @@ Scheduler::~Scheduler()
     }
     cv_.notify_all();
     dispatcher_.join();
-    completer_.join();
+    for (std::thread &t : completers_) t.join();
+}
+
+// Queues an admitted job (mu_ held by the caller).
+mirng_status Scheduler::enqueue(const Job &j, uint64_t *ticket,
+                                const Clock::time_point *arrival)
+{
+    Ticket t;
+    t.submitted = arrival ? *arrival : Clock::now();
+    t.bytes = request_bytes(j.req);
+    t.n = j.req.n;
+    const uint64_t id = tickets_.size();
+    tickets_.push_back(t);
+    waiting_.push_back({id, j});
+    if (!have_first_ || t.submitted < first_) {
+        first_ = t.submitted;
+        have_first_ = true;
+    }
+    *ticket = id;
+    cv_.notify_all();
+    return MIRNG_OK;
 }
 
 mirng_status Scheduler::submit(const mirng_request &r, uint64_t *ticket,
@@ -47,19 +87,54 @@ mirng_status Scheduler::submit(const mirng_request &r, uint64_t *ticket,
         ++refused_;
         return MIRNG_E_CAPACITY;
     }
-    Ticket t;
-    t.submitted = arrival ? *arrival : Clock::now();
-    t.bytes = bytes;
-    t.n = r.n;
-    const uint64_t id = tickets_.size();
-    tickets_.push_back(t);
-    waiting_.push_back({id, r});
-    if (!have_first_ || t.submitted < first_) {
-        first_ = t.submitted;
-        have_first_ = true;
+    Job j{};
+    j.req = r;
+    return enqueue(j, ticket, arrival);
+}
+
+mirng_status Scheduler::engine_add(uint32_t e, int32_t type)
+{
+    std::lock_guard<std::mutex> lk(mu_);
+    if (e >= engines_.size() || (type != MIRNG_PHILOX4X32_10 && type != MIRNG_MRG32K3A))
+        return MIRNG_E_INVALID_ARG;
+    engines_[e] = EngineCount{};
+    engines_[e].type = type;
+    return MIRNG_OK;
+}
+
+mirng_status Scheduler::submit_engine(uint32_t e, const mirng_request &r, uint64_t words,
+                                      uint64_t *ticket, const Clock::time_point *arrival)
+{
+    std::lock_guard<std::mutex> lk(mu_);
+    if (stop_ || e >= engines_.size() || engines_[e].type == 0) return MIRNG_E_INVALID_ARG;
+    Job j{};
+    j.req = r;
+    j.req.engine_type = engines_[e].type;
+    if (request_bytes(j.req) > capacity_) {
+        ++refused_;
+        return MIRNG_E_CAPACITY;
     }
-    *ticket = id;
-    cv_.notify_all();
+    j.ref.slot = e;
+    j.ref.flags = kRefEngine;
+    for (int i = 0; i < 3; ++i) j.ref.skip[i] = engines_[e].consumed[i];
+    add192(engines_[e].consumed, &words, 1);
+    return enqueue(j, ticket, arrival);
+}
+
+mirng_status Scheduler::engine_skip(uint32_t e, const uint64_t *limbs, size_t nlimbs)
+{
+    std::lock_guard<std::mutex> lk(mu_);
+    if (e >= engines_.size() || engines_[e].type == 0 || nlimbs > 3) return MIRNG_E_INVALID_ARG;
+    add192(engines_[e].consumed, limbs, nlimbs);
+    return MIRNG_OK;
+}
+
+mirng_status Scheduler::engine_consumed(uint32_t e, int32_t *type, uint64_t consumed[3])
+{
+    std::lock_guard<std::mutex> lk(mu_);
+    if (e >= engines_.size() || engines_[e].type == 0) return MIRNG_E_INVALID_ARG;
+    *type = engines_[e].type;
+    for (int i = 0; i < 3; ++i) consumed[i] = engines_[e].consumed[i];
     return MIRNG_OK;
 }
 
@@ -152,15 +227,15 @@ void Scheduler::dispatch_loop()
         });
         if (waiting_.empty()) break;   // stopping, nothing left to launch
         const int slot = free_slot();
-        std::vector<mirng_request> reqs;
-        InFlight b{slot, {}, 0};
-        while (!waiting_.empty() && reqs.size() < max_batch_) {
+        std::vector<Job> jobs;
+        InFlight b;
+        while (!waiting_.empty() && jobs.size() < max_batch_) {
             const Waiting &w = waiting_.front();
             const uint64_t bytes = tickets_[w.ticket].bytes;
             if (inflight_bytes_ + b.bytes + bytes > capacity_) break;
             b.bytes += bytes;
             b.tickets.push_back(w.ticket);
-            reqs.push_back(w.req);
+            jobs.push_back(w.job);
             waiting_.pop_front();
         }
         inflight_bytes_ += b.bytes;
@@ -169,30 +244,32 @@ void Scheduler::dispatch_loop()
         log_.push_back(b.tickets);
         ++launching_;
         lk.unlock();
-        const mirng_status st = ex_.launch(slot, reqs);
+        const mirng_status st = ex_.launch(slot, jobs);
         lk.lock();
         --launching_;
         b.failed = st;
-        inflight_.push_back(std::move(b));
+        slot_batch_[(size_t)slot] = std::move(b);
+        slot_ready_[(size_t)slot] = true;
         cv_.notify_all();
     }
 }
 
-void Scheduler::complete_loop()
+void Scheduler::complete_loop(int slot)
 {
     ex_.bind_thread();
+    const size_t k = (size_t)slot;
     std::unique_lock<std::mutex> lk(mu_);
     for (;;) {
         cv_.wait(lk, [&] {
-            return !inflight_.empty() || (stop_ && waiting_.empty() && launching_ == 0);
+            return slot_ready_[k] || (stop_ && waiting_.empty() && launching_ == 0);
         });
-        if (inflight_.empty()) break;   // stopping, nothing left in flight
-        InFlight b = std::move(inflight_.front());
-        inflight_.pop_front();
+        if (!slot_ready_[k]) break;   // stopping, nothing left for this slot
+        InFlight b = std::move(slot_batch_[k]);
+        slot_ready_[k] = false;
         lk.unlock();
         std::vector<int32_t> st;
         mirng_status s = b.failed;
-        if (s == MIRNG_OK) s = ex_.wait(b.slot, st);
+        if (s == MIRNG_OK) s = ex_.wait(slot, st);
         const Clock::time_point now = Clock::now();
         lk.lock();
         for (size_t i = 0; i < b.tickets.size(); ++i) {
@@ -205,9 +282,9 @@ void Scheduler::complete_loop()
                 t.status = i < st.size() ? st[i] : (int32_t)MIRNG_E_DEVICE;
             ++completed_;
         }
-        last_ = now;
+        if (now > last_) last_ = now;
         inflight_bytes_ -= b.bytes;
-        slot_busy_[(size_t)b.slot] = false;
+        slot_busy_[k] = false;
         cv_.notify_all();
     }
 }

@@ -38,7 +38,7 @@ def test_exports_every_declared_symbol(L):
 
 
 def test_abi_version_and_status_strings(L):
-    assert L.mirng_abi_version() == 1
+    assert L.mirng_abi_version() == 2
     for s in range(7):
         assert L.mirng_status_string(s)
     assert L.mirng_status_string(99) == b"unknown status"
@@ -211,33 +211,60 @@ def test_philox_config_validation():
 
 
 def test_per_kind_philox_config_validation():
-    """Per-kind shapes: unknown kinds are UNSUPPORTED, bad shapes INVALID_ARG
-    (nothing changes), NULL drops the kind's own shape, and the process-wide
-    set drops them all (no device needed)."""
+    """Per-kind, per-phase shapes: unknown kinds are UNSUPPORTED, bad shapes
+    or phases INVALID_ARG (nothing changes), NULL drops the kind's own
+    shape, a shape set at one phase serves that phase only, and the
+    process-wide set drops them all (no device needed)."""
     import ctypes
     L = mr.lib()
     c = mr.philox_config()
     out = mr.PhiloxConfig()
-    assert L.mirng_philox_config_get_kind(0, ctypes.byref(out)) == 2      # UNSUPPORTED
-    assert L.mirng_philox_config_get_kind(9, ctypes.byref(out)) == 2
-    assert L.mirng_philox_config_get_kind(mr.UNIFORM_F32, None) == 1      # INVALID_ARG
-    assert L.mirng_philox_config_set_kind(9, None) == 2
+    assert L.mirng_philox_config_get_kind(0, 0, ctypes.byref(out)) == 2      # UNSUPPORTED
+    assert L.mirng_philox_config_get_kind(9, 0, ctypes.byref(out)) == 2
+    assert L.mirng_philox_config_get_kind(mr.UNIFORM_F32, 0, None) == 1      # INVALID_ARG
+    assert L.mirng_philox_config_get_kind(mr.UNIFORM_F32, 4, ctypes.byref(out)) == 1
+    assert L.mirng_philox_config_get_kind(mr.UNIFORM_F32, -1, ctypes.byref(out)) == 1
+    assert L.mirng_philox_config_set_kind(9, -1, None) == 2
+    assert L.mirng_philox_config_set_kind(mr.UNIFORM_F32, -2, None) == 1
     bad = mr.PhiloxConfig.from_buffer_copy(c)
     bad.block = 100
-    assert L.mirng_philox_config_set_kind(mr.UNIFORM_F32, ctypes.byref(bad)) == 1
+    assert L.mirng_philox_config_set_kind(mr.UNIFORM_F32, -1, ctypes.byref(bad)) == 1
     assert mr.philox_config(mr.UNIFORM_F32).as_dict() == c.as_dict()
     try:
         mr.set_philox_config(kind=mr.GAUSSIAN_F32, walk=0, block=512, waves_per_cu=64)
-        assert mr.philox_config(mr.GAUSSIAN_F32).block == 512
+        for ph in range(4):
+            assert mr.philox_config(mr.GAUSSIAN_F32, ph).block == 512
         assert mr.philox_config().as_dict() == c.as_dict()
         assert mr.philox_config(mr.UNIFORM_F32).as_dict() == c.as_dict()
         mr.clear_philox_config(mr.GAUSSIAN_F32)
         assert mr.philox_config(mr.GAUSSIAN_F32).as_dict() == c.as_dict()
+        # one phase only
+        mr.set_philox_config(kind=mr.BITS_U32, phase=2, walk=2, waves_per_cu=1)
+        assert mr.philox_config(mr.BITS_U32, 2).walk == 2
+        for ph in (0, 1, 3):
+            assert mr.philox_config(mr.BITS_U32, ph).as_dict() == c.as_dict()
+        mr.clear_philox_config(mr.BITS_U32, 2)
+        assert mr.philox_config(mr.BITS_U32, 2).as_dict() == c.as_dict()
         mr.set_philox_config(kind=mr.BITS_U32, walk=2, waves_per_cu=1)
         mr.set_philox_config(c)
         assert mr.philox_config(mr.BITS_U32).as_dict() == c.as_dict()
     finally:
         mr.set_philox_config(c)
+
+
+def test_philox_phase_of_position_and_output():
+    """Phase = (position - head * words per element) mod 4, head = elements
+    before the output on the 16-byte grid; Gaussian pairs that would
+    straddle the grid start at the output itself (head 0)."""
+    for kind, esz, wpe in ((mr.UNIFORM_F32, 4, 1), (mr.BITS_U32, 4, 1), (mr.UNIFORM_F64, 8, 2),
+                           (mr.GAUSSIAN_F32, 4, 1), (mr.GAUSSIAN_F64, 8, 2)):
+        for pos in (0, 1, 2, 3, 2**40 + 1, 2**64 - 1):
+            for mis in range(0, 16, esz):
+                head = mis // esz
+                if kind in (mr.GAUSSIAN_F32, mr.GAUSSIAN_F64) and head % 2:
+                    head = 0
+                want = (pos - head * wpe) % 4
+                assert mr.philox_phase(kind, pos, 0x10000 + mis) == want, (kind, pos, mis)
 
 
 def test_request_record_layout():
@@ -274,13 +301,15 @@ def test_autotune_argument_validation(L):
     c = mr.PhiloxConfig()
     ms = ctypes.c_float()
     fake = ctypes.c_void_p(0x10000)
-    assert L.mirng_autotune_philox(9, 16, fake, None, 0, 1, 1, ctypes.byref(c), ctypes.byref(ms)) == 2
-    assert L.mirng_autotune_philox(2, 0, fake, None, 0, 1, 1, None, None) == 1
-    assert L.mirng_autotune_philox(2, 16, None, None, 0, 1, 1, None, None) == 1
-    assert L.mirng_autotune_philox(2, 16, fake, None, -1, 1, 1, None, None) == 1
-    assert L.mirng_autotune_philox(2, 16, fake, None, 0, 0, 1, None, None) == 1
-    assert L.mirng_autotune_philox(2, 16, fake, None, 0, 1, 0, None, None) == 1
-    assert L.mirng_autotune_philox(3, 16, ctypes.c_void_p(0x10004), None, 0, 1, 1, None, None) == 1
+    assert L.mirng_autotune_philox(9, 1, 16, fake, None, 0, 1, 1, ctypes.byref(c),
+                                   ctypes.byref(ms)) == 2
+    assert L.mirng_autotune_philox(2, 1, 0, fake, None, 0, 1, 1, None, None) == 1
+    assert L.mirng_autotune_philox(2, 1, 16, None, None, 0, 1, 1, None, None) == 1
+    assert L.mirng_autotune_philox(2, 1, 16, fake, None, -1, 1, 1, None, None) == 1
+    assert L.mirng_autotune_philox(2, 1, 16, fake, None, 0, 0, 1, None, None) == 1
+    assert L.mirng_autotune_philox(2, 1, 16, fake, None, 0, 1, 0, None, None) == 1
+    assert L.mirng_autotune_philox(3, 1, 16, ctypes.c_void_p(0x10004), None, 0, 1, 1,
+                                   None, None) == 1
     b = mr.Batcher()
     reqs = mr.make_requests(2)
     bc = mr.BatchConfig()

@@ -17,18 +17,58 @@ def test_autotune_philox_installs_a_valid_shape():
     prev = mr.philox_config()
     try:
         buf = torch.empty(n, dtype=torch.float32, device="cuda")
-        cfg, ms = mr.autotune_philox(mr.UNIFORM_F32, n, buf, prewarm_ms=50, rounds=2, reps=3)
+        cfg, ms = mr.autotune_philox(mr.UNIFORM_F32, n, buf, prewarm_ms=50, rounds=2, reps=3,
+                                     offset=12345)
         torch.cuda.synchronize()
         assert ms > 0.0
-        # installed for the tuned kind only
-        assert mr.philox_config(mr.UNIFORM_F32).as_dict() == cfg.as_dict()
+        # installed for the tuned kind at the tuned phase only (12345 mod 4)
+        assert mr.philox_config(mr.UNIFORM_F32, 1).as_dict() == cfg.as_dict()
         assert mr.philox_config().as_dict() == prev.as_dict()
-        assert mr.philox_config(mr.BITS_U32).as_dict() == prev.as_dict()
+        assert mr.philox_config(mr.BITS_U32, 1).as_dict() == prev.as_dict()
+        for ph in (0, 2, 3):
+            assert mr.philox_config(mr.UNIFORM_F32, ph).as_dict() == prev.as_dict()
         e = mr.Engine(mr.PHILOX4X32_10, 0xFEEDFACE12345678, 12345)
-        got, out = gh.generate(e, mr.UNIFORM_F32, n, 4)
-        assert gh.guards_intact(out, 4, n * 4)
+        got, out = gh.generate(e, mr.UNIFORM_F32, n, 0)
+        assert gh.guards_intact(out, 0, n * 4)
         gh.assert_match(mr.UNIFORM_F32, got, gh.oracle_philox(0xFEEDFACE12345678, 12345,
                                                                mr.UNIFORM_F32, n))
+    finally:
+        mr.set_philox_config(prev)
+
+
+def test_phase_keyed_shapes_differ_and_match_the_oracle():
+    """Shapes installed for phase 0 and phase 1 of a kind differ (one each
+    by the autotuner's phase keying, set here explicitly so that they surely
+    differ), each launch uses its phase's shape, and both give the
+    oracle's values; the autotuner run at a phase-0 and at a phase-1
+    position installs its results at those phases only."""
+    import torch
+    prev = mr.philox_config()
+    n = (1 << 20) + 9
+    try:
+        mr.set_philox_config(kind=mr.UNIFORM_F32, phase=0, walk=2, block=256,
+                             blocks_per_lane=1, nontemporal=0)
+        mr.set_philox_config(kind=mr.UNIFORM_F32, phase=1, walk=0, block=1024,
+                             waves_per_cu=256, nontemporal=1)
+        assert mr.philox_config(mr.UNIFORM_F32, 0).walk == 2
+        assert mr.philox_config(mr.UNIFORM_F32, 1).walk == 0
+        for pos in (2**40, 2**40 + 1, 2**40 + 2):
+            e = mr.Engine(mr.PHILOX4X32_10, 31337, pos)
+            got, buf = gh.generate(e, mr.UNIFORM_F32, n, 0)
+            gh.assert_match(mr.UNIFORM_F32, got,
+                            gh.oracle_philox(31337, pos, mr.UNIFORM_F32, n))
+            assert gh.guards_intact(buf, 0, n * 4)
+        buf = torch.empty(n, dtype=torch.float32, device="cuda")
+        c0, _ = mr.autotune_philox(mr.BITS_U32, n, buf, prewarm_ms=20, rounds=1, reps=2,
+                                   offset=8)
+        c1, _ = mr.autotune_philox(mr.BITS_U32, n, buf, prewarm_ms=20, rounds=1, reps=2,
+                                   offset=9)
+        assert mr.philox_config(mr.BITS_U32, 0).as_dict() == c0.as_dict()
+        assert mr.philox_config(mr.BITS_U32, 1).as_dict() == c1.as_dict()
+        for pos in (8, 9):
+            e = mr.Engine(mr.PHILOX4X32_10, 5, pos)
+            got, _ = gh.generate(e, mr.BITS_U32, n, 0)
+            gh.assert_match(mr.BITS_U32, got, gh.oracle_philox(5, pos, mr.BITS_U32, n))
     finally:
         mr.set_philox_config(prev)
 
@@ -65,7 +105,7 @@ def test_autotune_cache_hit_installs_stored_shape(tmp_path):
         t0 = time.perf_counter()
         cfg2, ms2 = mr.autotune_philox(mr.UNIFORM_F32, n, buf, cache=mr.TuningCache(cache.path))
         assert time.perf_counter() - t0 < 0.2          # no timing loop ran
-        assert cfg2.as_dict() == cfg.as_dict() == mr.philox_config(mr.UNIFORM_F32).as_dict()
+        assert cfg2.as_dict() == cfg.as_dict() == mr.philox_config(mr.UNIFORM_F32, 1).as_dict()
         assert ms2 == ms
     finally:
         mr.set_philox_config(prev)
