@@ -4,7 +4,7 @@
 Headline (one "step"): create a Philox4x32-10 engine at a bulk-workload seed
 and offset and generate n = 2^28 uniform FP32 samples into a resident 1 GiB
 device buffer -- the generator and output the paper measures (Philox4x32x10
-uniform FP32 batches, arXiv:2109.01329 Sec. 6), at the bulk size.  `value`
+uniform FP32 batches, arXiv:2109.01329 Sec. 7), at the bulk size.  `value`
 is samples per second of those steps (Gsamples/s); the roofline object
 prices the generation kernel's average duration (HIP events on the stream it
 runs on) against HBM write bandwidth.
@@ -427,7 +427,7 @@ def serve_leg(mr, synth, torch, dev, cells=None, counts=(10500, 20000, 20000), s
 
 
 def tts_leg(mr, torch, iters=100, decades=range(0, 9)):
-    """The paper's RNG burner on this GPU (Sec. 5.1, Sec. 6): per batch size
+    """The paper's RNG burner on this GPU (Sec. 5.1, Sec. 7): per batch size
     n = 10^0 .. 10^8, `iters` iterations of the whole flow, each timed on
     the host clock: host and device allocation, generator construction and
     seeding, Philox4x32-10 uniform FP32 generation, synchronisation, copy of

@@ -18,7 +18,7 @@
  *   - pointer-based (USM-style) memory: the caller owns device memory and
  *     orders work with streams, as the paper's USM API does (Sec. 4.1).
  * The engines are the ones the paper names (Philox4x32x10 and an MRG-based
- * generator, Sec. 4.1 and Sec. 6), defined by Salmon et al. (SC'11) and
+ * generator, Sec. 4.1 and Sec. 7), defined by Salmon et al. (SC'11) and
  * L'Ecuyer (Oper. Res. 1999); substreams follow L'Ecuyer et al. (Oper.
  * Res. 2002).
  *
@@ -233,7 +233,7 @@ mirng_status mirng_generate_streams(mirng_engine e,
 /* Batched generation: thousands of independent requests of uneven sizes in
  * one persistent launch -- the inter-event batching that the paper leaves
  * for future work for its calorimeter application, whose events each draw
- * three uniforms per hit (Sec. 5.2, Sec. 6).  A batcher owns a ring of
+ * three uniforms per hit (Sec. 5.2, Sec. 7).  A batcher owns a ring of
  * pinned host staging slots and device tables, reused across calls.
  * Requests are validated on the device, per request: a request that fails
  * validation writes nothing and gets a non-OK status (see
@@ -360,7 +360,7 @@ mirng_status mirng_philox_config_set_kind(int32_t kind, int32_t phase,
 /* A serving loop over the batched launch: requests arrive one at a time
  * from any host thread and are answered asynchronously (continuous
  * batching).  The paper measures time-to-solution of single calls and
- * notes that many small calls are dominated by per-call overheads (Sec. 6);
+ * notes that many small calls are dominated by per-call overheads (Sec. 7);
  * a server amortises them by launching whatever has arrived as one batch
  * whenever one of its S streams is free.
  *
@@ -501,8 +501,8 @@ mirng_status mirng_server_stats_get(mirng_server s, mirng_server_stats *out);
  * each timing `reps` back-to-back launches with HIP events; a candidate's
  * score is its median round.  It synchronises the stream (host-blocking).
  * The paper notes that the block size chosen for a kernel matters (256 vs
- * 1024 threads, Sec. 6) and that per-architecture tuning is future work
- * (Sec. 7).  Results: the chosen shape and its time per launch in
+ * 1024 threads, Sec. 7) and that per-architecture tuning is future work
+ * (Sec. 8).  Results: the chosen shape and its time per launch in
  * milliseconds; either pointer may be NULL.  mirng_autotune_philox times
  * n outputs of `kind` into `out` from an engine at word position `offset`
  * (every launch restarts there) and installs the shape as the shape of

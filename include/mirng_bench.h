@@ -4,7 +4,7 @@
  * pointers, `void *` hipStream_t, status codes, asynchronous on the stream).
  *
  * The paper profiles per-kernel durations of its seeding, generation and
- * range-transform kernels (arXiv:2109.01329, Sec. 6, kernel-time figure);
+ * range-transform kernels (arXiv:2109.01329, Sec. 7, kernel-time figure);
  * these probes give the ceilings those durations are compared with here:
  * the HBM write bandwidth a store-only kernel reaches, the VALU rate of the
  * Philox rounds without stores, and the issue rates of the instructions

@@ -10,7 +10,7 @@
  *
  * Sources.  The paper (Pascuzzi & Goli, arXiv:2109.01329) names the two
  * engine families it serves -- Philox- and MRG-based generators (Sec. 4.1)
- * and Philox4x32x10 for its measurements (Sec. 6) -- and the oneMKL-style
+ * and Philox4x32x10 for its measurements (Sec. 7) -- and the oneMKL-style
  * distributions with a range (a, b) or (mean, stddev) (Sec. 4.1), plus the
  * range transform r * (b - a) + a applied after generation (Sec. 4.3,
  * transform listing).  It does not define the engines; those come from:

@@ -1,7 +1,7 @@
 // Batched generation: many independent requests of uneven sizes in two
 // persistent launches, one for Philox4x32-10 and one for MRG32k3a requests
 // (the inter-event batching the paper defers for its calorimeter
-// application, arXiv:2109.01329 Sec. 6).
+// application, arXiv:2109.01329 Sec. 7).
 //
 // plan:  one thread per request validates it (the ABI's rules), derives
 //        its Philox slot run (as the plain path does on the host) or its

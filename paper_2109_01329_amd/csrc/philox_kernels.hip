@@ -2,7 +2,7 @@
 //
 // The engine is the counter-based Philox-4x32 bijection with 10 rounds of
 // Salmon et al. (SC'11); the paper measures exactly this generator with
-// uniform FP32 output (arXiv:2109.01329, Sec. 6).  Its separate range-
+// uniform FP32 output (arXiv:2109.01329, Sec. 7).  Its separate range-
 // transform kernel (Sec. 4.3) is fused here into the store epilogue.
 //
 // Contiguous walk (philox_fill_kernel).  The output is cut

@@ -100,7 +100,7 @@ __device__ __forceinline__ double ln_fast(double x)
 // (recip_fast, sqrt_fast) instead of the IEEE sequences, whose exactness
 // this accuracy does not need.
 //   ln u1: u1 = 2^e m, m in [sqrt(1/2), sqrt(2)), ln m = 2 atanh(s) with
-//          s = (m - 1)/(m + 1), |s| <= 0.1716, series to s^11.
+//          s = (m - 1)/(m + 1), |s| <= 0.1716, series to s^9.
 //   sin/cos(2 pi u2): 2 u2 = k 2^-23; j = nearest quarter turn; the exact
 //          remainder t = (k - j 2^22) 2^-23 in [-1/4, 1/4]; Taylor series of
 //          sin(pi t) through t^9 (the rest below (pi/4)^10 / 11! = 2.2e-9

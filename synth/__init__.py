@@ -5,7 +5,7 @@ meta-seeds (1329 + k for workload k).
 
 Shapes follow the paper's two workloads (arXiv:2109.01329):
   * the RNG burner: Philox4x32x10 uniform FP32 batches of 1 .. 10^8
-    (Sec. 5.1 and Sec. 6);
+    (Sec. 5.1 and Sec. 7);
   * FastCaloSim: three uniforms per calorimeter hit, hits per event ranging
     from a few to O(10^4) secondaries (Sec. 5.2) -- here a lognormal hit
     count per event plus one Gaussian per hit.
