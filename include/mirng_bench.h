@@ -46,6 +46,23 @@ mirng_status mirng_bench_philox_nostore(uint64_t nblocks, uint32_t k0, uint32_t 
 mirng_status mirng_bench_valu(int32_t op, uint32_t threads, uint32_t iters,
                               uint32_t *sink, void *stream);
 
+/* Test-only: the pieces of the FP32 Gaussian transforms on single 24-bit
+ * inputs, so that a test can check every input (all 2^24 of each) against
+ * the oracle.  For i < n, k = first + i, the engine word is w = k << 8:
+ *   which 0: out (double)[i] = the Box-Muller radius sqrt(-2 ln u1),
+ *            u1 = (k + 1) 2^-24, as the FP32 Gaussian computes it before
+ *            its one rounding;
+ *   which 1: out (double)[2i], [2i+1] = (cos, sin)(2 pi u2), u2 = k 2^-24,
+ *            likewise; a Gaussian FP32 pair (z0, z1) is exactly
+ *            (RN32(r cos), RN32(r sin)) of these two factors;
+ *   which 2: out (float)[i] = the inverse-CDF Gaussian FP32 of w (mean 0,
+ *            sd 1), u = (k + 1/2) 2^-24.
+ * first + n must not exceed 2^24; out is device memory of n doubles, 2n
+ * doubles or n floats.  Otherwise INVALID_ARG; unknown `which` ->
+ * UNSUPPORTED.  Asynchronous on `stream`. */
+mirng_status mirng_bench_transform_f32(int32_t which, uint32_t first, uint32_t n, void *out,
+                                       void *stream);
+
 /* Open-loop load generator for the serving loop: submits reqs[i] to `s` at
  * arrival_s[i] seconds after the call starts (non-decreasing times; the
  * caller's thread sleeps until each one, spinning for the last 50 us),

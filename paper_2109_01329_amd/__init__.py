@@ -184,6 +184,8 @@ def lib() -> ctypes.CDLL:
                                        ctypes.c_int),
         "mirng_bench_valu": ([ctypes.c_int32, ctypes.c_uint32, ctypes.c_uint32, vp, vp],
                              ctypes.c_int),
+        "mirng_bench_transform_f32": ([ctypes.c_int32, ctypes.c_uint32, ctypes.c_uint32, vp, vp],
+                                      ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -641,3 +643,10 @@ def bench_philox_nostore(nblocks: int, sink, k0: int = 1, k1: int = 2, stream=No
 def bench_valu(op: int, threads: int, iters: int, sink, stream=None) -> None:
     _check(lib().mirng_bench_valu(op, threads, iters, _ptr(sink), _stream(stream)),
            "bench_valu")
+
+
+def bench_transform_f32(which: int, first: int, n: int, out, stream=None) -> None:
+    """Test-only FP32 transform pieces on the 24-bit inputs first .. first + n - 1
+    (0: Box-Muller radius, 1: (cos, sin) pairs, 2: inverse-CDF Gaussian)."""
+    _check(lib().mirng_bench_transform_f32(which, first, n, _ptr(out), _stream(stream)),
+           "bench_transform_f32")

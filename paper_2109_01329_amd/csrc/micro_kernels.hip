@@ -118,6 +118,24 @@ __global__ __launch_bounds__(256) void valu_kernel(uint32_t iters, uint32_t *sin
     }
 }
 
+// One FP32-transform piece per thread (see mirng_bench_transform_f32).
+__global__ __launch_bounds__(256) void transform_probe_kernel(int32_t which, uint32_t first,
+                                                              uint32_t n, void *out)
+{
+    const uint32_t i = blockIdx.x * 256u + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t w = (first + i) << 8;
+    if (which == 0) {
+        ((double *)out)[i] = bm_radius(w);
+    } else if (which == 1) {
+        const f64x2 cs = bm_unit(w);
+        ((double *)out)[2 * (size_t)i] = cs.x;
+        ((double *)out)[2 * (size_t)i + 1] = cs.y;
+    } else {
+        ((float *)out)[i] = icdf_f32(w);
+    }
+}
+
 }  // namespace
 }  // namespace mirng
 
@@ -178,6 +196,18 @@ mirng_status mirng_bench_philox_nostore(uint64_t nblocks, uint32_t k0, uint32_t 
     tu.waves_per_cu = 32;   // a full complement of resident waves, whatever the walk
     hipLaunchKernelGGL(philox_nostore_kernel, dim3((uint32_t)grid_for(nblocks, tu)),
                        dim3(tu.block), 0, (hipStream_t)stream, nblocks, k0, k1, sink);
+    return hipGetLastError() == hipSuccess ? MIRNG_OK : MIRNG_E_LAUNCH;
+}
+
+mirng_status mirng_bench_transform_f32(int32_t which, uint32_t first, uint32_t n, void *out,
+                                       void *stream)
+{
+    if (which < 0 || which > 2) return MIRNG_E_UNSUPPORTED;
+    if (n == 0) return MIRNG_OK;
+    if (!out || (uint64_t)first + n > (1ull << 24)) return MIRNG_E_INVALID_ARG;
+    if (ensure_device(nullptr) != hipSuccess) return MIRNG_E_DEVICE;
+    hipLaunchKernelGGL(transform_probe_kernel, dim3((n + 255u) / 256u), dim3(256), 0,
+                       (hipStream_t)stream, which, first, n, out);
     return hipGetLastError() == hipSuccess ? MIRNG_OK : MIRNG_E_LAUNCH;
 }
 

@@ -7,10 +7,11 @@
 // grid.  Rows are padded by 16 bytes so that 8 consecutive lanes reading
 // 16 bytes hit distinct banks.
 //
-// The recurrence runs in FP64: all products are below 2^53 and exact, the
-// quotient by m is rounded to the nearest integer with the 1.5 * 2^52
-// constant, and one conditional addition finishes the reduction.  The
-// results are the exact integers of the definition.
+// The recurrence runs in FP64 on balanced residues: all products are below
+// 2^53 and exact, and the quotient by m is rounded to the nearest integer
+// with the 1.5 * 2^52 constant; the output combines the two components'
+// canonical residues in 32-bit integer arithmetic.  The results are the
+// exact integers of the definition.
 #pragma once
 
 #include "internal.hpp"
@@ -78,31 +79,52 @@ __device__ __forceinline__ MrgState mrg_state(const uint32_t v[6])
 // integer (round to nearest even); subtracting it again gives that integer.
 constexpr double kRound = 0x1.8p52;
 
-// One step; returns the combined output y in [1, m1] as an exact double.
-// For each component, p = a x[n-2] - b x[n-3] (or the x2 analogue) is an
-// exact integer below 2^53 in magnitude; k = RN(p * RN(1/m)) is the nearest
-// integer to p / m up to 2e-10, so r = fma(-k, m, p) is exact and lies in
-// (-m, m), and one conditional addition of m gives p mod m.  Only full-rate
-// FP64 adds, multiplies and FMAs are used (no floor).
-__device__ __forceinline__ double mrg_step(MrgState &s)
+// p mod m as a balanced representative r in [-m/2 - 2, m/2 + 2]: k =
+// RN(p * RN(1/m)) is within 4e-10 of p / m (|p / m| < 2^21), so
+// r = fma(-k, m, p) = p - k m is exact.
+__device__ __forceinline__ double mod_balanced(double p, double m, double inv_m)
 {
-    double p1 = __builtin_fma(1403580.0, s.a1, -810728.0 * s.a0);
-    const double k1 = __builtin_fma(p1, kInvM1, kRound) - kRound;
-    p1 = __builtin_fma(-k1, kM1d, p1);
-    p1 = (p1 < 0.0) ? p1 + kM1d : p1;
-    double p2 = __builtin_fma(527612.0, s.b2, -1370589.0 * s.b0);
-    const double k2 = __builtin_fma(p2, kInvM2, kRound) - kRound;
-    p2 = __builtin_fma(-k2, kM2d, p2);
-    p2 = (p2 < 0.0) ? p2 + kM2d : p2;
-    s.a0 = s.a1; s.a1 = s.a2; s.a2 = p1;
-    s.b0 = s.b1; s.b1 = s.b2; s.b2 = p2;
-    const double y = p1 - p2;
-    return (p1 <= p2) ? y + kM1d : y;
+    const double k = __builtin_fma(p, inv_m, kRound) - kRound;
+    return __builtin_fma(-k, m, p);
 }
 
-__device__ __forceinline__ float y_to_u01f(double y)
+// One step; returns the combined output y in [1, m1].
+// The state words are integers held as doubles, each either in [0, m) (the
+// start state) or a balanced representative in [-m/2 - 2, m/2 + 2] (every
+// word a step writes), so |p| = |a x[n-2] - b x[n-3]| stays below 7.8e15 <
+// 2^53 for both components and every product is exact; the recurrence is
+// linear modulo m, so any representative gives the right residues.  Only
+// the output needs the canonical residues x1 in [0, m1), x2 in [0, m2):
+// with i = the balanced word as an int32, (uint32) i + m (mod 2^32) =
+// (uint32) i - 209 (m1) or - 22853 (m2) for negative i, and
+// y = x1 - x2 (+ m1 = - 209 mod 2^32 when x1 <= x2) in 32-bit wrap-around
+// arithmetic.  Only full-rate FP64 adds, multiplies and FMAs touch the
+// state.
+__device__ __forceinline__ uint32_t mrg_step(MrgState &s)
 {
-    return (float)(__builtin_floor(y * 0x1p-8) * 0x1p-24);
+    const double p1 = mod_balanced(__builtin_fma(1403580.0, s.a1, -810728.0 * s.a0), kM1d,
+                                   kInvM1);
+    const double p2 = mod_balanced(__builtin_fma(527612.0, s.b2, -1370589.0 * s.b0), kM2d,
+                                   kInvM2);
+    s.a0 = s.a1; s.a1 = s.a2; s.a2 = p1;
+    s.b0 = s.b1; s.b1 = s.b2; s.b2 = p2;
+    const int32_t i1 = (int32_t)p1;
+    const int32_t i2 = (int32_t)p2;
+    const uint32_t x1 = (uint32_t)i1 - ((uint32_t)(i1 >> 31) & 209u);
+    const uint32_t x2 = (uint32_t)i2 - ((uint32_t)(i2 >> 31) & 22853u);
+    return x1 - x2 - (x1 <= x2 ? 209u : 0u);
+}
+
+// Uniform FP32 of an output y: (y >> 8) 2^-24.
+__device__ __forceinline__ float y_to_u01f(uint32_t y)
+{
+    return (float)(y >> 8) * 0x1p-24f;
+}
+
+// Uniform FP64 of an output y: y RN(1 / (m1 + 1)).
+__device__ __forceinline__ double y_to_u01d(uint32_t y)
+{
+    return (double)y * kNorm;
 }
 
 template <int KIND>
@@ -125,12 +147,12 @@ __device__ __forceinline__ void mrg_fill_row(MrgState &s, char *row, const Epilo
 #pragma unroll 1
         for (int l = 0; l < S::L; ++l) {
             if constexpr (KIND == kIcdf) {
-                float f = icdf_f32((uint32_t)mrg_step(s));
+                float f = icdf_f32(mrg_step(s));
                 if (ep.ranged) f = __builtin_fmaf(f, ep.d32, ep.a32);
                 *(float *)(row + l * 4) = f;
             } else {
                 // u = y / (m1 + 1) as for uniform FP64: never 0 or 1
-                double d = normal_quantile(mrg_step(s) * kNorm);
+                double d = normal_quantile(y_to_u01d(mrg_step(s)));
                 if (ep.ranged) d = __builtin_fma(d, ep.d64, ep.a64);
                 *(double *)(row + l * 8) = d;
             }
@@ -140,8 +162,8 @@ __device__ __forceinline__ void mrg_fill_row(MrgState &s, char *row, const Epilo
     for (int l = 0; l < S::L; l += S::EPV) {
         u32x4 pk;
         if constexpr (KIND == kBits) {
-            pk.x = (uint32_t)mrg_step(s); pk.y = (uint32_t)mrg_step(s);
-            pk.z = (uint32_t)mrg_step(s); pk.w = (uint32_t)mrg_step(s);
+            pk.x = mrg_step(s); pk.y = mrg_step(s);
+            pk.z = mrg_step(s); pk.w = mrg_step(s);
         } else if constexpr (KIND == kU32F) {
             f32x4 f;
             f.x = y_to_u01f(mrg_step(s)); f.y = y_to_u01f(mrg_step(s));
@@ -155,16 +177,16 @@ __device__ __forceinline__ void mrg_fill_row(MrgState &s, char *row, const Epilo
             pk = __builtin_bit_cast(u32x4, f);
         } else if constexpr (KIND == kU64F) {
             f64x2 d;
-            d.x = mrg_step(s) * kNorm;
-            d.y = mrg_step(s) * kNorm;
+            d.x = y_to_u01d(mrg_step(s));
+            d.y = y_to_u01d(mrg_step(s));
             if (ep.ranged) {
                 d.x = __builtin_fma(d.x, ep.d64, ep.a64);
                 d.y = __builtin_fma(d.y, ep.d64, ep.a64);
             }
             pk = __builtin_bit_cast(u32x4, d);
         } else if constexpr (KIND == kGauss64) {
-            const double u1 = mrg_step(s) * kNorm;
-            const double u2 = mrg_step(s) * kNorm;
+            const double u1 = y_to_u01d(mrg_step(s));
+            const double u2 = y_to_u01d(mrg_step(s));
             f64x2 d = box_muller64(u1, u2);
             if (ep.ranged) {
                 d.x = __builtin_fma(d.x, ep.d64, ep.a64);
@@ -172,16 +194,16 @@ __device__ __forceinline__ void mrg_fill_row(MrgState &s, char *row, const Epilo
             }
             pk = __builtin_bit_cast(u32x4, d);
         } else if constexpr (KIND == kI32) {
-            pk.x = uniform_i32((uint32_t)mrg_step(s), ep.ia, ep.irm1);
-            pk.y = uniform_i32((uint32_t)mrg_step(s), ep.ia, ep.irm1);
-            pk.z = uniform_i32((uint32_t)mrg_step(s), ep.ia, ep.irm1);
-            pk.w = uniform_i32((uint32_t)mrg_step(s), ep.ia, ep.irm1);
+            pk.x = uniform_i32(mrg_step(s), ep.ia, ep.irm1);
+            pk.y = uniform_i32(mrg_step(s), ep.ia, ep.irm1);
+            pk.z = uniform_i32(mrg_step(s), ep.ia, ep.irm1);
+            pk.w = uniform_i32(mrg_step(s), ep.ia, ep.irm1);
         } else {
             static_assert(KIND == kGauss, "unknown kind");
-            const uint32_t w0 = (uint32_t)mrg_step(s);
-            const uint32_t w1 = (uint32_t)mrg_step(s);
-            const uint32_t w2 = (uint32_t)mrg_step(s);
-            const uint32_t w3 = (uint32_t)mrg_step(s);
+            const uint32_t w0 = mrg_step(s);
+            const uint32_t w1 = mrg_step(s);
+            const uint32_t w2 = mrg_step(s);
+            const uint32_t w3 = mrg_step(s);
             f32x4 f;
             f.xy = box_muller(w0, w1);
             f.zw = box_muller(w2, w3);
@@ -222,8 +244,29 @@ __device__ void mrg_store_pass(const char *lds, uint64_t e0, uint64_t stride, ui
     using S = MrgShape<KIND>;
     constexpr int ESZ = S::ESZ, EPV = S::EPV, VPR = S::VPR, L = S::L;
     const uint32_t h = (uint32_t)(((uintptr_t)out & 15u) / ESZ);
-    const uint32_t nv = VPR + (h ? 1u : 0u);
     const uint32_t t = threadIdx.x;
+    if (h == 0 && e0 + (uint64_t)(kMrgThreads - 1) * stride + L <= n) {
+        // The whole pass lies inside the output and `out` is 16-byte
+        // aligned: thread t stores vector t mod VPR of rows t / VPR + i RPI,
+        // i < VPR, so its LDS and global addresses advance by fixed steps.
+        constexpr uint32_t RPI = kMrgThreads / VPR;
+        static_assert(RPI * VPR == kMrgThreads, "rows per step");
+        const uint32_t j = t % VPR;
+        const uint32_t r = t / VPR;
+        const char *src = lds + r * S::ROW + j * 16;
+        char *dst = out + (e0 + (uint64_t)r * stride + j * EPV) * ESZ;
+        const uint64_t dstep = (uint64_t)RPI * stride * ESZ;
+#pragma unroll
+        for (int i = 0; i < VPR; ++i) {
+            const u32x4 val = *(const u32x4 *)(src + i * RPI * S::ROW);
+            if (nt)
+                __builtin_nontemporal_store(val, (g_u32x4 *)(dst + i * dstep));
+            else
+                *(g_u32x4 *)(dst + i * dstep) = val;
+        }
+        return;
+    }
+    const uint32_t nv = VPR + (h ? 1u : 0u);
     for (uint32_t vi = t; vi < (uint32_t)kMrgThreads * nv; vi += kMrgThreads) {
         const uint32_t row = vi / nv;
         const uint32_t j = vi - row * nv;

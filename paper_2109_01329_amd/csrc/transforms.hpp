@@ -9,6 +9,8 @@
 
 #include <cstdint>
 
+#include "bm_tables.hpp"
+
 namespace mirng {
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
@@ -93,50 +95,74 @@ __device__ __forceinline__ double ln_fast(double x)
     return __builtin_fma((double)e, 0x1.62e42fefa39efp-1, ln_m);
 }
 
-// Box-Muller on one word pair.  The radius and the rotation are evaluated
-// in FP64 to about 2^-28 relative error and rounded once to FP32, so each
-// output is within 0.56 ulp of the exact transform of the same two inputs.
-// The one division and the square root use refined hardware estimates
-// (recip_fast, sqrt_fast) instead of the IEEE sequences, whose exactness
-// this accuracy does not need.
-//   ln u1: u1 = 2^e m, m in [sqrt(1/2), sqrt(2)), ln m = 2 atanh(s) with
-//          s = (m - 1)/(m + 1), |s| <= 0.1716, series to s^9.
-//   sin/cos(2 pi u2): 2 u2 = k 2^-23; j = nearest quarter turn; the exact
-//          remainder t = (k - j 2^22) 2^-23 in [-1/4, 1/4]; Taylor series of
-//          sin(pi t) through t^9 (the rest below (pi/4)^10 / 11! = 2.2e-9
-//          relative) and cos(pi t) through t^10 (below 1.6e-10); rotate by
-//          j quarters.
+// Box-Muller radius r = sqrt(-2 ln u1) for FP32 outputs, u1 = v 2^-24 with
+// v = (wa >> 8) + 1 in [1, 2^24], to about 2^-29 relative error:
+//   v = 2^(31 - nz) m, m in [1, 2), so u1 = 2^e m with e = 7 - nz;
+//   j = m's nearest multiple of 1/128 (table entry j = 0..128, |f| <= 2^-8
+//   below), f = m invc_j - 1 with invc_j ~ 1 / (1 + j/128), and
+//   ln u1 = e ln 2 + ln(1 / invc_j) + ln(1 + f), ln(1 + f) = f - f^2/2 + f^3/3
+//   (the rest is below f^4/4, 2^-26 relative);
+//   L = -2 ln u1 sums the exponent and table terms first: for u1 just below 1
+//   (e = -1, j = 128) and for u1 = 1 (e = 0, j = 0) they cancel exactly, so
+//   L keeps the relative accuracy of its series term;
+//   r = sqrt(L) from the hardware reciprocal square root y (within 2^-24 on
+//   gfx950) corrected once, r = L y + (y / 2)(L - (L y)^2); L = 0 gives 0.
+__device__ __forceinline__ double bm_radius(uint32_t wa)
+{
+    const uint32_t v = (wa >> 8) + 1u;
+    const uint32_t nz = (uint32_t)__builtin_clz(v);
+    const uint32_t mi = v << nz;                               // m 2^31
+    const uint32_t j = (((mi >> 23) & 255u) + 1u) >> 1;
+    const double f = __builtin_fma((double)mi, kBmLogTab[j][0], -1.0);
+    const double f2 = f * f;
+    const double q = __builtin_fma(f, 0x1.5555555555555p-2, -0.5);
+    const double s = __builtin_fma(f2, q, f);                  // ln(1 + f)
+    const double base = __builtin_fma((double)(7 - (int32_t)nz), -0x1.62e42fefa39efp+0,
+                                      kBmLogTab[j][1]);
+    const double L = __builtin_fma(s, -2.0, base);
+    const double y = __builtin_amdgcn_rsq(__builtin_fmax(L, 0x1p-100));
+    const double r0 = L * y;
+    return __builtin_fma(0.5 * y, __builtin_fma(-r0, r0, L), r0);
+}
+
+// (cos, sin) of 2 pi u2 for FP32 outputs, u2 = k 2^-24 with k = wb >> 8, to
+// about 2^-29 relative error: j = k's nearest multiple of 2^16 (table entry
+// j mod 256, the angle 2 pi j / 256), x = 2 pi (k - 2^16 j) 2^-24 exactly
+// reduced (|x| <= pi / 256), sin x = x - x^3/6 (the rest below x^5/120) and
+// cos x = 1 - x^2/2 (the rest below x^4/24 = 2^-30), then the rotation
+// cos = C cos x - S sin x, sin = S cos x + C sin x by the entry's (S, C).
+// The table is exact at quarter turns, so the exact zeros of cos and sin
+// come out as zeros, and values next to them keep the series' relative
+// accuracy (the entries there have |S| or |C| = sin(2 pi / 256), at most
+// twice the result).
+__device__ __forceinline__ f64x2 bm_unit(uint32_t wb)
+{
+    // j mod 256 = the top 8 bits of k + 2^15, and k - 2^16 j is k's low 16
+    // bits read as a signed integer
+    const uint32_t jr = (wb + 0x800000u) >> 24;
+    const int32_t rem = (int32_t)(int16_t)(uint16_t)(wb >> 8);
+    const double S = kBmRotTab[jr][0];
+    const double C = kBmRotTab[jr][1];
+    const double x = (double)rem * 0x1.921fb54442d18p-22;      // 2 pi 2^-24
+    const double x2 = x * x;
+    const double sx = __builtin_fma(x * x2, -0x1.5555555555555p-3, x);
+    const double cx = __builtin_fma(x2, -0.5, 1.0);
+    f64x2 cs;
+    cs.x = __builtin_fma(C, cx, -(S * sx));
+    cs.y = __builtin_fma(S, cx, C * sx);
+    return cs;
+}
+
+// Box-Muller on one word pair, FP32 outputs: z0 = RN32(r cos), z1 = RN32(r
+// sin) from the two FP64 factors above, each within about 2^-29, so every
+// output is within 0.55 ulp of the exact transform of the same two inputs.
 __device__ __forceinline__ f32x2 box_muller(uint32_t wa, uint32_t wb)
 {
-    const double u1 = (double)((wa >> 8) + 1u) * 0x1p-24;
-    const double r = sqrt_fast(-2.0 * ln_fast(u1));
-
-    const uint32_t k = wb >> 8;
-    const uint32_t j = (k + (1u << 21)) >> 22;     // 0..4
-    const int32_t ti = (int32_t)k - (int32_t)(j << 22);
-    const double t = (double)ti * 0x1p-23;
-    const double t2 = t * t;
-    double sp = 0x1.50783487ee782p-4;
-    sp = __builtin_fma(sp, t2, -0x1.32d2cce62bd86p-1);
-    sp = __builtin_fma(sp, t2, 0x1.466bc6775aae2p+1);
-    sp = __builtin_fma(sp, t2, -0x1.4abbce625be53p+2);
-    sp = __builtin_fma(sp, t2, 0x1.921fb54442d18p+1);
-    sp = sp * t;                                   // sin(pi t)
-    double cp = -0x1.a6d1f2a204a8cp-6;
-    cp = __builtin_fma(cp, t2, 0x1.e1f506891babbp-3);
-    cp = __builtin_fma(cp, t2, -0x1.55d3c7e3cbffap+0);
-    cp = __builtin_fma(cp, t2, 0x1.03c1f081b5ac4p+2);
-    cp = __builtin_fma(cp, t2, -0x1.3bd3cc9be45dep+2);
-    cp = __builtin_fma(cp, t2, 1.0);               // cos(pi t)
-    const float rs = (float)(r * sp);
-    const float rc = (float)(r * cp);
-    const uint32_t quad = j & 3u;
-    // quad 0: (cos, sin) = ( C,  S); 1: (-S,  C); 2: (-C, -S); 3: ( S, -C)
-    const float c_abs = (quad & 1u) ? rs : rc;
-    const float s_abs = (quad & 1u) ? rc : rs;
+    const double r = bm_radius(wa);
+    const f64x2 cs = bm_unit(wb);
     f32x2 z;
-    z.x = (quad == 1u || quad == 2u) ? -c_abs : c_abs;
-    z.y = (quad >= 2u) ? -s_abs : s_abs;
+    z.x = (float)(r * cs.x);
+    z.y = (float)(r * cs.y);
     return z;
 }
 

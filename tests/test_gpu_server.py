@@ -264,9 +264,12 @@ def test_resident_engine_checkpoint_and_resume():
     import torch
     srv = mr.Server(streams=2, capacity_bytes=1 << 28, max_batch=4, max_engines=2)
     e = srv.engine_create(mr.MRG32K3A, 99, 5)
+    g = torch.empty(333, dtype=torch.float32, device="cuda")
     a = torch.empty(10000, dtype=torch.float32, device="cuda")
     b = torch.empty(10000, dtype=torch.float32, device="cuda")
-    srv.submit_engine(e, mr.GAUSSIAN_F32, 333, a)
+    # requests in flight together may run in any order: each gets its own
+    # output buffer
+    srv.submit_engine(e, mr.GAUSSIAN_F32, 333, g)
     ck = srv.engine_state(e)
     srv.submit_engine(e, mr.UNIFORM_F32, 10000, a)
     srv.drain()
