@@ -290,6 +290,55 @@ mirng_status mirng_batcher_statuses(mirng_batcher b, int32_t *statuses, size_t c
 mirng_status mirng_batcher_config_get(mirng_batcher b, mirng_batch_config *c);
 mirng_status mirng_batcher_config_set(mirng_batcher b, const mirng_batch_config *c);
 
+/* ------------------------------------------------ allocation-free batches */
+
+/* Limits of mirng_generate_batch_noalloc: requests per call, waves of its
+ * Philox generation grid, and the size of its fixed device scratch array. */
+#define MIRNG_NOALLOC_MAX_REQUESTS 16384
+#define MIRNG_NOALLOC_MAX_WAVES 65536
+#define MIRNG_NOALLOC_SCRATCH_BYTES (4u << 20)
+
+/* For callers that cannot allocate memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation): the batched
+ * generation of mirng_generate_batch without a batcher.  Same request
+ * semantics and the same planning and generation kernels, so each valid
+ * request's output is identical to mirng_generate_batch's; only the
+ * launch order differs (see below).
+ *   reqs: host array of `count` requests, copied by one hipMemcpyAsync on
+ *     `stream` into the library's scratch array.  With pinned host memory
+ *     the copy is asynchronous and the array must stay unchanged until the
+ *     copy has run on the stream; with pageable memory the runtime may
+ *     block the host until the copy is done.
+ *   statuses: caller-owned device buffer of `count` int32 (4-byte
+ *     aligned), receiving each request's mirng_status from the planning
+ *     kernel on `stream`.
+ *   cfg: launch shape of the generation kernels (NULL: the shape a new
+ *     batcher starts with); the Philox grid is capped at
+ *     MIRNG_NOALLOC_MAX_WAVES waves.
+ * The batch's device tables (the request table, per-request plans, prefix
+ * and wave tables) live in one fixed library-owned array of
+ * MIRNG_NOALLOC_SCRATCH_BYTES per GPU, in device memory that the library
+ * holds from the device's set-up (mirng_device_init, or the first call of
+ * any entry point on that device) until the process ends; nothing in the
+ * array needs clearing between calls (planning writes every table before
+ * the generation kernels read it).  This call allocates no device or host
+ * memory, creates no stream or event and makes no host synchronisation of
+ * its own (after the device's one-time set-up).  All work runs in order on
+ * `stream`: the copy, planning, then the Philox and MRG32k3a generation
+ * kernels one after the other.
+ * Concurrency: every call on one GPU uses that GPU's one array, which keeps
+ * the last call's contents.  Calls on the same stream are ordered and safe;
+ * calls that overlap on one GPU (different streams, or different host
+ * threads without ordering) race and may produce wrong outputs.
+ * Errors: count == 0 -> OK (nothing enqueued); reqs or statuses NULL, or
+ * statuses misaligned, or a bad cfg -> INVALID_ARG; count >
+ * MIRNG_NOALLOC_MAX_REQUESTS -> CAPACITY (nothing enqueued); device ->
+ * DEVICE; a failed copy or launch -> LAUNCH.  Invalid requests get their
+ * status in `statuses` and write nothing. */
+mirng_status mirng_generate_batch_noalloc(const mirng_request *reqs, size_t count,
+                                          int32_t *statuses,
+                                          const mirng_batch_config *cfg, void *stream);
+
 /* ------------------------------------------------------ launch configuration */
 
 /* Launch shape of the Philox kernels: the search space of the autotuner.

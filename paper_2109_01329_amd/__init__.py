@@ -150,6 +150,8 @@ def lib() -> ctypes.CDLL:
         "mirng_batcher_stage": ([vp, ctypes.c_size_t, ctypes.POINTER(vp)], ctypes.c_int),
         "mirng_generate_batch": ([vp, vp, ctypes.c_size_t, vp], ctypes.c_int),
         "mirng_batcher_statuses": ([vp, vp, ctypes.c_size_t], ctypes.c_int),
+        "mirng_generate_batch_noalloc": ([vp, ctypes.c_size_t, vp, ctypes.POINTER(BatchConfig),
+                                          vp], ctypes.c_int),
         "mirng_batcher_config_get": ([vp, ctypes.POINTER(BatchConfig)], ctypes.c_int),
         "mirng_batcher_config_set": ([vp, ctypes.POINTER(BatchConfig)], ctypes.c_int),
         "mirng_words_consumed": ([ctypes.c_int32, ctypes.c_int32, u64], u64),
@@ -620,6 +622,23 @@ class Server:
                                                arr.ctypes.data, len(reqs), tickets.ctypes.data,
                                                st.ctypes.data), "server_replay")
         return tickets, st
+
+
+# Limits of the allocation-free batch (the C header's MIRNG_NOALLOC_* values).
+NOALLOC_MAX_REQUESTS = 16384
+NOALLOC_MAX_WAVES = 65536
+
+
+def generate_batch_noalloc(reqs, statuses, config: BatchConfig | None = None,
+                           stream=None) -> None:
+    """Batched generation through the allocation-free entry point: `reqs`
+    is a host record array of `request_dtype()`, `statuses` a device int32
+    buffer of len(reqs) that receives each request's status on `stream`."""
+    import numpy as np
+    reqs = np.ascontiguousarray(reqs, dtype=request_dtype())
+    cfg = ctypes.byref(config) if config is not None else None
+    _check(lib().mirng_generate_batch_noalloc(reqs.ctypes.data, len(reqs), _ptr(statuses), cfg,
+                                              _stream(stream)), "generate_batch_noalloc")
 
 
 def make_requests(count: int):

@@ -32,6 +32,7 @@ SOURCES = [
     "autotune.cpp",
     "scheduler.cpp",
     "server.cpp",
+    "noalloc.hip",
 ]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -110,6 +110,7 @@ hipError_t ensure_device(int *dev_out)
         } else {
             // one-time set-up of this device (host-synchronous copies)
             err = mrg_tables_init(dev);
+            if (err == hipSuccess) err = noalloc_scratch_init(dev);
             if (err != hipSuccess) return err;   // retried on the next call
             g_dev_checked[dev] = 1;
         }

@@ -260,6 +260,9 @@ hipError_t mrg_batch_tables(int dev, MrgBatchTables &t);
 // Per-device set-up, once per device with that device current (called by
 // ensure_device): the resident MRG jump tables.
 hipError_t mrg_tables_init(int dev);
+// Per-device set-up of the allocation-free batch: looks up the device
+// address of its fixed scratch array on `dev` (the current device).
+hipError_t noalloc_scratch_init(int dev);
 
 // Launch shape and grids of a batch from one pass over its requests (host):
 // fills a.waves, a.mgroups, a.block, a.groups, a.nt and the flags of which
