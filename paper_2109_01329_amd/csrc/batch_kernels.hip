@@ -517,6 +517,7 @@ constexpr uint32_t kWideBlock = 256;
 template <bool WIDE>
 __global__ __launch_bounds__(WIDE ? kWideBlock : 1024) void batch_main_kernel(BatchArgs a)
 {
+    bm_stage();
     const uint32_t lane = threadIdx.x & 63u;
     const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     // the chunk prefix and this wave's first request (from the start
@@ -600,6 +601,7 @@ __global__ __launch_bounds__(kMrgThreads) void batch_mrg_kernel(BatchArgs a)
     __shared__ __attribute__((aligned(16))) char lds[kMrgThreads * MrgShape<kU32F>::ROW];
     __shared__ uint32_t wg_state[6];
     static_assert(MrgShape<kU64F>::ROW == MrgShape<kU32F>::ROW, "row size");
+    bm_stage();
     const ChunkPrefix p = chunk_prefix(a, 1);
     const uint64_t per = (p.total + a.mgroups - 1) / a.mgroups;
     uint64_t c = (uint64_t)blockIdx.x * per;

@@ -122,6 +122,7 @@ __global__ __launch_bounds__(256) void valu_kernel(uint32_t iters, uint32_t *sin
 __global__ __launch_bounds__(256) void transform_probe_kernel(int32_t which, uint32_t first,
                                                               uint32_t n, void *out)
 {
+    bm_stage();
     const uint32_t i = blockIdx.x * 256u + threadIdx.x;
     if (i >= n) return;
     const uint32_t w = (first + i) << 8;

@@ -42,6 +42,7 @@ __global__ __launch_bounds__(kThreads) void mrg_kernel(MrgLaunch a)
     using S = MrgShape<KIND>;
     __shared__ __attribute__((aligned(16))) char lds[kThreads * S::ROW];
     __shared__ uint32_t wg_state[6];
+    if constexpr (KIND == kGauss) bm_stage();
 
     const uint32_t t = threadIdx.x;
     const uint32_t g = blockIdx.x;

@@ -95,6 +95,24 @@ __device__ __forceinline__ double ln_fast(double x)
     return __builtin_fma((double)e, 0x1.62e42fefa39efp-1, ln_m);
 }
 
+// LDS copies of the two Box-Muller tables (6 KiB per workgroup).  Every
+// kernel that evaluates box_muller() (or its factors) calls bm_stage() at
+// its start, before any of its threads returns; kernels that do not are
+// given no LDS for them.  Per-lane lookups into LDS cost one ds_read_b128
+// each; from constant memory the same lookups went through the vector
+// memory path, where a wave's 64 scattered addresses take many cycles.
+static __shared__ __attribute__((aligned(16))) double s_bm_log[129][2];
+static __shared__ __attribute__((aligned(16))) double s_bm_rot[256][2];
+
+__device__ __forceinline__ void bm_stage()
+{
+    for (uint32_t i = threadIdx.x; i < 129u * 2u; i += blockDim.x)
+        (&s_bm_log[0][0])[i] = (&kBmLogTab[0][0])[i];
+    for (uint32_t i = threadIdx.x; i < 256u * 2u; i += blockDim.x)
+        (&s_bm_rot[0][0])[i] = (&kBmRotTab[0][0])[i];
+    __syncthreads();
+}
+
 // Box-Muller radius r = sqrt(-2 ln u1) for FP32 outputs, u1 = v 2^-24 with
 // v = (wa >> 8) + 1 in [1, 2^24], to about 2^-29 relative error:
 //   v = 2^(31 - nz) m, m in [1, 2), so u1 = 2^e m with e = 7 - nz;
@@ -113,12 +131,12 @@ __device__ __forceinline__ double bm_radius(uint32_t wa)
     const uint32_t nz = (uint32_t)__builtin_clz(v);
     const uint32_t mi = v << nz;                               // m 2^31
     const uint32_t j = (((mi >> 23) & 255u) + 1u) >> 1;
-    const double f = __builtin_fma((double)mi, kBmLogTab[j][0], -1.0);
+    const double f = __builtin_fma((double)mi, s_bm_log[j][0], -1.0);
     const double f2 = f * f;
     const double q = __builtin_fma(f, 0x1.5555555555555p-2, -0.5);
     const double s = __builtin_fma(f2, q, f);                  // ln(1 + f)
     const double base = __builtin_fma((double)(7 - (int32_t)nz), -0x1.62e42fefa39efp+0,
-                                      kBmLogTab[j][1]);
+                                      s_bm_log[j][1]);
     const double L = __builtin_fma(s, -2.0, base);
     const double y = __builtin_amdgcn_rsq(__builtin_fmax(L, 0x1p-100));
     const double r0 = L * y;
@@ -141,8 +159,8 @@ __device__ __forceinline__ f64x2 bm_unit(uint32_t wb)
     // bits read as a signed integer
     const uint32_t jr = (wb + 0x800000u) >> 24;
     const int32_t rem = (int32_t)(int16_t)(uint16_t)(wb >> 8);
-    const double S = kBmRotTab[jr][0];
-    const double C = kBmRotTab[jr][1];
+    const double S = s_bm_rot[jr][0];
+    const double C = s_bm_rot[jr][1];
     const double x = (double)rem * 0x1.921fb54442d18p-22;      // 2 pi 2^-24
     const double x2 = x * x;
     const double sx = __builtin_fma(x * x2, -0x1.5555555555555p-3, x);
