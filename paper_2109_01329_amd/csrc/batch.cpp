@@ -138,6 +138,7 @@ struct Work {
     int32_t philox = 0, mrg = 0;
     int32_t wide = 0;   // a Philox request only the wide kernel holds
     int32_t mrg_wide = 0;   // an MRG request only the wide MRG kernel holds
+    int32_t bm = 0;         // a request whose transform reads the LDS tables (either engine)
 };
 
 // Philox kinds whose transforms need many registers (FP64 Box-Muller, the
@@ -159,6 +160,7 @@ Work scan_requests(const mirng_request *q, size_t count)
         w.wide |= ph && wide_kind(q[i].dist.kind);
         w.mrg_wide |= mg && (q[i].dist.kind == MIRNG_GAUSSIAN_ICDF_F32 ||
                              q[i].dist.kind == MIRNG_GAUSSIAN_ICDF_F64);
+        w.bm |= mirng::uses_lds_tables(q[i].dist.kind);
         const uint64_t n = q[i].n;
         if (n == 0 || n >= (1ull << 32)) continue;
         const bool f64 = q[i].dist.kind == MIRNG_UNIFORM_F64 ||
@@ -239,6 +241,7 @@ void batch_grids(const mirng_batch_config &cfg, const mirng_request *reqs, size_
     a.philox = w.philox;
     a.mrg = w.mrg;
     a.mrg_wide = w.mrg_wide;
+    a.bm = w.bm;
     a.block = (uint32_t)cfg.block;
     a.groups = (uint32_t)(waves / wpb);
 }

@@ -476,7 +476,10 @@ __device__ __forceinline__ void run_kind(const BatchDesc &d, uint32_t s0, uint32
 // WIDE: the batch holds Philox Gaussian FP64 or inverse-CDF Gaussian
 // requests.  Their transforms need many more registers, so batches without
 // them run a kernel that does not contain them (and keeps its occupancy).
-template <bool WIDE>
+// BM: the batch holds Gaussian requests (either method, FP32 or FP64),
+// whose log and rotation tables the kernel stages in LDS; batches without
+// them run a kernel that neither stages the tables nor holds their LDS.
+template <bool WIDE, bool BM>
 __device__ void run_segment(const BatchDesc &d, uint32_t s0, uint32_t lo, uint32_t hi,
                             uint32_t lane)
 {
@@ -484,14 +487,22 @@ __device__ void run_segment(const BatchDesc &d, uint32_t s0, uint32_t lo, uint32
     case kBits: run_kind<kBits>(d, s0, lo, hi, lane); break;
     case kU32F: run_kind<kU32F>(d, s0, lo, hi, lane); break;
     case kU64F: run_kind<kU64F>(d, s0, lo, hi, lane); break;
-    case kGauss: run_kind<kGauss>(d, s0, lo, hi, lane); break;
+    case kGauss:
+        if constexpr (BM) run_kind<kGauss>(d, s0, lo, hi, lane);
+        break;
     case kI32: run_kind<kI32>(d, s0, lo, hi, lane); break;
     default:
         if constexpr (WIDE) {
             switch (d.kind) {
-            case kGauss64: run_kind<kGauss64>(d, s0, lo, hi, lane); break;
-            case kIcdf: run_kind<kIcdf>(d, s0, lo, hi, lane); break;
-            default: run_kind<kIcdf64>(d, s0, lo, hi, lane); break;
+            case kGauss64:
+                if constexpr (BM) run_kind<kGauss64>(d, s0, lo, hi, lane);
+                break;
+            case kIcdf:
+                if constexpr (BM) run_kind<kIcdf>(d, s0, lo, hi, lane);
+                break;
+            default:
+                if constexpr (BM) run_kind<kIcdf64>(d, s0, lo, hi, lane);
+                break;
             }
         }
         break;
@@ -514,10 +525,10 @@ __device__ __forceinline__ BatchDesc load_desc(const BatchDesc *p)
 // to 512 registers per lane instead of spilling past 128.
 constexpr uint32_t kWideBlock = 256;
 
-template <bool WIDE>
+template <bool WIDE, bool BM>
 __global__ __launch_bounds__(WIDE ? kWideBlock : 1024) void batch_main_kernel(BatchArgs a)
 {
-    bm_stage();
+    if constexpr (BM) bm_stage();
     const uint32_t lane = threadIdx.x & 63u;
     const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     // the chunk prefix and this wave's first request (from the start
@@ -547,7 +558,7 @@ __global__ __launch_bounds__(WIDE ? kWideBlock : 1024) void batch_main_kernel(Ba
             const uint32_t v1 = (uint32_t)((seg - start) * 64);
             const uint32_t lo = v0 > d.slot0 ? v0 - d.slot0 : 0u;
             const uint32_t hi = min(v1 - d.slot0, d.nunits);
-            run_segment<WIDE>(d, v0 - d.slot0, lo, hi, lane);
+            run_segment<WIDE, BM>(d, v0 - d.slot0, lo, hi, lane);
             t = seg;
         }
         ++r;
@@ -594,14 +605,16 @@ __device__ void mrg_chunk(const BatchDesc &d, uint64_t k, const uint32_t *c_tab,
 
 // WIDE: the batch holds MRG inverse-CDF requests, whose transforms need
 // about twice the registers of the others (halving the resident groups).
-template <bool WIDE>
+// BM: as for the Philox kernel (here the tables' 6 KiB of LDS would cost a
+// resident group per CU).
+template <bool WIDE, bool BM>
 __global__ __launch_bounds__(kMrgThreads) void batch_mrg_kernel(BatchArgs a)
 {
     // LDS rows are 144 bytes for every kind (32 x 4 or 16 x 8, plus 16)
     __shared__ __attribute__((aligned(16))) char lds[kMrgThreads * MrgShape<kU32F>::ROW];
     __shared__ uint32_t wg_state[6];
     static_assert(MrgShape<kU64F>::ROW == MrgShape<kU32F>::ROW, "row size");
-    bm_stage();
+    if constexpr (BM) bm_stage();
     const ChunkPrefix p = chunk_prefix(a, 1);
     const uint64_t per = (p.total + a.mgroups - 1) / a.mgroups;
     uint64_t c = (uint64_t)blockIdx.x * per;
@@ -625,15 +638,21 @@ __global__ __launch_bounds__(kMrgThreads) void batch_mrg_kernel(BatchArgs a)
                 case kBits: mrg_chunk<kBits>(d, k, a.c_tab4, a.u_tab4, lds, wg_state); break;
                 case kU32F: mrg_chunk<kU32F>(d, k, a.c_tab4, a.u_tab4, lds, wg_state); break;
                 case kU64F: mrg_chunk<kU64F>(d, k, a.c_tab8, a.u_tab8, lds, wg_state); break;
-                case kGauss: mrg_chunk<kGauss>(d, k, a.c_tab4, a.u_tab4, lds, wg_state); break;
-                case kGauss64: mrg_chunk<kGauss64>(d, k, a.c_tab8, a.u_tab8, lds, wg_state); break;
+                case kGauss:
+                    if constexpr (BM) mrg_chunk<kGauss>(d, k, a.c_tab4, a.u_tab4, lds, wg_state);
+                    break;
+                case kGauss64:
+                    if constexpr (BM) mrg_chunk<kGauss64>(d, k, a.c_tab8, a.u_tab8, lds, wg_state);
+                    break;
                 case kI32: mrg_chunk<kI32>(d, k, a.c_tab4, a.u_tab4, lds, wg_state); break;
                 default:
                     if constexpr (WIDE) {
-                        if (d.kind == kIcdf)
-                            mrg_chunk<kIcdf>(d, k, a.c_tab4, a.u_tab4, lds, wg_state);
-                        else
+                        if (d.kind == kIcdf) {
+                            if constexpr (BM)
+                                mrg_chunk<kIcdf>(d, k, a.c_tab4, a.u_tab4, lds, wg_state);
+                        } else if constexpr (BM) {
                             mrg_chunk<kIcdf64>(d, k, a.c_tab8, a.u_tab8, lds, wg_state);
+                        }
                     }
                     break;
                 }
@@ -673,18 +692,32 @@ hipError_t launch_batch_generate(const BatchArgs &a, hipStream_t s)
             const uint32_t blk = a.block < kWideBlock ? a.block : kWideBlock;
             const uint32_t wpb = blk / 64u;
             const uint32_t groups = (a.waves + wpb - 1u) / wpb;
-            hipLaunchKernelGGL(batch_main_kernel<true>, dim3(groups), dim3(blk), 0, s, a);
-        } else
-            hipLaunchKernelGGL(batch_main_kernel<false>, dim3(a.groups), dim3(a.block), 0, s, a);
+            if (a.bm)
+                hipLaunchKernelGGL((batch_main_kernel<true, true>), dim3(groups), dim3(blk), 0, s,
+                                   a);
+            else
+                hipLaunchKernelGGL((batch_main_kernel<true, false>), dim3(groups), dim3(blk), 0,
+                                   s, a);
+        } else if (a.bm) {
+            hipLaunchKernelGGL((batch_main_kernel<false, true>), dim3(a.groups), dim3(a.block), 0,
+                               s, a);
+        } else {
+            hipLaunchKernelGGL((batch_main_kernel<false, false>), dim3(a.groups), dim3(a.block),
+                               0, s, a);
+        }
         err = hipGetLastError();
         if (err != hipSuccess) return err;
     }
     if (a.mrg) {
-        if (a.mrg_wide)
-            hipLaunchKernelGGL(batch_mrg_kernel<true>, dim3(a.mgroups), dim3(kMrgThreads), 0, s, a);
+        const dim3 grid(a.mgroups), block(kMrgThreads);
+        if (a.mrg_wide && a.bm)
+            hipLaunchKernelGGL((batch_mrg_kernel<true, true>), grid, block, 0, s, a);
+        else if (a.mrg_wide)
+            hipLaunchKernelGGL((batch_mrg_kernel<true, false>), grid, block, 0, s, a);
+        else if (a.bm)
+            hipLaunchKernelGGL((batch_mrg_kernel<false, true>), grid, block, 0, s, a);
         else
-            hipLaunchKernelGGL(batch_mrg_kernel<false>, dim3(a.mgroups), dim3(kMrgThreads), 0, s,
-                               a);
+            hipLaunchKernelGGL((batch_mrg_kernel<false, false>), grid, block, 0, s, a);
         err = hipGetLastError();
     }
     return err;

@@ -74,6 +74,12 @@ constexpr int elem_bytes(int kind)
 constexpr int philox_words_per_elem(int kind) { return elem_bytes(kind) == 8 ? 2 : 1; }
 // Kinds whose outputs come in pairs from one Box-Muller transform.
 constexpr bool paired(int kind) { return kind == kGauss || kind == kGauss64; }
+// Kinds whose transforms read the log and rotation tables that kernels
+// stage in LDS (bm_stage in transforms.hpp).
+constexpr bool uses_lds_tables(int kind)
+{
+    return kind == kGauss || kind == kGauss64 || kind == kIcdf || kind == kIcdf64;
+}
 // Kinds with a range (or mean / sd) step that the defaults make a no-op.
 constexpr bool has_range_step(int kind) { return kind != kBits && kind != kI32; }
 
@@ -241,6 +247,7 @@ struct BatchArgs {
     int32_t philox;         // some request names Philox4x32-10 (host scan)
     int32_t mrg;            // some request names MRG32k3a (host scan)
     int32_t mrg_wide;       // some MRG32k3a request is an inverse-CDF Gaussian
+    int32_t bm;             // some request's transform reads the LDS tables (uses_lds_tables)
     const uint32_t *pow2;   // MRG A^(2^k), k < 64: [k][comp][9]
     const uint32_t *c_tab4, *u_tab4;   // MRG chunk / thread jumps, 4-byte kinds
     const uint32_t *c_tab8, *u_tab8;   // MRG chunk / thread jumps, FP64

@@ -42,7 +42,7 @@ __global__ __launch_bounds__(kThreads) void mrg_kernel(MrgLaunch a)
     using S = MrgShape<KIND>;
     __shared__ __attribute__((aligned(16))) char lds[kThreads * S::ROW];
     __shared__ uint32_t wg_state[6];
-    if constexpr (KIND == kGauss) bm_stage();
+    if constexpr (uses_lds_tables(KIND)) bm_stage();
 
     const uint32_t t = threadIdx.x;
     const uint32_t g = blockIdx.x;
@@ -87,7 +87,7 @@ __global__ __launch_bounds__(kThreads) void mrg_kernel(MrgLaunch a)
         if (e0 >= a.n_each) break;   // uniform per group
         mrg_fill_row<KIND>(s, row, a.ep);
         __syncthreads();
-        mrg_store_pass<KIND>(lds, e0, a.q, a.n_each, sub_out, 1);
+        mrg_store_pass<KIND>(lds, e0, a.q, a.n_each, sub_out, a.ep.nt);
         __syncthreads();
     }
 }
@@ -198,11 +198,18 @@ hipError_t tables_for(int dev, uint32_t q, const uint32_t *&u, const uint32_t *&
 
 // Steps per thread: a power of two in [L, 1024] (L = outputs per pass: 32,
 // or 16 for FP64) chosen so that a launch has about 2048 workgroups (8 per
-// CU) when the size allows, without leaving half a group idle.
+// CU) for 4-byte outputs and 16384 for 8-byte ones, when the size allows,
+// without leaving half a group idle.  A pass writes one 128-byte row per
+// thread, rows q elements apart: FP64 outputs, at twice the bytes per step,
+// ran 1.5 times faster with the rows 512 bytes apart (q = 64 at 2^28
+// outputs) than 4 KiB apart (q = 512), while 4-byte outputs ran fastest at
+// q = 512, where the per-thread and per-group jumps cost least.
 uint32_t pick_q(int kind, uint64_t n_each, uint64_t nsub)
 {
-    uint32_t q = elem_bytes(kind) == 8 ? 16 : 32;   // L outputs per pass
-    while (q < 1024 && (uint64_t)kThreads * q * 2048 < n_each * nsub &&
+    const bool wide = elem_bytes(kind) == 8;
+    const uint64_t groups = wide ? 16384 : 2048;
+    uint32_t q = wide ? 16 : 32;   // L outputs per pass
+    while (q < 1024 && (uint64_t)kThreads * q * groups < n_each * nsub &&
            (uint64_t)kThreads * q * 2 <= n_each)
         q <<= 1;
     return q;
@@ -225,9 +232,12 @@ hipError_t launch(const MrgLaunch &a, int kind, uint64_t groups, hipStream_t s)
     return hipGetLastError();
 }
 
+// Streaming stores for 4-byte outputs; ordinary stores for FP64 outputs,
+// which measured faster with them (0.52 against 0.56 ms per 2^28 uniform
+// FP64 outputs at q = 512).
 void fill_params(MrgLaunch &a, const mirng_distribution *d)
 {
-    a.ep = epilogue_of(d->kind, d->p0, d->p1, 1);
+    a.ep = epilogue_of(d->kind, d->p0, d->p1, elem_bytes(d->kind) == 8 ? 0 : 1);
 }
 
 hipError_t run(const uint32_t st[6], const mirng_distribution *d, uint64_t s_first,

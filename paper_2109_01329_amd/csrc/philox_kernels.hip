@@ -56,7 +56,7 @@ __global__ __launch_bounds__(1024) void philox_blocks_kernel(PhiloxBlocks a)
     constexpr int EPB = 16 / elem_bytes(KIND);        // elements per block
     constexpr int ESZ = 16 / EPB;
     constexpr uint32_t PER = 64u * BPL;               // blocks per wave step
-    if constexpr (KIND == kGauss) bm_stage();
+    if constexpr (uses_lds_tables(KIND)) bm_stage();
     const uint32_t lane = threadIdx.x & 63u;
     const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
     const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
@@ -82,7 +82,7 @@ __global__ __launch_bounds__(1024) void philox_blocks_kernel(PhiloxBlocks a)
 template <int KIND, int PHASE>
 __global__ __launch_bounds__(1024) void philox_fill_kernel(PhiloxFill a)
 {
-    if constexpr (KIND == kGauss) bm_stage();
+    if constexpr (uses_lds_tables(KIND)) bm_stage();
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t wave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     const uint64_t first = (uint64_t)wave * a.slots_per_wave;
@@ -101,7 +101,7 @@ template <int KIND, int PHASE, int ITERS>
 __global__ __launch_bounds__(1024) void philox_chunk_kernel(PhiloxFill a)
 {
     constexpr uint32_t PER = (PHASE ? 63u : 64u) * ITERS;   // slots per wave
-    if constexpr (KIND == kGauss) bm_stage();
+    if constexpr (uses_lds_tables(KIND)) bm_stage();
     const uint32_t lane = threadIdx.x & 63u;
     const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     const uint64_t first = wave * PER;
@@ -171,7 +171,7 @@ template <int KIND, int PHASE, int ITERS>
 __global__ __launch_bounds__(1024) void philox_group_kernel(PhiloxFill a)
 {
     __shared__ u32x4 heads[16 * ITERS + 1];
-    if constexpr (KIND == kGauss) bm_stage();
+    if constexpr (uses_lds_tables(KIND)) bm_stage();
     const uint32_t nw = blockDim.x >> 6;
     // the group's blocks, the one past it included (group-uniform choice)
     const uint64_t last = ((uint64_t)blockIdx.x + 1u) * nw * ITERS * 64u;

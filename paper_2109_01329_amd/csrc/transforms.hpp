@@ -10,6 +10,7 @@
 #include <cstdint>
 
 #include "bm_tables.hpp"
+#include "icdf_coeffs.hpp"
 
 namespace mirng {
 
@@ -45,68 +46,53 @@ __device__ __forceinline__ double u01d(uint32_t lo, uint32_t hi)
     return __builtin_fma((double)hi, 0x1p-32, (double)(lo >> 11) * 0x1p-53);
 }
 
-// 1/d for positive normal d: the hardware estimate refined by one Newton
-// step, which squares its relative error.  The gfx950 estimate (v_rcp_f64)
-// measured within 4.6e-8 (2^-24.4) relative over 2^22 arguments spanning
-// 2^-40 .. 2^40, and within 2.2e-15 (2^-48.7) after the step.
-__device__ __forceinline__ double recip_fast(double d)
+// A constant-memory table behind a pointer that the compiler cannot see
+// through: its entries are then loaded as wave-uniform scalars and used
+// directly as FMA operands (folded into FP64 literals, each would need a
+// move into a VGPR pair first, on this chip one instruction per use).
+typedef const __attribute__((address_space(4))) double c_f64;
+
+__device__ __forceinline__ c_f64 *scalar_table(const double *p)
 {
-    const double r = __builtin_amdgcn_rcp(d);
-    const double e = __builtin_fma(-d, r, 1.0);
-    return __builtin_fma(r, e, r);
+    c_f64 *q = (c_f64 *)p;
+    asm volatile("" : "+s"(q));
+    return q;
 }
 
-// sqrt(x) for x in [0, 34] as x * (1 / sqrt(x)): the hardware reciprocal
-// square root of max(x, 2^-100) refined by one Newton step, so x = 0 gives
-// 0.  The gfx950 estimate (v_rsq_f64) measured within 5.2e-8 (2^-24.2)
-// relative over the same arguments, and within 4.1e-15 (2^-47.8) after the
-// step.
-__device__ __forceinline__ double sqrt_fast(double x)
+// a b + c with c a wave-uniform scalar: one v_fma_f64 with c in an SGPR
+// pair.  (The compiler's own choice for a Horner step is v_fmac_f64, whose
+// addend is also its destination, so every uniform coefficient was first
+// copied into a VGPR pair: three instructions per step instead of one.)
+__device__ __forceinline__ double fma_su(double a, double b, double c)
 {
-    const double xs = __builtin_fmax(x, 0x1p-100);
-    const double h = 0.5 * xs;
-    double y = __builtin_amdgcn_rsq(xs);
-    const double e = __builtin_fma(-h * y, y, 0.5);
-    y = __builtin_fma(y, e, y);
-    return x * y;
+    double r;
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(c));
+    return r;
 }
 
-// ln x for positive normal x in (0, 1], to about 2^-29 relative error (the
-// budget of FP32 outputs): x = 2^e m with m in [sqrt(1/2), sqrt(2)),
-// ln m = 2 atanh(s), s = (m - 1)/(m + 1), |s| <= 0.1716, series to s^9
-// (the omitted terms stay below s^10 / 11 * 1.03 <= 2.1e-9 relative), plus
-// e ln 2 (for e != 0, |ln x| >= ln 2 - |ln m|, so nothing cancels).
-__device__ __forceinline__ double ln_fast(double x)
+// c[0] + c[1] t + ... + c[N - 1] t^(N - 1) by Horner's rule, the
+// coefficients read as scalars.
+template <int N>
+__device__ __forceinline__ double horner_s(c_f64 *c, double t)
 {
-    int e;
-    double m = __builtin_frexp(x, &e);             // [0.5, 1)
-    const bool low = m < 0x1.6a09e667f3bcdp-1;     // sqrt(1/2)
-    m = low ? m * 2.0 : m;
-    e = low ? e - 1 : e;
-    const double f = m - 1.0;
-    const double s = f * recip_fast(m + 1.0);
-    const double s2 = s * s;
-    double q = 0x1.c71c71c71c71cp-4;               // 1/9
-    q = __builtin_fma(q, s2, 0x1.2492492492492p-3); // 1/7
-    q = __builtin_fma(q, s2, 0x1.999999999999ap-3); // 1/5
-    q = __builtin_fma(q, s2, 0x1.5555555555555p-2); // 1/3
-    q = __builtin_fma(q, s2, 1.0);
-    const double ln_m = 2.0 * s * q;
-    return __builtin_fma((double)e, 0x1.62e42fefa39efp-1, ln_m);
+    double p = fma_su(c[N - 1], t, c[N - 2]);
+#pragma unroll
+    for (int k = N - 3; k >= 0; --k) p = fma_su(p, t, c[k]);
+    return p;
 }
 
-// LDS copies of the two Box-Muller tables (6 KiB per workgroup).  Every
-// kernel that evaluates box_muller() (or its factors) calls bm_stage() at
-// its start, before any of its threads returns; kernels that do not are
-// given no LDS for them.  Per-lane lookups into LDS cost one ds_read_b128
+// LDS copies of the two Box-Muller tables (8 KiB per workgroup).  Every
+// kernel that evaluates box_muller() (or its factors), icdf_f32() or
+// normal_quantile() calls bm_stage() at its start, before any of its
+// threads returns; kernels that do not are given no LDS for them.  Per-lane lookups into LDS cost one ds_read_b128
 // each; from constant memory the same lookups went through the vector
 // memory path, where a wave's 64 scattered addresses take many cycles.
-static __shared__ __attribute__((aligned(16))) double s_bm_log[129][2];
+static __shared__ __attribute__((aligned(16))) double s_bm_log[129][4];
 static __shared__ __attribute__((aligned(16))) double s_bm_rot[256][2];
 
 __device__ __forceinline__ void bm_stage()
 {
-    for (uint32_t i = threadIdx.x; i < 129u * 2u; i += blockDim.x)
+    for (uint32_t i = threadIdx.x; i < 129u * 4u; i += blockDim.x)
         (&s_bm_log[0][0])[i] = (&kBmLogTab[0][0])[i];
     for (uint32_t i = threadIdx.x; i < 256u * 2u; i += blockDim.x)
         (&s_bm_rot[0][0])[i] = (&kBmRotTab[0][0])[i];
@@ -184,50 +170,6 @@ __device__ __forceinline__ f32x2 box_muller(uint32_t wa, uint32_t wb)
     return z;
 }
 
-// ln x for x in (0, 1] in FP64, to a few ulp: x = 2^e m with m in
-// [sqrt(1/2), sqrt(2)), f = m - 1 (exact), s = f / (m + 1) from the refined
-// reciprocal and one Newton step on the quotient, ln m = 2 atanh(s) =
-// 2 s + s^3 (2/3 + 2/5 s^2 + ... + 2/21 s^18) (|s| <= 0.1716: the omitted
-// terms stay below 2.4e-17 relative), plus e ln 2 with ln 2 split so that
-// e ln2_hi is exact (ln2_hi has 42 significant bits, |e| < 2^11).
-__device__ __forceinline__ double ln_f64(double x)
-{
-    int e;
-    double m = __builtin_frexp(x, &e);             // [0.5, 1)
-    const bool low = m < 0x1.6a09e667f3bcdp-1;     // sqrt(1/2)
-    m = low ? m * 2.0 : m;
-    e = low ? e - 1 : e;
-    const double f = m - 1.0;
-    const double d = m + 1.0;
-    const double r = recip_fast(d);
-    double s = f * r;
-    s = __builtin_fma(r, __builtin_fma(-s, d, f), s);
-    const double s2 = s * s;
-    double q = 0x1.8618618618618p-4;                 // 2/21
-    q = __builtin_fma(q, s2, 0x1.af286bca1af28p-4);  // 2/19
-    q = __builtin_fma(q, s2, 0x1.e1e1e1e1e1e1ep-4);  // 2/17
-    q = __builtin_fma(q, s2, 0x1.1111111111111p-3);  // 2/15
-    q = __builtin_fma(q, s2, 0x1.3b13b13b13b14p-3);  // 2/13
-    q = __builtin_fma(q, s2, 0x1.745d1745d1746p-3);  // 2/11
-    q = __builtin_fma(q, s2, 0x1.c71c71c71c71cp-3);  // 2/9
-    q = __builtin_fma(q, s2, 0x1.2492492492492p-2);  // 2/7
-    q = __builtin_fma(q, s2, 0x1.999999999999ap-2);  // 2/5
-    q = __builtin_fma(q, s2, 0x1.5555555555555p-1);  // 2/3
-    const double ln_m = __builtin_fma(s * s2, q, 2.0 * s);
-    const double de = (double)e;
-    return __builtin_fma(de, 0x1.62e42fefa3800p-1,
-                         __builtin_fma(de, 0x1.ef35793c76730p-45, ln_m));
-}
-
-// a / b in FP64 for positive normal b, to about one ulp: the refined
-// reciprocal, then one Newton step on the quotient.
-__device__ __forceinline__ double div_f64(double a, double b)
-{
-    const double r = recip_fast(b);
-    const double q = a * r;
-    return __builtin_fma(r, __builtin_fma(-q, b, a), q);
-}
-
 // sqrt(x) for x in [0, 80] in FP64, to about one ulp: the refined
 // reciprocal square root y of max(x, 2^-200), then r = x y corrected once,
 // r + (y / 2)(x - r^2); x = 0 gives 0.
@@ -241,46 +183,66 @@ __device__ __forceinline__ double sqrt_f64(double x)
     return __builtin_fma(0.5 * y, __builtin_fma(-r, r, x), r);
 }
 
+// Series of the FP64 table-driven transforms, lowest order first:
+// ln(1 + f) / f - 1 over f = -1/2 + f/3 - ... + f^5/7 (|f| <= 2^-8: the rest
+// below f^7/8 < 2^-59); (sin x / x - 1) / x^2 = -1/6 + x^2/120 - x^4/5040
+// and (cos x - 1) / x^2 = -1/2 + x^2/24 - x^4/720 for |x| <= pi/256 (the
+// rest below 1.5e-21 and 1.3e-20 relative).
+static __constant__ double kLn1pSeries[6] = {
+    -0.5, 0x1.5555555555555p-2, -0.25, 0x1.999999999999ap-3, -0x1.5555555555555p-3,
+    0x1.2492492492492p-3};
+static __constant__ double kSinSmall[3] = {-0x1.5555555555555p-3, 0x1.1111111111111p-7,
+                                           -0x1.a01a01a01a01ap-13};
+static __constant__ double kCosSmall[3] = {-0.5, 0x1.5555555555555p-5, -0x1.6c16c16c16c17p-10};
+
+// ln u for u in [2^-64, 1] in FP64, within about an ulp, from the LDS log
+// table: u = 2^e m (e and m in [1, 2) from u's bits), j = m's nearest
+// multiple of 1/128, f = m invc_j - 1 (|f| <= 2^-8), and
+// ln u = (e ln2_hi + hi_j) + ((e ln2_lo + lo_j) + ln(1 + f)), with
+// hi_j + lo_j = ln(1 / invc_j).  e ln2_hi + hi_j is exact, and for u just
+// below 1 (e = -1, j = 128) both exponent-table sums are exactly 0, so the
+// result keeps the series' relative accuracy where ln u is small.
+__device__ __forceinline__ double ln_tab64(double u)
+{
+    const uint64_t b = __builtin_bit_cast(uint64_t, u);
+    const uint32_t hi = (uint32_t)(b >> 32);
+    const int32_t e = (int32_t)(hi >> 20) - 1023;
+    const uint32_t j = (((hi >> 12) & 255u) + 1u) >> 1;
+    const double m31 =
+        __builtin_bit_cast(double, (b & 0x000FFFFFFFFFFFFFull) | 0x41E0000000000000ull);
+    const double f = __builtin_fma(m31, s_bm_log[j][0], -1.0);
+    const double s = __builtin_fma(f * f, horner_s<6>(scalar_table(kLn1pSeries), f), f);
+    const double de = (double)e;
+    const double h = __builtin_fma(de, 0x1.62e42fefa3800p-1, s_bm_log[j][2]);
+    const double l = __builtin_fma(de, 0x1.ef35793c76730p-45, s_bm_log[j][3]);
+    return h + (l + s);
+}
+
 // Box-Muller in FP64 on a pair of FP64 uniforms u1 in (0, 1], u2 in [0, 1):
-// r = sqrt(-2 ln u1), (z0, z1) = r (cos 2 pi u2, sin 2 pi u2), each within a
-// few ulp.  The angle 2 pi u2 = pi x, x = 2 u2 in [0, 2], is reduced
-// exactly: j = nearest quarter turn (x rounded to a multiple of 1/2) and
-// t = x - j/2 in [-1/4, 1/4] (exact, by Sterbenz's lemma); sin(pi t) by
-// its Taylor series through t^15 (the rest below 5.9e-17 relative) and
-// cos(pi t) through t^16 (below 2.1e-18); then a rotation by j quarter
-// turns.  u1 = 1 gives +-0.
+// r = sqrt(-2 ln u1) (ln_tab64, the FP64 square root), and (cos, sin) of
+// 2 pi u2 from the rotation table in LDS: j = u2's nearest multiple of 1/256
+// (by the 1.5 * 2^52 rounding constant), t = u2 - j/256 exactly (Sterbenz),
+// x = 2 pi t (|x| <= pi/256), sin x and cos x by their series through x^7
+// and x^6, rotated by the entry (S, C) = (sin, cos)(2 pi j / 256).  The
+// entries are exact at quarter turns, so zeros stay exact (u1 = 1 gives
+// +-0); next to them the entries' |S| or |C| is at most twice the result.
+// Each factor is within a few ulp.  Needs the tables in LDS.
 __device__ __forceinline__ f64x2 box_muller64(double u1, double u2)
 {
-    const double r = sqrt_f64(-2.0 * ln_f64(u1));
-    const double x = 2.0 * u2;
-    const double jd = __builtin_fma(x, 2.0, kRound2) - kRound2;   // 0..4
-    const double t = __builtin_fma(jd, -0.5, x);
-    const double t2 = t * t;
-    double sp = -0x1.6fadb9f155744p-16;
-    sp = __builtin_fma(sp, t2, 0x1.e8f434d018d63p-12);
-    sp = __builtin_fma(sp, t2, -0x1.e3074fde8871fp-8);
-    sp = __builtin_fma(sp, t2, 0x1.50783487ee782p-4);
-    sp = __builtin_fma(sp, t2, -0x1.32d2cce62bd86p-1);
-    sp = __builtin_fma(sp, t2, 0x1.466bc6775aae2p+1);
-    sp = __builtin_fma(sp, t2, -0x1.4abbce625be53p+2);
-    sp = __builtin_fma(sp, t2, 0x1.921fb54442d18p+1);
-    sp = sp * t;                                   // sin(pi t)
-    double cp = 0x1.20c62c2f2d7f5p-18;
-    cp = __builtin_fma(cp, t2, -0x1.b6e24f44b128fp-14);
-    cp = __builtin_fma(cp, t2, 0x1.f9d38a3763cc3p-10);
-    cp = __builtin_fma(cp, t2, -0x1.a6d1f2a204a8cp-6);
-    cp = __builtin_fma(cp, t2, 0x1.e1f506891babbp-3);
-    cp = __builtin_fma(cp, t2, -0x1.55d3c7e3cbffap+0);
-    cp = __builtin_fma(cp, t2, 0x1.03c1f081b5ac4p+2);
-    cp = __builtin_fma(cp, t2, -0x1.3bd3cc9be45dep+2);
-    cp = __builtin_fma(cp, t2, 1.0);               // cos(pi t)
-    const uint32_t quad = (uint32_t)jd & 3u;
-    // quad 0: (cos, sin) = ( C,  S); 1: (-S,  C); 2: (-C, -S); 3: ( S, -C)
-    const double c_abs = (quad & 1u) ? sp : cp;
-    const double s_abs = (quad & 1u) ? cp : sp;
+    const double r = sqrt_f64(-2.0 * ln_tab64(u1));
+    const double jb = __builtin_fma(u2, 256.0, kRound2);        // 1.5 2^52 + j
+    const double jd = jb - kRound2;
+    const uint32_t j = (uint32_t)__builtin_bit_cast(uint64_t, jb) & 255u;
+    const double t = __builtin_fma(jd, -0x1p-8, u2);
+    const double x = t * 0x1.921fb54442d18p+2;                  // 2 pi t
+    const double x2 = x * x;
+    const double sx = __builtin_fma(x * x2, horner_s<3>(scalar_table(kSinSmall), x2), x);
+    const double cx = __builtin_fma(x2, horner_s<3>(scalar_table(kCosSmall), x2), 1.0);
+    const double S = s_bm_rot[j][0];
+    const double C = s_bm_rot[j][1];
     f64x2 z;
-    z.x = r * ((quad == 1u || quad == 2u) ? -c_abs : c_abs);
-    z.y = r * ((quad >= 2u) ? -s_abs : s_abs);
+    z.x = r * __builtin_fma(C, cx, -(S * sx));
+    z.y = r * __builtin_fma(S, cx, C * sx);
     return z;
 }
 
@@ -293,117 +255,96 @@ __device__ __forceinline__ uint32_t uniform_i32(uint32_t w, int32_t ia, uint32_t
     return (uint32_t)ia + (uint32_t)(p >> 32);
 }
 
-// Coefficients of Wichura's algorithm AS 241 (PPND16; Applied Statistics
-// 37(3), 1988): numerator and denominator polynomials of degree 7, lowest
-// order first, for the central region (A / B), the near tails (C / D) and
-// the far tails (E / F).  Kept in constant memory: read as scalar operands
-// they cost no vector registers (FP64 literals would each need two).
-static __constant__ double kPpnd16[6][8] = {
-    {3.387132872796366608, 133.14166789178437745, 1971.5909503065514427,
-     13731.693765509461125, 45921.953931549871457, 67265.770927008700853,
-     33430.575583588128105, 2509.0809287301226727},
-    {1.0, 42.313330701600911252, 687.1870074920579083, 5394.1960214247511077,
-     21213.794301586595867, 39307.89580009271061, 28729.085735721942674,
-     5226.495278852545925},
-    {1.42343711074968357734, 4.6303378461565452959, 5.7694972214606914055,
-     3.64784832476320460504, 1.27045825245236838258, 0.24178072517745061177,
-     0.0227238449892691845833, 7.7454501427834140764e-4},
-    {1.0, 2.05319162663775882187, 1.6763848301838038494, 0.68976733498510000455,
-     0.14810397642748007459, 0.0151986665636164571966, 5.475938084995344946e-4,
-     1.05075007164441684324e-9},
-    {6.6579046435011037772, 5.4637849111641143699, 1.7848265399172913358,
-     0.29656057182850489123, 0.026532189526576123093, 0.0012426609473880784386,
-     2.71155556874348757815e-5, 2.01033439929228813265e-7},
-    {1.0, 0.59983220655588793769, 0.13692988092273580531, 0.0148753612908506148525,
-     7.868691311456132591e-4, 1.8463183175100546818e-5, 1.4215117583164458887e-7,
-     2.04426310338993978564e-15}};
-
-// Polynomial j of the table at x by Horner's rule with fused multiply-adds.
-__device__ __forceinline__ double ppnd16_poly(int j, double x)
+// -ln a for a in [2^-24, 1], to about 2^-50 absolute error, from the FP32
+// Box-Muller log table (in LDS): a = 2^e m with e and m in [1, 2) read from
+// a's bits, j = m's nearest multiple of 1/128 (|f| <= 2^-8 below),
+// f = m invc_j - 1, and -ln a = -e ln 2 + ln(invc_j) - ln(1 + f) with
+// ln(1 + f) = f - f^2/2 + f^3/3 (the rest below f^4/4 = 2^-34).  As in the
+// Box-Muller radius, the exponent and table terms cancel exactly where a is
+// just below 1.
+__device__ __forceinline__ double neg_ln_tab(double a)
 {
-    double r = kPpnd16[j][7];
-#pragma unroll
-    for (int k = 6; k >= 0; --k) r = __builtin_fma(r, x, kPpnd16[j][k]);
-    return r;
+    const uint64_t b = __builtin_bit_cast(uint64_t, a);
+    const uint32_t hi = (uint32_t)(b >> 32);
+    const int32_t e = (int32_t)(hi >> 20) - 1023;
+    const uint32_t j = (((hi >> 12) & 255u) + 1u) >> 1;
+    // m 2^31: a's significand under the exponent 1023 + 31
+    const double m31 =
+        __builtin_bit_cast(double, (b & 0x000FFFFFFFFFFFFFull) | 0x41E0000000000000ull);
+    const double f = __builtin_fma(m31, s_bm_log[j][0], -1.0);
+    const double f2 = f * f;
+    const double q = __builtin_fma(f, 0x1.5555555555555p-2, -0.5);
+    const double s = __builtin_fma(f2, q, f);                  // ln(1 + f)
+    return __builtin_fma((double)e, -0x1.62e42fefa39efp-1, 0.5 * s_bm_log[j][1]) - s;
 }
 
-// Phi^-1(u) by AS 241 (as normal_quantile below) for FP32 outputs: the
-// tail's logarithm, square root and both divisions use the refined
-// estimates above (ln_fast, sqrt_fast for -ln t <= 34, recip_fast), so z
-// carries about 2e-9 relative error (from the logarithm) before its one
-// rounding to FP32.
-__device__ __forceinline__ double normal_quantile_f32(double u)
+// Inverse-CDF Gaussian from one word, FP32 output: u = ((w >> 8) + 1/2)
+// 2^-24, and Phi^-1(u) = sqrt(2) erfinv(x) with x = 2u - 1, written as
+// x F(w) with w = -ln(1 - x^2) (the erfinv form of M. Giles, GPU Computing
+// Gems 2011; polynomials fitted for this range in icdf_coeffs.hpp):
+//   x = (2k + 1 - 2^24) 2^-24 and 1 - x^2 = (1 - x)(1 + x) are exact in FP64
+//   (26- and 25-bit factors), w = -ln(1 - x^2) <= 23 ln 2 from neg_ln_tab;
+//   F = P(w - 3.125) for w < 6.25 (all but 0.1% of uniforms), else
+//   Q(sqrt(w) - 3.25), each fitted within 6e-10 relative; sqrt from the
+//   hardware reciprocal square root corrected once.
+// z = x F is rounded once to FP32.  F varies slowly with w, so w's absolute
+// error costs far below 2^-40 relative.  Needs the Box-Muller tables in LDS.
+__device__ __forceinline__ float icdf_f32(uint32_t wd)
 {
-    const double q = u - 0.5;
-    if (__builtin_fabs(q) <= 0.425) {
-        const double r = __builtin_fma(-q, q, 0.180625);
-        return q * ppnd16_poly(0, r) * recip_fast(ppnd16_poly(1, r));
-    }
-    const double t = q < 0.0 ? u : 1.0 - u;
-    double r = sqrt_fast(-ln_fast(t));
-    double z;
-    if (r <= 5.0) {
-        r -= 1.6;
-        z = ppnd16_poly(2, r) * recip_fast(ppnd16_poly(3, r));
+    const int32_t xi = (int32_t)(((wd >> 8) << 1) + 1u) - (1 << 24);
+    const double x = (double)xi * 0x1p-24;
+    const double w = neg_ln_tab((1.0 - x) * (1.0 + x));
+    double p;
+    if (w < 6.25) {
+        p = horner_s<13>(scalar_table(kIcdfCentral), w - 3.125);
     } else {
-        r -= 5.0;
-        z = ppnd16_poly(4, r) * recip_fast(ppnd16_poly(5, r));
+        const double y = __builtin_amdgcn_rsq(w);
+        const double r0 = w * y;
+        const double t = __builtin_fma(0.5 * y, __builtin_fma(-r0, r0, w), r0) - 3.25;
+        p = horner_s<11>(scalar_table(kIcdfTail), t);
     }
-    return q < 0.0 ? -z : z;
+    return (float)(x * p);
 }
 
-// Standard normal quantile Phi^-1(u), u in (0, 1), in FP64 by AS 241,
-// whose rational approximations have relative error near 1e-16.  Central
-// region |u - 1/2| <= 0.425: z = q A(r) / B(r), q = u - 1/2 (exact),
-// r = 0.180625 - q^2.  Tails: r = sqrt(-ln min(u, 1 - u)), then
-// C(r - 1.6) / D(r - 1.6) for r <= 5 and E(r - 5) / F(r - 5) beyond, with
-// the sign of q.  (The device library's quantile is several times larger
-// and spills registers when inlined into the generation loops.)  The
-// logarithm, square root and divisions are the FP64 routines above (each
-// within about an ulp), so z is within a few ulp.
-__device__ __forceinline__ double normal_quantile(double u)
-{
-    const double q = u - 0.5;
-    if (__builtin_fabs(q) <= 0.425) {
-        const double r = __builtin_fma(-q, q, 0.180625);
-        return q * div_f64(ppnd16_poly(0, r), ppnd16_poly(1, r));
-    }
-    const double t = q < 0.0 ? u : 1.0 - u;   // exact; t <= 0.075
-    double r = sqrt_f64(-ln_f64(t));
-    double z;
-    if (r <= 5.0) {
-        r -= 1.6;
-        z = div_f64(ppnd16_poly(2, r), ppnd16_poly(3, r));
-    } else {
-        r -= 5.0;
-        z = div_f64(ppnd16_poly(4, r), ppnd16_poly(5, r));
-    }
-    return q < 0.0 ? -z : z;
-}
-
-// Inverse-CDF Gaussian from one word: u = ((w >> 8) + 1/2) 2^-24 (exact in
-// FP64, strictly inside (0, 1); -ln t <= 25 ln 2), z = Phi^-1(u) in FP64,
-// rounded once to FP32.
-__device__ __forceinline__ float icdf_f32(uint32_t w)
-{
-    const double u = ((double)(w >> 8) + 0.5) * 0x1p-24;
-    return (float)normal_quantile_f32(u);
-}
-
-// Four inverse-CDF Gaussians, two quantiles at a time (a rolled loop that
-// rotates the words through the vector), so that the registers of two
-// quantiles suffice while their two chains overlap.
+// Four inverse-CDF Gaussians.
 __device__ __forceinline__ f32x4 icdf4_f32(u32x4 w)
 {
-    f32x4 f = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll 1
-    for (int j = 0; j < 2; ++j) {
-        const float z0 = icdf_f32(w.x);
-        const float z1 = icdf_f32(w.y);
-        w = u32x4{w.z, w.w, w.x, w.y};
-        f = f32x4{f.z, f.w, z0, z1};
-    }
+    f32x4 f;
+    f.x = icdf_f32(w.x);
+    f.y = icdf_f32(w.y);
+    f.z = icdf_f32(w.z);
+    f.w = icdf_f32(w.w);
     return f;
+}
+
+// Standard normal quantile Phi^-1(u), u in (0, 1), in FP64: the erfinv form
+// of icdf_f32 with the FP64 polynomials of icdf_coeffs.hpp (fitted within
+// 1.1e-16 relative):
+//   x = 2u - 1 (exact for u >= 1/4; else within half an ulp, which x's role
+//   as a factor of the result tolerates);
+//   1 - x^2 = 4u(1 - u) from u itself, so that it keeps its relative
+//   accuracy however close u is to 0 or 1, and w = -ln(1 - x^2) from
+//   ln_tab64 (w <= 51 ln 2 for u >= 2^-53);
+//   F = P(w - 3.125) for w < 6.25 (all but 0.1% of uniforms), else with
+//   s = sqrt(w) (the FP64 square root), Q1(s - 3.25) for s < 4 and
+//   Q2(s - 5.05) beyond; z = x F.
+// F changes slowly with w (d ln F / dw < 0.3), so w's absolute error costs
+// about as much relative error in z.  Needs the Box-Muller tables in LDS.
+__device__ __forceinline__ double normal_quantile(double u)
+{
+    const double x = __builtin_fma(u, 2.0, -1.0);
+    const double w = -ln_tab64(4.0 * u * (1.0 - u));
+    double p;
+    if (w < 6.25) {
+        p = horner_s<25>(scalar_table(kIcdf64Central), w - 3.125);
+    } else {
+        const double r = sqrt_f64(w);
+        if (r < 4.0)
+            p = horner_s<21>(scalar_table(kIcdf64Mid), r - 3.25);
+        else
+            p = horner_s<19>(scalar_table(kIcdf64Tail), r - 5.05);
+    }
+    return x * p;
 }
 
 // The FP64 uniform of an inverse-CDF Gaussian from two Philox words: with
