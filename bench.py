@@ -34,22 +34,76 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
-# HBM bytes per launch of the headline kernel, per launch shape the counters
-# were taken on (walk, block, waves per CU, blocks per lane, streaming
-# stores): WRITE_SIZE 1048576 KiB x 1.0 + FETCH_SIZE (median of five
-# launches: 43.75, 45.125, 37.5 or 34.0 KiB) x 2.0, each scaled by what the same
-# counter reads for a plain 1 GiB device copy (WRITE 1048576 KiB, FETCH
-# 524300 KiB).  Other shapes report no traffic; reset whenever the kernel's
-# code changes.
+# HBM bytes per launch of the headline kernel (uniform FP32, 2^28 samples at
+# the bulk draw's phase 1) for every launch shape the autotuner can install
+# (walk, block, waves per CU, blocks per lane, streaming stores):
+# WRITE_SIZE x 1.0 + FETCH_SIZE x 2.0 (KiB, the second of two launches per
+# shape), each factor being what the same counter reads for a plain 1 GiB
+# device copy (WRITE 1048576 KiB, FETCH 524300 KiB).  Walks 1 and 2 at
+# this phase write a little more than the 1 GiB of outputs (partial lines
+# of 4-byte-aligned blocks and of 63-slot chunks).  Reset whenever the
+# uniform FP32 kernels' code changes.
 TRAFFIC_BY_SHAPE = {
-    (0, 256, 1024, 1, 1): 1073741824 + 89600,
-    (0, 1024, 256, 1, 1): 1073741824 + 92416,
-    (3, 256, 1, 1, 0): 1073741824 + 76800,
-    (3, 256, 1, 1, 1): 1073741824 + 76800,
-    (3, 128, 1, 2, 0): 1073741824 + 69632,
-    (3, 256, 1, 2, 0): 1073741824 + 69632,
-    (3, 256, 1, 2, 1): 1073741824 + 69632,
-    (3, 512, 1, 2, 0): 1073741824 + 69632,
+    (0, 256, 64, 1, 0): 1073741824 + 89086,
+    (0, 256, 64, 1, 1): 1073741824 + 89086,
+    (0, 256, 128, 1, 0): 1073741824 + 89086,
+    (0, 256, 128, 1, 1): 1073741824 + 89086,
+    (0, 256, 256, 1, 0): 1073741824 + 89086,
+    (0, 256, 256, 1, 1): 1073741824 + 89086,
+    (0, 256, 512, 1, 0): 1073741824 + 89086,
+    (0, 256, 512, 1, 1): 1073741824 + 89086,
+    (0, 256, 1024, 1, 0): 1073741824 + 89086,
+    (0, 256, 1024, 1, 1): 1073741824 + 89086,
+    (0, 512, 64, 1, 0): 1073741824 + 89086,
+    (0, 512, 64, 1, 1): 1073741824 + 89086,
+    (0, 512, 128, 1, 0): 1073741824 + 89086,
+    (0, 512, 128, 1, 1): 1073741824 + 89086,
+    (0, 512, 256, 1, 0): 1073741824 + 89086,
+    (0, 512, 256, 1, 1): 1073741824 + 89086,
+    (0, 512, 512, 1, 0): 1073741824 + 89086,
+    (0, 512, 512, 1, 1): 1073741824 + 89086,
+    (0, 512, 1024, 1, 0): 1073741824 + 89086,
+    (0, 512, 1024, 1, 1): 1073741824 + 89086,
+    (0, 1024, 64, 1, 0): 1073741824 + 89086,
+    (0, 1024, 64, 1, 1): 1073741824 + 89086,
+    (0, 1024, 128, 1, 0): 1073741824 + 89086,
+    (0, 1024, 128, 1, 1): 1073741824 + 89086,
+    (0, 1024, 256, 1, 0): 1073741824 + 89086,
+    (0, 1024, 256, 1, 1): 1073741824 + 89086,
+    (0, 1024, 512, 1, 0): 1073741824 + 89086,
+    (0, 1024, 512, 1, 1): 1073741824 + 89086,
+    (0, 1024, 1024, 1, 0): 1073741824 + 89086,
+    (0, 1024, 1024, 1, 1): 1073741824 + 89086,
+    (1, 256, 8, 1, 0): 1073741824 + 18049183,
+    (1, 256, 8, 2, 0): 1073741824 + 9550367,
+    (2, 256, 1, 1, 0): 1073741824 + 66559,
+    (2, 256, 1, 1, 1): 1073741824 + 66559,
+    (2, 256, 1, 2, 0): 1073741824 + 93054,
+    (2, 256, 1, 2, 1): 1073741824 + 180382,
+    (2, 256, 1, 4, 0): 1073741824 + 1251390,
+    (2, 256, 1, 4, 1): 1073741824 + 1269982,
+    (2, 1024, 1, 1, 0): 1073741824 + 66559,
+    (2, 1024, 1, 1, 1): 1073741824 + 66719,
+    (2, 1024, 1, 2, 0): 1073741824 + 88926,
+    (2, 1024, 1, 2, 1): 1073741824 + 96958,
+    (2, 1024, 1, 4, 0): 1073741824 + 1666270,
+    (2, 1024, 1, 4, 1): 1073741824 + 1676574,
+    (3, 128, 1, 1, 0): 1073741824 + 69630,
+    (3, 128, 1, 1, 1): 1073741824 + 69630,
+    (3, 128, 1, 2, 0): 1073741824 + 84990,
+    (3, 128, 1, 2, 1): 1073741824 + 84990,
+    (3, 256, 1, 1, 0): 1073741824 + 69630,
+    (3, 256, 1, 1, 1): 1073741824 + 69630,
+    (3, 256, 1, 2, 0): 1073741824 + 84990,
+    (3, 256, 1, 2, 1): 1073741824 + 84990,
+    (3, 512, 1, 1, 0): 1073741824 + 69630,
+    (3, 512, 1, 1, 1): 1073741824 + 69630,
+    (3, 512, 1, 2, 0): 1073741824 + 84990,
+    (3, 512, 1, 2, 1): 1073741824 + 84990,
+    (3, 1024, 1, 1, 0): 1073741824 + 69630,
+    (3, 1024, 1, 1, 1): 1073741824 + 69630,
+    (3, 1024, 1, 2, 0): 1073741824 + 84990,
+    (3, 1024, 1, 2, 1): 1073741824 + 84990,
 }
 
 # the kernel each walk of the plain Philox path launches
@@ -97,8 +151,26 @@ def parse():
                         "--profile-batch / --profile-scenario (default: the library's)")
     p.add_argument("--profile-shapes", action="store_true",
                    help="for rocprofv3 counters: the headline workload at every launch shape "
-                        "the autotuner can install, two launches each (warm-up, measured)")
+                        "the autotuner can install, two launches each (warm-up, measured), "
+                        "then 3 device copies of 1 GiB for counter calibration")
+    p.add_argument("--profile-mrg", action="store_true",
+                   help="for rocprofv3 counters: MRG32k3a bits, n = 2^28, into a 16-byte "
+                        "aligned and into a misaligned (4 bytes past) output, two launches "
+                        "each, then 3 device copies of 1 GiB for counter calibration")
     return p.parse_args()
+
+
+def copy_calibration(torch, stream, out, n, dev):
+    """Three device copies of 1 GiB (1 GiB read, 1 GiB written) after the
+    profiled launches: the kernel of known traffic that scales FETCH_SIZE
+    and WRITE_SIZE."""
+    with torch.cuda.stream(stream):
+        src = torch.empty(n, dtype=torch.float32, device=dev)
+        src.fill_(0.5)
+        dst = out.view(torch.float32)[:n] if out.dtype != torch.float32 else out[:n]
+        for _ in range(3):
+            dst.copy_(src)
+    torch.cuda.synchronize()
 
 
 def time_region(fn, reps, stream, warm=3):
@@ -585,10 +657,21 @@ def main():
             for _ in range(2):
                 step()
             order.append(c.as_dict())
-        stream.synchronize()
+        copy_calibration(torch, stream, out, n, dev)
         print(json.dumps({"profile": "headline workload at every autotuner shape, two launches "
-                                     "each (warm-up, measured)", "phase": phase,
-                          "order": order}), flush=True)
+                                     "each (warm-up, measured), then 1 GiB copy x3",
+                          "phase": phase, "order": order}), flush=True)
+        return
+
+    if args.profile_mrg:
+        big = torch.empty(n + 4, dtype=torch.int32, device=dev)
+        e = mr.Engine(mr.MRG32K3A, 0x9E3779B97F4A7C15, 12345)
+        for off in (0, 4):
+            for _ in range(2):
+                e.generate(mr.BITS_U32, n, int(big.data_ptr()) + off, stream=stream)
+        copy_calibration(torch, stream, out, n, dev)
+        print(json.dumps({"profile": "MRG32k3a bits n=2^28: aligned x2, 4 bytes past "
+                                     "alignment x2, then 1 GiB copy x3"}), flush=True)
         return
 
     if args.profile_batch:
