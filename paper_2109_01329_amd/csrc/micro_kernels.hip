@@ -127,11 +127,11 @@ __global__ __launch_bounds__(256) void transform_probe_kernel(int32_t which, uin
     if (i >= n) return;
     const uint32_t w = (first + i) << 8;
     if (which == 0) {
-        ((double *)out)[i] = bm_radius(w);
+        ((double *)out)[i] = 0.5 * bm_radius2(w);                 // exact halving
     } else if (which == 1) {
-        const f64x2 cs = bm_unit(w);
-        ((double *)out)[2 * (size_t)i] = cs.x;
-        ((double *)out)[2 * (size_t)i + 1] = cs.y;
+        const f64x2 cs = bm_unit_half(w);
+        ((double *)out)[2 * (size_t)i] = 2.0 * cs.x;             // exact doubling
+        ((double *)out)[2 * (size_t)i + 1] = 2.0 * cs.y;
     } else {
         ((float *)out)[i] = icdf_f32(w);
     }

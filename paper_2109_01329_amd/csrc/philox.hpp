@@ -208,6 +208,27 @@ __device__ __forceinline__ void emit_slot(const SlotRun &r, uint32_t slot, u32x4
               r.full_lo, r.full_count, e0, r.n, r.ep.nt);
 }
 
+// The 16 bytes of slot s of a run when the caller knows the whole slot lies
+// inside the output: one unconditional 16-byte store.
+template <int KIND, int RANGED = 2>
+__device__ __forceinline__ void emit_slot_whole(const SlotRun &r, uint32_t slot, u32x4 w)
+{
+    const u32x4 v = transform<KIND, RANGED>(r.ep, w);
+    g_u32x4_a4 *p = (g_u32x4_a4 *)(r.out_base + (uint64_t)slot * 16u);
+    if (r.ep.nt) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+
+// Whether the 64 slots sb .. sb + 63 all lie in [lo, lo + width) and inside
+// the output (wave-uniform when its arguments are): such a step stores 64
+// whole slots with no per-lane checks.
+__device__ __forceinline__ bool whole_step(const SlotRun &r, uint32_t sb, uint32_t lo,
+                                           uint32_t width)
+{
+    return width >= 64u && sb - lo <= width - 64u && r.full_count >= 64u &&
+           sb - r.full_lo <= r.full_count - 64u;
+}
+
 // Whether the blocks base + j, j <= last, stay clear of a carry out of the
 // counter's low word (wave-uniform).
 __device__ __forceinline__ bool no_carry(const SlotRun &r, uint64_t last)
@@ -224,28 +245,38 @@ __device__ __forceinline__ bool no_carry(const SlotRun &r, uint64_t last)
 // s0 may lie below lo (modulo 2^32, even "negative"): the lanes before lo
 // evaluate blocks that nobody stores, which lets a caller align the steps
 // to a memory grid.
+// s0, lo and hi are read from lane 0, so the loop control and the
+// whole-step test run on the scalar unit.
 template <int KIND, int PHASE, int RANGED, bool NC>
 __device__ __forceinline__ void walk_slots_body(const SlotRun &r, uint32_t s0, uint32_t lo,
                                                 uint32_t hi, uint32_t lane, uint32_t iters)
 {
-    const uint32_t width = hi - lo;
+    s0 = lane0(s0);
+    lo = lane0(lo);
+    const uint32_t width = lane0(hi) - lo;
+    iters = lane0(iters);
     if constexpr (PHASE == 0) {
         for (uint32_t it = 0; it < iters; ++it) {
-            const uint32_t slot = s0 + (it << 6) + lane;
+            const uint32_t sb = s0 + (it << 6);
+            const uint32_t slot = sb + lane;
             const u32x4 w = block_at<NC>(r.base, r.k0, r.k1, slot);
-            if (slot - lo < width) emit_slot<KIND, RANGED>(r, slot, w);
+            if (whole_step(r, sb, lo, width)) emit_slot_whole<KIND, RANGED>(r, slot, w);
+            else if (slot - lo < width) emit_slot<KIND, RANGED>(r, slot, w);
         }
     } else {
         u32x4 cur = block_at<NC>(r.base, r.k0, r.k1, s0 + lane);
         for (uint32_t it = 0; it < iters; ++it) {
-            const uint32_t slot = s0 + (it << 6) + lane;
+            const uint32_t sb = s0 + (it << 6);
+            const uint32_t slot = sb + lane;
             const u32x4 nxt = block_at<NC>(r.base, r.k0, r.k1, slot + 64u);
             // lane 63 takes lane 0's next-step block
             u32x4 nb;
             nb.x = from_next_lane(cur.x, lane0(nxt.x));
             if constexpr (PHASE >= 2) nb.y = from_next_lane(cur.y, lane0(nxt.y));
             if constexpr (PHASE >= 3) nb.z = from_next_lane(cur.z, lane0(nxt.z));
-            if (slot - lo < width) emit_slot<KIND, RANGED>(r, slot, funnel<PHASE>(cur, nb));
+            const u32x4 w = funnel<PHASE>(cur, nb);
+            if (whole_step(r, sb, lo, width)) emit_slot_whole<KIND, RANGED>(r, slot, w);
+            else if (slot - lo < width) emit_slot<KIND, RANGED>(r, slot, w);
             cur = nxt;
         }
     }
@@ -305,7 +336,10 @@ __device__ __forceinline__ void walk_chunks_body(const SlotRun &r, uint32_t s0, 
             if constexpr (PHASE >= 3) nb.z = from_next_lane(b[it].z, 0u);
             w = funnel<PHASE>(b[it], nb);
         }
-        if (lane < S && off < span) emit_slot<KIND, RANGED>(r, s0 + off, w);
+        if (PHASE == 0 && whole_step(r, s0 + it * S, s0, span))
+            emit_slot_whole<KIND, RANGED>(r, s0 + off, w);
+        else if (lane < S && off < span)
+            emit_slot<KIND, RANGED>(r, s0 + off, w);
     }
 }
 

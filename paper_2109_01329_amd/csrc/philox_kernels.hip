@@ -84,7 +84,7 @@ __global__ __launch_bounds__(1024) void philox_fill_kernel(PhiloxFill a)
 {
     if constexpr (uses_lds_tables(KIND)) bm_stage();
     const uint32_t lane = threadIdx.x & 63u;
-    const uint32_t wave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const uint32_t wave = blockIdx.x * (blockDim.x >> 6) + lane0(threadIdx.x >> 6);
     const uint64_t first = (uint64_t)wave * a.slots_per_wave;
     if (first >= a.nslots) return;
     const uint32_t s0 = (uint32_t)first;
@@ -103,7 +103,7 @@ __global__ __launch_bounds__(1024) void philox_chunk_kernel(PhiloxFill a)
     constexpr uint32_t PER = (PHASE ? 63u : 64u) * ITERS;   // slots per wave
     if constexpr (uses_lds_tables(KIND)) bm_stage();
     const uint32_t lane = threadIdx.x & 63u;
-    const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x >> 6) + lane0(threadIdx.x >> 6);
     const uint64_t first = wave * PER;
     if (first >= a.nslots) return;
     const uint32_t s0 = (uint32_t)first;
@@ -133,6 +133,11 @@ __device__ __forceinline__ void group_chunks(const PhiloxFill &a, u32x4 *heads)
     const uint32_t nw = blockDim.x >> 6;
     const uint32_t g0 = blockIdx.x * nw * ITERS * 64u;   // the group's first slot
     const SlotRun &r = a.run;
+    // Chunks that lie wholly inside the output store without per-lane
+    // checks for the 4-byte kinds; the 8-byte kinds keep the per-lane path,
+    // which measured 4-5% faster for them in this walk (and the whole-chunk
+    // path 3-5% faster for uniform FP32 at two chunks per wave).
+    constexpr bool kWhole = elem_bytes(KIND) == 4;
     u32x4 cur[ITERS];
 #pragma unroll
     for (int it = 0; it < ITERS; ++it)
@@ -140,8 +145,11 @@ __device__ __forceinline__ void group_chunks(const PhiloxFill &a, u32x4 *heads)
     if constexpr (PHASE == 0) {
 #pragma unroll
         for (int it = 0; it < ITERS; ++it) {
-            const uint32_t slot = g0 + (it * nw + w) * 64u + lane;
-            if (slot < a.nslots) emit_slot<KIND, RANGED>(r, slot, cur[it]);
+            const uint32_t cb = g0 + (it * nw + w) * 64u;
+            const uint32_t slot = cb + lane;
+            if (kWhole && whole_step(r, cb, 0u, a.nslots))
+                emit_slot_whole<KIND, RANGED>(r, slot, cur[it]);
+            else if (slot < a.nslots) emit_slot<KIND, RANGED>(r, slot, cur[it]);
         }
     } else {
         if (lane == 0) {
@@ -161,8 +169,12 @@ __device__ __forceinline__ void group_chunks(const PhiloxFill &a, u32x4 *heads)
             nb.x = from_next_lane(cur[it].x, head.x);
             if constexpr (PHASE >= 2) nb.y = from_next_lane(cur[it].y, head.y);
             if constexpr (PHASE >= 3) nb.z = from_next_lane(cur[it].z, head.z);
-            const uint32_t slot = g0 + c * 64u + lane;
-            if (slot < a.nslots) emit_slot<KIND, RANGED>(r, slot, funnel<PHASE>(cur[it], nb));
+            const uint32_t cb = g0 + c * 64u;
+            const uint32_t slot = cb + lane;
+            const u32x4 wv = funnel<PHASE>(cur[it], nb);
+            if (kWhole && whole_step(r, cb, 0u, a.nslots))
+                emit_slot_whole<KIND, RANGED>(r, slot, wv);
+            else if (slot < a.nslots) emit_slot<KIND, RANGED>(r, slot, wv);
         }
     }
 }

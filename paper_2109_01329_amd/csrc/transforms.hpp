@@ -99,74 +99,86 @@ __device__ __forceinline__ void bm_stage()
     __syncthreads();
 }
 
-// Box-Muller radius r = sqrt(-2 ln u1) for FP32 outputs, u1 = v 2^-24 with
-// v = (wa >> 8) + 1 in [1, 2^24], to about 2^-29 relative error:
+// Twice the Box-Muller radius, 2r = 2 sqrt(-2 ln u1), for FP32 outputs,
+// u1 = v 2^-24 with v = (wa >> 8) + 1 in [1, 2^24], to about 2^-29
+// relative error:
 //   v = 2^(31 - nz) m, m in [1, 2), so u1 = 2^e m with e = 7 - nz;
 //   j = m's nearest multiple of 1/128 (table entry j = 0..128, |f| <= 2^-8
 //   below), f = m invc_j - 1 with invc_j ~ 1 / (1 + j/128), and
-//   ln u1 = e ln 2 + ln(1 / invc_j) + ln(1 + f), ln(1 + f) = f - f^2/2 + f^3/3
-//   (the rest is below f^4/4, 2^-26 relative);
-//   L = -2 ln u1 sums the exponent and table terms first: for u1 just below 1
-//   (e = -1, j = 128) and for u1 = 1 (e = 0, j = 0) they cancel exactly, so
-//   L keeps the relative accuracy of its series term;
-//   r = sqrt(L) from the hardware reciprocal square root y (within 2^-24 on
-//   gfx950) corrected once, r = L y + (y / 2)(L - (L y)^2); L = 0 gives 0.
-__device__ __forceinline__ double bm_radius(uint32_t wa)
+//   -2 ln u1 = -2 e ln 2 - 2 ln(invc_j) - 2 ln(1 + f)
+//            = (nz C + T_j) + f (-2 + f (1 - 2f/3))
+//   (C = 2 ln 2 to 50 bits, T_j = 2 ln(invc_j) - 7 C from the table; the
+//   series' rest is below f^4/2, 2^-26 relative to its first term, and
+//   |f| <= 2^-9 where L is small);
+//   nz C + T_j is exactly 0 for u1 = 1 (nz = 7, j = 0) and for u1 just
+//   below 1 (nz = 8, j = 128), so L keeps the relative accuracy of its
+//   series term there;
+//   y = the hardware reciprocal square root of L (within 2^-24 on gfx950),
+//   r0 = L y, and 2r = r0 (3 - r0 y), one Newton step whose halving moves
+//   into the rotation table (which holds half of sin and cos).  L = 0
+//   (u1 = 1) gives 0.
+// The table entry's byte offset j * 32 is ((mi >> 19) - 4080) & 0x1FE0 for
+// mi = m 2^31: mi >> 19 is 4096 (m's leading bit) + 16 g + (4 lower bits)
+// with g m's top 8 fraction bits, so the difference is 16 (g + 1) plus
+// those bits, in [16, 4111], and the mask leaves 32 floor((g + 1) / 2).
+__device__ __forceinline__ double bm_radius2(uint32_t wa)
 {
     const uint32_t v = (wa >> 8) + 1u;
     const uint32_t nz = (uint32_t)__builtin_clz(v);
     const uint32_t mi = v << nz;                               // m 2^31
-    const uint32_t j = (((mi >> 23) & 255u) + 1u) >> 1;
-    const double f = __builtin_fma((double)mi, s_bm_log[j][0], -1.0);
-    const double f2 = f * f;
-    const double q = __builtin_fma(f, 0x1.5555555555555p-2, -0.5);
-    const double s = __builtin_fma(f2, q, f);                  // ln(1 + f)
-    const double base = __builtin_fma((double)(7 - (int32_t)nz), -0x1.62e42fefa39efp+0,
-                                      s_bm_log[j][1]);
-    const double L = __builtin_fma(s, -2.0, base);
+    const uint32_t off = ((mi >> 19) - 4080u) & 0x1FE0u;
+    const double *ent = (const double *)((const char *)&s_bm_log[0][0] + off);
+    const double f = __builtin_fma((double)mi, ent[0], -1.0);
+    const double base = __builtin_fma((double)nz, 0x1.62e42fefa39f0p+0, ent[1]);
+    const double q1 = __builtin_fma(f, -0x1.5555555555555p-1, 1.0);
+    const double q2 = __builtin_fma(f, q1, -2.0);
+    const double L = __builtin_fma(f, q2, base);
     const double y = __builtin_amdgcn_rsq(__builtin_fmax(L, 0x1p-100));
     const double r0 = L * y;
-    return __builtin_fma(0.5 * y, __builtin_fma(-r0, r0, L), r0);
+    return r0 * __builtin_fma(-r0, y, 3.0);
 }
 
-// (cos, sin) of 2 pi u2 for FP32 outputs, u2 = k 2^-24 with k = wb >> 8, to
-// about 2^-29 relative error: j = k's nearest multiple of 2^16 (table entry
-// j mod 256, the angle 2 pi j / 256), x = 2 pi (k - 2^16 j) 2^-24 exactly
-// reduced (|x| <= pi / 256), sin x = x - x^3/6 (the rest below x^5/120) and
-// cos x = 1 - x^2/2 (the rest below x^4/24 = 2^-30), then the rotation
-// cos = C cos x - S sin x, sin = S cos x + C sin x by the entry's (S, C).
+// Half of (cos, sin) of 2 pi u2 for FP32 outputs, u2 = k 2^-24 with
+// k = wb >> 8, to about 2^-29 relative error: j = k's nearest multiple of
+// 2^16 (table entry j mod 256, the angle 2 pi j / 256), and the rest of the
+// angle x = K t with t = k - 2^16 j (an integer, |t| <= 2^15) and
+// K = 2 pi 2^-24, |x| <= pi / 256:
+//   sin x = t (K - K^3 t^2 / 6) (the rest below x^5/120) and
+//   cos x = 1 - K^2 t^2 / 2 (the rest below x^4/24 = 2^-30), with t^2
+//   exact, then the rotation cos = C cos x - S sin x, sin = S cos x + C sin x
+//   by the entry's (S, C) / 2.
 // The table is exact at quarter turns, so the exact zeros of cos and sin
 // come out as zeros, and values next to them keep the series' relative
-// accuracy (the entries there have |S| or |C| = sin(2 pi / 256), at most
-// twice the result).
-__device__ __forceinline__ f64x2 bm_unit(uint32_t wb)
+// accuracy (the entries there have |S| or |C| = sin(2 pi / 256) / 2, at
+// most twice the result).
+__device__ __forceinline__ f64x2 bm_unit_half(uint32_t wb)
 {
     // j mod 256 = the top 8 bits of k + 2^15, and k - 2^16 j is k's low 16
     // bits read as a signed integer
     const uint32_t jr = (wb + 0x800000u) >> 24;
-    const int32_t rem = (int32_t)(int16_t)(uint16_t)(wb >> 8);
+    const double t = (double)(int32_t)(int16_t)(uint16_t)(wb >> 8);
     const double S = s_bm_rot[jr][0];
     const double C = s_bm_rot[jr][1];
-    const double x = (double)rem * 0x1.921fb54442d18p-22;      // 2 pi 2^-24
-    const double x2 = x * x;
-    const double sx = __builtin_fma(x * x2, -0x1.5555555555555p-3, x);
-    const double cx = __builtin_fma(x2, -0.5, 1.0);
+    const double t2 = t * t;
+    const double cx = __builtin_fma(t2, -0x1.3bd3cc9be45dep-44, 1.0);   // -K^2 / 2
+    const double sx = t * __builtin_fma(t2, -0x1.4abbce625be53p-67, 0x1.921fb54442d18p-22);
     f64x2 cs;
     cs.x = __builtin_fma(C, cx, -(S * sx));
     cs.y = __builtin_fma(S, cx, C * sx);
     return cs;
 }
 
-// Box-Muller on one word pair, FP32 outputs: z0 = RN32(r cos), z1 = RN32(r
-// sin) from the two FP64 factors above, each within about 2^-29, so every
-// output is within 0.55 ulp of the exact transform of the same two inputs.
+// Box-Muller on one word pair, FP32 outputs: z0 = RN32(2r (cos / 2)),
+// z1 = RN32(2r (sin / 2)) from the two FP64 factors above, each within
+// about 2^-29, so every output is within 0.55 ulp of the exact transform
+// of the same two inputs.
 __device__ __forceinline__ f32x2 box_muller(uint32_t wa, uint32_t wb)
 {
-    const double r = bm_radius(wa);
-    const f64x2 cs = bm_unit(wb);
+    const double r2 = bm_radius2(wa);
+    const f64x2 cs = bm_unit_half(wb);
     f32x2 z;
-    z.x = (float)(r * cs.x);
-    z.y = (float)(r * cs.y);
+    z.x = (float)(r2 * cs.x);
+    z.y = (float)(r2 * cs.y);
     return z;
 }
 
@@ -219,17 +231,18 @@ __device__ __forceinline__ double ln_tab64(double u)
 }
 
 // Box-Muller in FP64 on a pair of FP64 uniforms u1 in (0, 1], u2 in [0, 1):
-// r = sqrt(-2 ln u1) (ln_tab64, the FP64 square root), and (cos, sin) of
-// 2 pi u2 from the rotation table in LDS: j = u2's nearest multiple of 1/256
-// (by the 1.5 * 2^52 rounding constant), t = u2 - j/256 exactly (Sterbenz),
-// x = 2 pi t (|x| <= pi/256), sin x and cos x by their series through x^7
-// and x^6, rotated by the entry (S, C) = (sin, cos)(2 pi j / 256).  The
-// entries are exact at quarter turns, so zeros stay exact (u1 = 1 gives
-// +-0); next to them the entries' |S| or |C| is at most twice the result.
-// Each factor is within a few ulp.  Needs the tables in LDS.
+// 2r = sqrt(-8 ln u1) (ln_tab64, the FP64 square root), and half of
+// (cos, sin) of 2 pi u2 from the rotation table in LDS: j = u2's nearest
+// multiple of 1/256 (by the 1.5 * 2^52 rounding constant), t = u2 - j/256
+// exactly (Sterbenz), x = 2 pi t (|x| <= pi/256), sin x and cos x by their
+// series through x^7 and x^6, rotated by the entry (S, C) = (sin, cos)(2 pi
+// j / 256) / 2.  The entries are exact at quarter turns, so zeros stay
+// exact (u1 = 1 gives +-0); next to them the entries' |S| or |C| is at most
+// twice the result.  Each factor is within a few ulp.  Needs the tables in
+// LDS.
 __device__ __forceinline__ f64x2 box_muller64(double u1, double u2)
 {
-    const double r = sqrt_f64(-2.0 * ln_tab64(u1));
+    const double r = sqrt_f64(-8.0 * ln_tab64(u1));
     const double jb = __builtin_fma(u2, 256.0, kRound2);        // 1.5 2^52 + j
     const double jd = jb - kRound2;
     const uint32_t j = (uint32_t)__builtin_bit_cast(uint64_t, jb) & 255u;
@@ -255,18 +268,20 @@ __device__ __forceinline__ uint32_t uniform_i32(uint32_t w, int32_t ia, uint32_t
     return (uint32_t)ia + (uint32_t)(p >> 32);
 }
 
-// -ln a for a in [2^-24, 1], to about 2^-50 absolute error, from the FP32
+// -ln a for a in [2^-24, 1], to about 2^-45 absolute error, from the FP32
 // Box-Muller log table (in LDS): a = 2^e m with e and m in [1, 2) read from
 // a's bits, j = m's nearest multiple of 1/128 (|f| <= 2^-8 below),
-// f = m invc_j - 1, and -ln a = -e ln 2 + ln(invc_j) - ln(1 + f) with
-// ln(1 + f) = f - f^2/2 + f^3/3 (the rest below f^4/4 = 2^-34).  As in the
-// Box-Muller radius, the exponent and table terms cancel exactly where a is
-// just below 1.
+// f = m invc_j - 1, and -ln a = -e ln 2 + ln(invc_j) - ln(1 + f)
+// = (7 - e) C/2 + T_j/2 - ln(1 + f) with the table's T_j = 2 ln(invc_j) - 7 C
+// (C = 2 ln 2 to 50 bits, off by at most 2^-50 relative, which costs
+// (7 - e) 2^-51 absolute) and ln(1 + f) = f - f^2/2 + f^3/3 (the rest below
+// f^4/4 = 2^-34).  As in the Box-Muller radius, the exponent and table terms
+// cancel exactly where a is just below 1 (e = -1, j = 128).
 __device__ __forceinline__ double neg_ln_tab(double a)
 {
     const uint64_t b = __builtin_bit_cast(uint64_t, a);
     const uint32_t hi = (uint32_t)(b >> 32);
-    const int32_t e = (int32_t)(hi >> 20) - 1023;
+    const int32_t e7 = 1030 - (int32_t)(hi >> 20);             // 7 - e
     const uint32_t j = (((hi >> 12) & 255u) + 1u) >> 1;
     // m 2^31: a's significand under the exponent 1023 + 31
     const double m31 =
@@ -275,7 +290,7 @@ __device__ __forceinline__ double neg_ln_tab(double a)
     const double f2 = f * f;
     const double q = __builtin_fma(f, 0x1.5555555555555p-2, -0.5);
     const double s = __builtin_fma(f2, q, f);                  // ln(1 + f)
-    return __builtin_fma((double)e, -0x1.62e42fefa39efp-1, 0.5 * s_bm_log[j][1]) - s;
+    return __builtin_fma((double)e7, 0x1.62e42fefa39f0p-1, 0.5 * s_bm_log[j][1]) - s;
 }
 
 // Inverse-CDF Gaussian from one word, FP32 output: u = ((w >> 8) + 1/2)
