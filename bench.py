@@ -154,9 +154,10 @@ def parse():
                         "the autotuner can install, two launches each (warm-up, measured), "
                         "then 3 device copies of 1 GiB for counter calibration")
     p.add_argument("--profile-mrg", action="store_true",
-                   help="for rocprofv3 counters: MRG32k3a bits, n = 2^28, into a 16-byte "
-                        "aligned and into a misaligned (4 bytes past) output, two launches "
-                        "each, then 3 device copies of 1 GiB for counter calibration")
+                   help="for rocprofv3 counters: MRG32k3a bits and uniform FP64, n = 2^28, "
+                        "each into a 16-byte aligned and into a misaligned (one element "
+                        "past) output, two launches each, then 3 device copies of 1 GiB for "
+                        "counter calibration")
     return p.parse_args()
 
 
@@ -664,14 +665,16 @@ def main():
         return
 
     if args.profile_mrg:
-        big = torch.empty(n + 4, dtype=torch.int32, device=dev)
+        big = torch.empty(2 * n + 4, dtype=torch.int32, device=dev)
         e = mr.Engine(mr.MRG32K3A, 0x9E3779B97F4A7C15, 12345)
-        for off in (0, 4):
-            for _ in range(2):
-                e.generate(mr.BITS_U32, n, int(big.data_ptr()) + off, stream=stream)
+        for kind, offs in ((mr.BITS_U32, (0, 4)), (mr.UNIFORM_F64, (0, 8))):
+            for off in offs:
+                for _ in range(2):
+                    e.generate(kind, n, int(big.data_ptr()) + off, stream=stream)
         copy_calibration(torch, stream, out, n, dev)
-        print(json.dumps({"profile": "MRG32k3a bits n=2^28: aligned x2, 4 bytes past "
-                                     "alignment x2, then 1 GiB copy x3"}), flush=True)
+        print(json.dumps({"profile": "MRG32k3a n=2^28: bits aligned x2, 4 bytes past "
+                                     "alignment x2, uniform FP64 aligned x2, 8 bytes past x2, "
+                                     "then 1 GiB copy x3"}), flush=True)
         return
 
     if args.profile_batch:
@@ -802,6 +805,18 @@ def main():
                                    stream)[0]
             rates[name + "_Gops_s"] = round(threads * iters * 8 / (ms * 1e-3) / 1e9, 1)
         extra["valu_rates"] = rates
+        # the VALU probes leave the clocks low for a while: half a second of
+        # headline launches before the first cell (measured 0.182-0.190 ms
+        # for the uniform FP32 cell right after the probes, against
+        # 0.160-0.173 for the same launch in the timed region)
+        t_pre = time.perf_counter()
+        k = 0
+        while time.perf_counter() - t_pre < 0.5:
+            step()
+            k += 1
+            if k % 8 == 0:
+                stream.synchronize()
+        stream.synchronize()
         # every bulk cell
         res = {}
         big = torch.empty(n * 2, dtype=torch.float32, device=dev)   # 2 GiB

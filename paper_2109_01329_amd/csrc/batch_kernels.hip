@@ -566,13 +566,19 @@ __global__ __launch_bounds__(WIDE ? kWideBlock : 1024) void batch_main_kernel(Ba
 }
 
 // One chunk of an MRG request: 256 threads x kBatchMrgPasses passes of L.
+// As in the plain kernel, the thread ranges start h0 elements into the
+// output (its first 128-byte boundary; 0 for a paired kind with odd h0),
+// and chunk 0 writes the h0 head elements from the request's start state.
 template <int KIND>
 __device__ void mrg_chunk(const BatchDesc &d, uint64_t k, const uint32_t *c_tab,
-                          const uint32_t *u_tab, char *lds, uint32_t *wg_state)
+                          const uint32_t *u_tab, const uint32_t *pow2, char *lds,
+                          uint32_t *wg_state)
 {
     using S = MrgShape<KIND>;
     constexpr uint32_t q = kBatchMrgPasses * S::L;
     const uint32_t t = threadIdx.x;
+    uint32_t h0 = (uint32_t)((0u - (uint32_t)(uintptr_t)d.run.out_base) & 127u) / S::ESZ;
+    if (paired(KIND) && (h0 & 1u)) h0 = 0;
     if (t < 64) {
         uint32_t v[6];
 #pragma unroll
@@ -581,6 +587,8 @@ __device__ void mrg_chunk(const BatchDesc &d, uint64_t k, const uint32_t *c_tab,
             const uint32_t digit = (uint32_t)(k >> (6 * dg)) & 63u;
             if (digit) apply_mat(c_tab + (dg * 64 + digit) * kMatWords, v);
         }
+        for (int b = 0; b < 5; ++b)
+            if ((h0 >> b) & 1u) apply_mat(pow2 + b * kMatWords, v);
         if (t == 0) {
 #pragma unroll
             for (int i = 0; i < 6; ++i) wg_state[i] = v[i];
@@ -593,14 +601,35 @@ __device__ void mrg_chunk(const BatchDesc &d, uint64_t k, const uint32_t *c_tab,
     if (t) apply_mat(u_tab + t * kMatWords, v);
     MrgState s = mrg_state(v);
     const uint64_t e_wg = k * kMrgThreads * q;
+    const uint64_t n_rest = d.run.n > h0 ? d.run.n - h0 : 0;
+    char *rng_out = d.run.out_base + (uint64_t)h0 * S::ESZ;
+    char *row = mrg_row<KIND>(lds, t);
+    const uint32_t h = mrg_head<KIND>(rng_out);
+    bool pending = false;   // the previous pass left its rows' last h elements
+    uint64_t e_last = e_wg;
     for (uint32_t pass = 0; pass < kBatchMrgPasses; ++pass) {
         const uint64_t e0 = e_wg + (uint64_t)pass * S::L;
-        if (e0 >= d.run.n) break;   // uniform per group
-        mrg_fill_row<KIND>(s, lds + t * S::ROW, d.run.ep);
+        if (e0 >= n_rest) break;   // uniform per group
+        if (pending) mrg_carry_tail<KIND>(row, h);
+        mrg_fill_row<KIND>(s, row, d.run.ep);
         __syncthreads();
-        mrg_store_pass<KIND>(lds, e0, q, d.run.n, d.run.out_base, d.run.ep.nt);
+        pending = mrg_store_pass<KIND>(lds, e0, q, n_rest, rng_out, d.run.ep.nt, pending);
         __syncthreads();
+        e_last = e0;
     }
+    if (pending) mrg_store_tail<KIND>(row, e_last + (uint64_t)t * q, h, rng_out);
+    if (k == 0 && t == 0 && h0 != 0) {
+        uint32_t v[6];
+#pragma unroll
+        for (int i = 0; i < 6; ++i) v[i] = d.mst[i];
+        MrgState hs = mrg_state(v);
+        mrg_fill_row<KIND>(hs, row, d.run.ep);
+        const uint32_t m = d.run.n < h0 ? (uint32_t)d.run.n : h0;
+        for (uint32_t e = 0; e < m; ++e) put_elem<S::ESZ>(d.run.out_base, e, row + e * S::ESZ);
+    }
+    // the next chunk's wave 0 rewrites wg_state, and the head's row is this
+    // thread's own: both follow the loop's last barrier
+    __syncthreads();
 }
 
 // WIDE: the batch holds MRG inverse-CDF requests, whose transforms need
@@ -635,23 +664,23 @@ __global__ __launch_bounds__(kMrgThreads) void batch_mrg_kernel(BatchArgs a)
             const uint64_t seg = min(c1, end);
             for (uint64_t k = c - start; k < seg - start; ++k) {
                 switch (d.kind) {
-                case kBits: mrg_chunk<kBits>(d, k, a.c_tab4, a.u_tab4, lds, wg_state); break;
-                case kU32F: mrg_chunk<kU32F>(d, k, a.c_tab4, a.u_tab4, lds, wg_state); break;
-                case kU64F: mrg_chunk<kU64F>(d, k, a.c_tab8, a.u_tab8, lds, wg_state); break;
+                case kBits: mrg_chunk<kBits>(d, k, a.c_tab4, a.u_tab4, a.pow2, lds, wg_state); break;
+                case kU32F: mrg_chunk<kU32F>(d, k, a.c_tab4, a.u_tab4, a.pow2, lds, wg_state); break;
+                case kU64F: mrg_chunk<kU64F>(d, k, a.c_tab8, a.u_tab8, a.pow2, lds, wg_state); break;
                 case kGauss:
-                    if constexpr (BM) mrg_chunk<kGauss>(d, k, a.c_tab4, a.u_tab4, lds, wg_state);
+                    if constexpr (BM) mrg_chunk<kGauss>(d, k, a.c_tab4, a.u_tab4, a.pow2, lds, wg_state);
                     break;
                 case kGauss64:
-                    if constexpr (BM) mrg_chunk<kGauss64>(d, k, a.c_tab8, a.u_tab8, lds, wg_state);
+                    if constexpr (BM) mrg_chunk<kGauss64>(d, k, a.c_tab8, a.u_tab8, a.pow2, lds, wg_state);
                     break;
-                case kI32: mrg_chunk<kI32>(d, k, a.c_tab4, a.u_tab4, lds, wg_state); break;
+                case kI32: mrg_chunk<kI32>(d, k, a.c_tab4, a.u_tab4, a.pow2, lds, wg_state); break;
                 default:
                     if constexpr (WIDE) {
                         if (d.kind == kIcdf) {
                             if constexpr (BM)
-                                mrg_chunk<kIcdf>(d, k, a.c_tab4, a.u_tab4, lds, wg_state);
+                                mrg_chunk<kIcdf>(d, k, a.c_tab4, a.u_tab4, a.pow2, lds, wg_state);
                         } else if constexpr (BM) {
-                            mrg_chunk<kIcdf64>(d, k, a.c_tab8, a.u_tab8, lds, wg_state);
+                            mrg_chunk<kIcdf64>(d, k, a.c_tab8, a.u_tab8, a.pow2, lds, wg_state);
                         }
                     }
                     break;

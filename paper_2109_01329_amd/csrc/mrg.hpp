@@ -131,10 +131,20 @@ template <int KIND>
 struct MrgShape {
     static constexpr int ESZ = elem_bytes(KIND);
     static constexpr int L = 128 / ESZ;          // outputs per thread per pass
-    static constexpr int ROW = L * ESZ + 16;     // padded LDS row, bytes
+    static constexpr int ROW = L * ESZ + 16;     // LDS row slot, bytes
+    static constexpr int OFF = 16;               // the row's outputs start here
     static constexpr int VPR = L * ESZ / 16;     // 16-byte vectors per row
     static constexpr int EPV = 16 / ESZ;         // elements per vector
 };
+
+// Thread t's row in the pass buffer.  The 16 bytes before the row's outputs
+// hold, when the output is not 16-byte aligned, the previous pass's last
+// elements (see mrg_store_pass).
+template <int KIND>
+__device__ __forceinline__ char *mrg_row(char *lds, uint32_t t)
+{
+    return lds + t * MrgShape<KIND>::ROW + MrgShape<KIND>::OFF;
+}
 
 // Runs L steps of `s` and writes the L outputs into `row` (16-byte aligned).
 // The inverse-CDF kinds evaluate one quantile at a time (a rolled loop) so
@@ -229,53 +239,114 @@ __device__ __forceinline__ void put_elem(char *out, uint64_t e, const char *src)
         *(g_u64 *)(out + e * 8) = *(const uint64_t *)src;
 }
 
-// Writes one pass back to memory.  Row t of `lds` holds the L outputs of
-// elements [e0 + t * stride, + L) of an output array of n elements whose
-// element 0 is at `out` (element-aligned; e0 and stride are multiples of
-// L).  With h = elements between the previous 16-byte boundary and `out`,
-// every row spans VPR vectors of the 16-byte grid when h = 0 and VPR + 1
-// when not; the two end vectors are then shared with other rows and are
-// written element by element, the others with one 16-byte store.
-// Elements at or beyond n are not written.
+// Elements between the previous 16-byte boundary and element 0 of `out`.
 template <int KIND>
-__device__ void mrg_store_pass(const char *lds, uint64_t e0, uint64_t stride, uint64_t n,
-                               char *out, int nt)
+__device__ __forceinline__ uint32_t mrg_head(const char *out)
+{
+    return (uint32_t)(((uintptr_t)out & 15u) / MrgShape<KIND>::ESZ);
+}
+
+// Writes one pass back to memory.  Row t of `lds` (mrg_row) holds the L
+// outputs of elements [e0 + t * stride, + L) of an output array of n
+// elements whose element 0 is at `out` (element-aligned; e0 and stride are
+// multiples of L), and elements at or beyond n are not written.  With h =
+// mrg_head(out), the rows cut the 16-byte grid at row-local offset -h.
+// - h = 0: every row is VPR whole vectors.
+// - h != 0 and the whole pass inside the output: each row stores the VPR
+//   whole vectors at row-local [j EPV - h, + EPV), j < VPR; the first of
+//   them takes its h leading elements from the 16 bytes before the row,
+//   where the caller has put the previous pass's last h elements
+//   (`pending`), or, in a thread's first pass (no pending), is written
+//   element by element for its own EPV - h elements.  The row's last h
+//   elements are left to the next pass, or to mrg_store_tail after the
+//   last one: returns true.
+// - otherwise, every element of row-local [-h (if pending) or 0, L) below
+//   n is written, whole vectors where they lie inside; returns false.
+// A misaligned output thus costs two partial vectors per thread range
+// instead of two per pass.
+template <int KIND>
+__device__ bool mrg_store_pass(const char *lds, uint64_t e0, uint64_t stride, uint64_t n,
+                               char *out, int nt, bool pending)
 {
     using S = MrgShape<KIND>;
     constexpr int ESZ = S::ESZ, EPV = S::EPV, VPR = S::VPR, L = S::L;
-    const uint32_t h = (uint32_t)(((uintptr_t)out & 15u) / ESZ);
+    const uint32_t h = mrg_head<KIND>(out);
     const uint32_t t = threadIdx.x;
-    if (h == 0 && e0 + (uint64_t)(kMrgThreads - 1) * stride + L <= n) {
-        // The whole pass lies inside the output and `out` is 16-byte
-        // aligned: thread t stores vector t mod VPR of rows t / VPR + i RPI,
-        // i < VPR, so its LDS and global addresses advance by fixed steps.
+    if (e0 + (uint64_t)(kMrgThreads - 1) * stride + L <= n) {
+        // Thread t stores vector t mod VPR of rows t / VPR + i RPI, i < VPR,
+        // so its LDS and global addresses advance by fixed steps.
         constexpr uint32_t RPI = kMrgThreads / VPR;
         static_assert(RPI * VPR == kMrgThreads, "rows per step");
         const uint32_t j = t % VPR;
         const uint32_t r = t / VPR;
-        const char *src = lds + r * S::ROW + j * 16;
-        char *dst = out + (e0 + (uint64_t)r * stride + j * EPV) * ESZ;
+        if (h == 0) {
+            const char *src = lds + r * S::ROW + S::OFF + j * 16;
+            char *dst = out + (e0 + (uint64_t)r * stride + j * EPV) * ESZ;
+            const uint64_t dstep = (uint64_t)RPI * stride * ESZ;
+#pragma unroll
+            for (int i = 0; i < VPR; ++i) {
+                const u32x4 val = *(const u32x4 *)(src + i * RPI * S::ROW);
+                if (nt)
+                    __builtin_nontemporal_store(val, (g_u32x4 *)(dst + i * dstep));
+                else
+                    *(g_u32x4 *)(dst + i * dstep) = val;
+            }
+            return false;
+        }
+        const int32_t i0 = (int32_t)(j * EPV) - (int32_t)h;   // row-local, >= -h
+        const char *src = lds + r * S::ROW + S::OFF + i0 * ESZ;
+        char *dst = out + ((int64_t)(e0 + (uint64_t)r * stride) + i0) * ESZ;   // 16-aligned
         const uint64_t dstep = (uint64_t)RPI * stride * ESZ;
+        // (pending is the same in every thread: the loop below then has no
+        // per-lane branch, so its LDS reads issue ahead of the stores)
+        const bool part = j == 0 && !pending;
 #pragma unroll
         for (int i = 0; i < VPR; ++i) {
-            const u32x4 val = *(const u32x4 *)(src + i * RPI * S::ROW);
-            if (nt)
-                __builtin_nontemporal_store(val, (g_u32x4 *)(dst + i * dstep));
-            else
-                *(g_u32x4 *)(dst + i * dstep) = val;
+            const char *sp = src + i * RPI * S::ROW;
+            u32x4 val;
+            if constexpr (ESZ == 4) {
+                const uint32_t *p = (const uint32_t *)sp;
+                val = u32x4{p[0], p[1], p[2], p[3]};
+            } else {
+                const uint2 *p = (const uint2 *)sp;
+                const uint2 x = p[0], y = p[1];
+                val = u32x4{x.x, x.y, y.x, y.y};
+            }
+            if (pending || !part) {
+                if (nt)
+                    __builtin_nontemporal_store(val, (g_u32x4 *)(dst + i * dstep));
+                else
+                    *(g_u32x4 *)(dst + i * dstep) = val;
+            }
         }
-        return;
+        if (part) {
+            // a thread range's first vector: its h leading elements belong
+            // to the range before, which writes them as its tail
+#pragma unroll
+            for (int i = 0; i < VPR; ++i) {
+                const char *sp = src + i * RPI * S::ROW;
+                char *dp = dst + i * dstep;
+                for (int k = (int)h; k < EPV; ++k) {
+                    if constexpr (ESZ == 4)
+                        ((g_u32 *)dp)[k] = ((const uint32_t *)sp)[k];
+                    else
+                        ((g_u64 *)dp)[k] = ((const uint64_t *)sp)[k];
+                }
+            }
+        }
+        return true;
     }
+    const int32_t lo = pending ? -(int32_t)h : 0;   // first row-local element to write
     const uint32_t nv = VPR + (h ? 1u : 0u);
     for (uint32_t vi = t; vi < (uint32_t)kMrgThreads * nv; vi += kMrgThreads) {
         const uint32_t row = vi / nv;
         const uint32_t j = vi - row * nv;
         const uint64_t r0 = e0 + (uint64_t)row * stride;     // element of row offset 0
-        const char *src = lds + row * S::ROW;
+        const char *src = lds + row * S::ROW + S::OFF;
         // row-local index of the vector's first element (may be negative)
         const int32_t i0 = (int32_t)(j * EPV) - (int32_t)h;
-        if (r0 + (uint64_t)(i0 + EPV) <= n && i0 >= 0 && i0 + EPV <= L) {
-            char *dst = out + (r0 + (uint64_t)i0) * ESZ;
+        if (r0 + (uint64_t)(i0 + EPV) <= n && i0 >= lo && i0 + EPV <= L) {
+            char *dst = out + ((int64_t)r0 + i0) * ESZ;
             u32x4 val;
             if (h == 0) {
                 val = *(const u32x4 *)(src + i0 * ESZ);
@@ -295,11 +366,38 @@ __device__ void mrg_store_pass(const char *lds, uint64_t e0, uint64_t stride, ui
 #pragma unroll
             for (int k = 0; k < EPV; ++k) {
                 const int32_t i = i0 + k;
-                if (i >= 0 && i < L && r0 + (uint64_t)i < n)
-                    put_elem<ESZ>(out, r0 + (uint64_t)i, src + i * ESZ);
+                if (i >= lo && i < L && (int64_t)r0 + i < (int64_t)n)
+                    put_elem<ESZ>(out, (uint64_t)((int64_t)r0 + i), src + i * ESZ);
             }
         }
     }
+    return false;
+}
+
+// Before a pass fills its row: the previous pass's last h elements go to
+// the h element slots just before the row (each thread, its own row).
+template <int KIND>
+__device__ __forceinline__ void mrg_carry_tail(char *row, uint32_t h)
+{
+    using S = MrgShape<KIND>;
+    for (uint32_t k = 0; k < h; ++k) {
+        if constexpr (S::ESZ == 4)
+            ((uint32_t *)row)[(int32_t)k - (int32_t)h] = ((const uint32_t *)row)[S::L - h + k];
+        else
+            ((uint64_t *)row)[(int32_t)k - (int32_t)h] = ((const uint64_t *)row)[S::L - h + k];
+    }
+}
+
+// After the last pass, when it left its row's last h elements (its return
+// value): thread t writes them from its row, elements r0 + L - h .. r0 + L
+// - 1 with r0 = e0 + t * stride of that pass.
+template <int KIND>
+__device__ __forceinline__ void mrg_store_tail(const char *row, uint64_t r0, uint32_t h,
+                                               char *out)
+{
+    using S = MrgShape<KIND>;
+    for (uint32_t k = S::L - h; k < (uint32_t)S::L; ++k)
+        put_elem<S::ESZ>(out, r0 + k, row + k * S::ESZ);
 }
 
 }  // namespace mirng

@@ -9,6 +9,15 @@
 // base-64 digit powers (at most 4 + 5 matrix-vector products, done by one
 // wave); thread t then applies A^(t q) from a resident table and runs q
 // sequential steps, L at a time through LDS (the shared pass code).
+//
+// Line-aligned ranges.  The thread ranges start h0 elements into the
+// output, h0 = the elements before its first 128-byte boundary (a cache
+// line), so that every pass writes whole lines and no two threads share
+// one: the group state is advanced by A^h0 (from the A^(2^k) table), and
+// group 0 of a substream writes the h0 head elements at the end, from the
+// substream's start state.  Gaussian pairs must not straddle a range
+// start, so a paired kind with odd h0 keeps h0 = 0 (its passes then carry
+// their last elements to the next pass, see mrg_store_pass).
 #include <vector>
 
 #include "internal.hpp"
@@ -27,6 +36,7 @@ struct MrgLaunch {
     const uint32_t *u_tab;    // A^(t q): [t][comp][9]
     const uint32_t *c_tab;    // A^(k 64^d 256 q): [d][k][comp][9]
     const uint32_t *s_tab;    // A^(k 64^d 2^76): [d][k][comp][9]
+    const uint32_t *p_tab;    // A^(2^k): [k][comp][9]
     char *out;
     Epilogue ep;
 };
@@ -42,12 +52,17 @@ __global__ __launch_bounds__(kThreads) void mrg_kernel(MrgLaunch a)
     using S = MrgShape<KIND>;
     __shared__ __attribute__((aligned(16))) char lds[kThreads * S::ROW];
     __shared__ uint32_t wg_state[6];
+    __shared__ uint32_t wg_head[6];
     if constexpr (uses_lds_tables(KIND)) bm_stage();
 
     const uint32_t t = threadIdx.x;
     const uint32_t g = blockIdx.x;
     const uint32_t sub = g / a.chunks_per_sub;
     const uint32_t c = g - sub * a.chunks_per_sub;
+    char *sub_out = a.out + (uint64_t)sub * a.n_each * S::ESZ;
+    // elements before the substream's first 128-byte boundary
+    uint32_t h0 = (uint32_t)((0u - (uint32_t)(uintptr_t)sub_out) & 127u) / S::ESZ;
+    if (paired(KIND) && (h0 & 1u)) h0 = 0;
 
     if (t < 64) {
         uint32_t v[6];
@@ -60,10 +75,16 @@ __global__ __launch_bounds__(kThreads) void mrg_kernel(MrgLaunch a)
                 if (k) apply_mat(a.s_tab + (d * 64 + k) * kMatWords, v);
             }
         }
+        if (c == 0 && t == 0) {
+#pragma unroll
+            for (int i = 0; i < 6; ++i) wg_head[i] = v[i];
+        }
         for (int d = 0; d < kCDigits; ++d) {
             const uint32_t k = (c >> (6 * d)) & 63u;
             if (k) apply_mat(a.c_tab + (d * 64 + k) * kMatWords, v);
         }
+        for (int b = 0; b < 5; ++b)
+            if ((h0 >> b) & 1u) apply_mat(a.p_tab + b * kMatWords, v);
         if (t == 0) {
 #pragma unroll
             for (int i = 0; i < 6; ++i) wg_state[i] = v[i];
@@ -77,18 +98,37 @@ __global__ __launch_bounds__(kThreads) void mrg_kernel(MrgLaunch a)
     if (t) apply_mat(a.u_tab + t * kMatWords, v);
     MrgState s = mrg_state(v);
 
+    // the ranges' element 0 is element h0 of the substream
     const uint64_t e_wg = (uint64_t)c * kThreads * a.q;
-    char *sub_out = a.out + (uint64_t)sub * a.n_each * S::ESZ;
-    char *row = lds + t * S::ROW;
+    const uint64_t n_rest = a.n_each > h0 ? a.n_each - h0 : 0;
+    char *rng_out = sub_out + (uint64_t)h0 * S::ESZ;
+    char *row = mrg_row<KIND>(lds, t);
+    const uint32_t h = mrg_head<KIND>(rng_out);
     const uint32_t passes = a.q / S::L;
 
+    bool pending = false;   // the previous pass left its rows' last h elements
+    uint64_t e_last = e_wg;
     for (uint32_t pass = 0; pass < passes; ++pass) {
         const uint64_t e0 = e_wg + (uint64_t)pass * S::L;
-        if (e0 >= a.n_each) break;   // uniform per group
+        if (e0 >= n_rest) break;   // uniform per group
+        if (pending) mrg_carry_tail<KIND>(row, h);
         mrg_fill_row<KIND>(s, row, a.ep);
         __syncthreads();
-        mrg_store_pass<KIND>(lds, e0, a.q, a.n_each, sub_out, a.ep.nt);
+        pending = mrg_store_pass<KIND>(lds, e0, a.q, n_rest, rng_out, a.ep.nt, pending);
         __syncthreads();
+        e_last = e0;
+    }
+    if (pending) mrg_store_tail<KIND>(row, e_last + (uint64_t)t * a.q, h, rng_out);
+    if (c == 0 && t == 0 && h0 != 0) {
+        // the head: one row of L outputs from the substream's start state
+        // (h0 < L), of which the first min(h0, n) are the output's
+        uint32_t v[6];
+#pragma unroll
+        for (int i = 0; i < 6; ++i) v[i] = wg_head[i];
+        MrgState hs = mrg_state(v);
+        mrg_fill_row<KIND>(hs, row, a.ep);
+        const uint32_t m = a.n_each < h0 ? (uint32_t)a.n_each : h0;
+        for (uint32_t k = 0; k < m; ++k) put_elem<S::ESZ>(sub_out, k, row + k * S::ESZ);
     }
 }
 
@@ -265,6 +305,7 @@ hipError_t run(const uint32_t st[6], const mirng_distribution *d, uint64_t s_fir
     a.u_tab = utab;
     a.c_tab = ctab;
     a.s_tab = stab;
+    a.p_tab = tables_of(dev) + kOffPow2;
     a.out = out;
     fill_params(a, d);
     // one launch per at most 2^31 groups

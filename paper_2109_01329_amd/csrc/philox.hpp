@@ -208,13 +208,16 @@ __device__ __forceinline__ void emit_slot(const SlotRun &r, uint32_t slot, u32x4
               r.full_lo, r.full_count, e0, r.n, r.ep.nt);
 }
 
-// The 16 bytes of slot s of a run when the caller knows the whole slot lies
-// inside the output: one unconditional 16-byte store.
+// The 16 bytes of slot sb + lane of a run when the caller knows the whole
+// slot lies inside the output: one unconditional 16-byte store.  sb is the
+// step's (wave-uniform) first slot, so the address is a scalar base plus
+// the lane's 16-byte offset.
 template <int KIND, int RANGED = 2>
-__device__ __forceinline__ void emit_slot_whole(const SlotRun &r, uint32_t slot, u32x4 w)
+__device__ __forceinline__ void emit_slot_whole(const SlotRun &r, uint32_t sb, uint32_t lane,
+                                                u32x4 w)
 {
     const u32x4 v = transform<KIND, RANGED>(r.ep, w);
-    g_u32x4_a4 *p = (g_u32x4_a4 *)(r.out_base + (uint64_t)slot * 16u);
+    g_u32x4_a4 *p = (g_u32x4_a4 *)(r.out_base + (uint64_t)sb * 16u) + lane;
     if (r.ep.nt) __builtin_nontemporal_store(v, p);
     else *p = v;
 }
@@ -260,7 +263,7 @@ __device__ __forceinline__ void walk_slots_body(const SlotRun &r, uint32_t s0, u
             const uint32_t sb = s0 + (it << 6);
             const uint32_t slot = sb + lane;
             const u32x4 w = block_at<NC>(r.base, r.k0, r.k1, slot);
-            if (whole_step(r, sb, lo, width)) emit_slot_whole<KIND, RANGED>(r, slot, w);
+            if (whole_step(r, sb, lo, width)) emit_slot_whole<KIND, RANGED>(r, sb, lane, w);
             else if (slot - lo < width) emit_slot<KIND, RANGED>(r, slot, w);
         }
     } else {
@@ -275,7 +278,7 @@ __device__ __forceinline__ void walk_slots_body(const SlotRun &r, uint32_t s0, u
             if constexpr (PHASE >= 2) nb.y = from_next_lane(cur.y, lane0(nxt.y));
             if constexpr (PHASE >= 3) nb.z = from_next_lane(cur.z, lane0(nxt.z));
             const u32x4 w = funnel<PHASE>(cur, nb);
-            if (whole_step(r, sb, lo, width)) emit_slot_whole<KIND, RANGED>(r, slot, w);
+            if (whole_step(r, sb, lo, width)) emit_slot_whole<KIND, RANGED>(r, sb, lane, w);
             else if (slot - lo < width) emit_slot<KIND, RANGED>(r, slot, w);
             cur = nxt;
         }
@@ -337,7 +340,7 @@ __device__ __forceinline__ void walk_chunks_body(const SlotRun &r, uint32_t s0, 
             w = funnel<PHASE>(b[it], nb);
         }
         if (PHASE == 0 && whole_step(r, s0 + it * S, s0, span))
-            emit_slot_whole<KIND, RANGED>(r, s0 + off, w);
+            emit_slot_whole<KIND, RANGED>(r, s0 + it * S, lane, w);
         else if (lane < S && off < span)
             emit_slot<KIND, RANGED>(r, s0 + off, w);
     }

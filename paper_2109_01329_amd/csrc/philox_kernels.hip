@@ -148,7 +148,7 @@ __device__ __forceinline__ void group_chunks(const PhiloxFill &a, u32x4 *heads)
             const uint32_t cb = g0 + (it * nw + w) * 64u;
             const uint32_t slot = cb + lane;
             if (kWhole && whole_step(r, cb, 0u, a.nslots))
-                emit_slot_whole<KIND, RANGED>(r, slot, cur[it]);
+                emit_slot_whole<KIND, RANGED>(r, cb, lane, cur[it]);
             else if (slot < a.nslots) emit_slot<KIND, RANGED>(r, slot, cur[it]);
         }
     } else {
@@ -173,7 +173,7 @@ __device__ __forceinline__ void group_chunks(const PhiloxFill &a, u32x4 *heads)
             const uint32_t slot = cb + lane;
             const u32x4 wv = funnel<PHASE>(cur[it], nb);
             if (kWhole && whole_step(r, cb, 0u, a.nslots))
-                emit_slot_whole<KIND, RANGED>(r, slot, wv);
+                emit_slot_whole<KIND, RANGED>(r, cb, lane, wv);
             else if (slot < a.nslots) emit_slot<KIND, RANGED>(r, slot, wv);
         }
     }

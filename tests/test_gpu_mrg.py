@@ -1,6 +1,8 @@
 """GPU parity of the MRG32k3a path against the oracle's sequential stepping,
-through the C ABI: plain generate at ragged sizes and output alignments,
-continuity, and substreams 2^76 apart."""
+through the C ABI: plain generate at ragged sizes and output alignments (off
+the 16-byte and the 128-byte grid, where the thread ranges start at the first
+line boundary and the head is written separately), continuity, and
+substreams 2^76 apart."""
 import numpy as np
 import pytest
 
@@ -20,7 +22,7 @@ def test_plain_sizes_and_alignments(kind):
     esz = mr.ELEM_BYTES[kind]
     g = np.random.default_rng(61 + kind)
     for n in SIZES:
-        for off in ([0, 4, 8] if esz == 4 else [0, 8]):
+        for off in ([0, 4, 8, 12, 16, 72] if esz == 4 else [0, 8, 16, 72]):
             seed = int(g.integers(0, 2**64, dtype=np.uint64))
             offset = int(g.integers(0, 2**40, dtype=np.uint64))
             e = mr.Engine(mr.MRG32K3A, seed, offset)
