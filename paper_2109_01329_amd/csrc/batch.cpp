@@ -141,39 +141,48 @@ struct Work {
     int32_t bm = 0;         // a request whose transform reads the LDS tables (either engine)
 };
 
-// Philox kinds whose transforms need many registers (FP64 Box-Muller, the
-// inverse-CDF Gaussians) live in a separate generation kernel.
-bool wide_kind(int kind)
+// One pass over a request table: the Work it holds, and (copy != null) its
+// copy into `copy` on the way (the generate path's pinned staging).
+// Branch-light: every request costs the same few operations.
+Work scan_requests(const mirng_request *q, size_t count, mirng_request *copy = nullptr)
 {
-    return kind == MIRNG_GAUSSIAN_F64 || kind == MIRNG_GAUSSIAN_ICDF_F32 ||
-           kind == MIRNG_GAUSSIAN_ICDF_F64;
-}
-
-Work scan_requests(const mirng_request *q, size_t count)
-{
-    Work w;
+    uint64_t m = 0;   // kind bits (kind & 15): Philox at 0..15, MRG at 16..31, other at 32..47
+    uint64_t tiles = 0, chunks = 0;
     for (size_t i = 0; i < count; ++i) {
-        const bool ph = q[i].engine_type == MIRNG_PHILOX4X32_10;
-        const bool mg = q[i].engine_type == MIRNG_MRG32K3A;
-        w.philox |= ph;
-        w.mrg |= mg;
-        w.wide |= ph && wide_kind(q[i].dist.kind);
-        w.mrg_wide |= mg && (q[i].dist.kind == MIRNG_GAUSSIAN_ICDF_F32 ||
-                             q[i].dist.kind == MIRNG_GAUSSIAN_ICDF_F64);
-        w.bm |= mirng::uses_lds_tables(q[i].dist.kind);
-        const uint64_t n = q[i].n;
-        if (n == 0 || n >= (1ull << 32)) continue;
-        const bool f64 = q[i].dist.kind == MIRNG_UNIFORM_F64 ||
-                         q[i].dist.kind == MIRNG_GAUSSIAN_F64 ||
-                         q[i].dist.kind == MIRNG_GAUSSIAN_ICDF_F64;
-        if (mg) {
-            const uint64_t per = (uint64_t)256 * mirng::kBatchMrgPasses * (f64 ? 16 : 32);
-            w.chunks += (n + per - 1) / per;
-        } else if (ph) {
-            const uint64_t units = (n * (f64 ? 2 : 1) + 3) / 4 + 2;
-            w.tiles += (units + 63) / 64 + 1;
-        }
+        mirng_request r;
+        std::memcpy(&r, q + i, sizeof r);
+        if (copy) std::memcpy(copy + i, &r, sizeof r);
+        const uint32_t k = (uint32_t)r.dist.kind & 15u;
+        const bool ph = r.engine_type == MIRNG_PHILOX4X32_10;
+        const bool mg = r.engine_type == MIRNG_MRG32K3A;
+        m |= (uint64_t)1 << (k + (ph ? 0u : mg ? 16u : 32u));
+        const uint64_t n = r.n;
+        const bool ok = n - 1u < (1ull << 32) - 1u;             // 0 < n < 2^32
+        const bool f64 = ((1u << MIRNG_UNIFORM_F64 | 1u << MIRNG_GAUSSIAN_F64 |
+                           1u << MIRNG_GAUSSIAN_ICDF_F64) >> k) & 1u;
+        // MRG: chunks of 256 threads x kBatchMrgPasses passes of L outputs
+        const uint64_t per_log2 = 8 + 1 + (f64 ? 4 : 5);
+        static_assert(mirng::kBatchMrgPasses == 2, "chunk size");
+        chunks += (ok && mg) ? (n + ((uint64_t)1 << per_log2) - 1) >> per_log2 : 0;
+        // Philox: 16-byte units of n outputs plus the head and its slack
+        const uint64_t units = ((n << (f64 ? 1 : 0)) + 3) / 4 + 2;
+        tiles += (ok && ph) ? (units + 63) / 64 + 1 : 0;
     }
+    Work w;
+    w.tiles = tiles;
+    w.chunks = chunks;
+    w.philox = (m & 0xFFFFull) != 0;
+    w.mrg = (m & 0xFFFF0000ull) != 0;
+    // Philox kinds whose transforms need many registers (FP64 Box-Muller,
+    // the inverse-CDF Gaussians) live in a separate generation kernel
+    const uint64_t wide = 1u << MIRNG_GAUSSIAN_F64 | 1u << MIRNG_GAUSSIAN_ICDF_F32 |
+                          1u << MIRNG_GAUSSIAN_ICDF_F64;
+    w.wide = (m & wide) != 0;
+    w.mrg_wide = ((m >> 16) & (1u << MIRNG_GAUSSIAN_ICDF_F32 | 1u << MIRNG_GAUSSIAN_ICDF_F64)) != 0;
+    uint64_t lds = 0;
+    for (uint32_t kk = 0; kk < 16; ++kk)
+        if (mirng::uses_lds_tables((int)kk)) lds |= (uint64_t)1 << kk;
+    w.bm = (m & (lds | lds << 16 | lds << 32)) != 0;
     return w;
 }
 
@@ -215,12 +224,12 @@ size_t grid_waves(const mirng_batch_config &c)
     return (w + wpb - 1) / wpb * wpb;
 }
 
-void batch_grids(const mirng_batch_config &cfg, const mirng_request *reqs, size_t count,
-                 uint64_t max_waves, BatchArgs &a)
+namespace {
+
+void grids_of(const mirng_batch_config &cfg, const Work &w, uint64_t max_waves, BatchArgs &a)
 {
     const uint64_t wpb = (uint64_t)cfg.block / 64;
     uint64_t waves = grid_waves(cfg);
-    const Work w = scan_requests(reqs, count);
     // Philox: no more waves than about two tiles of work each
     const uint64_t want = ((w.tiles + 1) / 2 + wpb - 1) / wpb * wpb;
     waves = std::max<uint64_t>(wpb, std::min(waves, want));
@@ -244,6 +253,14 @@ void batch_grids(const mirng_batch_config &cfg, const mirng_request *reqs, size_
     a.bm = w.bm;
     a.block = (uint32_t)cfg.block;
     a.groups = (uint32_t)(waves / wpb);
+}
+
+}  // namespace
+
+void batch_grids(const mirng_batch_config &cfg, const mirng_request *reqs, size_t count,
+                 uint64_t max_waves, BatchArgs &a)
+{
+    grids_of(cfg, scan_requests(reqs, count), max_waves, a);
 }
 
 hipError_t batcher_reserve(mirng_batcher b, size_t count)
@@ -356,18 +373,20 @@ mirng_status mirng::generate_batch_refs(mirng_batcher b, const mirng_request *re
     MrgBatchTables tabs;
     if (mrg_batch_tables(dev, tabs) != hipSuccess) return MIRNG_E_DEVICE;
     BatchArgs a{};
-    batch_grids(b->cfg, reqs, count, 0, a);
     int k;
+    Work w;
     if (b->staged >= 0 && reqs == b->slots[b->staged].h_reqs &&
         count <= b->slots[b->staged].cap && b->slots[b->staged].dev == dev) {
         k = b->staged;                                   // filled in place
         if (prepare(b->slots[k], count, dev) != hipSuccess) return MIRNG_E_ALLOC;
+        w = scan_requests(reqs, count);
     } else {
         k = b->next;
         if (prepare(b->slots[k], count, dev) != hipSuccess) return MIRNG_E_ALLOC;
         b->next = (k + 1) % kSlots;
-        std::memcpy(b->slots[k].h_reqs, reqs, count * sizeof(mirng_request));
+        w = scan_requests(reqs, count, b->slots[k].h_reqs);   // copy and scan, one pass
     }
+    grids_of(b->cfg, w, 0, a);
     b->staged = -1;
     Slot &sl = b->slots[k];
     if (refs) std::memcpy(sl.h_refs, refs, count * sizeof(EngineRef));
