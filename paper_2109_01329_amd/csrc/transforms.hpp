@@ -290,7 +290,8 @@ __device__ __forceinline__ double neg_ln_tab(double a)
     const double f2 = f * f;
     const double q = __builtin_fma(f, 0x1.5555555555555p-2, -0.5);
     const double s = __builtin_fma(f2, q, f);                  // ln(1 + f)
-    return __builtin_fma((double)e7, 0x1.62e42fefa39f0p-1, 0.5 * s_bm_log[j][1]) - s;
+    // ((7 - e) C + T_j) / 2 - s: the halving is exact
+    return __builtin_fma(0.5, __builtin_fma((double)e7, 0x1.62e42fefa39f0p+0, s_bm_log[j][1]), -s);
 }
 
 // Inverse-CDF Gaussian from one word, FP32 output: u = ((w >> 8) + 1/2)
@@ -304,31 +305,65 @@ __device__ __forceinline__ double neg_ln_tab(double a)
 //   hardware reciprocal square root corrected once.
 // z = x F is rounded once to FP32.  F varies slowly with w, so w's absolute
 // error costs far below 2^-40 relative.  Needs the Box-Muller tables in LDS.
-__device__ __forceinline__ float icdf_f32(uint32_t wd)
+struct IcdfArg {
+    double x, w;
+};
+
+__device__ __forceinline__ IcdfArg icdf_arg(uint32_t wd)
 {
     const int32_t xi = (int32_t)(((wd >> 8) << 1) + 1u) - (1 << 24);
-    const double x = (double)xi * 0x1p-24;
-    const double w = neg_ln_tab((1.0 - x) * (1.0 + x));
-    double p;
-    if (w < 6.25) {
-        p = horner_s<13>(scalar_table(kIcdfCentral), w - 3.125);
-    } else {
-        const double y = __builtin_amdgcn_rsq(w);
-        const double r0 = w * y;
-        const double t = __builtin_fma(0.5 * y, __builtin_fma(-r0, r0, w), r0) - 3.25;
-        p = horner_s<11>(scalar_table(kIcdfTail), t);
-    }
-    return (float)(x * p);
+    IcdfArg a;
+    a.x = (double)xi * 0x1p-24;
+    a.w = neg_ln_tab((1.0 - a.x) * (1.0 + a.x));
+    return a;
 }
 
-// Four inverse-CDF Gaussians.
-__device__ __forceinline__ f32x4 icdf4_f32(u32x4 w)
+__device__ __forceinline__ double icdf_tail(double w)
 {
+    const double y = __builtin_amdgcn_rsq(w);
+    const double r0 = w * y;
+    const double t = __builtin_fma(0.5 * y, __builtin_fma(-r0, r0, w), r0) - 3.25;
+    return horner_s<11>(scalar_table(kIcdfTail), t);
+}
+
+__device__ __forceinline__ float icdf_f32(uint32_t wd)
+{
+    const IcdfArg a = icdf_arg(wd);
+    const double p = a.w < 6.25 ? horner_s<13>(scalar_table(kIcdfCentral), a.w - 3.125)
+                                : icdf_tail(a.w);
+    return (float)(a.x * p);
+}
+
+// Four inverse-CDF Gaussians, each with exactly icdf_f32's operations: the
+// four central polynomials run interleaved (each scalar coefficient is read
+// once for four FMAs, and four independent chains hide the FMA latency),
+// and the tail, which about one word in a thousand takes, replaces a
+// sample's central value under a branch of its own.
+__device__ __forceinline__ f32x4 icdf4_f32(u32x4 wv)
+{
+    const uint32_t wd[4] = {wv.x, wv.y, wv.z, wv.w};
+    IcdfArg a[4];
+    double t[4], p[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        a[k] = icdf_arg(wd[k]);
+        t[k] = a[k].w - 3.125;
+    }
+    c_f64 *c = scalar_table(kIcdfCentral);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) p[k] = fma_su(c[12], t[k], c[11]);
+#pragma unroll
+    for (int j = 10; j >= 0; --j) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) p[k] = fma_su(p[k], t[k], c[j]);
+    }
     f32x4 f;
-    f.x = icdf_f32(w.x);
-    f.y = icdf_f32(w.y);
-    f.z = icdf_f32(w.z);
-    f.w = icdf_f32(w.w);
+    float *fo = (float *)&f;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (!(a[k].w < 6.25)) p[k] = icdf_tail(a[k].w);
+        fo[k] = (float)(a[k].x * p[k]);
+    }
     return f;
 }
 
