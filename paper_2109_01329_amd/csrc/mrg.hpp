@@ -147,24 +147,37 @@ __device__ __forceinline__ char *mrg_row(char *lds, uint32_t t)
 }
 
 // Runs L steps of `s` and writes the L outputs into `row` (16-byte aligned).
-// The inverse-CDF kinds evaluate one quantile at a time (a rolled loop) so
-// that the registers of one quantile suffice.
+// The inverse-CDF kinds evaluate one 16-byte vector of quantiles at a time
+// (a rolled loop) so that the registers of one vector suffice.
 template <int KIND>
 __device__ __forceinline__ void mrg_fill_row(MrgState &s, char *row, const Epilogue &ep)
 {
     using S = MrgShape<KIND>;
     if constexpr (KIND == kIcdf || KIND == kIcdf64) {
 #pragma unroll 1
-        for (int l = 0; l < S::L; ++l) {
+        for (int l = 0; l < S::L; l += S::EPV) {
             if constexpr (KIND == kIcdf) {
-                float f = icdf_f32(mrg_step(s));
-                if (ep.ranged) f = __builtin_fmaf(f, ep.d32, ep.a32);
-                *(float *)(row + l * 4) = f;
+                u32x4 y;
+                y.x = mrg_step(s); y.y = mrg_step(s);
+                y.z = mrg_step(s); y.w = mrg_step(s);
+                f32x4 f = icdf4_f32(y);
+                if (ep.ranged) {
+                    f.x = __builtin_fmaf(f.x, ep.d32, ep.a32);
+                    f.y = __builtin_fmaf(f.y, ep.d32, ep.a32);
+                    f.z = __builtin_fmaf(f.z, ep.d32, ep.a32);
+                    f.w = __builtin_fmaf(f.w, ep.d32, ep.a32);
+                }
+                *(f32x4 *)(row + l * 4) = f;
             } else {
                 // u = y / (m1 + 1) as for uniform FP64: never 0 or 1
-                double d = normal_quantile(y_to_u01d(mrg_step(s)));
-                if (ep.ranged) d = __builtin_fma(d, ep.d64, ep.a64);
-                *(double *)(row + l * 8) = d;
+                const double u0 = y_to_u01d(mrg_step(s));
+                const double u1 = y_to_u01d(mrg_step(s));
+                f64x2 d = normal_quantile2(u0, u1);
+                if (ep.ranged) {
+                    d.x = __builtin_fma(d.x, ep.d64, ep.a64);
+                    d.y = __builtin_fma(d.y, ep.d64, ep.a64);
+                }
+                *(f64x2 *)(row + l * 8) = d;
             }
         }
     } else {

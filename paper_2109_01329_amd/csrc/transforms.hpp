@@ -380,21 +380,54 @@ __device__ __forceinline__ f32x4 icdf4_f32(u32x4 wv)
 //   Q2(s - 5.05) beyond; z = x F.
 // F changes slowly with w (d ln F / dw < 0.3), so w's absolute error costs
 // about as much relative error in z.  Needs the Box-Muller tables in LDS.
+struct QuantArg {
+    double x, w;
+};
+
+__device__ __forceinline__ QuantArg quantile_arg(double u)
+{
+    QuantArg a;
+    a.x = __builtin_fma(u, 2.0, -1.0);
+    a.w = -ln_tab64(4.0 * u * (1.0 - u));
+    return a;
+}
+
+// F beyond the central range, w >= 6.25.
+__device__ __forceinline__ double quantile_outer(double w)
+{
+    const double r = sqrt_f64(w);
+    if (r < 4.0)
+        return horner_s<21>(scalar_table(kIcdf64Mid), r - 3.25);
+    return horner_s<19>(scalar_table(kIcdf64Tail), r - 5.05);
+}
+
 __device__ __forceinline__ double normal_quantile(double u)
 {
-    const double x = __builtin_fma(u, 2.0, -1.0);
-    const double w = -ln_tab64(4.0 * u * (1.0 - u));
-    double p;
-    if (w < 6.25) {
-        p = horner_s<25>(scalar_table(kIcdf64Central), w - 3.125);
-    } else {
-        const double r = sqrt_f64(w);
-        if (r < 4.0)
-            p = horner_s<21>(scalar_table(kIcdf64Mid), r - 3.25);
-        else
-            p = horner_s<19>(scalar_table(kIcdf64Tail), r - 5.05);
+    const QuantArg a = quantile_arg(u);
+    const double p = a.w < 6.25 ? horner_s<25>(scalar_table(kIcdf64Central), a.w - 3.125)
+                                : quantile_outer(a.w);
+    return a.x * p;
+}
+
+// Two quantiles, each with exactly normal_quantile's operations, their
+// central polynomials interleaved as in icdf4_f32.
+__device__ __forceinline__ f64x2 normal_quantile2(double u0, double u1)
+{
+    const QuantArg a[2] = {quantile_arg(u0), quantile_arg(u1)};
+    const double t[2] = {a[0].w - 3.125, a[1].w - 3.125};
+    c_f64 *c = scalar_table(kIcdf64Central);
+    double p[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) p[k] = fma_su(c[24], t[k], c[23]);
+#pragma unroll
+    for (int j = 22; j >= 0; --j) {
+#pragma unroll
+        for (int k = 0; k < 2; ++k) p[k] = fma_su(p[k], t[k], c[j]);
     }
-    return x * p;
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+        if (!(a[k].w < 6.25)) p[k] = quantile_outer(a[k].w);
+    return f64x2{a[0].x * p[0], a[1].x * p[1]};
 }
 
 // The FP64 uniform of an inverse-CDF Gaussian from two Philox words: with
@@ -406,17 +439,10 @@ __device__ __forceinline__ double icdf_u64(uint32_t lo, uint32_t hi)
     return ((double)v + 0.5) * 0x1p-52;
 }
 
-// Two FP64 inverse-CDF Gaussians from four Philox words, one at a time.
+// Two FP64 inverse-CDF Gaussians from four Philox words.
 __device__ __forceinline__ f64x2 icdf2_f64(u32x4 w)
 {
-    f64x2 d = {0.0, 0.0};
-#pragma unroll 1
-    for (int j = 0; j < 2; ++j) {
-        const double z = normal_quantile(icdf_u64(w.x, w.y));
-        w = u32x4{w.z, w.w, w.x, w.y};
-        d = f64x2{d.y, z};
-    }
-    return d;
+    return normal_quantile2(icdf_u64(w.x, w.y), icdf_u64(w.z, w.w));
 }
 
 }  // namespace mirng
