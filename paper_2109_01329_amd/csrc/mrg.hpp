@@ -100,6 +100,17 @@ __device__ __forceinline__ double mod_balanced(double p, double m, double inv_m)
 // y = x1 - x2 (+ m1 = - 209 mod 2^32 when x1 <= x2) in 32-bit wrap-around
 // arithmetic.  Only full-rate FP64 adds, multiplies and FMAs touch the
 // state.
+//
+// The canonical residue is one v_mad_i32_i24: the sign bit of i (0 or 1,
+// a 24-bit operand) times -k (k = 209 or 22853), plus i.  (The compiler's
+// own form of the same select is a shift, an AND and an add.)
+__device__ __forceinline__ uint32_t canon_residue(int32_t i, int32_t neg_k)
+{
+    uint32_t r;
+    asm("v_mad_i32_i24 %0, %1, %2, %3" : "=v"(r) : "v"((uint32_t)i >> 31), "s"(neg_k), "v"(i));
+    return r;
+}
+
 __device__ __forceinline__ uint32_t mrg_step(MrgState &s)
 {
     const double p1 = mod_balanced(__builtin_fma(1403580.0, s.a1, -810728.0 * s.a0), kM1d,
@@ -110,8 +121,8 @@ __device__ __forceinline__ uint32_t mrg_step(MrgState &s)
     s.b0 = s.b1; s.b1 = s.b2; s.b2 = p2;
     const int32_t i1 = (int32_t)p1;
     const int32_t i2 = (int32_t)p2;
-    const uint32_t x1 = (uint32_t)i1 - ((uint32_t)(i1 >> 31) & 209u);
-    const uint32_t x2 = (uint32_t)i2 - ((uint32_t)(i2 >> 31) & 22853u);
+    const uint32_t x1 = canon_residue(i1, -209);
+    const uint32_t x2 = canon_residue(i2, -22853);
     return x1 - x2 - (x1 <= x2 ? 209u : 0u);
 }
 
