@@ -9,6 +9,11 @@
 // base-64 digit powers (at most 4 + 5 matrix-vector products, done by one
 // wave); thread t then applies A^(t q) from a resident table and runs q
 // sequential steps, L at a time through LDS (the shared pass code).
+// Short substreams (each within one group) whose outputs start on 128-byte
+// lines are instead laid out four to a group, 64 threads each, so that no
+// thread idles and each per-thread jump serves four times as many steps;
+// the group's four start states are formed side by side by the lanes of
+// one wave (pick_spg).
 //
 // Line-aligned ranges.  The thread ranges start h0 elements into the
 // output, h0 = the elements before its first 128-byte boundary (a cache
@@ -30,8 +35,9 @@ struct MrgLaunch {
     uint32_t q;               // steps per thread (multiple of L)
     uint32_t chunks_per_sub;  // workgroups per substream
     uint32_t use_sub;         // 0: plain generate (substream 0 only)
-    uint32_t pad;
+    uint32_t spg;             // substreams per workgroup: 1 or 4
     uint64_t n_each;          // outputs per substream
+    uint64_t nsub;            // substreams in the launch
     uint64_t s_first;         // first substream index
     const uint32_t *u_tab;    // A^(t q): [t][comp][9]
     const uint32_t *c_tab;    // A^(k 64^d 256 q): [d][k][comp][9]
@@ -51,16 +57,26 @@ __global__ __launch_bounds__(kThreads) void mrg_kernel(MrgLaunch a)
 {
     using S = MrgShape<KIND>;
     __shared__ __attribute__((aligned(16))) char lds[kThreads * S::ROW];
-    __shared__ uint32_t wg_state[6];
+    __shared__ uint32_t wg_state[4][6];
     __shared__ uint32_t wg_head[6];
     if constexpr (uses_lds_tables(KIND)) bm_stage();
 
     const uint32_t t = threadIdx.x;
     const uint32_t g = blockIdx.x;
-    const uint32_t sub = g / a.chunks_per_sub;
-    const uint32_t c = g - sub * a.chunks_per_sub;
-    char *sub_out = a.out + (uint64_t)sub * a.n_each * S::ESZ;
-    // elements before the substream's first 128-byte boundary
+    // spg = 4 (substream launches only): the group holds substreams
+    // sub .. sub + 3, each one whole range of 64 threads whose outputs
+    // start on a 128-byte line, so that the group's rows are contiguous as
+    // in a single substream.  Thread t serves substream sub + j from step
+    // tq q of it.
+    const uint32_t spg = a.spg;
+    const uint32_t tps_log2 = spg == 4 ? 6u : 8u;
+    const uint32_t j = t >> tps_log2;
+    const uint32_t tq = t & ((1u << tps_log2) - 1u);
+    const uint64_t sub = spg == 1 ? g / a.chunks_per_sub : (uint64_t)g * spg;
+    const uint32_t c = spg == 1 ? (uint32_t)(g - sub * a.chunks_per_sub) : 0u;
+    const uint64_t nsub_here = spg == 1 ? 1 : (a.nsub - sub < spg ? a.nsub - sub : spg);
+    char *sub_out = a.out + sub * a.n_each * S::ESZ;
+    // elements before the substream's first 128-byte boundary (0 when spg = 4)
     uint32_t h0 = (uint32_t)((0u - (uint32_t)(uintptr_t)sub_out) & 127u) / S::ESZ;
     if (paired(KIND) && (h0 & 1u)) h0 = 0;
 
@@ -69,7 +85,8 @@ __global__ __launch_bounds__(kThreads) void mrg_kernel(MrgLaunch a)
 #pragma unroll
         for (int i = 0; i < 6; ++i) v[i] = a.st[i];
         if (a.use_sub) {
-            const uint64_t s = a.s_first + sub;
+            // lane l forms the state of substream sub + l mod spg
+            const uint64_t s = a.s_first + sub + (t & (spg - 1u));
             for (int d = 0; d < kSDigits; ++d) {
                 const uint32_t k = (uint32_t)(s >> (6 * d)) & 63u;
                 if (k) apply_mat(a.s_tab + (d * 64 + k) * kMatWords, v);
@@ -85,22 +102,23 @@ __global__ __launch_bounds__(kThreads) void mrg_kernel(MrgLaunch a)
         }
         for (int b = 0; b < 5; ++b)
             if ((h0 >> b) & 1u) apply_mat(a.p_tab + b * kMatWords, v);
-        if (t == 0) {
+        if (t < spg) {
 #pragma unroll
-            for (int i = 0; i < 6; ++i) wg_state[i] = v[i];
+            for (int i = 0; i < 6; ++i) wg_state[t][i] = v[i];
         }
     }
     __syncthreads();
 
     uint32_t v[6];
 #pragma unroll
-    for (int i = 0; i < 6; ++i) v[i] = wg_state[i];
-    if (t) apply_mat(a.u_tab + t * kMatWords, v);
+    for (int i = 0; i < 6; ++i) v[i] = wg_state[j][i];
+    if (tq) apply_mat(a.u_tab + tq * kMatWords, v);
     MrgState s = mrg_state(v);
 
     // the ranges' element 0 is element h0 of the substream
     const uint64_t e_wg = (uint64_t)c * kThreads * a.q;
-    const uint64_t n_rest = a.n_each > h0 ? a.n_each - h0 : 0;
+    const uint64_t n_range = nsub_here * a.n_each;
+    const uint64_t n_rest = n_range > h0 ? n_range - h0 : 0;
     char *rng_out = sub_out + (uint64_t)h0 * S::ESZ;
     char *row = mrg_row<KIND>(lds, t);
     const uint32_t h = mrg_head<KIND>(rng_out);
@@ -255,6 +273,31 @@ uint32_t pick_q(int kind, uint64_t n_each, uint64_t nsub)
     return q;
 }
 
+// Substreams per workgroup for a substream launch whose substreams each
+// fit one workgroup of q1 steps per thread (n_each <= 256 q1): 4 when each
+// substream is exactly one range of 64 threads of q steps (q a power of two
+// in [L, 1024]) whose outputs start on a 128-byte line, else 1.  No thread
+// then idles, the per-thread jump A^(t q) serves four times more outputs,
+// and one wave forms the four substreams' start states side by side (one
+// per lane).  Where one substream already fills its group exactly, four
+// are taken only up to the q that measured fastest for plain launches (64
+// for FP64 outputs, 512 for 4-byte ones): 65536 x 4096 FP64 ran in 0.37
+// instead of 0.54 ms at q = 64, but 16384 x 16384 in 0.40 instead of 0.38
+// ms at q = 256.
+uint32_t pick_spg(int kind, uint64_t n_each, const char *out, uint32_t q1, uint32_t &q)
+{
+    const uint32_t esz = (uint32_t)elem_bytes(kind);
+    const uint32_t L = 128 / esz;
+    if (((uintptr_t)out & 127u) != 0 || (n_each * esz) % 128 != 0 ||
+        n_each > (uint64_t)kThreads * q1 || n_each % 64 != 0)
+        return 1;
+    const uint64_t qq = n_each / 64;
+    if (qq < L || qq > 1024 || (qq & (qq - 1)) != 0) return 1;
+    if (n_each == (uint64_t)kThreads * q1 && qq > (esz == 8 ? 64u : 512u)) return 1;
+    q = (uint32_t)qq;
+    return 4;
+}
+
 hipError_t launch(const MrgLaunch &a, int kind, uint64_t groups, hipStream_t s)
 {
     const dim3 grid((uint32_t)groups), block(kThreads);
@@ -286,11 +329,12 @@ hipError_t run(const uint32_t st[6], const mirng_distribution *d, uint64_t s_fir
     int dev = 0;
     hipError_t err = hipGetDevice(&dev);
     if (err != hipSuccess) return err;
-    const uint32_t q = pick_q(d->kind, n_each, nsub);
+    const bool use_sub = spacing_log2 > 0;
+    uint32_t q = pick_q(d->kind, n_each, nsub);
+    const uint32_t spg = use_sub ? pick_spg(d->kind, n_each, out, q, q) : 1u;
     const uint32_t *utab = nullptr, *ctab = nullptr;
     err = tables_for(dev, q, utab, ctab);
     if (err != hipSuccess) return err;
-    const bool use_sub = spacing_log2 > 0;
     const uint32_t *stab = nullptr;
     if (use_sub) stab = tables_of(dev) + (spacing_log2 == 76 ? kOffS76 : kOffS127);
     MrgLaunch a{};
@@ -300,7 +344,9 @@ hipError_t run(const uint32_t st[6], const mirng_distribution *d, uint64_t s_fir
     const uint64_t chunks = (n_each + per_group - 1) / per_group;
     a.chunks_per_sub = (uint32_t)chunks;
     a.use_sub = use_sub ? 1 : 0;
+    a.spg = spg;
     a.n_each = n_each;
+    a.nsub = nsub;
     a.s_first = s_first;
     a.u_tab = utab;
     a.c_tab = ctab;
@@ -309,7 +355,7 @@ hipError_t run(const uint32_t st[6], const mirng_distribution *d, uint64_t s_fir
     a.out = out;
     fill_params(a, d);
     // one launch per at most 2^31 groups
-    const uint64_t groups = chunks * nsub;
+    const uint64_t groups = spg == 1 ? chunks * nsub : (nsub + spg - 1) / spg;
     if (groups >= (1ull << 31) || chunks >= (1ull << (6 * kCDigits)))
         return hipErrorInvalidValue;
     return launch(a, d->kind, groups, s);

@@ -104,6 +104,30 @@ def test_substreams_ragged(kind, first, count, n_each, off):
     assert gh.guards_intact(buf, off, count * n_each * esz)
 
 
+@pytest.mark.parametrize("kind,first,count,n_each", [
+    (mr.UNIFORM_F32, 3, 7, 2048), (mr.GAUSSIAN_F32, 10, 6, 4096), (mr.UNIFORM_F64, 0, 5, 4096),
+    (mr.GAUSSIAN_F64, 100, 4, 2048), (mr.BITS_U32, 2**30 - 1026, 1026, 16384),
+    (mr.GAUSSIAN_ICDF_F32, 77, 4, 8192), (mr.UNIFORM_I32, 5000, 3, 64 * 32)])
+def test_substreams_four_per_group(kind, first, count, n_each):
+    """Short line-aligned substreams run four to a workgroup (64 threads
+    each, 32 to 256 steps per thread here); counts that are not a multiple
+    of four leave the last group partly empty.  Each substream checked
+    (all of them, or 9 spread over the 1026) equals the oracle's jump by
+    s * 2^76 followed by sequential stepping."""
+    esz = mr.ELEM_BYTES[kind]
+    e = mr.Engine(mr.MRG32K3A, 0x5EED, 77)
+    buf = gh.device_buffer(count * n_each * esz + 256)
+    buf.fill_(0xA5)
+    e.generate_substreams(kind, first, count, n_each, int(buf.data_ptr()) + 128)
+    got = gh.fetch(buf, 128, kind, count * n_each)
+    st0 = oracle.mrg_skip(oracle.mrg_seed(0x5EED), 77)
+    check = range(count) if count <= 16 else [0, 1, 2, 3, 4, 511, 1023, 1024, 1025]
+    for i in check:
+        st = oracle.mrg_skip(st0, (first + i) << 76)
+        gh.assert_match(kind, got[i * n_each:(i + 1) * n_each], gh.oracle_mrg(st, kind, n_each))
+    assert gh.guards_intact(buf, 128, count * n_each * esz)
+
+
 @pytest.mark.parametrize("kind,first,count,n_each,off", [
     (mr.UNIFORM_F64, 0, 5, 4097, 8), (mr.BITS_U32, 2**30 - 3, 3, 1000, 4),
     (mr.GAUSSIAN_F32, 77, 2, 12345, 0)])
