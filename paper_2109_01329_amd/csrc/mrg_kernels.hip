@@ -256,16 +256,20 @@ hipError_t tables_for(int dev, uint32_t q, const uint32_t *&u, const uint32_t *&
 
 // Steps per thread: a power of two in [L, 1024] (L = outputs per pass: 32,
 // or 16 for FP64) chosen so that a launch has about 2048 workgroups (8 per
-// CU) for 4-byte outputs and 16384 for 8-byte ones, when the size allows,
-// without leaving half a group idle.  A pass writes one 128-byte row per
-// thread, rows q elements apart: FP64 outputs, at twice the bytes per step,
-// ran 1.5 times faster with the rows 512 bytes apart (q = 64 at 2^28
-// outputs) than 4 KiB apart (q = 512), while 4-byte outputs ran fastest at
-// q = 512, where the per-thread and per-group jumps cost least.
+// CU) for 4-byte outputs, 16384 for uniform FP64 and 4096 for the FP64
+// Gaussians, when the size allows, without leaving half a group idle.  A
+// pass writes one 128-byte row per thread, rows q elements apart: uniform
+// FP64 outputs, at twice the bytes per step, ran 1.5 times faster with the
+// rows 512 bytes apart (q = 64 at 2^28 outputs) than 4 KiB apart (q = 512),
+// while 4-byte outputs ran fastest at q = 512, where the per-thread and
+// per-group jumps cost least.  The VALU-bound FP64 Gaussians gain more from
+// fewer jumps than they lose on the row spacing: q = 256 ran 0.565 against
+// 0.606 ms (Box-Muller) and 0.830 against 0.868 ms (inverse CDF) per 2^28
+// outputs, q = 128 in between; the 4-byte Gaussians ran slower at q = 1024.
 uint32_t pick_q(int kind, uint64_t n_each, uint64_t nsub)
 {
     const bool wide = elem_bytes(kind) == 8;
-    const uint64_t groups = wide ? 16384 : 2048;
+    const uint64_t groups = !wide ? 2048 : (kind == kGauss64 || kind == kIcdf64) ? 4096 : 16384;
     uint32_t q = wide ? 16 : 32;   // L outputs per pass
     while (q < 1024 && (uint64_t)kThreads * q * groups < n_each * nsub &&
            (uint64_t)kThreads * q * 2 <= n_each)
