@@ -191,6 +191,21 @@ def time_region(fn, reps, stream, warm=3):
     return a.elapsed_time(b) / reps
 
 
+def settle(fn, stream, seconds=0.03):
+    """Calls `fn()` back to back for at least `seconds` of wall time (a few
+    calls at a time, then a sync).  A cell's first tens of milliseconds after
+    another workload ran measured a few percent slower (the chip's clocks
+    adapt to the new mix), so every cell is timed after this."""
+    import time
+    t0 = time.perf_counter()
+    while True:
+        for _ in range(4):
+            fn()
+        stream.synchronize()
+        if time.perf_counter() - t0 >= seconds:
+            return
+
+
 def time_kernel_calls(fn, reps, stream):
     """Average duration (ms) of `fn()` over `reps` calls, each bracketed by
     HIP events recorded on `stream` (the stream the kernels run on)."""
@@ -831,7 +846,7 @@ def main():
             def gen(engine=engine, kind=kind, s=s, o=o):
                 mr.Engine(engine, s, o).generate(kind, n, big, stream=stream)
 
-            gen()
+            settle(gen, stream)
             ms = time_region(gen, 20, stream)
             nbytes = n * synth.ELEM_BYTES[kind]
             res[name] = {"ms": round(ms, 4), "Gsamples_s": round(n / (ms * 1e-3) / 1e9, 1),
@@ -848,7 +863,7 @@ def main():
             e.generate_substreams(mr.UNIFORM_F64, 0, cfg["count"], cfg["per_stream"], big,
                                   stream=stream)
 
-        subs()
+        settle(subs, stream)
         ms = time_region(subs, 20, stream)
         tot = cfg["count"] * cfg["per_stream"]
         res["mrg32k3a/substreams_65536x4096_f64"] = {
