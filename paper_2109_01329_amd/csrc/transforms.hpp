@@ -116,7 +116,9 @@ __device__ __forceinline__ void bm_stage()
 //   y = the hardware reciprocal square root of L (within 2^-24 on gfx950),
 //   r0 = L y, and 2r = r0 (3 - r0 y), one Newton step whose halving moves
 //   into the rotation table (which holds half of sin and cos).  L = 0
-//   (u1 = 1) gives 0.
+//   (u1 = 1) gives 0: y is taken of L + 2^-100, which is L itself for
+//   every other L (all above 2^-24), one full-rate add where v_max_f64
+//   issues at half rate.
 // The table entry's byte offset j * 32 is ((mi >> 19) - 4080) & 0x1FE0 for
 // mi = m 2^31: mi >> 19 is 4096 (m's leading bit) + 16 g + (4 lower bits)
 // with g m's top 8 fraction bits, so the difference is 16 (g + 1) plus
@@ -133,7 +135,7 @@ __device__ __forceinline__ double bm_radius2(uint32_t wa)
     const double q1 = __builtin_fma(f, -0x1.5555555555555p-1, 1.0);
     const double q2 = __builtin_fma(f, q1, -2.0);
     const double L = __builtin_fma(f, q2, base);
-    const double y = __builtin_amdgcn_rsq(__builtin_fmax(L, 0x1p-100));
+    const double y = __builtin_amdgcn_rsq(L + 0x1p-100);
     const double r0 = L * y;
     return r0 * __builtin_fma(-r0, y, 3.0);
 }
@@ -182,12 +184,13 @@ __device__ __forceinline__ f32x2 box_muller(uint32_t wa, uint32_t wb)
     return z;
 }
 
-// sqrt(x) for x in [0, 80] in FP64, to about one ulp: the refined
-// reciprocal square root y of max(x, 2^-200), then r = x y corrected once,
-// r + (y / 2)(x - r^2); x = 0 gives 0.
+// sqrt(x) for x = 0 or x in [2^-60, 80] in FP64, to about one ulp: the
+// refined reciprocal square root y of xs = x + 2^-200 (x itself but for
+// x = 0; one full-rate add where v_max_f64 issues at half rate), then
+// r = x y corrected once, r + (y / 2)(x - r^2); x = 0 gives 0.
 __device__ __forceinline__ double sqrt_f64(double x)
 {
-    const double xs = __builtin_fmax(x, 0x1p-200);
+    const double xs = x + 0x1p-200;
     const double h = 0.5 * xs;
     double y = __builtin_amdgcn_rsq(xs);
     y = __builtin_fma(y, __builtin_fma(-h * y, y, 0.5), y);
