@@ -316,7 +316,7 @@ struct ChunkPrefix {
     bool regs = false;
 };
 
-__device__ ChunkPrefix chunk_prefix(const BatchArgs &a, int j)
+__device__ __forceinline__ ChunkPrefix chunk_prefix(const BatchArgs &a, int j)
 {
     ChunkPrefix p;
     p.regs = a.nchunks <= kWaveChunks;
@@ -479,9 +479,11 @@ __device__ __forceinline__ void run_kind(const BatchDesc &d, uint32_t s0, uint32
 // BM: the batch holds Gaussian requests (either method, FP32 or FP64),
 // whose log and rotation tables the kernel stages in LDS; batches without
 // them run a kernel that neither stages the tables nor holds their LDS.
+// Forced inline: called as a function (the compiler's choice for the wide
+// instance), every segment stored the descriptor to scratch for the callee.
 template <bool WIDE, bool BM>
-__device__ void run_segment(const BatchDesc &d, uint32_t s0, uint32_t lo, uint32_t hi,
-                            uint32_t lane)
+__device__ __forceinline__ void run_segment(const BatchDesc &d, uint32_t s0, uint32_t lo,
+                                            uint32_t hi, uint32_t lane)
 {
     switch (d.kind) {
     case kBits: run_kind<kBits>(d, s0, lo, hi, lane); break;
