@@ -625,7 +625,7 @@ __device__ void mrg_chunk(const BatchDesc &d, uint64_t k, const uint32_t *c_tab,
 #pragma unroll
         for (int i = 0; i < 6; ++i) v[i] = d.mst[i];
         MrgState hs = mrg_state(v);
-        mrg_fill_row<KIND>(hs, row, d.run.ep);
+        mrg_fill_row<KIND, true>(hs, row, d.run.ep);
         const uint32_t m = d.run.n < h0 ? (uint32_t)d.run.n : h0;
         for (uint32_t e = 0; e < m; ++e) put_elem<S::ESZ>(d.run.out_base, e, row + e * S::ESZ);
     }

@@ -157,100 +157,77 @@ __device__ __forceinline__ char *mrg_row(char *lds, uint32_t t)
     return lds + t * MrgShape<KIND>::ROW + MrgShape<KIND>::OFF;
 }
 
-// Runs L steps of `s` and writes the L outputs into `row` (16-byte aligned).
-// The inverse-CDF kinds evaluate one 16-byte vector of quantiles at a time
-// (a rolled loop) so that the registers of one vector suffice.
+// One 16-byte vector of outputs (EPV of them) from the next steps of `s`.
 template <int KIND>
+__device__ __forceinline__ u32x4 mrg_vec(MrgState &s, const Epilogue &ep)
+{
+    u32x4 pk;
+    if constexpr (KIND == kBits) {
+        pk.x = mrg_step(s); pk.y = mrg_step(s);
+        pk.z = mrg_step(s); pk.w = mrg_step(s);
+    } else if constexpr (KIND == kU32F || KIND == kGauss || KIND == kIcdf) {
+        f32x4 f;
+        if constexpr (KIND == kU32F) {
+            f.x = y_to_u01f(mrg_step(s)); f.y = y_to_u01f(mrg_step(s));
+            f.z = y_to_u01f(mrg_step(s)); f.w = y_to_u01f(mrg_step(s));
+        } else {
+            u32x4 y;
+            y.x = mrg_step(s); y.y = mrg_step(s);
+            y.z = mrg_step(s); y.w = mrg_step(s);
+            if constexpr (KIND == kGauss) {
+                f.xy = box_muller(y.x, y.y);
+                f.zw = box_muller(y.z, y.w);
+            } else {
+                f = icdf4_f32(y);
+            }
+        }
+        if (ep.ranged) {
+            f.x = __builtin_fmaf(f.x, ep.d32, ep.a32);
+            f.y = __builtin_fmaf(f.y, ep.d32, ep.a32);
+            f.z = __builtin_fmaf(f.z, ep.d32, ep.a32);
+            f.w = __builtin_fmaf(f.w, ep.d32, ep.a32);
+        }
+        pk = __builtin_bit_cast(u32x4, f);
+    } else if constexpr (KIND == kI32) {
+        pk.x = uniform_i32(mrg_step(s), ep.ia, ep.irm1);
+        pk.y = uniform_i32(mrg_step(s), ep.ia, ep.irm1);
+        pk.z = uniform_i32(mrg_step(s), ep.ia, ep.irm1);
+        pk.w = uniform_i32(mrg_step(s), ep.ia, ep.irm1);
+    } else {
+        static_assert(KIND == kU64F || KIND == kGauss64 || KIND == kIcdf64, "unknown kind");
+        // u = y / (m1 + 1) as for uniform FP64: never 0 or 1
+        const double u0 = y_to_u01d(mrg_step(s));
+        const double u1 = y_to_u01d(mrg_step(s));
+        f64x2 d;
+        if constexpr (KIND == kU64F)
+            d = f64x2{u0, u1};
+        else if constexpr (KIND == kGauss64)
+            d = box_muller64(u0, u1);
+        else
+            d = normal_quantile2(u0, u1);
+        if (ep.ranged) {
+            d.x = __builtin_fma(d.x, ep.d64, ep.a64);
+            d.y = __builtin_fma(d.y, ep.d64, ep.a64);
+        }
+        pk = __builtin_bit_cast(u32x4, d);
+    }
+    return pk;
+}
+
+// Runs L steps of `s` and writes the L outputs into `row` (16-byte aligned).
+// The inverse-CDF kinds, and ROLLED callers (the one-off head row), evaluate
+// one 16-byte vector at a time in a rolled loop, so that the registers of
+// one vector suffice; the other kinds unroll the row.
+template <int KIND, bool ROLLED = false>
 __device__ __forceinline__ void mrg_fill_row(MrgState &s, char *row, const Epilogue &ep)
 {
     using S = MrgShape<KIND>;
-    if constexpr (KIND == kIcdf || KIND == kIcdf64) {
+    if constexpr (ROLLED || KIND == kIcdf || KIND == kIcdf64) {
 #pragma unroll 1
-        for (int l = 0; l < S::L; l += S::EPV) {
-            if constexpr (KIND == kIcdf) {
-                u32x4 y;
-                y.x = mrg_step(s); y.y = mrg_step(s);
-                y.z = mrg_step(s); y.w = mrg_step(s);
-                f32x4 f = icdf4_f32(y);
-                if (ep.ranged) {
-                    f.x = __builtin_fmaf(f.x, ep.d32, ep.a32);
-                    f.y = __builtin_fmaf(f.y, ep.d32, ep.a32);
-                    f.z = __builtin_fmaf(f.z, ep.d32, ep.a32);
-                    f.w = __builtin_fmaf(f.w, ep.d32, ep.a32);
-                }
-                *(f32x4 *)(row + l * 4) = f;
-            } else {
-                // u = y / (m1 + 1) as for uniform FP64: never 0 or 1
-                const double u0 = y_to_u01d(mrg_step(s));
-                const double u1 = y_to_u01d(mrg_step(s));
-                f64x2 d = normal_quantile2(u0, u1);
-                if (ep.ranged) {
-                    d.x = __builtin_fma(d.x, ep.d64, ep.a64);
-                    d.y = __builtin_fma(d.y, ep.d64, ep.a64);
-                }
-                *(f64x2 *)(row + l * 8) = d;
-            }
-        }
+        for (int v = 0; v < S::VPR; ++v) *(u32x4 *)(row + v * 16) = mrg_vec<KIND>(s, ep);
     } else {
 #pragma unroll
-    for (int l = 0; l < S::L; l += S::EPV) {
-        u32x4 pk;
-        if constexpr (KIND == kBits) {
-            pk.x = mrg_step(s); pk.y = mrg_step(s);
-            pk.z = mrg_step(s); pk.w = mrg_step(s);
-        } else if constexpr (KIND == kU32F) {
-            f32x4 f;
-            f.x = y_to_u01f(mrg_step(s)); f.y = y_to_u01f(mrg_step(s));
-            f.z = y_to_u01f(mrg_step(s)); f.w = y_to_u01f(mrg_step(s));
-            if (ep.ranged) {
-                f.x = __builtin_fmaf(f.x, ep.d32, ep.a32);
-                f.y = __builtin_fmaf(f.y, ep.d32, ep.a32);
-                f.z = __builtin_fmaf(f.z, ep.d32, ep.a32);
-                f.w = __builtin_fmaf(f.w, ep.d32, ep.a32);
-            }
-            pk = __builtin_bit_cast(u32x4, f);
-        } else if constexpr (KIND == kU64F) {
-            f64x2 d;
-            d.x = y_to_u01d(mrg_step(s));
-            d.y = y_to_u01d(mrg_step(s));
-            if (ep.ranged) {
-                d.x = __builtin_fma(d.x, ep.d64, ep.a64);
-                d.y = __builtin_fma(d.y, ep.d64, ep.a64);
-            }
-            pk = __builtin_bit_cast(u32x4, d);
-        } else if constexpr (KIND == kGauss64) {
-            const double u1 = y_to_u01d(mrg_step(s));
-            const double u2 = y_to_u01d(mrg_step(s));
-            f64x2 d = box_muller64(u1, u2);
-            if (ep.ranged) {
-                d.x = __builtin_fma(d.x, ep.d64, ep.a64);
-                d.y = __builtin_fma(d.y, ep.d64, ep.a64);
-            }
-            pk = __builtin_bit_cast(u32x4, d);
-        } else if constexpr (KIND == kI32) {
-            pk.x = uniform_i32(mrg_step(s), ep.ia, ep.irm1);
-            pk.y = uniform_i32(mrg_step(s), ep.ia, ep.irm1);
-            pk.z = uniform_i32(mrg_step(s), ep.ia, ep.irm1);
-            pk.w = uniform_i32(mrg_step(s), ep.ia, ep.irm1);
-        } else {
-            static_assert(KIND == kGauss, "unknown kind");
-            const uint32_t w0 = mrg_step(s);
-            const uint32_t w1 = mrg_step(s);
-            const uint32_t w2 = mrg_step(s);
-            const uint32_t w3 = mrg_step(s);
-            f32x4 f;
-            f.xy = box_muller(w0, w1);
-            f.zw = box_muller(w2, w3);
-            if (ep.ranged) {
-                f.x = __builtin_fmaf(f.x, ep.d32, ep.a32);
-                f.y = __builtin_fmaf(f.y, ep.d32, ep.a32);
-                f.z = __builtin_fmaf(f.z, ep.d32, ep.a32);
-                f.w = __builtin_fmaf(f.w, ep.d32, ep.a32);
-            }
-            pk = __builtin_bit_cast(u32x4, f);
-        }
-        *(u32x4 *)(row + (l / S::EPV) * 16) = pk;
-    }
+        for (int v = 0; v < S::VPR; ++v) *(u32x4 *)(row + v * 16) = mrg_vec<KIND>(s, ep);
     }
 }
 

@@ -144,7 +144,7 @@ __global__ __launch_bounds__(kThreads) void mrg_kernel(MrgLaunch a)
 #pragma unroll
         for (int i = 0; i < 6; ++i) v[i] = wg_head[i];
         MrgState hs = mrg_state(v);
-        mrg_fill_row<KIND>(hs, row, a.ep);
+        mrg_fill_row<KIND, true>(hs, row, a.ep);
         const uint32_t m = a.n_each < h0 ? (uint32_t)a.n_each : h0;
         for (uint32_t k = 0; k < m; ++k) put_elem<S::ESZ>(sub_out, k, row + k * S::ESZ);
     }
